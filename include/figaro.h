@@ -1,0 +1,208 @@
+/*
+ * figaro.h -- C ABI of the MI355X (gfx950) two-table Figaro library.
+ *
+ * The library computes, for two tables A (m1 x n1) and B (m2 x n2) and
+ * their int32 join keys, the upper-triangular factor R of the QR
+ * decomposition of the join matrix J and the singular values of J, without
+ * materialising J ("Figaro on GPUs: Two Tables", Section 1: Theory, the QR
+ * head/tail operators and Claim 1; Experiments section for the R/sigma
+ * pipeline).  J is the natural join of A and B on their keys: the rows
+ * [A_r | B_s] for every pair with key_A[r] == key_B[s]; with no keys it is
+ * the Cartesian product A x B (Section 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named "device" point to GPU memory; everything else is host.
+ *   - All memory is allocated and owned by the caller.  The library never
+ *     allocates on the compute path and never frees caller memory.
+ *   - Calls enqueue work on `stream` (a hipStream_t passed as void*; NULL is
+ *     the default stream) and return without waiting, except those marked
+ *     "synchronous".
+ *   - Matrices are row-major with a leading dimension `ld` (elements, >= cols).
+ *   - Return values are FIGARO_* codes; no exception crosses the ABI.  The
+ *     message of the last failure on the calling thread is available from
+ *     figaro_last_error().
+ *   - Calls that share one workspace race when they overlap on a device.
+ */
+#ifndef FIGARO_H
+#define FIGARO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- codes */
+#define FIGARO_OK 0
+#define FIGARO_EINVAL (-1)      /* invalid argument (null pointer, ld < cols, dtype mismatch, N = 0, keys on one side only, unsupported width) */
+#define FIGARO_EUNSORTED (-2)   /* keys not non-decreasing (detected on the device, reported by figaro_status) */
+#define FIGARO_EWORKSPACE (-3)  /* workspace smaller than the size query returned */
+#define FIGARO_EHIP (-4)        /* HIP runtime error; see figaro_last_error() */
+#define FIGARO_ETIMEOUT (-5)    /* a bounded device-side wait expired (reported by figaro_status) */
+
+/* element types */
+#define FIGARO_F32 0
+#define FIGARO_F64 1
+
+/* precision of the QR reduction */
+#define FIGARO_PLAIN_FP64 0        /* every stage in FP64 (FP32 inputs are widened exactly) */
+#define FIGARO_MIXED_FP32 1        /* compact matrix stored and reduced in FP32 (FP64 scans, FP64 reflector scalars, FP64 root) */
+#define FIGARO_MIXED_FP32_REFINE 2 /* FIGARO_MIXED_FP32 followed by one FP64 refinement sweep against the exact Gram matrix */
+
+/* largest supported join width N = n1 + n2 */
+#define FIGARO_MAX_N 512
+
+/*
+ * One input table.
+ *   data  device, rows x cols, row-major, leading dimension ld, element type dtype.
+ *   keys  device, `rows` int32 join keys, non-decreasing (the paper's inputs
+ *         are sorted by the join attribute, Experiments section); NULL on both
+ *         tables selects the Cartesian product.
+ */
+typedef struct figaro_table {
+    const void *data;
+    int64_t rows, cols, ld;
+    int32_t dtype;
+    const int32_t *keys;
+} figaro_table;
+
+/*
+ * Workspace bytes needed by figaro_r / figaro_compact for these shapes
+ * (host-only, no device access).  The size is an upper bound that does not
+ * depend on key values.  Returns FIGARO_EINVAL for invalid shapes.
+ */
+int figaro_r_workspace_size(const figaro_table *A, const figaro_table *B, int32_t precision,
+                            size_t *bytes);
+
+/*
+ * R of the join matrix (Section 1, Claim 1 and the QR step of the Experiments
+ * section).  Stages, all on the device: key grouping; per-group QR head and
+ * tail of B as scaled prefix sums (head H, tail T of Section 1); assembly of
+ * the compact matrix
+ *     region 1, one row per matched A row r of group g:  [ sqrt(m2_g) A_r | H(B_g) ]
+ *     region 2, m2_g - 1 rows per group:                [ 0 | sqrt(m1_g) T(B_g) ]
+ * Householder TSQR of the compact matrix; rows of R normalised to a
+ * non-negative diagonal (a negative diagonal negates the row, a zero
+ * diagonal negates it iff its first nonzero is negative, -0.0 becomes +0.0).
+ *   R     device, FP64, N x N row-major with leading dimension ldr >= N;
+ *         fully written (zeros below the diagonal).
+ *   ws    device workspace of at least figaro_r_workspace_size() bytes,
+ *         256-byte aligned.  After the call it holds the group table and
+ *         the device status word (read with figaro_status).
+ * An empty join (no common key) gives R = 0.  Unsorted keys give
+ * FIGARO_EUNSORTED from figaro_status and an unspecified R.
+ */
+int figaro_r(const figaro_table *A, const figaro_table *B, int32_t precision,
+             double *R, int64_t ldr, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Only the first stages of figaro_r: grouping, head/tail scan and assembly.
+ * Leaves the group table and the compact matrix in `ws` (locate them with
+ * figaro_inspect).  For tests and diagnostics.
+ */
+int figaro_compact(const figaro_table *A, const figaro_table *B, int32_t precision,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Device addresses, inside `ws`, of the intermediate results of
+ * figaro_compact / figaro_r for these shapes (host-only, no device access).
+ *   counts    int64[4]: G (groups), R1 (region-1 rows), R2 (region-2 rows),
+ *             join_rows (sum over groups of m1_g * m2_g)
+ *   group     int32 arrays of capacity group_cap: key, offA, m1, offB, m2, r1, r2
+ *             (r1_g, r2_g are the first rows of group g in regions 1 and 2)
+ *   heads     FP64, group_cap x n2: H(B_g)
+ *   m1        region 1, rows x N, element type m_dtype, ld = N
+ *   m2        region 2, rows x n2 (the zero block is implicit), element type m_dtype, ld = n2
+ *   status    int32[1], device status word
+ */
+typedef struct figaro_view {
+    int64_t *counts;
+    int32_t *g_key, *g_offA, *g_m1, *g_offB, *g_m2, *g_r1, *g_r2;
+    int64_t group_cap;
+    double *heads;
+    void *m1, *m2;
+    int32_t m_dtype;
+    int32_t *status;
+} figaro_view;
+
+int figaro_inspect(const figaro_table *A, const figaro_table *B, int32_t precision,
+                   void *ws, size_t ws_bytes, figaro_view *out);
+
+/*
+ * Workspace bytes needed by figaro_sigma for an n x n R.
+ */
+int figaro_sigma_workspace_size(int64_t n, size_t *bytes);
+
+/*
+ * Singular values of an upper-triangular R (equal to those of the join
+ * matrix; Related Works: SVD through QR) by one-sided Jacobi in FP64:
+ * Hestenes rotations on column pairs in a parallel (round-robin) order until
+ * a sweep finds every pair orthogonal to |c_p . c_q| <= n 2^-53 |c_p||c_q|
+ * (at most 60 sweeps).
+ *   R      device, FP64, n x n, leading dimension ldr (any square matrix is accepted).
+ *   sigma  device, FP64, n values, descending.
+ *   ws     device workspace of figaro_sigma_workspace_size() bytes.
+ */
+int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Synchronous: waits for `stream`, then reads the device status word left in
+ * `ws` by the last figaro_r / figaro_compact / plan execution that used it.
+ * *code receives FIGARO_OK, FIGARO_EUNSORTED or FIGARO_ETIMEOUT.
+ */
+int figaro_status(const void *ws, void *stream, int32_t *code);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *figaro_last_error(void);
+
+/*
+ * Per-stage device timing, for measurement.  Off by default.  When on, every
+ * kernel launch of the library is bracketed by two hipEventRecord calls on
+ * its stream, under a stage name ("group", "scan", "assemble", "tsqr_leaf_m1",
+ * "tsqr_leaf_m2", "tsqr_tree", "tsqr_root", "sign", "jacobi").
+ * figaro_timing_read is synchronous: it waits for the recorded events, writes
+ * up to `cap` entries (stage name, total milliseconds, number of launches)
+ * accumulated since the previous read, sets *count and clears the record.
+ * Names are static strings owned by the library.
+ */
+int figaro_timing_enable(int32_t on);
+int figaro_timing_read(const char **names, double *ms, int32_t *launches, int32_t cap,
+                       int32_t *count);
+
+/* ------------------------------------------------------------ batching */
+
+/*
+ * A plan runs many independent two-table problems (of uneven sizes) in one
+ * launch sequence, captured once in a HIP graph and replayed by
+ * figaro_plan_execute.  Each instance is a Cartesian product or natural join
+ * exactly as in figaro_r.  Outputs: R_i (FP64, N_i x N_i, row-major, packed
+ * one after another at offsets given by figaro_plan_offsets) and sigma_i.
+ */
+typedef struct figaro_instance {
+    figaro_table A, B;
+} figaro_instance;
+
+typedef struct figaro_plan figaro_plan;
+
+/* Host-only; copies the instance descriptors (the data pointers must stay valid). */
+int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t precision,
+                       figaro_plan **out);
+int figaro_plan_workspace_size(const figaro_plan *plan, size_t *bytes);
+/* r_off[i], s_off[i] (host, count entries): element offsets of R_i and sigma_i; totals in *r_total, *s_total. */
+int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
+                        int64_t *r_total, int64_t *s_total);
+/*
+ * Enqueue the whole batch on `stream`.  The first call with a given
+ * (ws, R, sigma, stream) captures the launch sequence into a HIP graph; later
+ * calls with the same arguments replay it.
+ */
+int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
+                        void *stream);
+void figaro_plan_destroy(figaro_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIGARO_H */

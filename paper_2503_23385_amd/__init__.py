@@ -1,0 +1,283 @@
+"""Python binding of the gfx950 two-table Figaro library (``libfigaro.so``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/figaro.h``.  PyTorch supplies
+device memory and the current HIP stream.  Importing this package does not
+load the library; the first call does, and raises if it is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfigaro.so")
+
+FIGARO_OK = 0
+FIGARO_EINVAL = -1
+FIGARO_EUNSORTED = -2
+FIGARO_EWORKSPACE = -3
+FIGARO_EHIP = -4
+FIGARO_ETIMEOUT = -5
+
+FIGARO_F32 = 0
+FIGARO_F64 = 1
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_refine": 2}
+
+
+class FigaroError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"figaro error {code}: {msg}")
+        self.code = code
+
+
+class Table(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("dtype", ctypes.c_int32), ("keys", ctypes.c_void_p)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("counts", ctypes.c_void_p), ("g_key", ctypes.c_void_p), ("g_offA", ctypes.c_void_p),
+                ("g_m1", ctypes.c_void_p), ("g_offB", ctypes.c_void_p), ("g_m2", ctypes.c_void_p),
+                ("g_r1", ctypes.c_void_p), ("g_r2", ctypes.c_void_p), ("group_cap", ctypes.c_int64),
+                ("heads", ctypes.c_void_p), ("m1", ctypes.c_void_p), ("m2", ctypes.c_void_p),
+                ("m_dtype", ctypes.c_int32), ("status", ctypes.c_void_p)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("A", Table), ("B", Table)]
+
+
+EXPORTS = [
+    "figaro_r_workspace_size", "figaro_r", "figaro_compact", "figaro_inspect",
+    "figaro_sigma_workspace_size", "figaro_sigma", "figaro_status", "figaro_last_error",
+    "figaro_plan_create", "figaro_plan_workspace_size", "figaro_plan_offsets",
+    "figaro_plan_execute", "figaro_plan_destroy", "figaro_timing_enable", "figaro_timing_read",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libfigaro.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python paper_2503_23385_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    TP = ctypes.POINTER(Table)
+    L.figaro_r_workspace_size.argtypes = [TP, TP, I32, ctypes.POINTER(SZ)]
+    L.figaro_r.argtypes = [TP, TP, I32, P, I64, P, SZ, P]
+    L.figaro_compact.argtypes = [TP, TP, I32, P, SZ, P]
+    L.figaro_inspect.argtypes = [TP, TP, I32, P, SZ, ctypes.POINTER(View)]
+    L.figaro_sigma_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
+    L.figaro_sigma.argtypes = [P, I64, I64, P, P, SZ, P]
+    L.figaro_status.argtypes = [P, P, ctypes.POINTER(I32)]
+    L.figaro_last_error.argtypes = []
+    L.figaro_last_error.restype = ctypes.c_char_p
+    L.figaro_plan_create.argtypes = [ctypes.POINTER(Instance), I32, I32, ctypes.POINTER(P)]
+    L.figaro_plan_workspace_size.argtypes = [P, ctypes.POINTER(SZ)]
+    L.figaro_plan_offsets.argtypes = [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    L.figaro_plan_execute.argtypes = [P, P, SZ, P, P, P]
+    L.figaro_plan_destroy.argtypes = [P]
+    L.figaro_plan_destroy.restype = None
+    L.figaro_timing_enable.argtypes = [I32]
+    L.figaro_timing_read.argtypes = [P, P, P, I32, ctypes.POINTER(I32)]
+    for name in EXPORTS:
+        if name not in ("figaro_last_error", "figaro_plan_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != FIGARO_OK:
+        raise FigaroError(rc, lib().figaro_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return FIGARO_F64
+    if t.dtype == torch.float32:
+        return FIGARO_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def make_table(X, keys=None) -> Table:
+    """Describe a device tensor (rows x cols, unit column stride) and optional int32 keys."""
+    torch = _torch()
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("table must be 2-D with unit column stride")
+    if keys is not None:
+        if keys.dtype != torch.int32 or not keys.is_contiguous():
+            raise TypeError("keys must be a contiguous int32 tensor")
+        if keys.numel() != X.shape[0]:
+            raise ValueError("one key per row")
+    ld = X.stride(0) if X.shape[0] > 1 else X.shape[1]
+    return Table(X.data_ptr() if X.numel() else None, X.shape[0], X.shape[1], max(ld, X.shape[1]),
+                 _dtype_code(X), keys.data_ptr() if keys is not None else None)
+
+
+def r_workspace_size(A, B, keys_A=None, keys_B=None, precision="fp64") -> int:
+    ta, tb = make_table(A, keys_A), make_table(B, keys_B)
+    n = ctypes.c_size_t(0)
+    _check(lib().figaro_r_workspace_size(ctypes.byref(ta), ctypes.byref(tb), PRECISIONS[precision],
+                                         ctypes.byref(n)))
+    return n.value
+
+
+def alloc_workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def r(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, out=None, stream=None):
+    """R (N x N, FP64, diag >= 0) of the join of A and B on the device.  Returns (R, ws)."""
+    torch = _torch()
+    ta, tb = make_table(A, keys_A), make_table(B, keys_B)
+    N = A.shape[1] + B.shape[1]
+    if ws is None:
+        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision), A.device)
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.float64, device=A.device)
+    _check(lib().figaro_r(ctypes.byref(ta), ctypes.byref(tb), PRECISIONS[precision],
+                          ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return out, ws
+
+
+def sigma(R, out=None, ws=None, stream=None):
+    """Singular values (descending, FP64) of a square device matrix R."""
+    torch = _torch()
+    n = R.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=R.device)
+    if ws is None:
+        nb = ctypes.c_size_t(0)
+        _check(lib().figaro_sigma_workspace_size(n, ctypes.byref(nb)))
+        ws = alloc_workspace(nb.value, R.device)
+    _check(lib().figaro_sigma(ctypes.c_void_p(R.data_ptr()), n, R.stride(0),
+                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel(), _stream_ptr(stream)))
+    return out
+
+
+def status(ws, stream=None) -> int:
+    code = ctypes.c_int32(0)
+    _check(lib().figaro_status(ctypes.c_void_p(ws.data_ptr()), _stream_ptr(stream), ctypes.byref(code)))
+    return code.value
+
+
+def compact(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, stream=None):
+    """Run grouping, head/tail scan and assembly; return host copies of the intermediates."""
+    torch = _torch()
+    ta, tb = make_table(A, keys_A), make_table(B, keys_B)
+    prec = PRECISIONS[precision]
+    if ws is None:
+        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision), A.device)
+    _check(lib().figaro_compact(ctypes.byref(ta), ctypes.byref(tb), prec,
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return inspect(A, B, keys_A, keys_B, precision, ws, stream)
+
+
+def inspect(A, B, keys_A, keys_B, precision, ws, stream=None):
+    """Copy the group table, counts, heads and compact matrix out of a workspace."""
+    torch = _torch()
+    ta, tb = make_table(A, keys_A), make_table(B, keys_B)
+    v = View()
+    _check(lib().figaro_inspect(ctypes.byref(ta), ctypes.byref(tb), PRECISIONS[precision],
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(v)))
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    base = ws.data_ptr()
+
+    def view(ptr, count, dtype):
+        off = ptr - base
+        esz = torch.empty((), dtype=dtype).element_size()
+        return ws[off:off + count * esz].view(dtype).cpu().numpy()
+
+    counts = view(v.counts, 4, torch.int64)
+    G, R1, R2 = int(counts[0]), int(counts[1]), int(counts[2])
+    groups = {name: view(getattr(v, "g_" + name), G, torch.int32)
+              for name in ("key", "offA", "m1", "offB", "m2", "r1", "r2")}
+    n1, n2 = A.shape[1], B.shape[1]
+    mdt = torch.float64 if v.m_dtype == FIGARO_F64 else torch.float32
+    return {
+        "counts": counts,
+        "groups": groups,
+        "heads": view(v.heads, G * n2, torch.float64).reshape(G, n2),
+        "M1": view(v.m1, R1 * (n1 + n2), mdt).reshape(R1, n1 + n2),
+        "M2": view(v.m2, R2 * n2, mdt).reshape(R2, n2),
+        "status": int(view(v.status, 1, torch.int32)[0]),
+    }
+
+
+def timing_enable(on=True):
+    _check(lib().figaro_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """Per-stage device time {stage: (ms, launches)} since the last read (synchronous)."""
+    cap = 64
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_double * cap)()
+    cnt = (ctypes.c_int32 * cap)()
+    n = ctypes.c_int32(0)
+    _check(lib().figaro_timing_read(ctypes.cast(names, ctypes.c_void_p), ctypes.cast(ms, ctypes.c_void_p),
+                                    ctypes.cast(cnt, ctypes.c_void_p), cap, ctypes.byref(n)))
+    return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(n.value, cap))}
+
+
+class Plan:
+    """Batched plan over many independent two-table instances."""
+
+    def __init__(self, instances, precision="fp64"):
+        """instances: list of (A, B, keys_A, keys_B) device tensors."""
+        self._keep = instances
+        arr = (Instance * len(instances))()
+        for i, (A, B, kA, kB) in enumerate(instances):
+            arr[i].A = make_table(A, kA)
+            arr[i].B = make_table(B, kB)
+        self._arr = arr
+        h = ctypes.c_void_p()
+        _check(lib().figaro_plan_create(arr, len(instances), PRECISIONS[precision], ctypes.byref(h)))
+        self.handle = h
+        nb = ctypes.c_size_t(0)
+        _check(lib().figaro_plan_workspace_size(h, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        import numpy as np
+        self.r_off = np.zeros(len(instances), dtype=np.int64)
+        self.s_off = np.zeros(len(instances), dtype=np.int64)
+        rt, st = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().figaro_plan_offsets(h, self.r_off.ctypes.data_as(ctypes.c_void_p),
+                                         self.s_off.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(rt), ctypes.byref(st)))
+        self.r_total, self.s_total = rt.value, st.value
+
+    def execute(self, ws, R, S, stream=None):
+        _check(lib().figaro_plan_execute(self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                         _stream_ptr(stream)))
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().figaro_plan_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

@@ -1,0 +1,82 @@
+// Internal declarations shared by the host runtime and the kernels of the
+// gfx950 Figaro library.  Nothing here is part of the public ABI (figaro.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace figaro {
+
+// device status codes (mirror the public FIGARO_* codes)
+constexpr int kStatusOk = 0;
+constexpr int kStatusUnsorted = -2;
+constexpr int kStatusTimeout = -5;
+
+// counts[] slots
+enum : int { CNT_G = 0, CNT_R1 = 1, CNT_R2 = 2, CNT_JOIN = 3, CNT_UA = 4, CNT_UB = 5, CNT_SLOTS = 8 };
+
+// Device view of the group table (structure of arrays, ascending key order).
+struct Groups {
+    int32_t *key, *offA, *m1, *offB, *m2, *r1, *r2;
+    int64_t *counts;  // CNT_* slots
+};
+
+// One source of rows for the TSQR stream: `rows` rows (device count if
+// rows_dev != nullptr, else rows_host) of width `width`, placed at column
+// `col_off` of the virtual row; ld in elements.
+struct RowSrc {
+    const void *p;
+    const int64_t *rows_dev;
+    int64_t rows_host;
+    int64_t ld;
+    int32_t col_off;
+    int32_t width;
+};
+
+// Elements handled per block by the grouping kernels.
+constexpr int kGroupBlock = 2048;
+constexpr int kGroupThreads = 256;
+
+// ---------------------------------------------------------------- launchers
+// grouping (kernels_group.hip)
+hipError_t launch_group_init(int32_t *status, int64_t *counts, int32_t *ticket, int32_t *flags,
+                             int64_t nflags, hipStream_t s);
+hipError_t launch_group_cartesian(Groups g, int64_t m1, int64_t m2, hipStream_t s);
+hipError_t launch_group_keys(const int32_t *kA, int64_t m1, const int32_t *kB, int64_t m2,
+                             Groups g, int32_t *blkA, int32_t *blkB, int32_t *runA, int32_t *runB,
+                             int32_t *matchA, int32_t *blkM, int64_t *blkS, int32_t *status,
+                             hipStream_t s);
+
+// head/tail scan and assembly (kernels_scan.hip)
+struct ScanPlan {
+    int q;        // row groups per tile
+    int rpt;      // rows per thread
+    int cpt;      // columns per thread
+    int tile_rows;
+    int64_t ntiles;
+};
+ScanPlan scan_plan(int64_t m2, int64_t n2, int in_bytes);
+hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, int64_t n2,
+                           Groups g, int cartesian, void *M2, int out_f64, double *heads,
+                           int32_t *flags, double *agg, double *incl, int32_t *ticket,
+                           int32_t *status, const ScanPlan &sp, hipStream_t s);
+hipError_t launch_assemble_a(const void *A, int in_f64, int64_t lda, int64_t m1, int64_t n1,
+                             int64_t n2, Groups g, int cartesian, const double *heads, void *M1,
+                             int out_f64, hipStream_t s);
+
+// TSQR (kernels_tsqr.hip)
+int tsqr_padded_width(int n);          // padded template width for n, 0 if unsupported
+int tsqr_block_rows(int np);           // rows per streamed block for padded width np
+// Reduce the rows of s0 (then s1) into nwg triangles of `width` rows x np columns (FP64),
+// triangle b at tri_out + b * tri_stride.  tri_rows > 0 marks sources made of stacked
+// triangles of that many rows (lets a block skip its known-zero leading columns).
+hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, RowSrc s0, RowSrc s1, int nsrc,
+                              int width, int tri_rows, int nwg, double *tri_out,
+                              int64_t tri_stride, hipStream_t s);
+hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,
+                                 int64_t ldr, hipStream_t s);
+
+// Jacobi (kernels_jacobi.hip)
+hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
+                         int32_t *sweeps_out, hipStream_t s);
+
+}  // namespace figaro

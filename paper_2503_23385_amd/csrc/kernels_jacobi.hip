@@ -1,0 +1,122 @@
+// Singular values of R by one-sided (Hestenes) Jacobi in FP64.
+//
+// The singular values of the join matrix equal those of R (Related Works:
+// SVD through QR); the paper obtains them with a dense SVD of R.  Here one
+// workgroup keeps R's columns in LDS and orthogonalises column pairs with
+// plane rotations until every pair satisfies |c_p . c_q| <= n 2^-53 |c_p||c_q|.
+// Pairs are visited in a round-robin (circle) order: each of the n-1 steps of
+// a sweep rotates n/2 disjoint pairs in parallel, so a sweep still meets
+// every pair once.  For a pair with alpha = |c_p|^2, beta = |c_q|^2,
+// gamma = c_p . c_q:
+//     zeta = (beta - alpha) / (2 gamma),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+//     c = 1 / sqrt(1 + t^2),  s = c t,   (c_p, c_q) <- (c c_p - s c_q, s c_p + c c_q).
+// sigma_k = |c_k| after convergence, sorted descending.
+#include "common.h"
+
+namespace figaro {
+namespace {
+
+constexpr int kJacobiThreads = 1024;
+constexpr int kJacobiMaxN = 128;
+
+__global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double *R, int n, int64_t ldr,
+                                                               double *sigma, int max_sweeps,
+                                                               int32_t *sweeps_out)
+{
+    __shared__ double C[kJacobiMaxN * kJacobiMaxN];  // column k at C[k * np]
+    __shared__ double sv[kJacobiMaxN];
+    __shared__ int s_rot;
+    const int tid = threadIdx.x;
+    const int np = n + (n & 1);
+    for (int e = tid; e < np * np; e += kJacobiThreads) {
+        const int k = e / np, i = e - k * np;
+        C[e] = (k < n && i < n) ? R[(int64_t)i * ldr + k] : 0.0;
+    }
+    const int pairs = np / 2;
+    int tpp = 64;
+    while (tpp > 1 && tpp * pairs > kJacobiThreads) tpp >>= 1;
+    const int pair = tid / tpp, sub = tid % tpp;
+    const bool active = pair < pairs;
+    const double tol = (double)n * 0x1p-53;
+    int sweeps = 0;
+    __syncthreads();
+    for (int sweep = 0; sweep < max_sweeps; sweep++) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int step = 0; step < np - 1; step++) {
+            int p = 0, q = 0;
+            if (active) {
+                if (pair == 0) {
+                    p = step;
+                    q = np - 1;
+                } else {
+                    const int m = np - 1;
+                    p = (step + pair) % m;
+                    q = (step - pair + m) % m;
+                }
+                if (p > q) { const int t = p; p = q; q = t; }
+            }
+            double a = 0.0, b = 0.0, g = 0.0;
+            if (active) {
+                const double *cp = C + p * np, *cq = C + q * np;
+                for (int i = sub; i < np; i += tpp) {
+                    const double xp = cp[i], xq = cq[i];
+                    a += xp * xp;
+                    b += xq * xq;
+                    g += xp * xq;
+                }
+            }
+            for (int off = tpp >> 1; off > 0; off >>= 1) {
+                a += __shfl_xor(a, off, 64);
+                b += __shfl_xor(b, off, 64);
+                g += __shfl_xor(g, off, 64);
+            }
+            if (active && fabs(g) > tol * sqrt(a * b)) {
+                const double zeta = (b - a) / (2.0 * g);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = c * t;
+                double *cp = C + p * np, *cq = C + q * np;
+                for (int i = sub; i < np; i += tpp) {
+                    const double xp = cp[i], xq = cq[i];
+                    cp[i] = c * xp - s * xq;
+                    cq[i] = s * xp + c * xq;
+                }
+                if (sub == 0) s_rot = 1;
+            }
+            __syncthreads();
+        }
+        sweeps++;
+        const int any = s_rot;
+        __syncthreads();
+        if (!any) break;
+    }
+    for (int k = tid; k < n; k += kJacobiThreads) {
+        double acc = 0.0;
+        for (int i = 0; i < np; i++) acc += C[k * np + i] * C[k * np + i];
+        sv[k] = sqrt(acc);
+    }
+    __syncthreads();
+    for (int k = tid; k < n; k += kJacobiThreads) {
+        const double v = sv[k];
+        int rank = 0;
+        for (int j = 0; j < n; j++) {
+            const double u = sv[j];
+            rank += (u > v) || (u == v && j < k);
+        }
+        sigma[rank] = v;
+    }
+    if (tid == 0 && sweeps_out) *sweeps_out = sweeps;
+}
+
+}  // namespace
+
+hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
+                         int32_t *sweeps_out, hipStream_t s)
+{
+    if (n <= 0 || n > kJacobiMaxN) return hipErrorInvalidValue;
+    k_jacobi_lds<<<1, kJacobiThreads, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+    return hipGetLastError();
+}
+
+}  // namespace figaro

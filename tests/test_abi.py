@@ -1,0 +1,107 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+declared symbol, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2503_23385_amd as fg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "figaro.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(figaro_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    assert declared_functions() == sorted(fg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = fg.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def table(rows=4, cols=3, ld=None, dtype=fg.FIGARO_F64, data=1, keys=None):
+    return fg.Table(ctypes.c_void_p(data) if data else None, rows, cols, ld if ld is not None else cols,
+                    dtype, ctypes.c_void_p(keys) if keys else None)
+
+
+def ws_size(A, B, prec=0):
+    n = ctypes.c_size_t(0)
+    rc = fg.lib().figaro_r_workspace_size(ctypes.byref(A), ctypes.byref(B), prec, ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_size_ok_and_monotone():
+    rc, n1 = ws_size(table(100, 4), table(100, 4))
+    assert rc == 0 and n1 > 0
+    rc, n2 = ws_size(table(1000, 4), table(1000, 4))
+    assert rc == 0 and n2 > n1
+    rc, nk = ws_size(table(1000, 4, keys=8), table(1000, 4, keys=8))
+    assert rc == 0 and nk > n2
+
+
+@pytest.mark.parametrize("A,B,prec", [
+    (table(4, 3, ld=2), table(), 0),                      # ld < cols
+    (table(dtype=fg.FIGARO_F32), table(), 0),             # dtype mismatch
+    (table(keys=8), table(), 0),                          # keys on one side only
+    (table(cols=0), table(), 0),                          # empty width
+    (table(data=0), table(), 0),                          # null data
+    (table(dtype=7), table(dtype=7), 0),                  # bad dtype
+    (table(), table(), 9),                                # bad precision
+    (table(cols=300), table(cols=300), 1),                # N > 512
+    (table(cols=100), table(cols=100), 0),                # N = 200 > FP64 limit of this build
+])
+def test_invalid_arguments_rejected_on_host(A, B, prec):
+    rc, _ = ws_size(A, B, prec)
+    assert rc == fg.FIGARO_EINVAL
+    msg = fg.lib().figaro_last_error().decode()
+    assert msg
+
+
+def test_figaro_r_host_checks():
+    L = fg.lib()
+    A, B = table(), table()
+    rc, n = ws_size(A, B)
+    # null R
+    assert L.figaro_r(ctypes.byref(A), ctypes.byref(B), 0, None, 6, ctypes.c_void_p(256), n, None) == fg.FIGARO_EINVAL
+    # ldr < N
+    assert L.figaro_r(ctypes.byref(A), ctypes.byref(B), 0, ctypes.c_void_p(256), 5, ctypes.c_void_p(256), n, None) == fg.FIGARO_EINVAL
+    # workspace too small
+    assert L.figaro_r(ctypes.byref(A), ctypes.byref(B), 0, ctypes.c_void_p(256), 6, ctypes.c_void_p(256), n - 1, None) == fg.FIGARO_EWORKSPACE
+    # misaligned workspace
+    assert L.figaro_r(ctypes.byref(A), ctypes.byref(B), 0, ctypes.c_void_p(256), 6, ctypes.c_void_p(264), n, None) == fg.FIGARO_EINVAL
+
+
+def test_sigma_host_checks():
+    L = fg.lib()
+    n = ctypes.c_size_t(0)
+    assert L.figaro_sigma_workspace_size(0, ctypes.byref(n)) == fg.FIGARO_EINVAL
+    assert L.figaro_sigma_workspace_size(8, ctypes.byref(n)) == 0 and n.value > 0
+    assert L.figaro_sigma(None, 8, 8, ctypes.c_void_p(256), ctypes.c_void_p(256), n.value, None) == fg.FIGARO_EINVAL
+    assert L.figaro_sigma(ctypes.c_void_p(256), 8, 4, ctypes.c_void_p(256), ctypes.c_void_p(256), n.value, None) == fg.FIGARO_EINVAL
+
+
+def test_plan_host_checks():
+    L = fg.lib()
+    arr = (fg.Instance * 2)()
+    arr[0].A, arr[0].B = table(10, 3), table(12, 2)
+    arr[1].A, arr[1].B = table(5, 4), table(7, 4)
+    h = ctypes.c_void_p()
+    assert L.figaro_plan_create(arr, 2, 0, ctypes.byref(h)) == 0
+    import numpy as np
+    ro, so = np.zeros(2, np.int64), np.zeros(2, np.int64)
+    rt, st = ctypes.c_int64(), ctypes.c_int64()
+    assert L.figaro_plan_offsets(h, ro.ctypes.data_as(ctypes.c_void_p), so.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(rt), ctypes.byref(st)) == 0
+    assert list(ro) == [0, 25] and list(so) == [0, 5] and rt.value == 25 + 64 and st.value == 13
+    L.figaro_plan_destroy(h)
+    bad = (fg.Instance * 1)()
+    bad[0].A, bad[0].B = table(10, 3, ld=1), table(12, 2)
+    assert L.figaro_plan_create(bad, 1, 0, ctypes.byref(h)) == fg.FIGARO_EINVAL

@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Gates:
+  - group table, counts and offsets: bit-exact;
+  - compact matrix (diagnostic): max |diff| <= 1e-13 * max |M|;
+  - R: relative Frobenius error <= 1e-12 (plain FP64 form), <= 1e-5 (FP32 form);
+  - sigma: relative 2-norm error <= 1e-12 (FP64 Jacobi on the GPU's R vs the oracle's).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from bruteforce import gram_closed_form, relF
+from paper_2503_23385_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL_R = {"fp64": 1e-12, "fp32": 1e-5}
+TOL_S = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(inst, dtype=None):
+    d = dev()
+    A = torch.from_numpy(np.ascontiguousarray(inst.A if dtype is None else inst.A.astype(dtype))).to(d)
+    B = torch.from_numpy(np.ascontiguousarray(inst.B if dtype is None else inst.B.astype(dtype))).to(d)
+    kA = None if inst.keys_A is None else torch.from_numpy(inst.keys_A).to(d)
+    kB = None if inst.keys_B is None else torch.from_numpy(inst.keys_B).to(d)
+    return A, B, kA, kB
+
+
+def fg():
+    import paper_2503_23385_amd as m
+    return m
+
+
+def small_cases():
+    rng = lambda k: W.rng_for(700, k)  # noqa: E731
+    cases = {
+        "cart_tiny": W.random_instance(rng(1), 3, 2, 5, 3),
+        "cart_one_row_B": W.random_instance(rng(2), 50, 3, 1, 4),
+        "cart_one_row_A": W.random_instance(rng(3), 1, 3, 70, 4),
+        "cart_ragged": W.random_instance(rng(4), 4099, 13, 3001, 19),
+        "cart_uniform_paper": W.cartesian_uniform(800, 16, seed_k=5),
+        "keyed_zipf_n64": W.random_instance(rng(6), 20000, 32, 15000, 32, n_values=300, key_skew=1.1),
+        "keyed_uniform_sparse": W.random_instance(rng(7), 5000, 7, 6000, 9, n_values=4000),
+        "keyed_n128": W.random_instance(rng(8), 3000, 64, 3500, 64, n_values=40),
+        "keyed_one_big_group": W.random_instance(rng(9), 40, 5, 50000, 8, n_values=1),
+        "keyed_narrow": W.random_instance(rng(10), 1000, 1, 1200, 1, n_values=30),
+    }
+    # every group has one B row: no tails at all
+    inst = W.random_instance(rng(11), 3000, 6, 1, 5)
+    kB = np.arange(0, 600, dtype=np.int32)
+    B = rng(12).standard_normal((600, 5))
+    kA = np.sort(rng(13).integers(-50, 650, size=3000)).astype(np.int32)
+    cases["keyed_singleton_B"] = W.Instance(inst.A, B, kA, kB)
+    return cases
+
+
+CASES = small_cases()
+
+
+def oracle_results(inst):
+    Ro = oracle.r(inst)
+    return Ro, oracle.sigma(Ro)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_groups_bit_exact(name):
+    inst = CASES[name]
+    say(f"[groups] {name} shape={inst.shape}")
+    A, B, kA, kB = to_dev(inst)
+    out = fg().compact(A, B, kA, kB, "fp64")
+    assert out["status"] == 0
+    if inst.keys_A is None:
+        tab, counts = oracle.groups(None, None, inst.A.shape[0], inst.B.shape[0])
+    else:
+        tab, counts = oracle.groups(inst.keys_A, inst.keys_B)
+    assert np.array_equal(out["counts"], counts), (out["counts"], counts)
+    G = int(counts[0])
+    got = np.stack([out["groups"][k] for k in ("key", "offA", "m1", "offB", "m2", "r1", "r2")], axis=1)
+    assert np.array_equal(got.astype(np.int64), tab[:G])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_compact_matrix_diagnostic(name):
+    inst = CASES[name]
+    say(f"[compact] {name}")
+    A, B, kA, kB = to_dev(inst)
+    out = fg().compact(A, B, kA, kB, "fp64")
+    M, heads, tab, counts = oracle.compact(inst)
+    R1, R2 = int(counts[1]), int(counts[2])
+    n1 = inst.A.shape[1]
+    scale = max(1.0, np.abs(M).max() if M.size else 1.0)
+    assert out["M1"].shape == (R1, M.shape[1]) and out["M2"].shape == (R2, inst.B.shape[1])
+    if R1:
+        assert np.abs(out["M1"] - M[:R1]).max() <= 1e-13 * scale
+    if R2:
+        assert np.abs(out["M2"] - M[R1:, n1:]).max() <= 1e-13 * scale
+    if heads.size:
+        assert np.abs(out["heads"] - heads).max() <= 1e-13 * max(1.0, np.abs(heads).max())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_r_and_sigma_parity(name, prec):
+    inst = CASES[name]
+    say(f"[r+sigma] {name} {prec}")
+    A, B, kA, kB = to_dev(inst)
+    R, ws = fg().r(A, B, kA, kB, prec)
+    S = fg().sigma(R)
+    torch.cuda.synchronize()
+    assert fg().status(ws) == 0
+    Ro, So = oracle_results(inst)
+    Rg, Sg = R.cpu().numpy(), S.cpu().numpy()
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) >= 0)
+    d = np.abs(np.diag(Ro))
+    if d.size and d.min() <= 1e-10 * max(d.max(), 1e-300):
+        # rank deficient: R not unique beyond the rank (parity unpinned); check R^T R only
+        Gm = gram_closed_form(inst)
+        assert np.allclose(Rg.T @ Rg, Gm, rtol=1e-10, atol=1e-10 * max(1, np.abs(Gm).max()))
+        return
+    er = relF(Rg, Ro)
+    es = np.linalg.norm(Sg - So) / max(np.linalg.norm(So), 1e-300)
+    say(f"    relF(R)={er:.3e} rel2(sigma)={es:.3e}")
+    assert er <= TOL_R[prec]
+    assert es <= TOL_S[prec]
+
+
+def test_fp32_inputs_widened_exactly():
+    inst = CASES["keyed_zipf_n64"]
+    i32 = W.Instance(inst.A.astype(np.float32), inst.B.astype(np.float32), inst.keys_A, inst.keys_B)
+    A, B, kA, kB = to_dev(i32)
+    R, ws = fg().r(A, B, kA, kB, "fp64")
+    Ro = oracle.r(i32)
+    assert relF(R.cpu().numpy(), Ro) <= 1e-12
+
+
+def test_empty_join():
+    inst = W.Instance(np.ones((10, 3)), np.ones((8, 2)), np.arange(10, dtype=np.int32),
+                      np.arange(100, 108, dtype=np.int32))
+    A, B, kA, kB = to_dev(inst)
+    R, ws = fg().r(A, B, kA, kB, "fp64")
+    S = fg().sigma(R)
+    assert torch.count_nonzero(R).item() == 0 and torch.count_nonzero(S).item() == 0
+    out = fg().compact(A, B, kA, kB, "fp64")
+    assert list(out["counts"]) == [0, 0, 0, 0]
+
+
+def test_unsorted_keys_reported():
+    inst = W.random_instance(W.rng_for(701), 100, 3, 100, 3, n_values=10)
+    kA = inst.keys_A.copy()
+    kA[10], kA[90] = kA[90], kA[10]
+    bad = W.Instance(inst.A, inst.B, kA, inst.keys_B)
+    A, B, kA_d, kB_d = to_dev(bad)
+    R, ws = fg().r(A, B, kA_d, kB_d, "fp64")
+    assert fg().status(ws) == fg().FIGARO_EUNSORTED
+
+
+def test_deterministic():
+    inst = CASES["keyed_zipf_n64"]
+    A, B, kA, kB = to_dev(inst)
+    R1, ws = fg().r(A, B, kA, kB, "fp64")
+    R1 = R1.clone()
+    S1 = fg().sigma(R1).clone()
+    R2, _ = fg().r(A, B, kA, kB, "fp64", ws=ws)
+    S2 = fg().sigma(R2)
+    assert torch.equal(R1, R2) and torch.equal(S1, S2)
+
+
+def test_strided_inputs():
+    inst = W.random_instance(W.rng_for(702), 2000, 6, 2500, 10, n_values=50)
+    A, B, kA, kB = to_dev(inst)
+    Abig = torch.zeros((2000, 11), dtype=torch.float64, device=A.device)
+    Abig[:, 2:8] = A
+    Bbig = torch.zeros((2500, 17), dtype=torch.float64, device=A.device)
+    Bbig[:, 5:15] = B
+    R, ws = fg().r(Abig[:, 2:8], Bbig[:, 5:15], kA, kB, "fp64")
+    assert relF(R.cpu().numpy(), oracle.r(inst)) <= 1e-12
+
+
+# ------------------------------------------------------------------ full sizes
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_full_config_parity(cfg):
+    inst = W.CONFIGS[cfg]()
+    say(f"[full] config {cfg} shape={inst.shape}")
+    A, B, kA, kB = to_dev(inst)
+    R, ws = fg().r(A, B, kA, kB, "fp64")
+    S = fg().sigma(R)
+    torch.cuda.synchronize()
+    Ro, So = oracle_results(inst)
+    er = relF(R.cpu().numpy(), Ro)
+    es = np.linalg.norm(S.cpu().numpy() - So) / np.linalg.norm(So)
+    say(f"    relF(R)={er:.3e} rel2(sigma)={es:.3e}")
+    assert er <= 1e-12 and es <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_config3(prec):
+    inst = W.config3()
+    say(f"[full] config 3 {prec}")
+    A, B, kA, kB = to_dev(inst)
+    out = fg().compact(A, B, kA, kB, prec)
+    tab, counts = oracle.groups(inst.keys_A, inst.keys_B)
+    assert np.array_equal(out["counts"], counts)
+    got = np.stack([out["groups"][k] for k in ("key", "offA", "m1", "offB", "m2", "r1", "r2")], axis=1)
+    assert np.array_equal(got.astype(np.int64), tab)
+    del out
+    R, ws = fg().r(A, B, kA, kB, prec)
+    S = fg().sigma(R)
+    torch.cuda.synchronize()
+    # property that holds at any size: R is the Cholesky factor of J^T J (closed-form Gram)
+    L = np.linalg.cholesky(gram_closed_form(inst))
+    er = relF(R.cpu().numpy(), L.T)
+    say(f"    relF(R vs chol(Gram))={er:.3e}")
+    assert er <= TOL_R[prec]
