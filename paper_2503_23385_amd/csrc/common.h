@@ -55,10 +55,12 @@ struct ScanPlan {
     int64_t ntiles;
 };
 ScanPlan scan_plan(int64_t m2, int64_t n2, int in_bytes);
+// Three launches: tile reduce, carry scan, tile write (tileF: ntiles ints; tileS, carry:
+// ntiles x n2 doubles of scratch).
 hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, int64_t n2,
                            Groups g, int cartesian, void *M2, int out_f64, double *heads,
-                           int32_t *flags, double *agg, double *incl, int32_t *ticket,
-                           int32_t *status, const ScanPlan &sp, hipStream_t s);
+                           int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp,
+                           hipStream_t s);
 hipError_t launch_assemble_a(const void *A, int in_f64, int64_t lda, int64_t m1, int64_t n1,
                              int64_t n2, Groups g, int cartesian, const double *heads, void *M1,
                              int out_f64, hipStream_t s);

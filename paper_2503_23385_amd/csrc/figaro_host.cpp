@@ -111,7 +111,7 @@ struct Layout {
     size_t blkA, blkB, runA, runB, matchA, blkM, blkS;
     size_t g[7];
     int64_t gcap;
-    size_t heads, flags, agg, incl;
+    size_t heads, tileF, tileS, carry;
     size_t M1, M2;
     int m_f64;
     size_t triA[2], triB[2];
@@ -123,9 +123,9 @@ struct Layout {
     int nbA, nbB;
 };
 
-constexpr int kTreeArity = 4;
-constexpr int kRootMax = 4;
-constexpr int kMaxLeaves = 2048;
+constexpr int kTreeArity = 2;
+constexpr int kRootMax = 2;
+constexpr int kMaxLeaves = 4096;
 
 TreePlan plan_tree(int64_t rows_upper, int width, int col_off, int np_root_acc)
 {
@@ -135,7 +135,7 @@ TreePlan plan_tree(int64_t rows_upper, int width, int col_off, int np_root_acc)
     t.width = width;
     t.col_off = col_off;
     const int br = tsqr_block_rows(t.np);
-    const int64_t per_wg = std::max<int64_t>(4 * (int64_t)width, 8 * (int64_t)br);
+    const int64_t per_wg = std::max<int64_t>(2 * (int64_t)width, 4 * (int64_t)br);
     int64_t leaves = (rows_upper + per_wg - 1) / per_wg;
     leaves = std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxLeaves));
     t.leaves = (int)leaves;
@@ -223,9 +223,9 @@ Layout make_layout(const Shape &s)
     L.m_f64 = s.precision == FIGARO_PLAIN_FP64;
     const size_t esz = L.m_f64 ? 8 : 4;
     L.sp = scan_plan(s.m2, s.n2, s.in_f64 ? 8 : 4);
-    L.flags = take(sizeof(int32_t) * std::max<int64_t>(1, L.sp.ntiles));
-    L.agg = take(sizeof(double) * std::max<int64_t>(1, L.sp.ntiles) * s.n2);
-    L.incl = take(sizeof(double) * std::max<int64_t>(1, L.sp.ntiles) * s.n2);
+    L.tileF = take(sizeof(int32_t) * std::max<int64_t>(1, L.sp.ntiles));
+    L.tileS = take(sizeof(double) * std::max<int64_t>(1, L.sp.ntiles) * s.n2);
+    L.carry = take(sizeof(double) * std::max<int64_t>(1, L.sp.ntiles) * s.n2);
     const int64_t N = s.N();
     L.M1 = take(esz * std::max<int64_t>(1, s.m1) * N);
     L.M2 = take(esz * std::max<int64_t>(1, s.m2 - 1) * s.n2);
@@ -282,10 +282,8 @@ int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, c
 {
     Groups g = groups_of(ws, L);
     int32_t *status = at<int32_t>(ws, L.status);
-    int32_t *ticket = at<int32_t>(ws, L.ticket);
-    int32_t *flags = at<int32_t>(ws, L.flags);
     Stage st_group("group", s);
-    HIPCHK(launch_group_init(status, g.counts, ticket, flags, L.sp.ntiles, s), "init");
+    HIPCHK(launch_group_init(status, g.counts, nullptr, nullptr, 0, s), "init");
     if (sh.keyed) {
         HIPCHK(launch_group_keys(A->keys, sh.m1, B->keys, sh.m2, g, at<int32_t>(ws, L.blkA),
                                  at<int32_t>(ws, L.blkB), at<int32_t>(ws, L.runA),
@@ -299,8 +297,8 @@ int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, c
     {
     Stage st("scan", s);
     HIPCHK(launch_seg_scan(B->data, sh.in_f64, sh.ldb, sh.m2, sh.n2, g, !sh.keyed,
-                           at<void>(ws, L.M2), L.m_f64, heads, flags, at<double>(ws, L.agg),
-                           at<double>(ws, L.incl), ticket, status, L.sp, s),
+                           at<void>(ws, L.M2), L.m_f64, heads, at<int32_t>(ws, L.tileF),
+                           at<double>(ws, L.tileS), at<double>(ws, L.carry), L.sp, s),
            "head/tail scan");
     }
     Stage st_asm("assemble", s);

@@ -11,73 +11,88 @@
 //     zeta = (beta - alpha) / (2 gamma),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 //     c = 1 / sqrt(1 + t^2),  s = c t,   (c_p, c_q) <- (c c_p - s c_q, s c_p + c c_q).
 // sigma_k = |c_k| after convergence, sorted descending.
+//
+// Eight lanes share a pair: each holds n/8 rows of both columns, the three
+// dot products are reduced with DPP moves inside the lane octet, and one
+// workgroup barrier separates the steps.
 #include "common.h"
 
 namespace figaro {
 namespace {
 
-constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiMaxN = 128;
+constexpr int kLanesPerPair = 8;
 
-__global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double *R, int n, int64_t ldr,
-                                                               double *sigma, int max_sweeps,
-                                                               int32_t *sweeps_out)
+// Sum over the 8-lane group (lanes 8g..8g+7) with DPP: xor 1, xor 2, then the
+// mirror of the half-row (lane i <-> 7 - i), which swaps the two quads.
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double octet_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    return v;
+}
+
+__global__ __launch_bounds__(512) void k_jacobi_lds(const double *R, int n, int64_t ldr,
+                                                    double *sigma, int max_sweeps,
+                                                    int32_t *sweeps_out)
 {
     __shared__ double C[kJacobiMaxN * kJacobiMaxN];  // column k at C[k * np]
     __shared__ double sv[kJacobiMaxN];
     __shared__ int s_rot;
     const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
     const int np = n + (n & 1);
-    for (int e = tid; e < np * np; e += kJacobiThreads) {
+    for (int e = tid; e < np * np; e += nthr) {
         const int k = e / np, i = e - k * np;
         C[e] = (k < n && i < n) ? R[(int64_t)i * ldr + k] : 0.0;
     }
     const int pairs = np / 2;
-    int tpp = 64;
-    while (tpp > 1 && tpp * pairs > kJacobiThreads) tpp >>= 1;
-    const int pair = tid / tpp, sub = tid % tpp;
+    const int pair = tid / kLanesPerPair, sub = tid % kLanesPerPair;
     const bool active = pair < pairs;
-    const double tol = (double)n * 0x1p-53;
+    const double tol2 = ((double)n * 0x1p-53) * ((double)n * 0x1p-53);
+    const int m = np - 1;
     int sweeps = 0;
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; sweep++) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
-        for (int step = 0; step < np - 1; step++) {
+        for (int step = 0; step < m; step++) {
             int p = 0, q = 0;
-            if (active) {
-                if (pair == 0) {
-                    p = step;
-                    q = np - 1;
-                } else {
-                    const int m = np - 1;
-                    p = (step + pair) % m;
-                    q = (step - pair + m) % m;
-                }
-                if (p > q) { const int t = p; p = q; q = t; }
+            if (pair == 0) {
+                p = step;
+                q = np - 1;
+            } else if (active) {
+                p = (step + pair) % m;
+                q = (step - pair + m) % m;
             }
+            if (p > q) { const int t = p; p = q; q = t; }
+            double *cp = C + p * np, *cq = C + q * np;
             double a = 0.0, b = 0.0, g = 0.0;
             if (active) {
-                const double *cp = C + p * np, *cq = C + q * np;
-                for (int i = sub; i < np; i += tpp) {
+                for (int i = sub; i < np; i += kLanesPerPair) {
                     const double xp = cp[i], xq = cq[i];
                     a += xp * xp;
                     b += xq * xq;
                     g += xp * xq;
                 }
             }
-            for (int off = tpp >> 1; off > 0; off >>= 1) {
-                a += __shfl_xor(a, off, 64);
-                b += __shfl_xor(b, off, 64);
-                g += __shfl_xor(g, off, 64);
-            }
-            if (active && fabs(g) > tol * sqrt(a * b)) {
+            a = octet_sum(a);
+            b = octet_sum(b);
+            g = octet_sum(g);
+            if (active && g * g > tol2 * a * b) {
                 const double zeta = (b - a) / (2.0 * g);
                 const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t);
                 const double s = c * t;
-                double *cp = C + p * np, *cq = C + q * np;
-                for (int i = sub; i < np; i += tpp) {
+                for (int i = sub; i < np; i += kLanesPerPair) {
                     const double xp = cp[i], xq = cq[i];
                     cp[i] = c * xp - s * xq;
                     cq[i] = s * xp + c * xq;
@@ -91,13 +106,13 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double *R, 
         __syncthreads();
         if (!any) break;
     }
-    for (int k = tid; k < n; k += kJacobiThreads) {
+    for (int k = tid; k < n; k += nthr) {
         double acc = 0.0;
         for (int i = 0; i < np; i++) acc += C[k * np + i] * C[k * np + i];
         sv[k] = sqrt(acc);
     }
     __syncthreads();
-    for (int k = tid; k < n; k += kJacobiThreads) {
+    for (int k = tid; k < n; k += nthr) {
         const double v = sv[k];
         int rank = 0;
         for (int j = 0; j < n; j++) {
@@ -115,7 +130,10 @@ hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int
                          int32_t *sweeps_out, hipStream_t s)
 {
     if (n <= 0 || n > kJacobiMaxN) return hipErrorInvalidValue;
-    k_jacobi_lds<<<1, kJacobiThreads, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+    const int np = n + (n & 1);
+    int threads = (np / 2) * kLanesPerPair;
+    threads = ((threads + 63) / 64) * 64;
+    k_jacobi_lds<<<1, threads, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
     return hipGetLastError();
 }
 

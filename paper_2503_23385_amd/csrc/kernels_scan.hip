@@ -4,13 +4,18 @@
 // T(B)_i = (sqrt(i) B_{i+1} - S_i / sqrt(i)) / sqrt(i+1) with S_i the sum of the
 // first i rows, and Claim 1's compact form).
 //
-// Head/tail: one pass over B.  Rows are cut into tiles; a tile is taken by a
-// workgroup in ticket order, each thread owns one column (or two) of a
-// contiguous run of rows, keeps the rows in registers and accumulates FP64
-// running sums that restart at every group start.  Carries across tiles come
-// from a decoupled look-back over per-tile aggregates, so B is read from HBM
-// exactly once.  A tail row i of group g goes to region-2 row r2_g + i - 1,
-// scaled by sqrt(m1_g); the head goes to heads[g] (FP64).
+// Head/tail: a segmented column scan of B (sums restart at every group start),
+// accumulated in FP64 whatever the input or storage type.  Three launches:
+//   1. tile reduce: each tile of rows produces its segmented aggregate
+//      (F = "a group starts in the tile", S = column sums since the last start);
+//   2. carry scan: one workgroup scans the tile aggregates in a fixed order and
+//      writes, per tile, the sums carried into its first (continuing) group;
+//   3. tile write: each tile rescans its rows with the carry and writes tail
+//      row i of group g to region-2 row r2_g + i - 1, scaled by sqrt(m1_g), and
+//      the head of a group that ends in the tile to heads[g].
+// Every sum is formed in the same order on every run (no atomics, no
+// timing-dependent look-back), so results are bitwise reproducible.  The
+// second read of B is served by the Infinity Cache when B fits in it.
 //
 // Region 1: row r of A in group g becomes [sqrt(m2_g) A_r | H(B_g)] at row
 // r1_g + (r - offA_g).
@@ -22,9 +27,7 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kMaxTileRows = 512;
 constexpr int kMaxCols = 512;
-constexpr int kLookbackSpinLimit = 1 << 24;
-
-constexpr int FLAG_EMPTY = 0, FLAG_AGG = 1, FLAG_INCL = 2;
+constexpr int kCarryThreads = 1024;
 
 template <typename T>
 __device__ inline double to_f64(T v) { return (double)v; }
@@ -52,11 +55,12 @@ __device__ inline int first_end_gt(const int32_t *start, const int32_t *size, in
     return lo;
 }
 
-template <typename Tin, typename Tout, int CPT, int RPT>
-__global__ __launch_bounds__(kScanThreads) void k_seg_scan(
+// One tile of B rows: reduce (WRITE = false) or write tails/heads (WRITE = true).
+template <typename Tin, typename Tout, int CPT, int RPT, bool WRITE>
+__global__ __launch_bounds__(kScanThreads) void k_seg_tile(
     const Tin *__restrict__ B, int64_t ldb, int m2, int n2, int Q, Groups g, int cartesian,
-    Tout *__restrict__ M2, double *__restrict__ heads, int32_t *flags, double *agg, double *incl,
-    int32_t *ticket, int32_t *status, int ntiles)
+    Tout *__restrict__ M2, double *__restrict__ heads, int32_t *__restrict__ tileF,
+    double *__restrict__ tileS, const double *__restrict__ carry)
 {
     const int tid = threadIdx.x;
     const int ncolthr = (n2 + CPT - 1) / CPT;
@@ -64,22 +68,17 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(
     const int q = tid / ncolthr;
     const bool active = q < Q;
     const int TR = Q * RPT;
+    const int t = blockIdx.x;
+    const int64_t t0 = (int64_t)t * TR;
+    const int G = (int)g.counts[CNT_G];
 
-    __shared__ int s_tile, s_g0, s_need;
+    __shared__ int s_g0;
     __shared__ int m_g[kMaxTileRows], m_pos[kMaxTileRows], m_out[kMaxTileRows];
     __shared__ double m_c1[kMaxTileRows], m_c2[kMaxTileRows], m_hs[kMaxTileRows];
     __shared__ int a_f[kScanThreads];
     __shared__ double a_s[kMaxCols];
-    __shared__ double carry[kMaxCols];
 
-    if (tid == 0) s_tile = atomicAdd(ticket, 1);
-    __syncthreads();
-    const int t = s_tile;
-    if (t >= ntiles) return;  // uniform
-    const int64_t t0 = (int64_t)t * TR;
-    const int G = (int)g.counts[CNT_G];
-
-    // Issue the tile's loads first; they stay in flight during the row metadata search.
+    // The tile's loads are issued first; they stay in flight during the metadata search.
     double x[RPT][CPT];
 #pragma unroll
     for (int i = 0; i < RPT; i++) {
@@ -112,7 +111,7 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(
         }
         m_g[r] = gi;
         m_pos[r] = pos;
-        if (gi >= 0) {
+        if (WRITE && gi >= 0) {
             const double sm1 = sqrt((double)g.m1[gi]);
             const int m2g = g.m2[gi];
             m_out[r] = g.r2[gi] + pos - 1;
@@ -126,7 +125,7 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(
     }
     __syncthreads();
 
-    // Thread aggregate over its rows: (f, s) with f = "a segment starts here".
+    // Thread aggregate over its rows: (f, s), f = "a segment starts in these rows".
     int f = 0;
     double sacc[CPT];
 #pragma unroll
@@ -145,17 +144,13 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(
                 for (int cc = 0; cc < CPT; cc++) sacc[cc] += x[i][cc];
             }
         }
-    }
-    // Row-group aggregates to LDS: a_f[q], a_s[q * n2 + col].
-    if (active && c == 0) a_f[q] = f;
-    if (active) {
+        if (c == 0) a_f[q] = f;
 #pragma unroll
         for (int cc = 0; cc < CPT; cc++) {
             const int col = c + cc * ncolthr;
             if (col < n2) a_s[q * n2 + col] = sacc[cc];
         }
     }
-    if (tid == 0) s_need = (m_g[0] >= 0 && m_pos[0] > 0) ? 1 : 0;
     __syncthreads();
 
     // Exclusive prefix over earlier row groups (e) and the tile aggregate (F, S).
@@ -177,93 +172,27 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(
             F |= af;
         }
     }
-    // Every thread computed the same F (it depends on rows only); thread 0's copy is used.
-    __shared__ int s_F;
-    if (tid == 0) s_F = F;
-    __syncthreads();
-    const int tileF = s_F;
-    const int need = s_need;
 
-    // Publish this tile's aggregate (or its inclusive prefix when it holds a segment start).
-    if (active && q == 0) {
-#pragma unroll
-        for (int cc = 0; cc < CPT; cc++) {
-            const int col = c + cc * ncolthr;
-            if (col < n2) {
-                if (tileF || t == 0) incl[(int64_t)t * n2 + col] = S[cc];
-                else agg[(int64_t)t * n2 + col] = S[cc];
-            }
-        }
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&flags[t], (tileF || t == 0) ? FLAG_INCL : FLAG_AGG, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
-
-    // Decoupled look-back for the carry into the tile's first (continuing) group.
-    if (need && tid < 64) {
-        double acc[kMaxCols / 64];
-#pragma unroll
-        for (int k = 0; k < kMaxCols / 64; k++) acc[k] = 0.0;
-        int j = t - 1;
-        int spins = 0;
-        bool timed_out = false;
-        while (j >= 0) {
-            int fl = __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            while (fl == FLAG_EMPTY) {
-                if (++spins > kLookbackSpinLimit) { timed_out = true; break; }
-                __builtin_amdgcn_s_sleep(2);
-                fl = __hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (timed_out) break;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const double *src = (fl == FLAG_INCL) ? incl : agg;
-#pragma unroll
-            for (int k = 0; k < kMaxCols / 64; k++) {
-                const int col = tid + 64 * k;
-                if (col < n2)
-                    acc[k] += __hip_atomic_load(&src[(int64_t)j * n2 + col], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (fl == FLAG_INCL) break;
-            j--;
-        }
-        if (timed_out && tid == 0) atomicExch(status, kStatusTimeout);
-#pragma unroll
-        for (int k = 0; k < kMaxCols / 64; k++) {
-            const int col = tid + 64 * k;
-            if (col < n2) carry[col] = acc[k];
-        }
-    }
-    __syncthreads();
-
-    if (need && !tileF) {
-        // Inclusive prefix for successors: carry + this tile's sum.
+    if (!WRITE) {
         if (active && q == 0) {
 #pragma unroll
             for (int cc = 0; cc < CPT; cc++) {
                 const int col = c + cc * ncolthr;
-                if (col < n2) incl[(int64_t)t * n2 + col] = carry[col] + S[cc];
+                if (col < n2) tileS[(int64_t)t * n2 + col] = S[cc];
             }
+            if (c == 0) tileF[t] = F;
         }
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(&flags[t], FLAG_INCL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        return;
     }
 
     // Second pass: tails and heads with the running FP64 prefix.
     if (!active) return;
+    const bool need = m_g[0] >= 0 && m_pos[0] > 0;  // tile starts inside a group
     double run[CPT];
 #pragma unroll
     for (int cc = 0; cc < CPT; cc++) {
         const int col = c + cc * ncolthr;
-        const double cin = (need && col < n2) ? carry[col] : 0.0;
+        const double cin = (need && col < n2) ? carry[(int64_t)t * n2 + col] : 0.0;
         run[cc] = (ef ? 0.0 : cin) + es[cc];
     }
 #pragma unroll
@@ -298,6 +227,54 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(
                 if (col < n2) heads[(int64_t)gi * n2 + col] = run[cc] * hs;
             }
         }
+    }
+}
+
+// Exclusive segmented scan of the tile aggregates, per column, in a fixed order:
+// carry[t] = sums carried into tile t.  One workgroup: columns x tile segments.
+__global__ __launch_bounds__(kCarryThreads) void k_carry_scan(const int32_t *__restrict__ tileF,
+                                                              const double *__restrict__ tileS,
+                                                              double *__restrict__ carry, int T,
+                                                              int n2)
+{
+    const int CT = min(n2, kCarryThreads);
+    const int NS = kCarryThreads / CT;
+    const int tid = threadIdx.x;
+    const int c0 = tid % CT, sg = tid / CT;
+    const bool active = sg < NS;
+    const int L = (T + NS - 1) / NS;
+    const int tb = sg * L, te = min(T, tb + L);
+    __shared__ int segF[kCarryThreads];
+    __shared__ double segS[kCarryThreads];
+    for (int c = c0; c < n2; c += CT) {
+        int F = 0;
+        double S = 0.0;
+        if (active) {
+            for (int t = tb; t < te; t++) {
+                const int ft = tileF[t];
+                const double st = tileS[(int64_t)t * n2 + c];
+                S = ft ? st : S + st;
+                F |= ft;
+            }
+            segF[sg * CT + c0] = F;
+            segS[sg * CT + c0] = S;
+        }
+        __syncthreads();
+        if (active) {
+            double run = 0.0;
+            for (int s = 0; s < sg; s++) {
+                const int fs = segF[s * CT + c0];
+                const double ss = segS[s * CT + c0];
+                run = fs ? ss : run + ss;
+            }
+            for (int t = tb; t < te; t++) {
+                carry[(int64_t)t * n2 + c] = run;
+                const int ft = tileF[t];
+                const double st = tileS[(int64_t)t * n2 + c];
+                run = ft ? st : run + st;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -365,28 +342,39 @@ ScanPlan scan_plan(int64_t m2, int64_t n2, int in_bytes)
 
 hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, int64_t n2,
                            Groups g, int cartesian, void *M2, int out_f64, double *heads,
-                           int32_t *flags, double *agg, double *incl, int32_t *ticket,
-                           int32_t *status, const ScanPlan &sp, hipStream_t s)
+                           int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp,
+                           hipStream_t s)
 {
     if (sp.ntiles == 0) return hipSuccess;
     if (n2 > kMaxCols) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)sp.ntiles;
-#define FIGARO_SCAN(TI, TO, CPT)                                                                  \
-    k_seg_scan<TI, TO, CPT, 16><<<grid, kScanThreads, 0, s>>>(                                   \
-        (const TI *)B, ldb, (int)m2, (int)n2, sp.q, g, cartesian, (TO *)M2, heads, flags, agg,    \
-        incl, ticket, status, (int)sp.ntiles)
-    if (sp.cpt == 1) {
-        if (in_f64 && out_f64) FIGARO_SCAN(double, double, 1);
-        else if (in_f64) FIGARO_SCAN(double, float, 1);
-        else if (out_f64) FIGARO_SCAN(float, double, 1);
-        else FIGARO_SCAN(float, float, 1);
-    } else {
-        if (in_f64 && out_f64) FIGARO_SCAN(double, double, 2);
-        else if (in_f64) FIGARO_SCAN(double, float, 2);
-        else if (out_f64) FIGARO_SCAN(float, double, 2);
-        else FIGARO_SCAN(float, float, 2);
-    }
-#undef FIGARO_SCAN
+#define FIGARO_TILE(TI, TO, CPT, WR)                                                              \
+    k_seg_tile<TI, TO, CPT, 16, WR><<<grid, kScanThreads, 0, s>>>(                               \
+        (const TI *)B, ldb, (int)m2, (int)n2, sp.q, g, cartesian, (TO *)M2, heads, tileF, tileS,  \
+        carry)
+#define FIGARO_TILE_ALL(WR)                                                                       \
+    do {                                                                                          \
+        if (sp.cpt == 1) {                                                                        \
+            if (in_f64 && out_f64) FIGARO_TILE(double, double, 1, WR);                            \
+            else if (in_f64) FIGARO_TILE(double, float, 1, WR);                                   \
+            else if (out_f64) FIGARO_TILE(float, double, 1, WR);                                  \
+            else FIGARO_TILE(float, float, 1, WR);                                                \
+        } else {                                                                                  \
+            if (in_f64 && out_f64) FIGARO_TILE(double, double, 2, WR);                            \
+            else if (in_f64) FIGARO_TILE(double, float, 2, WR);                                   \
+            else if (out_f64) FIGARO_TILE(float, double, 2, WR);                                  \
+            else FIGARO_TILE(float, float, 2, WR);                                                \
+        }                                                                                         \
+    } while (0)
+    FIGARO_TILE_ALL(false);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_carry_scan<<<1, kCarryThreads, 0, s>>>(tileF, tileS, carry, (int)sp.ntiles, (int)n2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    FIGARO_TILE_ALL(true);
+#undef FIGARO_TILE_ALL
+#undef FIGARO_TILE
     return hipGetLastError();
 }
 

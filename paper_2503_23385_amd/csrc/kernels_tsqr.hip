@@ -145,6 +145,134 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_stream(RowSrc s0, RowSrc 
     }
 }
 
+__device__ inline double readlane_f64(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float readlane_f32(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double readlane_t(double v, int l) { return readlane_f64(v, l); }
+__device__ inline float readlane_t(float v, int l) { return readlane_f32(v, l); }
+
+// One wave per triangle (widths up to 64): lane (k, h) holds RPT rows of column k of the
+// block for row set h (H = 64 / NP row sets).  Column j of the block is broadcast through a
+// per-wave LDS slot; all reductions stay inside the wave, so there is no workgroup barrier.
+// With d_k = x_j . x_k (d_j = |x_j|^2) and p = beta (alpha - beta):
+//     w_k = R_jk + d_k / (alpha - beta),  R_jk -= tau w_k,  x_k += (w_k / beta) x_j,
+// which is the reflector update above with tau * scale = -1 / beta folded in.
+constexpr int kWavesPerBlock = 4;
+
+template <int NP, typename Tin, typename Tacc, int RPT>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_wave(RowSrc s0, RowSrc s1, int nsrc,
+                                                                  int width, int tri_rows, int ntri,
+                                                                  double *tri_out, int64_t tri_stride)
+{
+    constexpr int H = NP >= 64 ? 1 : 64 / NP;
+    constexpr int BR = H * RPT;
+    constexpr int PS = packed_size(NP);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gw = blockIdx.x * kWavesPerBlock + wv;
+    const int k = lane % NP;
+    const int h = lane / NP;
+    __shared__ Tacc Rs[kWavesPerBlock][PS];
+    __shared__ __align__(16) Tacc Xs[kWavesPerBlock][BR];
+    if (gw >= ntri) return;  // waves are independent: no block-level barrier follows
+    Tacc *Rp = Rs[wv];
+    Tacc *xb = Xs[wv] + h * RPT;
+    for (int i = lane; i < PS; i += 64) Rp[i] = Tacc(0);
+
+    const int64_t rows0 = src_rows(s0);
+    const int64_t total = rows0 + (nsrc > 1 ? src_rows(s1) : 0);
+    int64_t chunk = (total + ntri - 1) / ntri;
+    chunk = ((chunk + BR - 1) / BR) * BR;
+    const int64_t r_begin = (int64_t)gw * chunk;
+    const int64_t r_end = min(total, r_begin + chunk);
+    const bool col_ok = k < width;
+
+    for (int64_t rb = r_begin; rb < r_end; rb += BR) {
+        Tacc x[RPT];
+#pragma unroll
+        for (int i = 0; i < RPT; i++) {
+            const int64_t r = rb + h * RPT + i;
+            Tacc v = Tacc(0);
+            if (r < r_end && col_ok) {
+                if (r < rows0) v = load_src<Tin, Tacc>(s0, r, k);
+                else v = load_src<Tin, Tacc>(s1, r - rows0, k);
+            }
+            x[i] = v;
+        }
+        int jstart = 0;
+        if (tri_rows > 0) {
+            const int64_t off = rb % tri_rows;
+            if (off + BR <= tri_rows) jstart = (int)off;
+        }
+        for (int j = jstart; j < width; j++) {
+            __builtin_amdgcn_wave_barrier();
+            if (k == j) {
+#pragma unroll
+                for (int i = 0; i < RPT; i++) xb[i] = x[i];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            Tacc xj[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; i++) xj[i] = xb[i];
+            const double alpha = (double)Rp[pidx(NP, j, j)];
+            const Tacc rjk = (k > j && col_ok) ? Rp[pidx(NP, j, k)] : Tacc(0);
+            Tacc d0 = Tacc(0), d1 = Tacc(0);
+#pragma unroll
+            for (int i = 0; i < RPT; i += 2) {
+                d0 += xj[i] * x[i];
+                if (i + 1 < RPT) d1 += xj[i + 1] * x[i + 1];
+            }
+            Tacc d = d0 + d1;
+#pragma unroll
+            for (int off = NP; off < 64; off <<= 1) d += shfl_xor_t(d, off);
+            double s;
+            if constexpr (sizeof(Tacc) == 8) {
+                s = readlane_t(d, j);
+            } else {
+                // reflector scalars in FP64 for the FP32 form
+                double sd = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; i++) sd += (double)xj[i] * (double)xj[i];
+#pragma unroll
+                for (int off = NP; off < 64; off <<= 1) sd += shfl_xor_t(sd, off);
+                s = readlane_f64(sd, j);
+            }
+            if (s > 0.0) {
+                const double nrm = sqrt(alpha * alpha + s);
+                const double beta = alpha >= 0.0 ? -nrm : nrm;
+                const double amb = alpha - beta;
+                const double rp = 1.0 / (beta * amb);
+                const double inv_beta = amb * rp;
+                const double scl = beta * rp;
+                const double tau = 1.0 - alpha * inv_beta;
+                if (k > j && col_ok) {
+                    const double w = (double)rjk + scl * (double)d;
+                    if (h == 0) Rp[pidx(NP, j, k)] = (Tacc)((double)rjk - tau * w);
+                    const Tacc c = (Tacc)(w * inv_beta);
+#pragma unroll
+                    for (int i = 0; i < RPT; i++) x[i] += c * xj[i];
+                }
+                if (k == j && h == 0) Rp[pidx(NP, j, j)] = (Tacc)beta;
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    double *out = tri_out + (int64_t)gw * tri_stride;
+    for (int e = lane; e < width * NP; e += 64) {
+        const int j = e / NP, kk = e - j * NP;
+        out[e] = (kk >= j && kk < width) ? (double)Rp[pidx(NP, j, kk)] : 0.0;
+    }
+}
+
 __global__ void k_sign_normalise(const double *Rin, int64_t ldin, int n, double *R, int64_t ldr)
 {
     // one wave per row
@@ -172,6 +300,20 @@ template <int NP>
 hipError_t launch_np(int acc_f64, int in_f64, RowSrc s0, RowSrc s1, int nsrc, int width, int tri_rows,
                      int nwg, double *tri, int64_t stride, hipStream_t s)
 {
+    if constexpr (NP <= 64) {
+        const unsigned grid = (unsigned)((nwg + kWavesPerBlock - 1) / kWavesPerBlock);
+#define FIGARO_WAVE(TI, TA) \
+    k_tsqr_wave<NP, TI, TA, 16><<<grid, 64 * kWavesPerBlock, 0, s>>>(s0, s1, nsrc, width, tri_rows, nwg, tri, stride)
+        if (acc_f64) {
+            if (in_f64) FIGARO_WAVE(double, double);
+            else FIGARO_WAVE(float, double);
+        } else {
+            if (in_f64) FIGARO_WAVE(double, float);
+            else FIGARO_WAVE(float, float);
+        }
+#undef FIGARO_WAVE
+        return hipGetLastError();
+    }
     if (acc_f64) {
         if constexpr (packed_size(NP) * 8 + 2 * 16 * (256 / NP) * 8 <= 160 * 1024) {
             if (in_f64)
@@ -200,7 +342,11 @@ int tsqr_padded_width(int n)
     return np <= 256 ? np : 0;
 }
 
-int tsqr_block_rows(int np) { return (np >= 4 ? 64 / (np / 4) : 64) * 16; }
+int tsqr_block_rows(int np)
+{
+    if (np <= 64) return (64 / np) * 16;  // wave kernel: row sets x rows per thread
+    return (256 / np) * 16;               // workgroup kernel
+}
 
 hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, RowSrc s0, RowSrc s1, int nsrc,
                               int width, int tri_rows, int nwg, double *tri,

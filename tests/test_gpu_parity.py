@@ -132,7 +132,8 @@ def test_r_and_sigma_parity(name, prec):
     if d.size and d.min() <= 1e-10 * max(d.max(), 1e-300):
         # rank deficient: R not unique beyond the rank (parity unpinned); check R^T R only
         Gm = gram_closed_form(inst)
-        assert np.allclose(Rg.T @ Rg, Gm, rtol=1e-10, atol=1e-10 * max(1, np.abs(Gm).max()))
+        tol = 1e-10 if prec == "fp64" else 1e-5
+        assert np.allclose(Rg.T @ Rg, Gm, rtol=tol, atol=tol * max(1, np.abs(Gm).max()))
         return
     er = relF(Rg, Ro)
     es = np.linalg.norm(Sg - So) / max(np.linalg.norm(So), 1e-300)
