@@ -50,6 +50,16 @@ extern "C" {
 #define FIGARO_MIXED_FP32 1        /* compact matrix stored and reduced in FP32 (FP64 scans, FP64 reflector scalars, FP64 root) */
 #define FIGARO_MIXED_FP32_REFINE 2 /* FIGARO_MIXED_FP32 followed by one FP64 refinement sweep against the exact Gram matrix */
 
+/*
+ * Flag OR'ed into `precision`: the two-sided form.  Each group's region-1
+ * rows [sqrt(m2_g) A_r | H(B_g)] are themselves replaced by their QR head
+ * and tail (the faster variant noted after Claim 1: the head operator is
+ * applied to both tables), giving per group one head row
+ * [sqrt(m2_g) H(A_g) | sqrt(m1_g) H(B_g)], m1_g - 1 rows [sqrt(m2_g) T(A_g) | 0]
+ * and the m2_g - 1 rows [0 | sqrt(m1_g) T(B_g)].  Same R, fewer flops.
+ */
+#define FIGARO_TWO_SIDED 0x100
+
 /* largest supported join width N = n1 + n2 */
 #define FIGARO_MAX_N 512
 
@@ -112,8 +122,14 @@ int figaro_compact(const figaro_table *A, const figaro_table *B, int32_t precisi
  *   group     int32 arrays of capacity group_cap: key, offA, m1, offB, m2, r1, r2
  *             (r1_g, r2_g are the first rows of group g in regions 1 and 2)
  *   heads     FP64, group_cap x n2: H(B_g)
- *   m1        region 1, rows x N, element type m_dtype, ld = N
- *   m2        region 2, rows x n2 (the zero block is implicit), element type m_dtype, ld = n2
+ *   m1        Claim 1 form: region 1, R1 rows x N, ld = N;
+ *             two-sided form: the G head rows, G x N, ld = N
+ *   m2        region 2, R2 rows x n2 (the zero block is implicit), ld = n2
+ *   heads_a   two-sided form only (else NULL): FP64, group_cap x n1, H(A_g)
+ *   tails_a   two-sided form only (else NULL): (R1 - G) x n1, ld = n1,
+ *             rows sqrt(m2_g) T(A_g) of group g from row r1_g - g
+ *   m_dtype   element type of m1, m2 and tails_a (FIGARO_F64 for
+ *             FIGARO_PLAIN_FP64, FIGARO_F32 otherwise)
  *   status    int32[1], device status word
  */
 typedef struct figaro_view {
@@ -122,6 +138,8 @@ typedef struct figaro_view {
     int64_t group_cap;
     double *heads;
     void *m1, *m2;
+    double *heads_a;
+    void *tails_a;
     int32_t m_dtype;
     int32_t *status;
 } figaro_view;
@@ -195,8 +213,9 @@ int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
                         int64_t *r_total, int64_t *s_total);
 /*
  * Enqueue the whole batch on `stream`.  The first call with a given
- * (ws, R, sigma, stream) captures the launch sequence into a HIP graph; later
- * calls with the same arguments replay it.
+ * (ws, R, sigma) captures the launch sequence into a HIP graph on a private
+ * stream; every call (the first included) launches that graph on `stream`.
+ * Instances need n1 + n2 <= 128.
  */
 int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
                         void *stream);

@@ -24,6 +24,11 @@ FIGARO_F32 = 0
 FIGARO_F64 = 1
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_refine": 2}
+FIGARO_TWO_SIDED = 0x100
+
+
+def precision_code(precision, two_sided=False):
+    return PRECISIONS[precision] | (FIGARO_TWO_SIDED if two_sided else 0)
 
 
 class FigaroError(RuntimeError):
@@ -42,6 +47,7 @@ class View(ctypes.Structure):
                 ("g_m1", ctypes.c_void_p), ("g_offB", ctypes.c_void_p), ("g_m2", ctypes.c_void_p),
                 ("g_r1", ctypes.c_void_p), ("g_r2", ctypes.c_void_p), ("group_cap", ctypes.c_int64),
                 ("heads", ctypes.c_void_p), ("m1", ctypes.c_void_p), ("m2", ctypes.c_void_p),
+                ("heads_a", ctypes.c_void_p), ("tails_a", ctypes.c_void_p),
                 ("m_dtype", ctypes.c_int32), ("status", ctypes.c_void_p)]
 
 
@@ -134,11 +140,11 @@ def make_table(X, keys=None) -> Table:
                  _dtype_code(X), keys.data_ptr() if keys is not None else None)
 
 
-def r_workspace_size(A, B, keys_A=None, keys_B=None, precision="fp64") -> int:
+def r_workspace_size(A, B, keys_A=None, keys_B=None, precision="fp64", two_sided=False) -> int:
     ta, tb = make_table(A, keys_A), make_table(B, keys_B)
     n = ctypes.c_size_t(0)
-    _check(lib().figaro_r_workspace_size(ctypes.byref(ta), ctypes.byref(tb), PRECISIONS[precision],
-                                         ctypes.byref(n)))
+    _check(lib().figaro_r_workspace_size(ctypes.byref(ta), ctypes.byref(tb),
+                                         precision_code(precision, two_sided), ctypes.byref(n)))
     return n.value
 
 
@@ -147,16 +153,17 @@ def alloc_workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def r(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, out=None, stream=None):
+def r(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, out=None, stream=None,
+      two_sided=False):
     """R (N x N, FP64, diag >= 0) of the join of A and B on the device.  Returns (R, ws)."""
     torch = _torch()
     ta, tb = make_table(A, keys_A), make_table(B, keys_B)
     N = A.shape[1] + B.shape[1]
     if ws is None:
-        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision), A.device)
+        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision, two_sided), A.device)
     if out is None:
         out = torch.empty((N, N), dtype=torch.float64, device=A.device)
-    _check(lib().figaro_r(ctypes.byref(ta), ctypes.byref(tb), PRECISIONS[precision],
+    _check(lib().figaro_r(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided),
                           ctypes.c_void_p(out.data_ptr()), out.stride(0),
                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
     return out, ws
@@ -184,24 +191,23 @@ def status(ws, stream=None) -> int:
     return code.value
 
 
-def compact(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, stream=None):
-    """Run grouping, head/tail scan and assembly; return host copies of the intermediates."""
-    torch = _torch()
+def compact(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, stream=None, two_sided=False):
+    """Run grouping, head/tail scans and assembly; return host copies of the intermediates."""
     ta, tb = make_table(A, keys_A), make_table(B, keys_B)
-    prec = PRECISIONS[precision]
+    code = precision_code(precision, two_sided)
     if ws is None:
-        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision), A.device)
-    _check(lib().figaro_compact(ctypes.byref(ta), ctypes.byref(tb), prec,
+        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision, two_sided), A.device)
+    _check(lib().figaro_compact(ctypes.byref(ta), ctypes.byref(tb), code,
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
-    return inspect(A, B, keys_A, keys_B, precision, ws, stream)
+    return inspect(A, B, keys_A, keys_B, precision, ws, stream, two_sided)
 
 
-def inspect(A, B, keys_A, keys_B, precision, ws, stream=None):
-    """Copy the group table, counts, heads and compact matrix out of a workspace."""
+def inspect(A, B, keys_A, keys_B, precision, ws, stream=None, two_sided=False):
+    """Copy the group table, counts, heads and compact-matrix regions out of a workspace."""
     torch = _torch()
     ta, tb = make_table(A, keys_A), make_table(B, keys_B)
     v = View()
-    _check(lib().figaro_inspect(ctypes.byref(ta), ctypes.byref(tb), PRECISIONS[precision],
+    _check(lib().figaro_inspect(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided),
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(v)))
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     base = ws.data_ptr()
@@ -217,14 +223,20 @@ def inspect(A, B, keys_A, keys_B, precision, ws, stream=None):
               for name in ("key", "offA", "m1", "offB", "m2", "r1", "r2")}
     n1, n2 = A.shape[1], B.shape[1]
     mdt = torch.float64 if v.m_dtype == FIGARO_F64 else torch.float32
-    return {
+    out = {
         "counts": counts,
         "groups": groups,
         "heads": view(v.heads, G * n2, torch.float64).reshape(G, n2),
-        "M1": view(v.m1, R1 * (n1 + n2), mdt).reshape(R1, n1 + n2),
         "M2": view(v.m2, R2 * n2, mdt).reshape(R2, n2),
         "status": int(view(v.status, 1, torch.int32)[0]),
     }
+    if two_sided:
+        out["heads_rows"] = view(v.m1, G * (n1 + n2), mdt).reshape(G, n1 + n2)
+        out["heads_a"] = view(v.heads_a, G * n1, torch.float64).reshape(G, n1)
+        out["tails_a"] = view(v.tails_a, (R1 - G) * n1, mdt).reshape(R1 - G, n1)
+    else:
+        out["M1"] = view(v.m1, R1 * (n1 + n2), mdt).reshape(R1, n1 + n2)
+    return out
 
 
 def timing_enable(on=True):
@@ -246,7 +258,7 @@ def timing_read():
 class Plan:
     """Batched plan over many independent two-table instances."""
 
-    def __init__(self, instances, precision="fp64"):
+    def __init__(self, instances, precision="fp64", two_sided=False):
         """instances: list of (A, B, keys_A, keys_B) device tensors."""
         self._keep = instances
         arr = (Instance * len(instances))()
@@ -255,7 +267,8 @@ class Plan:
             arr[i].B = make_table(B, kB)
         self._arr = arr
         h = ctypes.c_void_p()
-        _check(lib().figaro_plan_create(arr, len(instances), PRECISIONS[precision], ctypes.byref(h)))
+        _check(lib().figaro_plan_create(arr, len(instances), precision_code(precision, two_sided),
+                                        ctypes.byref(h)))
         self.handle = h
         nb = ctypes.c_size_t(0)
         _check(lib().figaro_plan_workspace_size(h, ctypes.byref(nb)))

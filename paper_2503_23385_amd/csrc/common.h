@@ -11,8 +11,12 @@ constexpr int kStatusOk = 0;
 constexpr int kStatusUnsorted = -2;
 constexpr int kStatusTimeout = -5;
 
-// counts[] slots
-enum : int { CNT_G = 0, CNT_R1 = 1, CNT_R2 = 2, CNT_JOIN = 3, CNT_UA = 4, CNT_UB = 5, CNT_SLOTS = 8 };
+// counts[] slots: groups, region-1 rows (sum m1_g), region-2 rows (sum m2_g - 1),
+// join rows, runs of A and B (scratch), a scratch slot, and sum (m1_g - 1).
+enum : int {
+    CNT_G = 0, CNT_R1 = 1, CNT_R2 = 2, CNT_JOIN = 3, CNT_UA = 4, CNT_UB = 5, CNT_TMP = 6,
+    CNT_TA = 7, CNT_SLOTS = 8
+};
 
 // Device view of the group table (structure of arrays, ascending key order).
 struct Groups {
@@ -20,9 +24,18 @@ struct Groups {
     int64_t *counts;  // CNT_* slots
 };
 
-// One source of rows for the TSQR stream: `rows` rows (device count if
-// rows_dev != nullptr, else rows_host) of width `width`, placed at column
-// `col_off` of the virtual row; ld in elements.
+// Which table a head/tail scan runs over: for group g its rows start at off[g],
+// it has size[g] rows, the other table has other[g] rows (the tails are scaled by
+// sqrt(other[g])), and tail i of the group goes to output row
+// obase[g] - (sub_g ? g : 0) + i - 1.
+struct ScanSide {
+    const int32_t *off, *size, *other, *obase;
+    int32_t sub_g;
+};
+
+// One source of rows for the TSQR: `rows` rows (device count if rows_dev != nullptr,
+// else rows_host) of width `width`, placed at column `col_off` of the virtual row;
+// ld in elements.
 struct RowSrc {
     const void *p;
     const int64_t *rows_dev;
@@ -46,7 +59,7 @@ hipError_t launch_group_keys(const int32_t *kA, int64_t m1, const int32_t *kB, i
                              int32_t *matchA, int32_t *blkM, int64_t *blkS, int32_t *status,
                              hipStream_t s);
 
-// head/tail scan and assembly (kernels_scan.hip)
+// head/tail scans and assembly (kernels_scan.hip)
 struct ScanPlan {
     int q;        // row groups per tile
     int rpt;      // rows per thread
@@ -54,26 +67,37 @@ struct ScanPlan {
     int tile_rows;
     int64_t ntiles;
 };
-ScanPlan scan_plan(int64_t m2, int64_t n2, int in_bytes);
+ScanPlan scan_plan(int64_t m, int64_t n, int in_bytes);
 // Three launches: tile reduce, carry scan, tile write (tileF: ntiles ints; tileS, carry:
-// ntiles x n2 doubles of scratch).
-hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, int64_t n2,
-                           Groups g, int cartesian, void *M2, int out_f64, double *heads,
+// ntiles x n doubles of scratch).  heads[g] receives H(X_g) = (sum of the group's rows) / sqrt(size).
+hipError_t launch_seg_scan(const void *X, int in_f64, int64_t ldx, int64_t m, int64_t n, Groups g,
+                           ScanSide side, int cartesian, void *out, int out_f64, double *heads,
                            int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp,
                            hipStream_t s);
+// Claim 1 region 1: [sqrt(m2_g) A_r | H(B_g)].
 hipError_t launch_assemble_a(const void *A, int in_f64, int64_t lda, int64_t m1, int64_t n1,
                              int64_t n2, Groups g, int cartesian, const double *heads, void *M1,
                              int out_f64, hipStream_t s);
+// Head rows of the two-sided form: row g = [sqrt(m2_g) H(A_g) | sqrt(m1_g) H(B_g)].
+hipError_t launch_head_rows(Groups g, int64_t gcap, const double *headsA, const double *headsB,
+                            int64_t n1, int64_t n2, void *out, int out_f64, hipStream_t s);
 
 // TSQR (kernels_tsqr.hip)
-int tsqr_padded_width(int n);          // padded template width for n, 0 if unsupported
-int tsqr_block_rows(int np);           // rows per streamed block for padded width np
+int tsqr_padded_width(int n);  // padded template width for n, 0 if unsupported
+int tsqr_block_rows(int np);   // rows per streamed block for padded width np
+// Slots (triangles) and counters needed by the in-kernel tree over nleaves leaves.
+void tsqr_tree_sizes(int nleaves, int64_t *slots, int64_t *counters);
 // Reduce the rows of s0 (then s1) into nwg triangles of `width` rows x np columns (FP64),
-// triangle b at tri_out + b * tri_stride.  tri_rows > 0 marks sources made of stacked
-// triangles of that many rows (lets a block skip its known-zero leading columns).
-hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, RowSrc s0, RowSrc s1, int nsrc,
-                              int width, int tri_rows, int nwg, double *tri_out,
-                              int64_t tri_stride, hipStream_t s);
+// triangle b at tri + b * tri_stride, each starting from `init` (a triangle, ld init_ld)
+// when init != nullptr, else from zero.  tri_rows > 0: the sources are stacks of triangles
+// of that many rows (lets a block skip known-zero leading columns).
+hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *init, int64_t init_ld,
+                              RowSrc s0, RowSrc s1, int nsrc, int width, int tri_rows, int nwg,
+                              double *tri, int64_t tri_stride, hipStream_t s);
+// One launch: nleaves wave-level leaves over src, then the in-kernel binary tree; the
+// region's triangle (width rows x np, FP64) lands in root.  np <= 64 only.
+hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, RowSrc src, int width, int nleaves,
+                            double *slots, int32_t *counters, double *root, hipStream_t s);
 hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,
                                  int64_t ldr, hipStream_t s);
 

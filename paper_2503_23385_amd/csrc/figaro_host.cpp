@@ -2,17 +2,27 @@
 // layout, and the launch sequence behind the C ABI of include/figaro.h.
 //
 // The pipeline follows the paper's Figaro-GPU steps (Experiments section):
-// heads/tails of B per key group, the compact matrix of Claim 1, a
-// Householder QR of that matrix for R, and the singular values of R.  The
-// differences are in how each step runs on the device: a segmented scan with
-// look-back instead of one thread per column, no row/column-major transpose,
-// and a TSQR reduction instead of a library QR.
+// heads and tails per key group, the compact matrix of Claim 1, a Householder
+// QR of that matrix for R, and the singular values of R.  How each step runs
+// on the device differs: segmented scans instead of one thread per column,
+// no row/column-major transpose, and TSQR reductions instead of a library QR.
+//
+// The rows to be reduced are organised in regions, each reduced by its own
+// TSQR to one triangle; the triangles are then merged into R:
+//   Claim 1 form:   M1 = [sqrt(m2_g) A_r | H(B_g)] (width N) and
+//                   M2 = [0 | sqrt(m1_g) T(B_g)]   (width n2 at column n1);
+//   two-sided form: the same matrix with each group's M1 rows also replaced by
+//                   their head and tail (the faster variant noted after Claim 1):
+//                   heads [sqrt(m2_g) H(A_g) | sqrt(m1_g) H(B_g)] (width N),
+//                   [sqrt(m2_g) T(A_g) | 0] (width n1) and M2 as above.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -44,6 +54,7 @@ struct TimingRec {
 
 struct Timing {
     bool on = false;
+    bool capturing = false;
     std::vector<TimingRec> recs;
     std::vector<hipEvent_t> pool;
     hipEvent_t get()
@@ -68,7 +79,7 @@ struct Stage {
     hipEvent_t a = nullptr;
     Stage(const char *n, hipStream_t st) : name(n), s(st)
     {
-        if (g_timing.on) {
+        if (g_timing.on && !g_timing.capturing) {
             a = g_timing.get();
             if (a) (void)hipEventRecord(a, s);
         }
@@ -90,63 +101,51 @@ struct Stage {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+constexpr int kPrecMask = 0xff;
+constexpr int kMaxTreeLeaves = 2048;
+constexpr int kTreeArityWG = 4;
+
 struct Shape {
     int64_t m1, n1, lda, m2, n2, ldb;
     int in_f64;
     bool keyed;
-    int precision;
+    int precision;  // FIGARO_PLAIN_FP64 / FIGARO_MIXED_FP32 / FIGARO_MIXED_FP32_REFINE
+    bool two_sided;
     int64_t N() const { return n1 + n2; }
 };
 
-// TSQR reduction plan for one region: leaves, then levels of the tree.
-struct TreePlan {
-    int np = 0, width = 0, col_off = 0;
-    int leaves = 0;
-    std::vector<int> levels;  // workgroups per level after the leaves
-    int final_count = 0;      // triangles entering the root
+// A region: rows (device count in counts[cnt]) of `width` columns at column col_off,
+// stored at `buf` (storage type of the form), reduced to one triangle at `root`.
+struct Region {
+    const char *name;
+    size_t buf;
+    int64_t rows_cap;
+    int cnt;
+    int width, col_off, np;
+    bool wave;                // in-kernel tree (np <= 64)
+    int leaves;
+    std::vector<int> levels;  // workgroup tree levels (wave == false)
+    size_t slots, counters, root, tri[2];
+    int64_t ncounters;
 };
 
 struct Layout {
-    size_t status, counts, ticket;
+    size_t status, counts;
     size_t blkA, blkB, runA, runB, matchA, blkM, blkS;
     size_t g[7];
     int64_t gcap;
-    size_t heads, tileF, tileS, carry;
-    size_t M1, M2;
+    size_t headsA, headsB;
+    size_t tileF[2], tileS[2], carry[2];
+    ScanPlan spA, spB;
     int m_f64;
-    size_t triA[2], triB[2];
-    size_t rtmp;
-    size_t total;
-    ScanPlan sp;
-    TreePlan ta, tb;
+    std::vector<Region> regions;
+    size_t counters_base;
+    int64_t counters_total;
+    size_t rtmp[2];
     int np_root;
+    size_t total;
     int nbA, nbB;
 };
-
-constexpr int kTreeArity = 2;
-constexpr int kRootMax = 2;
-constexpr int kMaxLeaves = 4096;
-
-TreePlan plan_tree(int64_t rows_upper, int width, int col_off, int np_root_acc)
-{
-    (void)np_root_acc;
-    TreePlan t;
-    t.np = tsqr_padded_width(width);
-    t.width = width;
-    t.col_off = col_off;
-    const int br = tsqr_block_rows(t.np);
-    const int64_t per_wg = std::max<int64_t>(2 * (int64_t)width, 4 * (int64_t)br);
-    int64_t leaves = (rows_upper + per_wg - 1) / per_wg;
-    leaves = std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxLeaves));
-    t.leaves = (int)leaves;
-    int cur = t.leaves;
-    while (cur > kRootMax) {
-        cur = (cur + kTreeArity - 1) / kTreeArity;
-        t.levels.push_back(cur);
-    }
-    t.final_count = cur;
-    return t;
-}
 
 int check_table(const figaro_table *t, const char *name)
 {
@@ -168,15 +167,17 @@ int make_shape(const figaro_table *A, const figaro_table *B, int32_t precision, 
     if (A->dtype != B->dtype) return fail(FIGARO_EINVAL, "A and B must share a dtype");
     if ((A->keys == nullptr) != (B->keys == nullptr))
         return fail(FIGARO_EINVAL, "keys must be given for both tables or for neither");
-    if (precision != FIGARO_PLAIN_FP64 && precision != FIGARO_MIXED_FP32 &&
-        precision != FIGARO_MIXED_FP32_REFINE)
-        return fail(FIGARO_EINVAL, "unknown precision");
+    const int prec = precision & kPrecMask;
+    if ((precision & ~(kPrecMask | FIGARO_TWO_SIDED)) != 0 ||
+        (prec != FIGARO_PLAIN_FP64 && prec != FIGARO_MIXED_FP32 && prec != FIGARO_MIXED_FP32_REFINE))
+        return fail(FIGARO_EINVAL, "unknown precision or flag");
     const int64_t N = A->cols + B->cols;
     if (N > FIGARO_MAX_N) return fail(FIGARO_EINVAL, "n1 + n2 exceeds FIGARO_MAX_N");
-    // Widths this build's TSQR kernels accept.
-    const bool fp64_acc = precision == FIGARO_PLAIN_FP64;
+    // Widths this build's TSQR kernels accept: every region width must pad to a kernel.
+    const bool fp64_acc = prec == FIGARO_PLAIN_FP64;
+    const int limit = fp64_acc ? 128 : 256;
     const int np = tsqr_padded_width((int)N);
-    if (np == 0 || (fp64_acc && np > 128))
+    if (np == 0 || np > limit)
         return fail(FIGARO_EINVAL, "n1 + n2 wider than this build supports for the chosen precision");
     if (B->cols > 512) return fail(FIGARO_EINVAL, "n2 > 512");
     sh->m1 = A->rows;
@@ -187,8 +188,35 @@ int make_shape(const figaro_table *A, const figaro_table *B, int32_t precision, 
     sh->ldb = B->ld;
     sh->in_f64 = A->dtype == FIGARO_F64;
     sh->keyed = A->keys != nullptr;
-    sh->precision = precision;
+    sh->precision = prec;
+    sh->two_sided = (precision & FIGARO_TWO_SIDED) != 0;
     return FIGARO_OK;
+}
+
+Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int col_off)
+{
+    Region r;
+    r.name = name;
+    r.rows_cap = std::max<int64_t>(0, rows_cap);
+    r.cnt = cnt;
+    r.width = width;
+    r.col_off = col_off;
+    r.np = tsqr_padded_width(width);
+    r.wave = r.np <= 64;
+    const int br = tsqr_block_rows(r.np);
+    // Leaves of about eight blocks (wave tree) or four (workgroup tree) each.
+    const int64_t per = (r.wave ? 8 : 4) * (int64_t)br;
+    const int64_t leaves = (r.rows_cap + per - 1) / per;
+    r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxTreeLeaves));
+    r.ncounters = 0;
+    if (!r.wave) {
+        int cur = r.leaves;
+        while (cur > 1) {
+            cur = (cur + kTreeArityWG - 1) / kTreeArityWG;
+            r.levels.push_back(cur);
+        }
+    }
+    return r;
 }
 
 Layout make_layout(const Shape &s)
@@ -202,7 +230,6 @@ Layout make_layout(const Shape &s)
     };
     L.status = take(sizeof(int32_t) * 4);
     L.counts = take(sizeof(int64_t) * CNT_SLOTS);
-    L.ticket = take(sizeof(int32_t) * 4);
     L.nbA = (int)((s.m1 + kGroupBlock - 1) / kGroupBlock);
     L.nbB = (int)((s.m2 + kGroupBlock - 1) / kGroupBlock);
     if (s.keyed) {
@@ -219,28 +246,63 @@ Layout make_layout(const Shape &s)
         L.gcap = 1;
     }
     for (int i = 0; i < 7; i++) L.g[i] = take(sizeof(int32_t) * L.gcap);
-    L.heads = take(sizeof(double) * L.gcap * s.n2);
+    L.headsB = take(sizeof(double) * L.gcap * s.n2);
+    L.headsA = s.two_sided ? take(sizeof(double) * L.gcap * s.n1) : 0;
     L.m_f64 = s.precision == FIGARO_PLAIN_FP64;
     const size_t esz = L.m_f64 ? 8 : 4;
-    L.sp = scan_plan(s.m2, s.n2, s.in_f64 ? 8 : 4);
-    L.tileF = take(sizeof(int32_t) * std::max<int64_t>(1, L.sp.ntiles));
-    L.tileS = take(sizeof(double) * std::max<int64_t>(1, L.sp.ntiles) * s.n2);
-    L.carry = take(sizeof(double) * std::max<int64_t>(1, L.sp.ntiles) * s.n2);
-    const int64_t N = s.N();
-    L.M1 = take(esz * std::max<int64_t>(1, s.m1) * N);
-    L.M2 = take(esz * std::max<int64_t>(1, s.m2 - 1) * s.n2);
-    L.ta = plan_tree(s.m1, (int)N, 0, 0);
-    L.tb = plan_tree(std::max<int64_t>(0, s.m2 - 1), (int)s.n2, (int)s.n1, 0);
-    L.np_root = L.ta.np;
-    const size_t triA_sz = sizeof(double) * (size_t)L.ta.leaves * N * L.ta.np;
-    const size_t triA2_sz = sizeof(double) * (size_t)(L.ta.levels.empty() ? 1 : L.ta.levels[0]) * N * L.ta.np;
-    const size_t triB_sz = sizeof(double) * (size_t)L.tb.leaves * s.n2 * L.tb.np;
-    const size_t triB2_sz = sizeof(double) * (size_t)(L.tb.levels.empty() ? 1 : L.tb.levels[0]) * s.n2 * L.tb.np;
-    L.triA[0] = take(triA_sz);
-    L.triA[1] = take(triA2_sz);
-    L.triB[0] = take(triB_sz);
-    L.triB[1] = take(triB2_sz);
-    L.rtmp = take(sizeof(double) * N * L.np_root);
+    L.spB = scan_plan(s.m2, s.n2, s.in_f64 ? 8 : 4);
+    L.tileF[1] = take(sizeof(int32_t) * std::max<int64_t>(1, L.spB.ntiles));
+    L.tileS[1] = take(sizeof(double) * std::max<int64_t>(1, L.spB.ntiles) * s.n2);
+    L.carry[1] = take(sizeof(double) * std::max<int64_t>(1, L.spB.ntiles) * s.n2);
+    if (s.two_sided) {
+        L.spA = scan_plan(s.m1, s.n1, s.in_f64 ? 8 : 4);
+        L.tileF[0] = take(sizeof(int32_t) * std::max<int64_t>(1, L.spA.ntiles));
+        L.tileS[0] = take(sizeof(double) * std::max<int64_t>(1, L.spA.ntiles) * s.n1);
+        L.carry[0] = take(sizeof(double) * std::max<int64_t>(1, L.spA.ntiles) * s.n1);
+    } else {
+        L.spA = ScanPlan{};
+        L.tileF[0] = L.tileS[0] = L.carry[0] = 0;
+    }
+    const int N = (int)s.N();
+    if (!s.two_sided) {
+        Region a = make_region("tsqr_m1", s.m1, CNT_R1, N, 0);
+        Region b = make_region("tsqr_m2", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1);
+        a.buf = take(esz * std::max<int64_t>(1, a.rows_cap) * N);
+        b.buf = take(esz * std::max<int64_t>(1, b.rows_cap) * s.n2);
+        L.regions = {a, b};
+    } else {
+        Region h = make_region("tsqr_heads", L.gcap, CNT_G, N, 0);
+        Region ta = make_region("tsqr_ta", s.m1 - 1, CNT_TA, (int)s.n1, 0);
+        Region tb = make_region("tsqr_tb", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1);
+        h.buf = take(esz * h.rows_cap * N);
+        ta.buf = take(esz * std::max<int64_t>(1, ta.rows_cap) * s.n1);
+        tb.buf = take(esz * std::max<int64_t>(1, tb.rows_cap) * s.n2);
+        L.regions = {h, ta, tb};
+    }
+    int64_t ctot = 0;
+    for (Region &r : L.regions) {
+        const size_t tsz = sizeof(double) * (size_t)r.width * r.np;
+        if (r.wave) {
+            int64_t ns, nc;
+            tsqr_tree_sizes(r.leaves, &ns, &nc);
+            r.slots = take(tsz * ns);
+            r.ncounters = nc;
+            r.counters = (size_t)ctot;  // index into the shared counter block
+            ctot += nc;
+            r.tri[0] = r.tri[1] = 0;
+        } else {
+            r.slots = 0;
+            r.counters = 0;
+            r.tri[0] = take(tsz * r.leaves);
+            r.tri[1] = take(tsz * (r.levels.empty() ? 1 : r.levels[0]));
+        }
+        r.root = take(tsz);
+    }
+    L.counters_total = ctot;
+    L.counters_base = take(sizeof(int32_t) * std::max<int64_t>(1, ctot));
+    L.np_root = tsqr_padded_width(N);
+    L.rtmp[0] = take(sizeof(double) * N * L.np_root);
+    L.rtmp[1] = take(sizeof(double) * N * L.np_root);
     L.total = off;
     return L;
 }
@@ -271,70 +333,100 @@ int check_ws(const Layout &L, void *ws, size_t ws_bytes)
     return FIGARO_OK;
 }
 
-#define HIPCHK(expr, where)                          \
-    do {                                             \
-        hipError_t e_ = (expr);                      \
+#define HIPCHK(expr, where)                               \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
         if (e_ != hipSuccess) return hip_fail(e_, where); \
     } while (0)
 
+// Grouping, head/tail scans and assembly: fills the regions' row buffers.
 int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L,
                 void *ws, hipStream_t s)
 {
     Groups g = groups_of(ws, L);
     int32_t *status = at<int32_t>(ws, L.status);
-    Stage st_group("group", s);
-    HIPCHK(launch_group_init(status, g.counts, nullptr, nullptr, 0, s), "init");
-    if (sh.keyed) {
-        HIPCHK(launch_group_keys(A->keys, sh.m1, B->keys, sh.m2, g, at<int32_t>(ws, L.blkA),
-                                 at<int32_t>(ws, L.blkB), at<int32_t>(ws, L.runA),
-                                 at<int32_t>(ws, L.runB), at<int32_t>(ws, L.matchA),
-                                 at<int32_t>(ws, L.blkM), at<int64_t>(ws, L.blkS), status, s),
-               "grouping");
-    } else {
-        HIPCHK(launch_group_cartesian(g, sh.m1, sh.m2, s), "grouping");
-    }
-    double *heads = at<double>(ws, L.heads);
     {
-    Stage st("scan", s);
-    HIPCHK(launch_seg_scan(B->data, sh.in_f64, sh.ldb, sh.m2, sh.n2, g, !sh.keyed,
-                           at<void>(ws, L.M2), L.m_f64, heads, at<int32_t>(ws, L.tileF),
-                           at<double>(ws, L.tileS), at<double>(ws, L.carry), L.sp, s),
-           "head/tail scan");
+        Stage st("group", s);
+        HIPCHK(launch_group_init(status, g.counts, nullptr, at<int32_t>(ws, L.counters_base),
+                                 L.counters_total, s),
+               "init");
+        if (sh.keyed) {
+            HIPCHK(launch_group_keys(A->keys, sh.m1, B->keys, sh.m2, g, at<int32_t>(ws, L.blkA),
+                                     at<int32_t>(ws, L.blkB), at<int32_t>(ws, L.runA),
+                                     at<int32_t>(ws, L.runB), at<int32_t>(ws, L.matchA),
+                                     at<int32_t>(ws, L.blkM), at<int64_t>(ws, L.blkS), status, s),
+                   "grouping");
+        } else {
+            HIPCHK(launch_group_cartesian(g, sh.m1, sh.m2, s), "grouping");
+        }
     }
-    Stage st_asm("assemble", s);
-    HIPCHK(launch_assemble_a(A->data, sh.in_f64, sh.lda, sh.m1, sh.n1, sh.n2, g, !sh.keyed, heads,
-                             at<void>(ws, L.M1), L.m_f64, s),
-           "region-1 assembly");
+    double *hB = at<double>(ws, L.headsB);
+    const Region &rb = L.regions.back();  // region of B's tails in both forms
+    {
+        Stage st("scan", s);
+        ScanSide sideB{g.offB, g.m2, g.m1, g.r2, 0};
+        HIPCHK(launch_seg_scan(B->data, sh.in_f64, sh.ldb, sh.m2, sh.n2, g, sideB, !sh.keyed,
+                               at<void>(ws, rb.buf), L.m_f64, hB, at<int32_t>(ws, L.tileF[1]),
+                               at<double>(ws, L.tileS[1]), at<double>(ws, L.carry[1]), L.spB, s),
+               "head/tail scan of B");
+    }
+    if (!sh.two_sided) {
+        Stage st("assemble", s);
+        HIPCHK(launch_assemble_a(A->data, sh.in_f64, sh.lda, sh.m1, sh.n1, sh.n2, g, !sh.keyed, hB,
+                                 at<void>(ws, L.regions[0].buf), L.m_f64, s),
+               "region-1 assembly");
+    } else {
+        double *hA = at<double>(ws, L.headsA);
+        {
+            Stage st("scan", s);
+            ScanSide sideA{g.offA, g.m1, g.m2, g.r1, 1};
+            HIPCHK(launch_seg_scan(A->data, sh.in_f64, sh.lda, sh.m1, sh.n1, g, sideA, !sh.keyed,
+                                   at<void>(ws, L.regions[1].buf), L.m_f64, hA,
+                                   at<int32_t>(ws, L.tileF[0]), at<double>(ws, L.tileS[0]),
+                                   at<double>(ws, L.carry[0]), L.spA, s),
+                   "head/tail scan of A");
+        }
+        Stage st("assemble", s);
+        HIPCHK(launch_head_rows(g, L.gcap, hA, hB, sh.n1, sh.n2, at<void>(ws, L.regions[0].buf),
+                                L.m_f64, s),
+               "head rows");
+    }
     return FIGARO_OK;
 }
 
-// Run one region's leaves and tree levels; returns the buffer holding its final triangles.
-int run_tree(const TreePlan &t, RowSrc leaf_src, int acc_f64_leaf, int acc_f64_tree, int in_f64,
-             void *ws, const size_t bufs[2], double **final_buf, const char *leaf_name, hipStream_t s)
+// Reduce one region to its triangle (FP64, width rows x np at r.root).
+int run_region(const Region &r, const Layout &L, int acc_f64, void *ws, hipStream_t s)
 {
+    Groups g = groups_of(ws, L);
+    RowSrc src{at<void>(ws, r.buf), g.counts + r.cnt, 0, r.width, 0, r.width};
     RowSrc none{};
-    double *cur = at<double>(ws, bufs[0]);
-    const int64_t stride = (int64_t)t.width * t.np;
-    {
-        Stage st(leaf_name, s);
-        HIPCHK(launch_tsqr_stream(t.np, acc_f64_leaf, in_f64, leaf_src, none, 1, t.width, 0, t.leaves,
-                                  cur, stride, s),
-               "tsqr leaves");
-    }
-    int count = t.leaves;
-    int which = 0;
-    for (int nwg : t.levels) {
-        double *nxt = at<double>(ws, bufs[which ^ 1]);
-        RowSrc src{cur, nullptr, (int64_t)count * t.width, t.np, 0, t.width};
-        Stage st("tsqr_tree", s);
-        HIPCHK(launch_tsqr_stream(t.np, acc_f64_tree, 1, src, none, 1, t.width, t.width, nwg, nxt,
-                                  stride, s),
+    double *root = at<double>(ws, r.root);
+    const int64_t tsz = (int64_t)r.width * r.np;
+    Stage st(r.name, s);
+    if (r.wave) {
+        HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, src, r.width, r.leaves,
+                                at<double>(ws, r.slots),
+                                at<int32_t>(ws, L.counters_base) + r.counters, root, s),
                "tsqr tree");
+        return FIGARO_OK;
+    }
+    // Workgroup kernel: leaves, then levels of kTreeArityWG, the last level into root.
+    double *cur = r.levels.empty() ? root : at<double>(ws, r.tri[0]);
+    HIPCHK(launch_tsqr_stream(r.np, acc_f64, L.m_f64, nullptr, 0, src, none, 1, r.width, 0,
+                              r.leaves, cur, tsz, s),
+           "tsqr leaves");
+    int count = r.leaves, which = 0;
+    for (size_t i = 0; i < r.levels.size(); i++) {
+        const int nwg = r.levels[i];
+        double *nxt = (i + 1 == r.levels.size()) ? root : at<double>(ws, r.tri[which ^ 1]);
+        RowSrc lv{cur, nullptr, (int64_t)count * r.width, r.np, 0, r.width};
+        HIPCHK(launch_tsqr_stream(r.np, acc_f64, 1, nullptr, 0, lv, none, 1, r.width, r.width, nwg,
+                                  nxt, tsz, s),
+               "tsqr tree level");
         cur = nxt;
         which ^= 1;
         count = nwg;
     }
-    *final_buf = cur;
     return FIGARO_OK;
 }
 
@@ -343,28 +435,32 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
 {
     int rc = run_compact(A, B, sh, L, ws, s);
     if (rc) return rc;
-    Groups g = groups_of(ws, L);
     const int N = (int)sh.N();
-    const int acc_leaf = sh.precision == FIGARO_PLAIN_FP64;
-    const int acc_tree = acc_leaf;
-    RowSrc srcA{at<void>(ws, L.M1), g.counts + CNT_R1, 0, N, 0, N};
-    RowSrc srcB{at<void>(ws, L.M2), g.counts + CNT_R2, 0, sh.n2, 0, (int)sh.n2};
-    double *fa = nullptr, *fb = nullptr;
-    rc = run_tree(L.ta, srcA, acc_leaf, acc_tree, L.m_f64, ws, L.triA, &fa, "tsqr_leaf_m1", s);
-    if (rc) return rc;
-    rc = run_tree(L.tb, srcB, acc_leaf, acc_tree, L.m_f64, ws, L.triB, &fb, "tsqr_leaf_m2", s);
-    if (rc) return rc;
-    // Root: [R_1 ; 0 | R_2] -> R in FP64.
-    RowSrc ra{fa, nullptr, (int64_t)L.ta.final_count * N, L.ta.np, 0, N};
-    RowSrc rb{fb, nullptr, (int64_t)L.tb.final_count * sh.n2, L.tb.np, (int)sh.n1, (int)sh.n2};
-    double *rt = at<double>(ws, L.rtmp);
+    const int acc = sh.precision == FIGARO_PLAIN_FP64;
+    for (const Region &r : L.regions) {
+        rc = run_region(r, L, acc, ws, s);
+        if (rc) return rc;
+    }
+    // Merge in FP64: start from the N-wide region's triangle, absorb the others in order.
+    const Region &r0 = L.regions[0];
+    const double *cur = at<double>(ws, r0.root);
+    int64_t cur_ld = r0.np;
+    RowSrc none{};
     {
         Stage st("tsqr_root", s);
-        HIPCHK(launch_tsqr_stream(L.np_root, 1, 1, ra, rb, 2, N, 0, 1, rt, (int64_t)N * L.np_root, s),
-               "tsqr root");
+        for (size_t i = 1; i < L.regions.size(); i++) {
+            const Region &r = L.regions[i];
+            double *out = at<double>(ws, L.rtmp[(i - 1) & 1]);
+            RowSrc tri{at<double>(ws, r.root), nullptr, r.width, r.np, r.col_off, r.width};
+            HIPCHK(launch_tsqr_stream(L.np_root, 1, 1, cur, cur_ld, tri, none, 1, N, r.width, 1, out,
+                                      (int64_t)N * L.np_root, s),
+                   "tsqr merge");
+            cur = out;
+            cur_ld = L.np_root;
+        }
     }
     Stage st("sign", s);
-    HIPCHK(launch_sign_normalise(rt, 1, L.np_root, N, R, ldr, s), "sign normalisation");
+    HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, R, ldr, s), "sign normalisation");
     return FIGARO_OK;
 }
 
@@ -405,9 +501,11 @@ int figaro_inspect(const figaro_table *A, const figaro_table *B, int32_t precisi
     out->g_r1 = g.r1;
     out->g_r2 = g.r2;
     out->group_cap = L.gcap;
-    out->heads = at<double>(ws, L.heads);
-    out->m1 = at<void>(ws, L.M1);
-    out->m2 = at<void>(ws, L.M2);
+    out->heads = at<double>(ws, L.headsB);
+    out->m1 = at<void>(ws, L.regions[0].buf);
+    out->m2 = at<void>(ws, L.regions.back().buf);
+    out->heads_a = sh.two_sided ? at<double>(ws, L.headsA) : nullptr;
+    out->tails_a = sh.two_sided ? at<void>(ws, L.regions[1].buf) : nullptr;
     out->m_dtype = L.m_f64 ? FIGARO_F64 : FIGARO_F32;
     out->status = at<int32_t>(ws, L.status);
     return FIGARO_OK;
@@ -516,9 +614,9 @@ int figaro_status(const void *ws, void *stream, int32_t *code)
     return FIGARO_OK;
 }
 
-// ------------------------------------------------------------------ plans
-
 }  // extern "C"
+
+// ------------------------------------------------------------------ plans
 
 struct figaro_plan {
     std::vector<figaro_instance> inst;
@@ -526,10 +624,31 @@ struct figaro_plan {
     std::vector<Layout> layouts;
     std::vector<int64_t> r_off, s_off;
     int64_t r_total = 0, s_total = 0;
-    int precision = 0;
     size_t ws_bytes = 0;
-    size_t sig_ws = 0;
+    hipStream_t cap_stream = nullptr;
+    // One captured graph per (ws, R, sigma) triple.
+    std::map<std::tuple<void *, double *, double *>, hipGraphExec_t> graphs;
 };
+
+namespace {
+
+int plan_enqueue(figaro_plan *plan, void *ws, double *R, double *sigma, hipStream_t s)
+{
+    for (size_t i = 0; i < plan->inst.size(); i++) {
+        const Shape &sh = plan->shapes[i];
+        const int64_t N = sh.N();
+        int rc = run_r(&plan->inst[i].A, &plan->inst[i].B, sh, plan->layouts[i],
+                       R + plan->r_off[i], N, ws, s);
+        if (rc) return rc;
+        Stage st("jacobi", s);
+        hipError_t e = launch_jacobi(R + plan->r_off[i], (int)N, N, sigma + plan->s_off[i], 60,
+                                     nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "jacobi");
+    }
+    return FIGARO_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -538,7 +657,6 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
 {
     if (!inst || count < 1 || !out) return fail(FIGARO_EINVAL, "bad plan arguments");
     figaro_plan *p = new figaro_plan();
-    p->precision = precision;
     size_t wsmax = 0;
     for (int i = 0; i < count; i++) {
         Shape sh;
@@ -546,6 +664,10 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
         if (rc) {
             delete p;
             return rc;
+        }
+        if (sh.N() > 128) {
+            delete p;
+            return fail(FIGARO_EINVAL, "plan instances need n1 + n2 <= 128 in this build");
         }
         Layout L = make_layout(sh);
         p->inst.push_back(inst[i]);
@@ -589,20 +711,40 @@ int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R,
     if (((uintptr_t)ws) % kAlign) return fail(FIGARO_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < plan->ws_bytes) return fail(FIGARO_EWORKSPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
-    for (size_t i = 0; i < plan->inst.size(); i++) {
-        const Shape &sh = plan->shapes[i];
-        const int64_t N = sh.N();
-        int rc = run_r(&plan->inst[i].A, &plan->inst[i].B, sh, plan->layouts[i], R + plan->r_off[i], N,
-                       ws, s);
-        if (rc) return rc;
-        Stage st("jacobi", s);
-        hipError_t e = launch_jacobi(R + plan->r_off[i], (int)N, N, sigma + plan->s_off[i], 60,
-                                     nullptr, s);
-        if (e != hipSuccess) return hip_fail(e, "jacobi");
+    auto key = std::make_tuple(ws, R, sigma);
+    auto it = plan->graphs.find(key);
+    if (it == plan->graphs.end()) {
+        if (!plan->cap_stream)
+            HIPCHK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking), "plan stream");
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal),
+               "begin capture");
+        g_timing.capturing = true;
+        int rc = plan_enqueue(plan, ws, R, sigma, plan->cap_stream);
+        g_timing.capturing = false;
+        hipError_t e = hipStreamEndCapture(plan->cap_stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+        it = plan->graphs.emplace(key, exec).first;
     }
+    Stage st("plan_graph", s);
+    HIPCHK(hipGraphLaunch(it->second, s), "graph launch");
     return FIGARO_OK;
 }
 
-void figaro_plan_destroy(figaro_plan *plan) { delete plan; }
+void figaro_plan_destroy(figaro_plan *plan)
+{
+    if (!plan) return;
+    for (auto &kv : plan->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    delete plan;
+}
 
 }  // extern "C"

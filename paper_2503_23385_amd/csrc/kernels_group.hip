@@ -38,6 +38,7 @@ __global__ void k_cartesian(Groups g, int64_t m1, int64_t m2)
     g.counts[CNT_R1] = nonempty ? m1 : 0;
     g.counts[CNT_R2] = nonempty ? m2 - 1 : 0;
     g.counts[CNT_JOIN] = nonempty ? m1 * m2 : 0;
+    g.counts[CNT_TA] = nonempty ? m1 - 1 : 0;
     g.key[0] = 0;
     g.offA[0] = 0;
     g.m1[0] = (int32_t)m1;
@@ -287,7 +288,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets(const int64_t *
 
 __global__ void k_set_G(const int64_t *Gtot, int64_t *counts)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) counts[CNT_G] = *Gtot;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        counts[CNT_G] = *Gtot;
+        counts[CNT_TA] = counts[CNT_R1] - *Gtot;
+    }
 }
 
 }  // namespace
@@ -324,14 +328,14 @@ hipError_t launch_group_keys(const int32_t *kA, int64_t m1, const int32_t *kB, i
     if (nbA == 0 || nbB == 0) return hipGetLastError();
     k_match<<<nbA, kGroupThreads, 0, s>>>(kA, runA, counts + CNT_UA, kB, runB, counts + CNT_UB,
                                           matchA, blkM);
-    // G lands in counts[CNT_G] via the scan total (slot 6 used as a temporary).
-    k_scan_small<int32_t><<<1, 1024, 0, s>>>(blkM, nbA, counts + 6, nullptr, 0, nullptr, nullptr, 0,
+    // G lands in counts[CNT_G] via the scan total (CNT_TMP used as a temporary).
+    k_scan_small<int32_t><<<1, 1024, 0, s>>>(blkM, nbA, counts + CNT_TMP, nullptr, 0, nullptr, nullptr, 0,
                                              nullptr, 0);
     k_group_emit<<<nbA, kGroupThreads, 0, s>>>(kA, runA, counts + CNT_UA, runB, matchA, blkM, g,
                                                blkS, nbA);
     k_scan_sums<<<1, 1024, 0, s>>>(blkS, nbA, counts);
     k_group_offsets<<<nbA, kGroupThreads, 0, s>>>(counts + CNT_UA, matchA, blkM, blkS, nbA, g);
-    k_set_G<<<1, 64, 0, s>>>(counts + 6, counts);
+    k_set_G<<<1, 64, 0, s>>>(counts + CNT_TMP, counts);
     return hipGetLastError();
 }
 

@@ -58,8 +58,8 @@ __device__ inline int first_end_gt(const int32_t *start, const int32_t *size, in
 // One tile of B rows: reduce (WRITE = false) or write tails/heads (WRITE = true).
 template <typename Tin, typename Tout, int CPT, int RPT, bool WRITE>
 __global__ __launch_bounds__(kScanThreads) void k_seg_tile(
-    const Tin *__restrict__ B, int64_t ldb, int m2, int n2, int Q, Groups g, int cartesian,
-    Tout *__restrict__ M2, double *__restrict__ heads, int32_t *__restrict__ tileF,
+    const Tin *__restrict__ B, int64_t ldb, int m2, int n2, int Q, Groups g, ScanSide side,
+    int cartesian, Tout *__restrict__ M2, double *__restrict__ heads, int32_t *__restrict__ tileF,
     double *__restrict__ tileS, const double *__restrict__ carry)
 {
     const int tid = threadIdx.x;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_tile(
         }
     }
 
-    if (tid == 0) s_g0 = cartesian ? 0 : first_end_gt(g.offB, g.m2, G, t0);
+    if (tid == 0) s_g0 = cartesian ? 0 : first_end_gt(side.off, side.size, G, t0);
     __syncthreads();
     const int g0 = s_g0;
     for (int r = tid; r < TR; r += kScanThreads) {
@@ -102,19 +102,19 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_tile(
                 pos = (int)s;
             } else if (g0 < G) {
                 const int hi = min(G, g0 + r + 1);
-                const int cand = last_start_le(g.offB, g0, hi, s);
-                if (g.offB[cand] <= s && s < (int64_t)g.offB[cand] + g.m2[cand]) {
+                const int cand = last_start_le(side.off, g0, hi, s);
+                if (side.off[cand] <= s && s < (int64_t)side.off[cand] + side.size[cand]) {
                     gi = cand;
-                    pos = (int)(s - g.offB[cand]);
+                    pos = (int)(s - side.off[cand]);
                 }
             }
         }
         m_g[r] = gi;
         m_pos[r] = pos;
         if (WRITE && gi >= 0) {
-            const double sm1 = sqrt((double)g.m1[gi]);
-            const int m2g = g.m2[gi];
-            m_out[r] = g.r2[gi] + pos - 1;
+            const double sm1 = sqrt((double)side.other[gi]);
+            const int m2g = side.size[gi];
+            m_out[r] = side.obase[gi] - (side.sub_g ? gi : 0) + pos - 1;
             if (pos > 0) {
                 const double sp = sqrt((double)pos), sp1 = sqrt((double)pos + 1.0);
                 m_c1[r] = sm1 * sp / sp1;
@@ -322,7 +322,33 @@ __global__ __launch_bounds__(256) void k_assemble_a(const Tin *__restrict__ A, i
     }
 }
 
+__global__ __launch_bounds__(256) void k_head_rows(Groups g, const double *__restrict__ hA,
+                                                  const double *__restrict__ hB, int n1, int n2,
+                                                  void *out, int out_f64)
+{
+    const int N = n1 + n2;
+    const int64_t G = g.counts[CNT_G];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gi = e / N;
+    const int c = (int)(e - gi * N);
+    if (gi >= G) return;
+    const double v = c < n1 ? sqrt((double)g.m2[gi]) * hA[gi * n1 + c]
+                            : sqrt((double)g.m1[gi]) * hB[gi * n2 + (c - n1)];
+    if (out_f64) ((double *)out)[e] = v;
+    else ((float *)out)[e] = (float)v;
+}
+
 }  // namespace
+
+hipError_t launch_head_rows(Groups g, int64_t gcap, const double *headsA, const double *headsB,
+                            int64_t n1, int64_t n2, void *out, int out_f64, hipStream_t s)
+{
+    const int64_t total = gcap * (n1 + n2);
+    if (total == 0) return hipSuccess;
+    k_head_rows<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(g, headsA, headsB, (int)n1, (int)n2,
+                                                                 out, out_f64);
+    return hipGetLastError();
+}
 
 ScanPlan scan_plan(int64_t m2, int64_t n2, int in_bytes)
 {
@@ -340,8 +366,8 @@ ScanPlan scan_plan(int64_t m2, int64_t n2, int in_bytes)
     return p;
 }
 
-hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, int64_t n2,
-                           Groups g, int cartesian, void *M2, int out_f64, double *heads,
+hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, int64_t n2, Groups g,
+                           ScanSide side, int cartesian, void *M2, int out_f64, double *heads,
                            int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp,
                            hipStream_t s)
 {
@@ -350,8 +376,8 @@ hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, i
     const unsigned grid = (unsigned)sp.ntiles;
 #define FIGARO_TILE(TI, TO, CPT, WR)                                                              \
     k_seg_tile<TI, TO, CPT, 16, WR><<<grid, kScanThreads, 0, s>>>(                               \
-        (const TI *)B, ldb, (int)m2, (int)n2, sp.q, g, cartesian, (TO *)M2, heads, tileF, tileS,  \
-        carry)
+        (const TI *)B, ldb, (int)m2, (int)n2, sp.q, g, side, cartesian, (TO *)M2, heads, tileF,   \
+        tileS, carry)
 #define FIGARO_TILE_ALL(WR)                                                                       \
     do {                                                                                          \
         if (sp.cpt == 1) {                                                                        \

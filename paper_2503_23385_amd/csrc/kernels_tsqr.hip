@@ -1,31 +1,37 @@
 // Householder TSQR of the compact matrix (the QR step of the paper's
-// pipeline, Experiments section: dense Householder QR of the concatenated
-// heads and tails; here done as a tall-skinny reduction instead of a
-// library geqrf).
+// pipeline, Experiments section: a dense Householder QR of the concatenated
+// heads and tails; here a tall-skinny reduction instead of a library geqrf).
 //
-// Each workgroup owns one N x N upper triangle R (packed in LDS) and streams
-// its share of rows through it in blocks X of BR rows:
+// The unit of work is one upper triangle R that absorbs blocks X of rows:
 //     R <- triu(QR([R; X])).
-// Reflector j of a step involves only row j of R and column j of X
-// (structured TSQR): with alpha = R_jj and s = |X_:j|^2,
-//     beta = -sign(alpha) sqrt(alpha^2 + s),  tau = (beta - alpha) / beta,
-//     v = X_:j / (alpha - beta),  w_k = R_jk + v . X_:k,
-//     R_jk -= tau w_k,  X_:k -= tau w_k v          (k > j),  R_jj = beta.
-// Q is never formed: only R is wanted.  Thread layout: wave w owns columns
-// [w*CW, (w+1)*CW); lane (k, q) keeps RPT rows of column k of X in registers,
-// so every reduction over rows is a shuffle inside one wave and the only
-// cross-wave exchange per column is the reflector v (one LDS broadcast and
-// one barrier per column, double-buffered).
+// Reflector j involves only row j of R and column j of X (structured TSQR).
+// With alpha = R_jj, d_k = x_j . x_k (so d_j = |x_j|^2) and
+//     beta = -sign(alpha) sqrt(alpha^2 + d_j),  tau = 1 - alpha / beta,
+// the reflector with v = x_j / (alpha - beta) updates, for k > j,
+//     w_k = R_jk + d_k / (alpha - beta),  R_jk -= tau w_k,  x_k += (w_k / beta) x_j,
+// and sets R_jj = beta (tau * scale = -1 / beta folded in).  Q is never formed.
 //
-// The same kernel reduces stacked triangles (tree levels) and the final
-// [R_1 ; 0 | R_2] merge of the two compact-matrix regions; sign
-// normalisation of the root is a separate tiny kernel.
+// Widths up to 64: one wave owns one triangle (packed in LDS); lane (k, h)
+// keeps RPT rows of column k of X in registers for row set h, column j is
+// broadcast through a per-wave LDS slot, and every reduction stays inside the
+// wave -- no workgroup barrier.  A region is reduced in one launch: each wave
+// reduces its rows to a leaf triangle, then the waves climb a binary tree;
+// at each node the second of the two children to arrive (per-node atomic
+// counter) combines them, always as left absorbing right, so results do not
+// depend on timing; the first to arrive exits.  Nothing waits on anything.
+//
+// Widths 128 and 256: a workgroup owns the triangle; wave w owns a slab of
+// columns and the reflector is exchanged through LDS with one barrier per
+// column.  Tree levels are separate launches there.
+#include <float.h>
+
 #include "common.h"
 
 namespace figaro {
 namespace {
 
 constexpr int kTsqrThreads = 256;
+constexpr int kWavesPerBlock = 4;
 
 __host__ __device__ constexpr int packed_size(int np) { return np * (np + 1) / 2; }
 __device__ inline int pidx(int np, int j, int k) { return j * np - (j * (j - 1)) / 2 + (k - j); }
@@ -43,8 +49,35 @@ __device__ inline Tacc load_src(const RowSrc &s, int64_t lr, int k)
 
 __device__ inline int64_t src_rows(const RowSrc &s) { return s.rows_dev ? *s.rows_dev : s.rows_host; }
 
+__device__ inline double readlane_f64(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Hardware reciprocal / reciprocal square root refined by two Newton steps.
+__device__ inline double rcp_refined(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+__device__ inline double rsq_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
+// ------------------------------------------------------------------ workgroup kernel (NP 128, 256)
+
 template <int NP, typename Tin, typename Tacc>
-__global__ __launch_bounds__(kTsqrThreads) void k_tsqr_stream(RowSrc s0, RowSrc s1, int nsrc,
+__global__ __launch_bounds__(kTsqrThreads) void k_tsqr_stream(const double *init, int64_t init_ld,
+                                                              RowSrc s0, RowSrc s1, int nsrc,
                                                               int width, int tri_rows,
                                                               double *tri_out, int64_t tri_stride)
 {
@@ -61,7 +94,10 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_stream(RowSrc s0, RowSrc 
     __shared__ Tacc vbuf[2][BR];
     __shared__ double sc[2][2];
 
-    for (int i = tid; i < packed_size(NP); i += kTsqrThreads) Rp[i] = Tacc(0);
+    for (int e = tid; e < width * NP; e += kTsqrThreads) {
+        const int j = e / NP, kk = e - j * NP;
+        if (kk >= j) Rp[pidx(NP, j, kk)] = (init && kk < width) ? (Tacc)init[(int64_t)j * init_ld + kk] : Tacc(0);
+    }
 
     const int64_t rows0 = src_rows(s0);
     const int64_t total = rows0 + (nsrc > 1 ? src_rows(s1) : 0);
@@ -84,11 +120,16 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_stream(RowSrc s0, RowSrc 
             }
             x[i] = v;
         }
-        // Rows of a stacked triangle are zero left of their index within it.
+        // Leading columns known to be zero in this block: source column offset, and
+        // for stacked triangles the row index inside its triangle.
         int jstart = 0;
-        if (tri_rows > 0) {
-            const int64_t off = rb % tri_rows;
-            if (off + BR <= tri_rows) jstart = (int)off;
+        const int64_t rlast = min(r_end, rb + BR) - 1;
+        if (rlast < rows0) jstart = s0.col_off;
+        else if (rb >= rows0) jstart = s1.col_off;
+        if (tri_rows > 0 && jstart == (rb < rows0 ? s0.col_off : s1.col_off)) {
+            const int64_t lr = rb < rows0 ? rb : rb - rows0;
+            const int64_t off = lr % tri_rows;
+            if (off + BR <= tri_rows) jstart += (int)off;
         }
         for (int j = jstart; j < width; j++, it++) {
             const int buf = it & 1;
@@ -145,132 +186,238 @@ __global__ __launch_bounds__(kTsqrThreads) void k_tsqr_stream(RowSrc s0, RowSrc 
     }
 }
 
-__device__ inline double readlane_f64(double v, int l)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
-__device__ inline float readlane_f32(float v, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ inline double readlane_t(double v, int l) { return readlane_f64(v, l); }
-__device__ inline float readlane_t(float v, int l) { return readlane_f32(v, l); }
+// ------------------------------------------------------------------ one wave per triangle (NP <= 64)
 
-// One wave per triangle (widths up to 64): lane (k, h) holds RPT rows of column k of the
-// block for row set h (H = 64 / NP row sets).  Column j of the block is broadcast through a
-// per-wave LDS slot; all reductions stay inside the wave, so there is no workgroup barrier.
-// With d_k = x_j . x_k (d_j = |x_j|^2) and p = beta (alpha - beta):
-//     w_k = R_jk + d_k / (alpha - beta),  R_jk -= tau w_k,  x_k += (w_k / beta) x_j,
-// which is the reflector update above with tau * scale = -1 / beta folded in.
-constexpr int kWavesPerBlock = 4;
+template <int NP>
+struct WaveGeom {
+    static constexpr int H = NP >= 64 ? 1 : 64 / NP;    // row sets per wave
+    static constexpr int RPT = NP >= 64 ? 32 : 16;      // rows per lane per block
+    static constexpr int BR = H * RPT;                  // rows per block
+    static constexpr int PS = packed_size(NP);
+};
 
-template <int NP, typename Tin, typename Tacc, int RPT>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_wave(RowSrc s0, RowSrc s1, int nsrc,
-                                                                  int width, int tri_rows, int ntri,
-                                                                  double *tri_out, int64_t tri_stride)
+// Absorb one block (RPT rows per lane, already in x) into R for columns [jstart, width).
+template <int NP, typename Tacc>
+__device__ inline void wave_block(Tacc (&x)[WaveGeom<NP>::RPT], Tacc *Rp, Tacc *xb, int k, int h,
+                                  int jstart, int width)
 {
-    constexpr int H = NP >= 64 ? 1 : 64 / NP;
-    constexpr int BR = H * RPT;
-    constexpr int PS = packed_size(NP);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int gw = blockIdx.x * kWavesPerBlock + wv;
-    const int k = lane % NP;
-    const int h = lane / NP;
-    __shared__ Tacc Rs[kWavesPerBlock][PS];
-    __shared__ __align__(16) Tacc Xs[kWavesPerBlock][BR];
-    if (gw >= ntri) return;  // waves are independent: no block-level barrier follows
-    Tacc *Rp = Rs[wv];
-    Tacc *xb = Xs[wv] + h * RPT;
-    for (int i = lane; i < PS; i += 64) Rp[i] = Tacc(0);
-
-    const int64_t rows0 = src_rows(s0);
-    const int64_t total = rows0 + (nsrc > 1 ? src_rows(s1) : 0);
-    int64_t chunk = (total + ntri - 1) / ntri;
-    chunk = ((chunk + BR - 1) / BR) * BR;
-    const int64_t r_begin = (int64_t)gw * chunk;
-    const int64_t r_end = min(total, r_begin + chunk);
+    constexpr int RPT = WaveGeom<NP>::RPT;
     const bool col_ok = k < width;
+    for (int j = jstart; j < width; j++) {
+        __builtin_amdgcn_wave_barrier();
+        if (k == j) {
+#pragma unroll
+            for (int i = 0; i < RPT; i++) xb[i] = x[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        Tacc xj[RPT];
+#pragma unroll
+        for (int i = 0; i < RPT; i++) xj[i] = xb[i];
+        const double alpha = (double)Rp[pidx(NP, j, j)];
+        const Tacc rjk = (k > j && col_ok) ? Rp[pidx(NP, j, k)] : Tacc(0);
+        Tacc dp[4] = {Tacc(0), Tacc(0), Tacc(0), Tacc(0)};
+#pragma unroll
+        for (int i = 0; i < RPT; i++) dp[i & 3] += xj[i] * x[i];
+        Tacc d = (dp[0] + dp[1]) + (dp[2] + dp[3]);
+#pragma unroll
+        for (int off = NP; off < 64; off <<= 1) d += shfl_xor_t(d, off);
+        double s;
+        if constexpr (sizeof(Tacc) == 8) {
+            s = readlane_f64(d, j);
+        } else {
+            // reflector scalars in FP64 for the FP32 form
+            double sp[2] = {0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < RPT; i++) sp[i & 1] += (double)xj[i] * (double)xj[i];
+            double sd = sp[0] + sp[1];
+#pragma unroll
+            for (int off = NP; off < 64; off <<= 1) sd += shfl_xor_t(sd, off);
+            s = readlane_f64(sd, j);
+        }
+        const double q = fma(alpha, alpha, s);
+        // A column whose norm is below the normal range is left untouched (tau = 0).
+        if (s > 0.0 && q >= DBL_MIN) {
+            const double r = rsq_refined(q);  // 1 / |(alpha, x_j)|
+            const double sg = alpha >= 0.0 ? 1.0 : -1.0;
+            const double nrm = q * r;
+            const double beta = -sg * nrm;
+            const double inv_beta = -sg * r;
+            const double scl = rcp_refined(alpha + sg * nrm);  // 1 / (alpha - beta)
+            const double tau = 1.0 - alpha * inv_beta;
+            if (k > j && col_ok) {
+                const double w = (double)rjk + scl * (double)d;
+                if (h == 0) Rp[pidx(NP, j, k)] = (Tacc)((double)rjk - tau * w);
+                const Tacc c = (Tacc)(w * inv_beta);
+#pragma unroll
+                for (int i = 0; i < RPT; i++) x[i] += c * xj[i];
+            }
+            if (k == j && h == 0) Rp[pidx(NP, j, j)] = (Tacc)beta;
+        }
+    }
+}
 
-    for (int64_t rb = r_begin; rb < r_end; rb += BR) {
+// R <- triangle T (width rows of ld doubles, entries left of the diagonal ignored).
+template <int NP, typename Tacc>
+__device__ inline void wave_init_tri(Tacc *Rp, const double *T, int64_t ld, int width, int lane)
+{
+    for (int e = lane; e < width * NP; e += 64) {
+        const int j = e / NP, kk = e - j * NP;
+        if (kk >= j) Rp[pidx(NP, j, kk)] = kk < width ? (Tacc)T[(int64_t)j * ld + kk] : Tacc(0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int NP, typename Tacc>
+__device__ inline void wave_zero(Tacc *Rp, int lane)
+{
+    for (int e = lane; e < WaveGeom<NP>::PS; e += 64) Rp[e] = Tacc(0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int NP, typename Tacc>
+__device__ inline void wave_store(const Tacc *Rp, double *out, int width, int lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < width * NP; e += 64) {
+        const int j = e / NP, kk = e - j * NP;
+        out[e] = (kk >= j && kk < width) ? (double)Rp[pidx(NP, j, kk)] : 0.0;
+    }
+}
+
+// Absorb a triangle of `trows` rows (ld doubles each) whose columns sit at [off, off + tw):
+// row i has nonzeros only from column off + i on.
+template <int NP, typename Tacc>
+__device__ inline void wave_absorb_tri(Tacc *Rp, Tacc *xb, const double *T, int64_t ld, int trows,
+                                       int off, int tw, int width, int k, int h)
+{
+    constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR;
+    for (int b0 = 0; b0 < trows; b0 += BR) {
+        Tacc x[RPT];
+#pragma unroll
+        for (int i = 0; i < RPT; i++) {
+            const int r = b0 + h * RPT + i;
+            const int c = k - off;
+            x[i] = (r < trows && c >= 0 && c < tw) ? (Tacc)T[(int64_t)r * ld + c] : Tacc(0);
+        }
+        wave_block<NP, Tacc>(x, Rp, xb, k, h, off + b0, width);
+    }
+}
+
+// Absorb rows [r0, r1) of up to two sources (concatenated) in blocks.
+template <int NP, typename Tin, typename Tacc>
+__device__ inline void wave_absorb_rows(Tacc *Rp, Tacc *xb, const RowSrc &s0, const RowSrc &s1,
+                                        int64_t rows0, int64_t r0, int64_t r1, int tri_rows,
+                                        int width, int k, int h)
+{
+    constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR;
+    for (int64_t rb = r0; rb < r1; rb += BR) {
         Tacc x[RPT];
 #pragma unroll
         for (int i = 0; i < RPT; i++) {
             const int64_t r = rb + h * RPT + i;
             Tacc v = Tacc(0);
-            if (r < r_end && col_ok) {
+            if (r < r1 && k < width) {
                 if (r < rows0) v = load_src<Tin, Tacc>(s0, r, k);
                 else v = load_src<Tin, Tacc>(s1, r - rows0, k);
             }
             x[i] = v;
         }
         int jstart = 0;
-        if (tri_rows > 0) {
-            const int64_t off = rb % tri_rows;
-            if (off + BR <= tri_rows) jstart = (int)off;
+        const int64_t rlast = min(r1, rb + BR) - 1;
+        if (rlast < rows0) jstart = s0.col_off;
+        else if (rb >= rows0) jstart = s1.col_off;
+        if (tri_rows > 0 && (rlast < rows0 || rb >= rows0)) {
+            const int64_t lr = rb < rows0 ? rb : rb - rows0;
+            const int64_t off = lr % tri_rows;
+            if (off + BR <= tri_rows) jstart += (int)off;
         }
-        for (int j = jstart; j < width; j++) {
-            __builtin_amdgcn_wave_barrier();
-            if (k == j) {
-#pragma unroll
-                for (int i = 0; i < RPT; i++) xb[i] = x[i];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            Tacc xj[RPT];
-#pragma unroll
-            for (int i = 0; i < RPT; i++) xj[i] = xb[i];
-            const double alpha = (double)Rp[pidx(NP, j, j)];
-            const Tacc rjk = (k > j && col_ok) ? Rp[pidx(NP, j, k)] : Tacc(0);
-            Tacc d0 = Tacc(0), d1 = Tacc(0);
-#pragma unroll
-            for (int i = 0; i < RPT; i += 2) {
-                d0 += xj[i] * x[i];
-                if (i + 1 < RPT) d1 += xj[i + 1] * x[i + 1];
-            }
-            Tacc d = d0 + d1;
-#pragma unroll
-            for (int off = NP; off < 64; off <<= 1) d += shfl_xor_t(d, off);
-            double s;
-            if constexpr (sizeof(Tacc) == 8) {
-                s = readlane_t(d, j);
-            } else {
-                // reflector scalars in FP64 for the FP32 form
-                double sd = 0.0;
-#pragma unroll
-                for (int i = 0; i < RPT; i++) sd += (double)xj[i] * (double)xj[i];
-#pragma unroll
-                for (int off = NP; off < 64; off <<= 1) sd += shfl_xor_t(sd, off);
-                s = readlane_f64(sd, j);
-            }
-            if (s > 0.0) {
-                const double nrm = sqrt(alpha * alpha + s);
-                const double beta = alpha >= 0.0 ? -nrm : nrm;
-                const double amb = alpha - beta;
-                const double rp = 1.0 / (beta * amb);
-                const double inv_beta = amb * rp;
-                const double scl = beta * rp;
-                const double tau = 1.0 - alpha * inv_beta;
-                if (k > j && col_ok) {
-                    const double w = (double)rjk + scl * (double)d;
-                    if (h == 0) Rp[pidx(NP, j, k)] = (Tacc)((double)rjk - tau * w);
-                    const Tacc c = (Tacc)(w * inv_beta);
-#pragma unroll
-                    for (int i = 0; i < RPT; i++) x[i] += c * xj[i];
-                }
-                if (k == j && h == 0) Rp[pidx(NP, j, j)] = (Tacc)beta;
-            }
+        wave_block<NP, Tacc>(x, Rp, xb, k, h, jstart, width);
+    }
+}
+
+// Rows of s0 then s1 reduced into ntri triangles (optionally starting from `init`).
+template <int NP, typename Tin, typename Tacc>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_wave(const double *init, int64_t init_ld,
+                                                                  RowSrc s0, RowSrc s1, int nsrc,
+                                                                  int width, int tri_rows, int ntri,
+                                                                  double *tri_out, int64_t tri_stride)
+{
+    using Gm = WaveGeom<NP>;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gw = blockIdx.x * kWavesPerBlock + wv;
+    const int k = lane % NP, h = lane / NP;
+    __shared__ Tacc Rs[kWavesPerBlock][Gm::PS];
+    __shared__ __align__(16) Tacc Xs[kWavesPerBlock][Gm::BR];
+    if (gw >= ntri) return;  // waves are independent: no block-level barrier follows
+    Tacc *Rp = Rs[wv];
+    Tacc *xb = Xs[wv] + h * Gm::RPT;
+    if (init) wave_init_tri<NP, Tacc>(Rp, init, init_ld, width, lane);
+    else wave_zero<NP, Tacc>(Rp, lane);
+    const int64_t rows0 = src_rows(s0);
+    const int64_t total = rows0 + (nsrc > 1 ? src_rows(s1) : 0);
+    int64_t chunk = (total + ntri - 1) / ntri;
+    chunk = ((chunk + Gm::BR - 1) / Gm::BR) * Gm::BR;
+    const int64_t r0 = (int64_t)gw * chunk, r1 = min(total, r0 + chunk);
+    wave_absorb_rows<NP, Tin, Tacc>(Rp, xb, s0, s1, rows0, r0, r1, tri_rows, width, k, h);
+    wave_store<NP, Tacc>(Rp, tri_out + (int64_t)gw * tri_stride, width, lane);
+}
+
+// One region in one launch: leaves, then the binary tree (see the file comment).
+// slots: sum over levels of the node count, each width x NP doubles; counters: one
+// int per parent node (zero on entry).
+template <int NP, typename Tin, typename Tacc>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_tree(RowSrc src, int width, int nleaves,
+                                                                  double *slots, int32_t *counters,
+                                                                  double *root_out)
+{
+    using Gm = WaveGeom<NP>;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gw = blockIdx.x * kWavesPerBlock + wv;
+    const int k = lane % NP, h = lane / NP;
+    __shared__ Tacc Rs[kWavesPerBlock][Gm::PS];
+    __shared__ __align__(16) Tacc Xs[kWavesPerBlock][Gm::BR];
+    if (gw >= nleaves) return;
+    Tacc *Rp = Rs[wv];
+    Tacc *xb = Xs[wv] + h * Gm::RPT;
+    wave_zero<NP, Tacc>(Rp, lane);
+    const int64_t rows = src_rows(src);
+    int64_t chunk = (rows + nleaves - 1) / nleaves;
+    chunk = ((chunk + Gm::BR - 1) / Gm::BR) * Gm::BR;
+    const int64_t r0 = (int64_t)gw * chunk, r1 = min(rows, r0 + chunk);
+    RowSrc none{};
+    wave_absorb_rows<NP, Tin, Tacc>(Rp, xb, src, none, rows, r0, r1, 0, width, k, h);
+
+    const int64_t tsz = (int64_t)width * NP;
+    int node = gw, n = nleaves;
+    int64_t soff = 0, coff = 0;
+    while (n > 1) {
+        const int sib = node ^ 1;
+        if (sib < n) {
+            wave_store<NP, Tacc>(Rp, slots + (soff + node) * tsz, width, lane);
+            __threadfence();
+            int old = 0;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(&counters[coff + (node >> 1)], 1, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            old = __builtin_amdgcn_readfirstlane(old);
+            if (old == 0) return;  // the sibling finishes this node
+            __threadfence();
+            const int left = node & ~1;
+            wave_init_tri<NP, Tacc>(Rp, slots + (soff + left) * tsz, NP, width, lane);
+            wave_absorb_tri<NP, Tacc>(Rp, xb, slots + (soff + left + 1) * tsz, NP, width, 0, width,
+                                      width, k, h);
         }
+        node >>= 1;
+        soff += n;
+        coff += (n + 1) / 2;
+        n = (n + 1) / 2;
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    double *out = tri_out + (int64_t)gw * tri_stride;
-    for (int e = lane; e < width * NP; e += 64) {
-        const int j = e / NP, kk = e - j * NP;
-        out[e] = (kk >= j && kk < width) ? (double)Rp[pidx(NP, j, kk)] : 0.0;
-    }
+    wave_store<NP, Tacc>(Rp, root_out, width, lane);
 }
 
 __global__ void k_sign_normalise(const double *Rin, int64_t ldin, int n, double *R, int64_t ldr)
@@ -297,13 +444,15 @@ __global__ void k_sign_normalise(const double *Rin, int64_t ldin, int n, double 
 }
 
 template <int NP>
-hipError_t launch_np(int acc_f64, int in_f64, RowSrc s0, RowSrc s1, int nsrc, int width, int tri_rows,
-                     int nwg, double *tri, int64_t stride, hipStream_t s)
+hipError_t launch_np(int acc_f64, int in_f64, const double *init, int64_t init_ld, RowSrc s0,
+                     RowSrc s1, int nsrc, int width, int tri_rows, int nwg, double *tri,
+                     int64_t stride, hipStream_t s)
 {
     if constexpr (NP <= 64) {
         const unsigned grid = (unsigned)((nwg + kWavesPerBlock - 1) / kWavesPerBlock);
-#define FIGARO_WAVE(TI, TA) \
-    k_tsqr_wave<NP, TI, TA, 16><<<grid, 64 * kWavesPerBlock, 0, s>>>(s0, s1, nsrc, width, tri_rows, nwg, tri, stride)
+#define FIGARO_WAVE(TI, TA)                                                                    \
+    k_tsqr_wave<NP, TI, TA><<<grid, 64 * kWavesPerBlock, 0, s>>>(init, init_ld, s0, s1, nsrc,  \
+                                                                 width, tri_rows, nwg, tri, stride)
         if (acc_f64) {
             if (in_f64) FIGARO_WAVE(double, double);
             else FIGARO_WAVE(float, double);
@@ -313,22 +462,42 @@ hipError_t launch_np(int acc_f64, int in_f64, RowSrc s0, RowSrc s1, int nsrc, in
         }
 #undef FIGARO_WAVE
         return hipGetLastError();
-    }
-    if (acc_f64) {
-        if constexpr (packed_size(NP) * 8 + 2 * 16 * (256 / NP) * 8 <= 160 * 1024) {
-            if (in_f64)
-                k_tsqr_stream<NP, double, double><<<nwg, kTsqrThreads, 0, s>>>(s0, s1, nsrc, width, tri_rows, tri, stride);
-            else
-                k_tsqr_stream<NP, float, double><<<nwg, kTsqrThreads, 0, s>>>(s0, s1, nsrc, width, tri_rows, tri, stride);
-        } else {
-            return hipErrorInvalidValue;
-        }
     } else {
-        if (in_f64)
-            k_tsqr_stream<NP, double, float><<<nwg, kTsqrThreads, 0, s>>>(s0, s1, nsrc, width, tri_rows, tri, stride);
-        else
-            k_tsqr_stream<NP, float, float><<<nwg, kTsqrThreads, 0, s>>>(s0, s1, nsrc, width, tri_rows, tri, stride);
+#define FIGARO_WG(TI, TA)                                                                      \
+    k_tsqr_stream<NP, TI, TA><<<nwg, kTsqrThreads, 0, s>>>(init, init_ld, s0, s1, nsrc, width,  \
+                                                          tri_rows, tri, stride)
+        if (acc_f64) {
+            if constexpr (packed_size(NP) * 8 + 2 * 16 * (256 / NP) * 8 <= 160 * 1024) {
+                if (in_f64) FIGARO_WG(double, double);
+                else FIGARO_WG(float, double);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        } else {
+            if (in_f64) FIGARO_WG(double, float);
+            else FIGARO_WG(float, float);
+        }
+#undef FIGARO_WG
+        return hipGetLastError();
     }
+}
+
+template <int NP>
+hipError_t launch_tree_np(int acc_f64, int in_f64, RowSrc src, int width, int nleaves,
+                          double *slots, int32_t *counters, double *root, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((nleaves + kWavesPerBlock - 1) / kWavesPerBlock);
+#define FIGARO_TREE(TI, TA)                                                                      \
+    k_tsqr_tree<NP, TI, TA><<<grid, 64 * kWavesPerBlock, 0, s>>>(src, width, nleaves, slots,     \
+                                                                 counters, root)
+    if (acc_f64) {
+        if (in_f64) FIGARO_TREE(double, double);
+        else FIGARO_TREE(float, double);
+    } else {
+        if (in_f64) FIGARO_TREE(double, float);
+        else FIGARO_TREE(float, float);
+    }
+#undef FIGARO_TREE
     return hipGetLastError();
 }
 
@@ -344,22 +513,44 @@ int tsqr_padded_width(int n)
 
 int tsqr_block_rows(int np)
 {
-    if (np <= 64) return (64 / np) * 16;  // wave kernel: row sets x rows per thread
-    return (256 / np) * 16;               // workgroup kernel
+    if (np <= 64) return np >= 64 ? 32 : (64 / np) * 16;  // wave kernel: row sets x rows per lane
+    return (256 / np) * 16;                               // workgroup kernel
 }
 
-hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, RowSrc s0, RowSrc s1, int nsrc,
-                              int width, int tri_rows, int nwg, double *tri,
-                              int64_t tri_stride, hipStream_t s)
+void tsqr_tree_sizes(int nleaves, int64_t *slots, int64_t *counters)
+{
+    int64_t s = 0, c = 0;
+    int n = nleaves;
+    while (n > 1) {
+        s += n;
+        c += (n + 1) / 2;
+        n = (n + 1) / 2;
+    }
+    *slots = s + 1;
+    *counters = c + 1;
+}
+
+hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *init, int64_t init_ld,
+                              RowSrc s0, RowSrc s1, int nsrc, int width, int tri_rows, int nwg,
+                              double *tri, int64_t tri_stride, hipStream_t s)
 {
     switch (np) {
-    case 4: return launch_np<4>(acc_f64, in_f64, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
-    case 8: return launch_np<8>(acc_f64, in_f64, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
-    case 16: return launch_np<16>(acc_f64, in_f64, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
-    case 32: return launch_np<32>(acc_f64, in_f64, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
-    case 64: return launch_np<64>(acc_f64, in_f64, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
-    case 128: return launch_np<128>(acc_f64, in_f64, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
-    case 256: return launch_np<256>(acc_f64, in_f64, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
+#define FIGARO_CASE(NPV) \
+    case NPV: return launch_np<NPV>(acc_f64, in_f64, init, init_ld, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
+    FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64) FIGARO_CASE(128) FIGARO_CASE(256)
+#undef FIGARO_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, RowSrc src, int width, int nleaves,
+                            double *slots, int32_t *counters, double *root, hipStream_t s)
+{
+    switch (np) {
+#define FIGARO_CASE(NPV) \
+    case NPV: return launch_tree_np<NPV>(acc_f64, in_f64, src, width, nleaves, slots, counters, root, s);
+    FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64)
+#undef FIGARO_CASE
     default: return hipErrorInvalidValue;
     }
 }

@@ -57,12 +57,20 @@ def test_workspace_size_ok_and_monotone():
     (table(), table(), 9),                                # bad precision
     (table(cols=300), table(cols=300), 1),                # N > 512
     (table(cols=100), table(cols=100), 0),                # N = 200 > FP64 limit of this build
+    (table(), table(), 0x200),                            # unknown flag
+    (table(), table(), 0x101 | 0x400),                    # unknown flag beside a valid one
 ])
 def test_invalid_arguments_rejected_on_host(A, B, prec):
     rc, _ = ws_size(A, B, prec)
     assert rc == fg.FIGARO_EINVAL
     msg = fg.lib().figaro_last_error().decode()
     assert msg
+
+
+def test_two_sided_flag_accepted_and_sized():
+    rc, n_c = ws_size(table(1000, 4, keys=8), table(1000, 4, keys=8), 0)
+    rc2, n_t = ws_size(table(1000, 4, keys=8), table(1000, 4, keys=8), 0x100)
+    assert rc == 0 and rc2 == 0 and n_t > 0
 
 
 def test_figaro_r_host_checks():

@@ -61,6 +61,9 @@ def small_cases():
         "keyed_n128": W.random_instance(rng(8), 3000, 64, 3500, 64, n_values=40),
         "keyed_one_big_group": W.random_instance(rng(9), 40, 5, 50000, 8, n_values=1),
         "keyed_narrow": W.random_instance(rng(10), 1000, 1, 1200, 1, n_values=30),
+        # A tail leaf with a single row: its rank-deficient residual columns shrink
+        # geometrically (regression case for reflector scalars that must not underflow).
+        "cart_tail_leaf": W.random_instance(rng(14), 4097, 5, 2000, 59),
     }
     # every group has one B row: no tails at all
     inst = W.random_instance(rng(11), 3000, 6, 1, 5)
@@ -117,11 +120,12 @@ def test_compact_matrix_diagnostic(name):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_r_and_sigma_parity(name, prec):
+@pytest.mark.parametrize("form", ["claim1", "two_sided"])
+def test_r_and_sigma_parity(name, prec, form):
     inst = CASES[name]
-    say(f"[r+sigma] {name} {prec}")
+    say(f"[r+sigma] {name} {prec} {form}")
     A, B, kA, kB = to_dev(inst)
-    R, ws = fg().r(A, B, kA, kB, prec)
+    R, ws = fg().r(A, B, kA, kB, prec, two_sided=(form == "two_sided"))
     S = fg().sigma(R)
     torch.cuda.synchronize()
     assert fg().status(ws) == 0
@@ -140,6 +144,36 @@ def test_r_and_sigma_parity(name, prec):
     say(f"    relF(R)={er:.3e} rel2(sigma)={es:.3e}")
     assert er <= TOL_R[prec]
     assert es <= TOL_S[prec]
+
+
+@pytest.mark.parametrize("name", ["cart_ragged", "keyed_zipf_n64", "keyed_uniform_sparse", "keyed_singleton_B"])
+def test_two_sided_intermediates(name):
+    """Two-sided form: H(A_g) and the A tails against per-group sums and the Helmert rows."""
+    inst = CASES[name]
+    say(f"[two-sided compact] {name}")
+    A, B, kA, kB = to_dev(inst)
+    out = fg().compact(A, B, kA, kB, "fp64", two_sided=True)
+    tab, counts = (oracle.groups(inst.keys_A, inst.keys_B) if inst.keys_A is not None
+                   else oracle.groups(None, None, inst.A.shape[0], inst.B.shape[0]))
+    assert np.array_equal(out["counts"], counts)
+    Af = np.asarray(inst.A, dtype=np.float64)
+    Bf = np.asarray(inst.B, dtype=np.float64)
+    n1 = Af.shape[1]
+    ta = out["tails_a"]
+    hr = out["heads_rows"]
+    for g, (key, oa, ma, ob, mb, r1, r2) in enumerate(tab.tolist()):
+        Ag = Af[oa:oa + ma]
+        hA = Ag.sum(axis=0) / np.sqrt(ma)
+        assert np.allclose(out["heads_a"][g], hA, rtol=1e-13, atol=1e-13)
+        hB = Bf[ob:ob + mb].sum(axis=0) / np.sqrt(mb)
+        assert np.allclose(hr[g], np.concatenate([np.sqrt(mb) * hA, np.sqrt(ma) * hB]), rtol=1e-13, atol=1e-12)
+        # tail i: (i * A_{i+1} - S_i) / sqrt(i (i+1)), scaled by sqrt(m2_g)
+        if ma > 1:
+            i = np.arange(1, ma)[:, None]
+            S = np.cumsum(Ag, axis=0)[:-1]
+            ref = np.sqrt(mb) * (i * Ag[1:] - S) / np.sqrt(i * (i + 1.0))
+            got = ta[r1 - g:r1 - g + ma - 1]
+            assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * max(1.0, np.abs(ref).max()))
 
 
 def test_fp32_inputs_widened_exactly():
@@ -172,15 +206,17 @@ def test_unsorted_keys_reported():
     assert fg().status(ws) == fg().FIGARO_EUNSORTED
 
 
-def test_deterministic():
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_deterministic(two_sided):
     inst = CASES["keyed_zipf_n64"]
     A, B, kA, kB = to_dev(inst)
-    R1, ws = fg().r(A, B, kA, kB, "fp64")
+    R1, ws = fg().r(A, B, kA, kB, "fp64", two_sided=two_sided)
     R1 = R1.clone()
     S1 = fg().sigma(R1).clone()
-    R2, _ = fg().r(A, B, kA, kB, "fp64", ws=ws)
-    S2 = fg().sigma(R2)
-    assert torch.equal(R1, R2) and torch.equal(S1, S2)
+    for _ in range(3):
+        R2, _ = fg().r(A, B, kA, kB, "fp64", ws=ws, two_sided=two_sided)
+        S2 = fg().sigma(R2)
+        assert torch.equal(R1, R2) and torch.equal(S1, S2)
 
 
 def test_strided_inputs():
@@ -197,11 +233,12 @@ def test_strided_inputs():
 # ------------------------------------------------------------------ full sizes
 
 @pytest.mark.parametrize("cfg", [1, 2])
-def test_full_config_parity(cfg):
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_full_config_parity(cfg, two_sided):
     inst = W.CONFIGS[cfg]()
-    say(f"[full] config {cfg} shape={inst.shape}")
+    say(f"[full] config {cfg} shape={inst.shape} two_sided={two_sided}")
     A, B, kA, kB = to_dev(inst)
-    R, ws = fg().r(A, B, kA, kB, "fp64")
+    R, ws = fg().r(A, B, kA, kB, "fp64", two_sided=two_sided)
     S = fg().sigma(R)
     torch.cuda.synchronize()
     Ro, So = oracle_results(inst)
@@ -212,9 +249,10 @@ def test_full_config_parity(cfg):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_full_config3(prec):
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_full_config3(prec, two_sided):
     inst = W.config3()
-    say(f"[full] config 3 {prec}")
+    say(f"[full] config 3 {prec} two_sided={two_sided}")
     A, B, kA, kB = to_dev(inst)
     out = fg().compact(A, B, kA, kB, prec)
     tab, counts = oracle.groups(inst.keys_A, inst.keys_B)
@@ -222,7 +260,7 @@ def test_full_config3(prec):
     got = np.stack([out["groups"][k] for k in ("key", "offA", "m1", "offB", "m2", "r1", "r2")], axis=1)
     assert np.array_equal(got.astype(np.int64), tab)
     del out
-    R, ws = fg().r(A, B, kA, kB, prec)
+    R, ws = fg().r(A, B, kA, kB, prec, two_sided=two_sided)
     S = fg().sigma(R)
     torch.cuda.synchronize()
     # property that holds at any size: R is the Cholesky factor of J^T J (closed-form Gram)
@@ -230,3 +268,41 @@ def test_full_config3(prec):
     er = relF(R.cpu().numpy(), L.T)
     say(f"    relF(R vs chol(Gram))={er:.3e}")
     assert er <= TOL_R[prec]
+
+
+# ------------------------------------------------------------------ batched plan (graph)
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_plan_graph_replays_match_oracle(prec, tol, two_sided):
+    """A batch of uneven instances in one captured graph; every replay checked against the oracle."""
+    insts = W.config4(count=10, lo=2.0, hi=3.3)
+    say(f"[plan] {prec} two_sided={two_sided} shapes={[i.shape for i in insts]}")
+    tens = [to_dev(i) for i in insts]
+    plan = fg().Plan(tens, prec, two_sided=two_sided)
+    d = tens[0][0].device
+    ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=d)
+    R = torch.zeros(plan.r_total, dtype=torch.float64, device=d)
+    S = torch.zeros(plan.s_total, dtype=torch.float64, device=d)
+    refs = []
+    for inst in insts:
+        Ro = oracle.r(inst)
+        refs.append((Ro, oracle.sigma(Ro)))
+    for rep in range(3):
+        R.zero_()
+        S.zero_()
+        plan.execute(ws, R, S)
+        torch.cuda.synchronize()
+        # eager work between replays
+        junk = torch.randn(1000, device=d).sum()
+        torch.cuda.synchronize()
+        Rh, Sh = R.cpu().numpy(), S.cpu().numpy()
+        for i, inst in enumerate(insts):
+            N = inst.A.shape[1] + inst.B.shape[1]
+            Rg = Rh[plan.r_off[i]:plan.r_off[i] + N * N].reshape(N, N)
+            Sg = Sh[plan.s_off[i]:plan.s_off[i] + N]
+            Ro, So = refs[i]
+            er = relF(Rg, Ro)
+            es = np.linalg.norm(Sg - So) / np.linalg.norm(So)
+            assert er <= tol and es <= tol, (rep, i, er, es)
+        del junk
