@@ -32,6 +32,23 @@ __device__ inline double dpp_f64(double v)
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
+// Hardware reciprocal / reciprocal square root refined by two Newton steps.
+__device__ inline double rcp_refined(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+__device__ inline double rsq_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
 __device__ inline double octet_sum(double v)
 {
     v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
@@ -88,9 +105,16 @@ __global__ __launch_bounds__(512) void k_jacobi_lds(const double *R, int n, int6
             b = octet_sum(b);
             g = octet_sum(g);
             if (active && g * g > tol2 * a * b) {
-                const double zeta = (b - a) / (2.0 * g);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double zeta = (b - a) * rcp_refined(2.0 * g);
+                double t;
+                if (fabs(zeta) > 1e150) {
+                    t = 0.5 * rcp_refined(zeta);  // sign(zeta) / (2 |zeta|): 1 + zeta^2 would overflow
+                } else {
+                    const double q = fma(zeta, zeta, 1.0);
+                    const double sq = q * rsq_refined(q);  // sqrt(1 + zeta^2)
+                    t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_refined(fabs(zeta) + sq);
+                }
+                const double c = rsq_refined(fma(t, t, 1.0));
                 const double s = c * t;
                 for (int i = sub; i < np; i += kLanesPerPair) {
                     const double xp = cp[i], xq = cq[i];
