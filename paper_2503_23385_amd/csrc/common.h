@@ -94,10 +94,19 @@ void tsqr_tree_sizes(int nleaves, int64_t *slots, int64_t *counters);
 hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *init, int64_t init_ld,
                               RowSrc s0, RowSrc s1, int nsrc, int width, int tri_rows, int nwg,
                               double *tri, int64_t tri_stride, hipStream_t s);
-// One launch: nleaves wave-level leaves over src, then the in-kernel binary tree; the
-// region's triangle (width rows x np, FP64) lands in root.  np <= 64 only.
-hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, RowSrc src, int width, int nleaves,
-                            double *slots, int32_t *counters, double *root, hipStream_t s);
+// One region for the in-kernel tree: nleaves wave-level leaves over src, then a binary
+// tree whose nodes live in `slots` (width x np FP64 each) and whose per-node counters
+// (zero on entry) live in `counters`; the region's triangle lands in root.
+struct TreeRegion {
+    RowSrc src;
+    int32_t width, nleaves;
+    double *slots;
+    int32_t *counters;
+    double *root;
+};
+// One launch for one or two regions of the same padded width np (np <= 64).
+hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
+                            hipStream_t s);
 hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,
                                  int64_t ldr, hipStream_t s);
 

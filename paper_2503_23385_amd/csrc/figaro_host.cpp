@@ -394,8 +394,22 @@ int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, c
     return FIGARO_OK;
 }
 
-// Reduce one region to its triangle (FP64, width rows x np at r.root).
-int run_region(const Region &r, const Layout &L, int acc_f64, void *ws, hipStream_t s)
+TreeRegion tree_region(const Region &r, const Layout &L, void *ws)
+{
+    Groups g = groups_of(ws, L);
+    TreeRegion t;
+    t.src = RowSrc{at<void>(ws, r.buf), g.counts + r.cnt, 0, r.width, 0, r.width};
+    t.width = r.width;
+    t.nleaves = r.leaves;
+    t.slots = at<double>(ws, r.slots);
+    t.counters = at<int32_t>(ws, L.counters_base) + r.counters;
+    t.root = at<double>(ws, r.root);
+    return t;
+}
+
+// Reduce one region to its triangle (FP64, width rows x np at r.root) with the workgroup
+// kernel: leaves, then levels of kTreeArityWG, the last level into root.
+int run_region_wg(const Region &r, const Layout &L, int acc_f64, void *ws, hipStream_t s)
 {
     Groups g = groups_of(ws, L);
     RowSrc src{at<void>(ws, r.buf), g.counts + r.cnt, 0, r.width, 0, r.width};
@@ -403,14 +417,6 @@ int run_region(const Region &r, const Layout &L, int acc_f64, void *ws, hipStrea
     double *root = at<double>(ws, r.root);
     const int64_t tsz = (int64_t)r.width * r.np;
     Stage st(r.name, s);
-    if (r.wave) {
-        HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, src, r.width, r.leaves,
-                                at<double>(ws, r.slots),
-                                at<int32_t>(ws, L.counters_base) + r.counters, root, s),
-               "tsqr tree");
-        return FIGARO_OK;
-    }
-    // Workgroup kernel: leaves, then levels of kTreeArityWG, the last level into root.
     double *cur = r.levels.empty() ? root : at<double>(ws, r.tri[0]);
     HIPCHK(launch_tsqr_stream(r.np, acc_f64, L.m_f64, nullptr, 0, src, none, 1, r.width, 0,
                               r.leaves, cur, tsz, s),
@@ -430,6 +436,36 @@ int run_region(const Region &r, const Layout &L, int acc_f64, void *ws, hipStrea
     return FIGARO_OK;
 }
 
+// All regions: wave-tree regions of equal padded width share one launch.
+int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
+{
+    const size_t nr = L.regions.size();
+    std::vector<bool> done(nr, false);
+    for (size_t i = 0; i < nr; i++) {
+        if (done[i]) continue;
+        const Region &r = L.regions[i];
+        done[i] = true;
+        if (!r.wave) {
+            int rc = run_region_wg(r, L, acc_f64, ws, s);
+            if (rc) return rc;
+            continue;
+        }
+        TreeRegion tr[2] = {tree_region(r, L, ws), TreeRegion{}};
+        int n = 1;
+        const char *name = r.name;
+        for (size_t j = i + 1; j < nr && n < 2; j++) {
+            if (!done[j] && L.regions[j].wave && L.regions[j].np == r.np) {
+                tr[n++] = tree_region(L.regions[j], L, ws);
+                done[j] = true;
+                name = "tsqr_tails";
+            }
+        }
+        Stage st(name, s);
+        HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr tree");
+    }
+    return FIGARO_OK;
+}
+
 int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
           int64_t ldr, void *ws, hipStream_t s)
 {
@@ -437,10 +473,8 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
     if (rc) return rc;
     const int N = (int)sh.N();
     const int acc = sh.precision == FIGARO_PLAIN_FP64;
-    for (const Region &r : L.regions) {
-        rc = run_region(r, L, acc, ws, s);
-        if (rc) return rc;
-    }
+    rc = run_regions(L, acc, ws, s);
+    if (rc) return rc;
     // Merge in FP64: start from the N-wide region's triangle, absorb the others in order.
     const Region &r0 = L.regions[0];
     const double *cur = at<double>(ws, r0.root);

@@ -367,30 +367,33 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_wave(const double 
     wave_store<NP, Tacc>(Rp, tri_out + (int64_t)gw * tri_stride, width, lane);
 }
 
-// One region in one launch: leaves, then the binary tree (see the file comment).
-// slots: sum over levels of the node count, each width x NP doubles; counters: one
-// int per parent node (zero on entry).
+// Up to two regions (same width class) in one launch: waves [0, leaves0) reduce region 0,
+// the rest region 1; each region runs its own leaves and binary tree (see the file comment).
+// slots: sum over levels of the node count, each width x NP doubles; counters: one int per
+// parent node (zero on entry).
 template <int NP, typename Tin, typename Tacc>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_tree(RowSrc src, int width, int nleaves,
-                                                                  double *slots, int32_t *counters,
-                                                                  double *root_out)
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_tree(TreeRegion reg0, TreeRegion reg1)
 {
     using Gm = WaveGeom<NP>;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int gw = blockIdx.x * kWavesPerBlock + wv;
+    int gw = blockIdx.x * kWavesPerBlock + wv;
     const int k = lane % NP, h = lane / NP;
     __shared__ Tacc Rs[kWavesPerBlock][Gm::PS];
     __shared__ __align__(16) Tacc Xs[kWavesPerBlock][Gm::BR];
-    if (gw >= nleaves) return;
+    const bool second = gw >= reg0.nleaves;
+    const TreeRegion &rg = second ? reg1 : reg0;
+    if (second) gw -= reg0.nleaves;
+    if (gw >= rg.nleaves) return;
+    const int width = rg.width, nleaves = rg.nleaves;
     Tacc *Rp = Rs[wv];
     Tacc *xb = Xs[wv] + h * Gm::RPT;
     wave_zero<NP, Tacc>(Rp, lane);
-    const int64_t rows = src_rows(src);
+    const int64_t rows = src_rows(rg.src);
     int64_t chunk = (rows + nleaves - 1) / nleaves;
     chunk = ((chunk + Gm::BR - 1) / Gm::BR) * Gm::BR;
     const int64_t r0 = (int64_t)gw * chunk, r1 = min(rows, r0 + chunk);
     RowSrc none{};
-    wave_absorb_rows<NP, Tin, Tacc>(Rp, xb, src, none, rows, r0, r1, 0, width, k, h);
+    wave_absorb_rows<NP, Tin, Tacc>(Rp, xb, rg.src, none, rows, r0, r1, 0, width, k, h);
 
     const int64_t tsz = (int64_t)width * NP;
     int node = gw, n = nleaves;
@@ -398,18 +401,18 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_tree(RowSrc src, i
     while (n > 1) {
         const int sib = node ^ 1;
         if (sib < n) {
-            wave_store<NP, Tacc>(Rp, slots + (soff + node) * tsz, width, lane);
+            wave_store<NP, Tacc>(Rp, rg.slots + (soff + node) * tsz, width, lane);
             __threadfence();
             int old = 0;
             if (lane == 0)
-                old = __hip_atomic_fetch_add(&counters[coff + (node >> 1)], 1, __ATOMIC_ACQ_REL,
+                old = __hip_atomic_fetch_add(&rg.counters[coff + (node >> 1)], 1, __ATOMIC_ACQ_REL,
                                              __HIP_MEMORY_SCOPE_AGENT);
             old = __builtin_amdgcn_readfirstlane(old);
             if (old == 0) return;  // the sibling finishes this node
             __threadfence();
             const int left = node & ~1;
-            wave_init_tri<NP, Tacc>(Rp, slots + (soff + left) * tsz, NP, width, lane);
-            wave_absorb_tri<NP, Tacc>(Rp, xb, slots + (soff + left + 1) * tsz, NP, width, 0, width,
+            wave_init_tri<NP, Tacc>(Rp, rg.slots + (soff + left) * tsz, NP, width, lane);
+            wave_absorb_tri<NP, Tacc>(Rp, xb, rg.slots + (soff + left + 1) * tsz, NP, width, 0, width,
                                       width, k, h);
         }
         node >>= 1;
@@ -417,7 +420,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_tree(RowSrc src, i
         coff += (n + 1) / 2;
         n = (n + 1) / 2;
     }
-    wave_store<NP, Tacc>(Rp, root_out, width, lane);
+    wave_store<NP, Tacc>(Rp, rg.root, width, lane);
 }
 
 __global__ void k_sign_normalise(const double *Rin, int64_t ldin, int n, double *R, int64_t ldr)
@@ -483,13 +486,13 @@ hipError_t launch_np(int acc_f64, int in_f64, const double *init, int64_t init_l
 }
 
 template <int NP>
-hipError_t launch_tree_np(int acc_f64, int in_f64, RowSrc src, int width, int nleaves,
-                          double *slots, int32_t *counters, double *root, hipStream_t s)
+hipError_t launch_tree_np(int acc_f64, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s)
 {
-    const unsigned grid = (unsigned)((nleaves + kWavesPerBlock - 1) / kWavesPerBlock);
-#define FIGARO_TREE(TI, TA)                                                                      \
-    k_tsqr_tree<NP, TI, TA><<<grid, 64 * kWavesPerBlock, 0, s>>>(src, width, nleaves, slots,     \
-                                                                 counters, root)
+    TreeRegion r0 = regs[0];
+    TreeRegion r1 = nreg > 1 ? regs[1] : TreeRegion{};
+    const int waves = r0.nleaves + r1.nleaves;
+    const unsigned grid = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+#define FIGARO_TREE(TI, TA) k_tsqr_tree<NP, TI, TA><<<grid, 64 * kWavesPerBlock, 0, s>>>(r0, r1)
     if (acc_f64) {
         if (in_f64) FIGARO_TREE(double, double);
         else FIGARO_TREE(float, double);
@@ -543,12 +546,13 @@ hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *ini
     }
 }
 
-hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, RowSrc src, int width, int nleaves,
-                            double *slots, int32_t *counters, double *root, hipStream_t s)
+hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
+                            hipStream_t s)
 {
+    if (nreg < 1 || nreg > 2) return hipErrorInvalidValue;
     switch (np) {
 #define FIGARO_CASE(NPV) \
-    case NPV: return launch_tree_np<NPV>(acc_f64, in_f64, src, width, nleaves, slots, counters, root, s);
+    case NPV: return launch_tree_np<NPV>(acc_f64, in_f64, regs, nreg, s);
     FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64)
 #undef FIGARO_CASE
     default: return hipErrorInvalidValue;
