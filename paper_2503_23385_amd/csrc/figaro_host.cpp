@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -193,6 +194,14 @@ int make_shape(const figaro_table *A, const figaro_table *B, int32_t precision, 
     return FIGARO_OK;
 }
 
+int env_int(const char *name, int dflt)
+{
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    const int x = std::atoi(v);
+    return x > 0 ? x : dflt;
+}
+
 Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int col_off)
 {
     Region r;
@@ -204,8 +213,10 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     r.np = tsqr_padded_width(width);
     r.wave = r.np <= 64;
     const int br = tsqr_block_rows(r.np);
-    // Leaves of about eight blocks (wave tree) or four (workgroup tree) each.
-    const int64_t per = (r.wave ? 8 : 4) * (int64_t)br;
+    // Leaves of a few blocks each (tunable through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS).
+    static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 8);
+    static const int wg_blocks = env_int("FIGARO_WG_LEAF_BLOCKS", 4);
+    const int64_t per = (r.wave ? wave_blocks : wg_blocks) * (int64_t)br;
     const int64_t leaves = (r.rows_cap + per - 1) / per;
     r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxTreeLeaves));
     r.ncounters = 0;
