@@ -5,8 +5,9 @@ HBM: key grouping, head/tail scans, compact-matrix assembly, Householder TSQR
 (leaves, tree, merge, sign) -> R, then one-sided Jacobi -> sigma.
 
 Workload: Cartesian product of two 1e5 x 32 FP64 N(0,1) tables (a 1e10 x 64
-join that is never materialised).  Four forms are timed: the Claim 1 compact
-matrix and the two-sided form, each with FP64 and FP32 reductions.  `value`
+join that is never materialised).  Six forms are timed: the Claim 1 compact
+matrix and the two-sided form, each with an FP64 reduction, an FP32 one, and
+an FP32 one followed by the FP64 refinement sweep.  `value`
 is the fastest form whose R and sigma are within 1e-5 of the oracle; every
 form is listed under "forms".  Prints one JSON line.
 """
@@ -35,7 +36,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--forms", default="claim1:fp64,two_sided:fp64,claim1:fp32,two_sided:fp32")
+    ap.add_argument("--forms", default="claim1:fp64,two_sided:fp64,claim1:fp32,two_sided:fp32,"
+                                       "claim1:fp32_refine,two_sided:fp32_refine")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -123,13 +125,14 @@ def main():
         fg.timing_enable(False)
         stage_ms = {k: v[0] / args.steps for k, v in stages.items()}
         launches = {k: v[1] / args.steps for k, v in stages.items()}
+        sweeps = int(sws[:4].view(torch.int32)[0].item())
         errs = None
         if Ro is not None:
             Rg, Sg = R.cpu().numpy(), S.cpu().numpy()
             errs = {"R_relF": float(np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)),
                     "sigma_rel2": float(np.linalg.norm(Sg - So) / np.linalg.norm(So))}
         forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3), "stage_ms": stage_ms,
-                       "launches_per_step": launches, "errors_vs_oracle": errs,
+                       "launches_per_step": launches, "errors_vs_oracle": errs, "jacobi_sweeps": sweeps,
                        "layout": layout, "precision": prec}
         del ws, R, S
 
@@ -141,7 +144,7 @@ def main():
 
     # Dominant kernel of the chosen form and its algorithmic work per launch.
     esz = 8 if f["precision"] == "fp64" else 4
-    peak_alu = PEAK_FP64_TFLOPS if f["precision"] == "fp64" else PEAK_FP32_TFLOPS
+    peak_tsqr = PEAK_FP64_TFLOPS if f["precision"] == "fp64" else PEAK_FP32_TFLOPS
     two = f["layout"] == "two_sided"
     work = {
         # B read once per pass of the scan (FP64) + region 2 written once
@@ -152,6 +155,10 @@ def main():
         "tsqr_m2": ("alu", 2.0 * (m2 - 1) * n2 * n2 / 1e12),
         "tsqr_ta": ("alu", 2.0 * (m1 - 1) * n1 * n1 / 1e12),
         "tsqr_tb": ("alu", 2.0 * (m2 - 1) * n2 * n2 / 1e12),
+        # both tail regions of the two-sided form in one launch
+        "tsqr_tails": ("alu", 2.0 * ((m1 - 1) * n1 * n1 + (m2 - 1) * n2 * n2) / 1e12),
+        # one sweep: n(n-1)/2 pairs, 3 dot products and a rotation of two n-vectors (12 n flops)
+        "jacobi": ("alu", 6.0 * N * N * (N - 1) * f["jacobi_sweeps"] / 1e12),
     }
     stage_ms = f["stage_ms"]
     dom = max((k for k in stage_ms if k in work), key=lambda k: stage_ms[k])
@@ -162,6 +169,8 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": amount / t, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": amount / t / PEAK_HBM_GBS, "traffic": None}
     else:
+        # the FP32 forms' TSQR updates run in FP32; Jacobi always runs in FP64
+        peak_alu = PEAK_FP64_TFLOPS if dom == "jacobi" else peak_tsqr
         roof = {"kernel": dom, "bound": "alu", "achieved": amount / t, "peak": peak_alu,
                 "unit": "TFLOP/s", "frac": amount / t / peak_alu, "traffic": None}
 
@@ -176,7 +185,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if f["precision"] == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32_refine": "f32+f64"}[f["precision"]],
         "data": "synthetic",
         "config": {"workload": "cartesian product, A and B 1e5 x 32 FP64 N(0,1), join 1e10 x 64 "
                                "(never materialised), R 64x64 + sigma",

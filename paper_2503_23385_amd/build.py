@@ -21,6 +21,7 @@ SOURCES = [
     "kernels_scan.hip",
     "kernels_tsqr.hip",
     "kernels_jacobi.hip",
+    "kernels_refine.hip",
     "figaro_host.cpp",
 ]
 

@@ -110,6 +110,17 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
 hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,
                                  int64_t ldr, hipStream_t s);
 
+// One FP64 refinement sweep (kernels_refine.hip): from the approximate R~ (Rt, upper,
+// positive diagonal) and the exact per-group Gram matrix of the join, R = chol(X)^T R~ with
+// X = R~^-T (J^T J) R~^-1.  hB: the groups' heads of B (H(B_g), gcap x n2).  Scratch: gram
+// and Y (N x N each), partial (partial_cap doubles, at least refine_partial_elems), failed
+// (one int: 1 when X was not positive definite, then R = R~).
+int64_t refine_partial_elems(int64_t n1, int64_t n2);
+hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B,
+                         int64_t ldb, int64_t m2, int n2, Groups g, int cartesian, const double *hB,
+                         const double *Rt, int ldt, double *gram, double *Y, double *partial,
+                         int64_t partial_cap, int32_t *failed, double *R, int64_t ldr, hipStream_t s);
+
 // Jacobi (kernels_jacobi.hip)
 hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                          int32_t *sweeps_out, hipStream_t s);

@@ -143,6 +143,10 @@ struct Layout {
     size_t counters_base;
     int64_t counters_total;
     size_t rtmp[2];
+    // refinement sweep (FIGARO_MIXED_FP32_REFINE only)
+    bool refine;
+    size_t rt, gram, gy, partial, failed;
+    int64_t partial_cap;
     int np_root;
     size_t total;
     int nbA, nbB;
@@ -314,6 +318,18 @@ Layout make_layout(const Shape &s)
     L.np_root = tsqr_padded_width(N);
     L.rtmp[0] = take(sizeof(double) * N * L.np_root);
     L.rtmp[1] = take(sizeof(double) * N * L.np_root);
+    L.refine = s.precision == FIGARO_MIXED_FP32_REFINE;
+    if (L.refine) {
+        L.rt = take(sizeof(double) * N * N);
+        L.gram = take(sizeof(double) * N * N);
+        L.gy = take(sizeof(double) * N * N);
+        L.partial_cap = refine_partial_elems(s.n1, s.n2);
+        L.partial = take(sizeof(double) * L.partial_cap);
+        L.failed = take(sizeof(int32_t));
+    } else {
+        L.rt = L.gram = L.gy = L.partial = L.failed = 0;
+        L.partial_cap = 0;
+    }
     L.total = off;
     return L;
 }
@@ -504,8 +520,22 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
             cur_ld = L.np_root;
         }
     }
-    Stage st("sign", s);
-    HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, R, ldr, s), "sign normalisation");
+    if (!L.refine) {
+        Stage st("sign", s);
+        HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, R, ldr, s), "sign normalisation");
+        return FIGARO_OK;
+    }
+    double *rt = at<double>(ws, L.rt);
+    {
+        Stage st("sign", s);
+        HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, rt, N, s), "sign normalisation");
+    }
+    Stage st("refine", s);
+    HIPCHK(launch_refine(A->data, sh.in_f64, sh.lda, sh.m1, (int)sh.n1, B->data, sh.ldb, sh.m2, (int)sh.n2,
+                         groups_of(ws, L), !sh.keyed, at<double>(ws, L.headsB), rt, N,
+                         at<double>(ws, L.gram), at<double>(ws, L.gy), at<double>(ws, L.partial),
+                         L.partial_cap, at<int32_t>(ws, L.failed), R, ldr, s),
+           "refinement sweep");
     return FIGARO_OK;
 }
 

@@ -73,6 +73,16 @@ def test_two_sided_flag_accepted_and_sized():
     assert rc == 0 and rc2 == 0 and n_t > 0
 
 
+def test_refine_precision_adds_workspace():
+    """The refinement sweep needs FP64 Gram and solve buffers beyond the FP32 form's."""
+    A, B = table(5000, 64, keys=8), table(4000, 64, keys=8)
+    rc1, n32 = ws_size(A, B, 1)
+    rc2, nref = ws_size(A, B, 2)
+    rc3, nref2 = ws_size(A, B, 2 | 0x100)
+    assert rc1 == rc2 == rc3 == 0
+    assert nref >= n32 + 3 * 128 * 128 * 8
+
+
 def test_figaro_r_host_checks():
     L = fg.lib()
     A, B = table(), table()

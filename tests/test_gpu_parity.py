@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-TOL_R = {"fp64": 1e-12, "fp32": 1e-5}
+TOL_R = {"fp64": 1e-12, "fp32": 1e-5, "fp32_refine": 1e-12}
 TOL_S = {"fp64": 1e-12, "fp32": 1e-5}
 
 
@@ -230,6 +230,63 @@ def test_strided_inputs():
     assert relF(R.cpu().numpy(), oracle.r(inst)) <= 1e-12
 
 
+# ------------------------------------------------------------------ refinement sweep
+
+def refine_cases():
+    c = {k: CASES[k] for k in ("cart_ragged", "keyed_zipf_n64", "keyed_uniform_sparse",
+                               "keyed_singleton_B", "cart_tail_leaf", "keyed_n128")}
+    # the wide workload's value recipe at a small size: columns scaled by 10^U(-3,0), kappa ~ 1e3
+    c["keyed_scaled_small"] = W.config5(m=1 << 13, n=32, n_values=256)
+    return c
+
+
+REFINE_CASES = refine_cases()
+
+
+@pytest.mark.parametrize("name", list(REFINE_CASES))
+@pytest.mark.parametrize("form", ["claim1", "two_sided"])
+def test_refine_sweep(name, form):
+    """One FP64 sweep against the exact Gram matrix lifts the FP32 form's R to FP64 accuracy."""
+    inst = REFINE_CASES[name]
+    two = form == "two_sided"
+    say(f"[refine] {name} {form} shape={inst.shape}")
+    A, B, kA, kB = to_dev(inst)
+    R32, _ = fg().r(A, B, kA, kB, "fp32", two_sided=two)
+    Rr, ws = fg().r(A, B, kA, kB, "fp32_refine", two_sided=two)
+    Sr = fg().sigma(Rr)
+    torch.cuda.synchronize()
+    assert fg().status(ws) == 0
+    Ro, So = oracle_results(inst)
+    e32 = relF(R32.cpu().numpy(), Ro)
+    er = relF(Rr.cpu().numpy(), Ro)
+    es = np.linalg.norm(Sr.cpu().numpy() - So) / np.linalg.norm(So)
+    say(f"    relF(R) fp32={e32:.3e} refined={er:.3e} rel2(sigma)={es:.3e}")
+    Rg = Rr.cpu().numpy()
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0)
+    assert er <= 1e-12 and es <= 1e-12
+    assert er <= e32
+
+
+def test_refine_rank_deficient_keeps_gram():
+    """Rank-deficient join (one A row): R is not unique; R^T R must still equal J^T J."""
+    inst = CASES["cart_one_row_A"]
+    A, B, kA, kB = to_dev(inst)
+    Rr, ws = fg().r(A, B, kA, kB, "fp32_refine")
+    torch.cuda.synchronize()
+    Rg = Rr.cpu().numpy()
+    Gm = gram_closed_form(inst)
+    assert np.all(np.isfinite(Rg))
+    assert np.allclose(Rg.T @ Rg, Gm, rtol=1e-5, atol=1e-5 * np.abs(Gm).max())
+
+
+def test_refine_empty_join():
+    inst = W.Instance(np.ones((10, 3)), np.ones((8, 2)), np.arange(10, dtype=np.int32),
+                      np.arange(100, 108, dtype=np.int32))
+    A, B, kA, kB = to_dev(inst)
+    R, ws = fg().r(A, B, kA, kB, "fp32_refine")
+    assert torch.count_nonzero(R).item() == 0
+
+
 # ------------------------------------------------------------------ full sizes
 
 @pytest.mark.parametrize("cfg", [1, 2])
@@ -248,7 +305,7 @@ def test_full_config_parity(cfg, two_sided):
     assert er <= 1e-12 and es <= 1e-12
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_refine"])
 @pytest.mark.parametrize("two_sided", [False, True])
 def test_full_config3(prec, two_sided):
     inst = W.config3()
@@ -272,7 +329,7 @@ def test_full_config3(prec, two_sided):
 
 # ------------------------------------------------------------------ batched plan (graph)
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("fp32_refine", 1e-12)])
 @pytest.mark.parametrize("two_sided", [False, True])
 def test_plan_graph_replays_match_oracle(prec, tol, two_sided):
     """A batch of uneven instances in one captured graph; every replay checked against the oracle."""
