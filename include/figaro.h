@@ -157,10 +157,14 @@ int figaro_sigma_workspace_size(int64_t n, size_t *bytes);
  * matrix; Related Works: SVD through QR) by one-sided Jacobi in FP64:
  * Hestenes rotations on column pairs in a parallel (round-robin) order until
  * a sweep finds every pair orthogonal to |c_p . c_q| <= n 2^-53 |c_p||c_q|
- * (at most 60 sweeps).
+ * (at most 60 sweeps).  n <= 128: one workgroup with R in LDS; 128 < n <= 512:
+ * block Jacobi over blocks of 16 columns, one workgroup per block pair, with
+ * bounded grid-wide waits between rounds.
  *   R      device, FP64, n x n, leading dimension ldr (any square matrix is accepted).
- *   sigma  device, FP64, n values, descending.
- *   ws     device workspace of figaro_sigma_workspace_size() bytes.
+ *   sigma  device, FP64, n values, descending (NaN if a bounded wait expired).
+ *   ws     device workspace of figaro_sigma_workspace_size() bytes, 256-byte
+ *          aligned; afterwards its first int32 holds the number of sweeps
+ *          (-1 if a bounded wait expired).
  */
 int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma,
                  void *ws, size_t ws_bytes, void *stream);

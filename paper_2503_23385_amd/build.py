@@ -20,6 +20,7 @@ SOURCES = [
     "kernels_group.hip",
     "kernels_scan.hip",
     "kernels_tsqr.hip",
+    "kernels_panel.hip",
     "kernels_jacobi.hip",
     "kernels_refine.hip",
     "figaro_host.cpp",

@@ -83,10 +83,18 @@ hipError_t launch_head_rows(Groups g, int64_t gcap, const double *headsA, const 
                             int64_t n1, int64_t n2, void *out, int out_f64, hipStream_t s);
 
 // TSQR (kernels_tsqr.hip)
-int tsqr_padded_width(int n);  // padded template width for n, 0 if unsupported
-int tsqr_block_rows(int np);   // rows per streamed block for padded width np
+int tsqr_padded_width(int n);               // padded template width for n, 0 if unsupported
+int tsqr_block_rows(int np, int acc_f64);   // rows per streamed block for padded width np
+int tsqr_panel_rows(int np, int acc_f64);   // rows per block of the panel kernel (np 128..512)
+// Blocked panel kernel for padded widths 128, 256, 512 (same contract as launch_tsqr_stream).
+hipError_t launch_tsqr_panel(int np, int acc_f64, int in_f64, const double *init, int64_t init_ld, RowSrc s0,
+                             RowSrc s1, int nsrc, int width, int tri_rows, int nwg, double *tri, int64_t tri_stride,
+                             hipStream_t s);
+// Arity of the in-kernel tree for a region of `width` columns at padded width np: one
+// block of rows holds arity - 1 sibling triangles.
+int tsqr_tree_arity(int np, int width);
 // Slots (triangles) and counters needed by the in-kernel tree over nleaves leaves.
-void tsqr_tree_sizes(int nleaves, int64_t *slots, int64_t *counters);
+void tsqr_tree_sizes(int nleaves, int arity, int64_t *slots, int64_t *counters);
 // Reduce the rows of s0 (then s1) into nwg triangles of `width` rows x np columns (FP64),
 // triangle b at tri + b * tri_stride, each starting from `init` (a triangle, ld init_ld)
 // when init != nullptr, else from zero.  tri_rows > 0: the sources are stacks of triangles
@@ -94,12 +102,12 @@ void tsqr_tree_sizes(int nleaves, int64_t *slots, int64_t *counters);
 hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *init, int64_t init_ld,
                               RowSrc s0, RowSrc s1, int nsrc, int width, int tri_rows, int nwg,
                               double *tri, int64_t tri_stride, hipStream_t s);
-// One region for the in-kernel tree: nleaves wave-level leaves over src, then a binary
-// tree whose nodes live in `slots` (width x np FP64 each) and whose per-node counters
-// (zero on entry) live in `counters`; the region's triangle lands in root.
+// One region for the in-kernel tree: nleaves wave-level leaves over src, then a tree of
+// the given arity whose nodes live in `slots` (width x np FP64 each) and whose per-node
+// counters (zero on entry) live in `counters`; the region's triangle lands in root.
 struct TreeRegion {
     RowSrc src;
-    int32_t width, nleaves;
+    int32_t width, nleaves, arity;
     double *slots;
     int32_t *counters;
     double *root;
@@ -107,6 +115,9 @@ struct TreeRegion {
 // One launch for one or two regions of the same padded width np (np <= 64).
 hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
                             hipStream_t s);
+// out (na + nb rows, ld ldo) <- the upper triangular block diagonal [Ta 0; 0 Tb].
+hipError_t launch_block_diag(const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
+                             double *out, int64_t ldo, hipStream_t s);
 hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,
                                  int64_t ldr, hipStream_t s);
 
@@ -122,7 +133,10 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
                          int64_t partial_cap, int32_t *failed, double *R, int64_t ldr, hipStream_t s);
 
 // Jacobi (kernels_jacobi.hip)
+// ctrl: 8 ints (ctrl[0] receives the sweep count, -1 after a timed-out run); scratch:
+// jacobi_scratch_doubles(n) doubles (none for n <= 128).
+int64_t jacobi_scratch_doubles(int n);
 hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
-                         int32_t *sweeps_out, hipStream_t s);
+                         int32_t *ctrl, double *scratch, hipStream_t s);
 
 }  // namespace figaro

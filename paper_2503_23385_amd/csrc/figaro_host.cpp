@@ -124,7 +124,8 @@ struct Region {
     int cnt;
     int width, col_off, np;
     bool wave;                // in-kernel tree (np <= 64)
-    int leaves;
+    bool skip;                // rows absorbed directly by the root merge (no tree of its own)
+    int leaves, arity;
     std::vector<int> levels;  // workgroup tree levels (wave == false)
     size_t slots, counters, root, tri[2];
     int64_t ncounters;
@@ -178,13 +179,7 @@ int make_shape(const figaro_table *A, const figaro_table *B, int32_t precision, 
         return fail(FIGARO_EINVAL, "unknown precision or flag");
     const int64_t N = A->cols + B->cols;
     if (N > FIGARO_MAX_N) return fail(FIGARO_EINVAL, "n1 + n2 exceeds FIGARO_MAX_N");
-    // Widths this build's TSQR kernels accept: every region width must pad to a kernel.
-    const bool fp64_acc = prec == FIGARO_PLAIN_FP64;
-    const int limit = fp64_acc ? 128 : 256;
-    const int np = tsqr_padded_width((int)N);
-    if (np == 0 || np > limit)
-        return fail(FIGARO_EINVAL, "n1 + n2 wider than this build supports for the chosen precision");
-    if (B->cols > 512) return fail(FIGARO_EINVAL, "n2 > 512");
+    if (tsqr_padded_width((int)N) == 0) return fail(FIGARO_EINVAL, "n1 + n2 wider than the TSQR kernels support");
     sh->m1 = A->rows;
     sh->n1 = A->cols;
     sh->lda = A->ld;
@@ -206,7 +201,7 @@ int env_int(const char *name, int dflt)
     return x > 0 ? x : dflt;
 }
 
-Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int col_off)
+Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int col_off, int acc_f64)
 {
     Region r;
     r.name = name;
@@ -216,7 +211,7 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     r.col_off = col_off;
     r.np = tsqr_padded_width(width);
     r.wave = r.np <= 64;
-    const int br = tsqr_block_rows(r.np);
+    const int br = tsqr_block_rows(r.np, acc_f64);
     // Leaves of a few blocks each (tunable through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS).
     static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 8);
     static const int wg_blocks = env_int("FIGARO_WG_LEAF_BLOCKS", 4);
@@ -224,6 +219,8 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     const int64_t leaves = (r.rows_cap + per - 1) / per;
     r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxTreeLeaves));
     r.ncounters = 0;
+    r.skip = false;
+    r.arity = r.wave ? tsqr_tree_arity(r.np, width) : kTreeArityWG;
     if (!r.wave) {
         int cur = r.leaves;
         while (cur > 1) {
@@ -280,15 +277,17 @@ Layout make_layout(const Shape &s)
     }
     const int N = (int)s.N();
     if (!s.two_sided) {
-        Region a = make_region("tsqr_m1", s.m1, CNT_R1, N, 0);
-        Region b = make_region("tsqr_m2", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1);
+        Region a = make_region("tsqr_m1", s.m1, CNT_R1, N, 0, L.m_f64);
+        Region b = make_region("tsqr_m2", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64);
         a.buf = take(esz * std::max<int64_t>(1, a.rows_cap) * N);
         b.buf = take(esz * std::max<int64_t>(1, b.rows_cap) * s.n2);
         L.regions = {a, b};
     } else {
-        Region h = make_region("tsqr_heads", L.gcap, CNT_G, N, 0);
-        Region ta = make_region("tsqr_ta", s.m1 - 1, CNT_TA, (int)s.n1, 0);
-        Region tb = make_region("tsqr_tb", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1);
+        Region h = make_region("tsqr_heads", L.gcap, CNT_G, N, 0, L.m_f64);
+        // Cartesian product: a single head row, absorbed by the root merge itself.
+        h.skip = !s.keyed;
+        Region ta = make_region("tsqr_ta", s.m1 - 1, CNT_TA, (int)s.n1, 0, L.m_f64);
+        Region tb = make_region("tsqr_tb", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64);
         h.buf = take(esz * h.rows_cap * N);
         ta.buf = take(esz * std::max<int64_t>(1, ta.rows_cap) * s.n1);
         tb.buf = take(esz * std::max<int64_t>(1, tb.rows_cap) * s.n2);
@@ -299,7 +298,7 @@ Layout make_layout(const Shape &s)
         const size_t tsz = sizeof(double) * (size_t)r.width * r.np;
         if (r.wave) {
             int64_t ns, nc;
-            tsqr_tree_sizes(r.leaves, &ns, &nc);
+            tsqr_tree_sizes(r.leaves, r.arity, &ns, &nc);
             r.slots = take(tsz * ns);
             r.ncounters = nc;
             r.counters = (size_t)ctot;  // index into the shared counter block
@@ -428,6 +427,7 @@ TreeRegion tree_region(const Region &r, const Layout &L, void *ws)
     t.src = RowSrc{at<void>(ws, r.buf), g.counts + r.cnt, 0, r.width, 0, r.width};
     t.width = r.width;
     t.nleaves = r.leaves;
+    t.arity = r.arity;
     t.slots = at<double>(ws, r.slots);
     t.counters = at<int32_t>(ws, L.counters_base) + r.counters;
     t.root = at<double>(ws, r.root);
@@ -472,6 +472,7 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
         if (done[i]) continue;
         const Region &r = L.regions[i];
         done[i] = true;
+        if (r.skip) continue;
         if (!r.wave) {
             int rc = run_region_wg(r, L, acc_f64, ws, s);
             if (rc) return rc;
@@ -481,7 +482,7 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
         int n = 1;
         const char *name = r.name;
         for (size_t j = i + 1; j < nr && n < 2; j++) {
-            if (!done[j] && L.regions[j].wave && L.regions[j].np == r.np) {
+            if (!done[j] && !L.regions[j].skip && L.regions[j].wave && L.regions[j].np == r.np) {
                 tr[n++] = tree_region(L.regions[j], L, ws);
                 done[j] = true;
                 name = "tsqr_tails";
@@ -502,12 +503,31 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
     const int acc = sh.precision == FIGARO_PLAIN_FP64;
     rc = run_regions(L, acc, ws, s);
     if (rc) return rc;
-    // Merge in FP64: start from the N-wide region's triangle, absorb the others in order.
+    // Merge in FP64.
     const Region &r0 = L.regions[0];
     const double *cur = at<double>(ws, r0.root);
     int64_t cur_ld = r0.np;
     RowSrc none{};
-    {
+    if (sh.two_sided) {
+        // The tails' triangles occupy disjoint column ranges, so diag(R_TA, R_TB) is
+        // already upper triangular: start from it and absorb the heads (their triangle,
+        // or the single head row of a Cartesian product) in one pass.
+        const Region &ra = L.regions[1], &rb = L.regions[2];
+        double *init = at<double>(ws, L.rtmp[0]);
+        double *out = at<double>(ws, L.rtmp[1]);
+        Stage st("tsqr_root", s);
+        HIPCHK(launch_block_diag(at<double>(ws, ra.root), ra.np, ra.width, at<double>(ws, rb.root), rb.np,
+                                 rb.width, init, L.np_root, s),
+               "block diagonal");
+        Groups g = groups_of(ws, L);
+        const RowSrc heads = r0.skip ? RowSrc{at<void>(ws, r0.buf), g.counts + CNT_G, 0, N, 0, N}
+                                     : RowSrc{cur, nullptr, N, r0.np, 0, N};
+        HIPCHK(launch_tsqr_stream(L.np_root, 1, r0.skip ? L.m_f64 : 1, init, L.np_root, heads, none, 1, N,
+                                  r0.skip ? 0 : N, 1, out, (int64_t)N * L.np_root, s),
+               "tsqr merge");
+        cur = out;
+        cur_ld = L.np_root;
+    } else {
         Stage st("tsqr_root", s);
         for (size_t i = 1; i < L.regions.size(); i++) {
             const Region &r = L.regions[i];
@@ -616,7 +636,7 @@ int figaro_sigma_workspace_size(int64_t n, size_t *bytes)
 {
     if (n < 1 || n > FIGARO_MAX_N) return fail(FIGARO_EINVAL, "n out of range");
     if (!bytes) return fail(FIGARO_EINVAL, "bytes is NULL");
-    *bytes = kAlign;
+    *bytes = kAlign + sizeof(double) * (size_t)jacobi_scratch_doubles((int)n);
     return FIGARO_OK;
 }
 
@@ -627,10 +647,13 @@ int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma, void *w
     if (!R || !sigma) return fail(FIGARO_EINVAL, "R or sigma is NULL");
     if (ldr < n) return fail(FIGARO_EINVAL, "ldr < n");
     if (!ws) return fail(FIGARO_EINVAL, "workspace is NULL");
-    if (ws_bytes < kAlign) return fail(FIGARO_EWORKSPACE, "workspace too small");
-    if (n > 128) return fail(FIGARO_EINVAL, "n > 128 is not supported by this build's Jacobi");
+    if (((uintptr_t)ws) % kAlign) return fail(FIGARO_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    figaro_sigma_workspace_size(n, &need);
+    if (ws_bytes < need) return fail(FIGARO_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
     Stage st("jacobi", (hipStream_t)stream);
-    hipError_t e = launch_jacobi(R, (int)n, ldr, sigma, 60, (int32_t *)ws, (hipStream_t)stream);
+    double *scratch = jacobi_scratch_doubles((int)n) ? at<double>(ws, kAlign) : nullptr;
+    hipError_t e = launch_jacobi(R, (int)n, ldr, sigma, 60, (int32_t *)ws, scratch, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "jacobi");
     return FIGARO_OK;
 }
@@ -717,7 +740,7 @@ int plan_enqueue(figaro_plan *plan, void *ws, double *R, double *sigma, hipStrea
         if (rc) return rc;
         Stage st("jacobi", s);
         hipError_t e = launch_jacobi(R + plan->r_off[i], (int)N, N, sigma + plan->s_off[i], 60,
-                                     nullptr, s);
+                                     nullptr, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "jacobi");
     }
     return FIGARO_OK;

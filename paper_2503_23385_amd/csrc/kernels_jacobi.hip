@@ -7,22 +7,22 @@
 // Pairs are visited in a round-robin (circle) order: each of the n-1 steps of
 // a sweep rotates n/2 disjoint pairs in parallel, so a sweep still meets
 // every pair once.  For a pair with alpha = |c_p|^2, beta = |c_q|^2,
-// gamma = c_p . c_q:
-//     zeta = (beta - alpha) / (2 gamma),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-//     c = 1 / sqrt(1 + t^2),  s = c t,   (c_p, c_q) <- (c c_p - s c_q, s c_p + c c_q).
+// gamma = c_p . c_q, the rotation that zeroes gamma with |angle| <= pi/4 is
+//     u = beta - alpha, v = 2 gamma, h = sqrt(u^2 + v^2),
+//     c = sqrt((1 + |u|/h) / 2),  s = sign(u) v / (2 h c),
+//     (c_p, c_q) <- (c c_p - s c_q, s c_p + c c_q)
+// (the same rotation as t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
+// zeta = u / v, written with two reciprocal square roots and no division).
 // sigma_k = |c_k| after convergence, sorted descending.
 //
-// Eight lanes share a pair and keep its two columns in registers for the
-// whole step (one batch of LDS loads, one of stores); the three dot products
-// are reduced with DPP moves inside the lane octet; one workgroup barrier
-// separates the steps.  The width is a template parameter so every loop over
-// rows is unrolled.
+// A lane group (16 lanes, 8 for the narrowest widths) shares a pair and keeps
+// its two columns in registers for the whole step; the three dot products are
+// reduced with DPP moves inside the group; one workgroup barrier separates the
+// steps.  The width is a template parameter so every loop over rows is unrolled.
 #include "common.h"
 
 namespace figaro {
 namespace {
-
-constexpr int kLanesPerPair = 8;
 
 // Hardware reciprocal / reciprocal square root refined by two Newton steps.
 __device__ inline double rcp_refined(double x)
@@ -41,8 +41,6 @@ __device__ inline double rsq_refined(double x)
     return y;
 }
 
-// Sum over the 8-lane group (lanes 8g..8g+7) with DPP: xor 1, xor 2, then the
-// mirror of the half-row (lane i <-> 7 - i), which swaps the two quads.
 template <int CTRL>
 __device__ inline double dpp_f64(double v)
 {
@@ -50,32 +48,62 @@ __device__ inline double dpp_f64(double v)
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
-__device__ inline double octet_sum(double v)
+// Sum over an aligned group of LP (8 or 16) lanes with DPP: xor 1, xor 2, the
+// half-row mirror (lane i <-> 7 - i, swapping the quads of 8 lanes) and, for 16,
+// the row mirror (lane i <-> 15 - i, swapping the halves of the row).
+template <int LP>
+__device__ inline double group_sum(double v)
 {
     v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_f64<0x141>(v);  // row_half_mirror
+    if constexpr (LP == 16) v += dpp_f64<0x140>(v);  // row_mirror
     return v;
+}
+
+// Rotation (c, s) that zeroes gamma for the pair (alpha, beta, gamma), gamma != 0.
+// u and v are scaled by a power of two first so that u^2 + v^2 neither overflows
+// nor underflows (c and s depend only on their ratio).
+__device__ inline void jacobi_rotation(double alpha, double beta, double gamma, double &c, double &s)
+{
+    double u = beta - alpha, v = 2.0 * gamma;
+    const int e = ilogb(fmax(fabs(u), fabs(v)));
+    u = ldexp(u, -e);
+    v = ldexp(v, -e);
+    const double rh = rsq_refined(fma(u, u, v * v));  // 1 / h
+    const double x = fma(0.5 * fabs(u), rh, 0.5);      // (1 + cos 2 theta) / 2, in [1/2, 1]
+    const double rc = rsq_refined(x);                   // 1 / c
+    c = x * rc;
+    s = (u >= 0.0 ? 0.5 : -0.5) * v * rh * rc;
 }
 
 // NPC: padded (even, power of two) column count; columns n..NPC-1 are zero.
 template <int NPC>
-__global__ __launch_bounds__(NPC * kLanesPerPair / 2 < 64 ? 64 : NPC * kLanesPerPair / 2)
+struct JacobiGeom {
+    static constexpr int LP = NPC >= 16 ? 16 : 8;   // lanes per pair
+    static constexpr int RPL = NPC / LP;           // rows per lane (NPC >= LP)
+    static constexpr int PAIRS = NPC / 2;
+    static constexpr int THREADS = PAIRS * LP < 64 ? 64 : PAIRS * LP;
+    static constexpr int LDC = NPC + (NPC >= 16 ? 16 : 0);  // column stride (bank spread)
+};
+
+template <int NPC>
+__global__ __launch_bounds__(JacobiGeom<NPC>::THREADS)
 void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                   int32_t *sweeps_out)
 {
-    constexpr int RPL = NPC / kLanesPerPair;  // rows per lane
-    constexpr int PAIRS = NPC / 2;
-    __shared__ double C[NPC * NPC];  // column k at C[k * NPC]
+    using Gm = JacobiGeom<NPC>;
+    constexpr int LP = Gm::LP, RPL = Gm::RPL, PAIRS = Gm::PAIRS, LDC = Gm::LDC;
+    __shared__ double C[NPC * LDC];  // column k at C[k * LDC]
     __shared__ double sv[NPC];
     __shared__ int s_rot;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     for (int e = tid; e < NPC * NPC; e += nthr) {
         const int k = e / NPC, i = e - k * NPC;
-        C[e] = (k < n && i < n) ? R[(int64_t)i * ldr + k] : 0.0;
+        C[k * LDC + i] = (k < n && i < n) ? R[(int64_t)i * ldr + k] : 0.0;
     }
-    const int pair = tid / kLanesPerPair, sub = tid % kLanesPerPair;
+    const int pair = tid / LP, sub = tid % LP;
     const bool active = pair < PAIRS;
     const double tol2 = ((double)n * 0x1p-53) * ((double)n * 0x1p-53);
     constexpr int M = NPC - 1;
@@ -94,12 +122,12 @@ void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sw
                 q = (step - pair + M) % M;
             }
             if (p > q) { const int t = p; p = q; q = t; }
-            double *cp = C + p * NPC + sub, *cq = C + q * NPC + sub;
+            double *cp = C + p * LDC + sub, *cq = C + q * LDC + sub;
             double xp[RPL], xq[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; r++) {
-                xp[r] = active ? cp[r * kLanesPerPair] : 0.0;
-                xq[r] = active ? cq[r * kLanesPerPair] : 0.0;
+                xp[r] = active ? cp[r * LP] : 0.0;
+                xq[r] = active ? cq[r * LP] : 0.0;
             }
             double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
@@ -108,25 +136,16 @@ void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sw
                 b = fma(xq[r], xq[r], b);
                 g = fma(xp[r], xq[r], g);
             }
-            a = octet_sum(a);
-            b = octet_sum(b);
-            g = octet_sum(g);
+            a = group_sum<LP>(a);
+            b = group_sum<LP>(b);
+            g = group_sum<LP>(g);
             if (active && g * g > tol2 * a * b) {
-                const double zeta = (b - a) * rcp_refined(2.0 * g);
-                double t;
-                if (fabs(zeta) > 1e150) {
-                    t = 0.5 * rcp_refined(zeta);  // sign(zeta) / (2 |zeta|): 1 + zeta^2 would overflow
-                } else {
-                    const double qq = fma(zeta, zeta, 1.0);
-                    const double sq = qq * rsq_refined(qq);  // sqrt(1 + zeta^2)
-                    t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_refined(fabs(zeta) + sq);
-                }
-                const double c = rsq_refined(fma(t, t, 1.0));
-                const double s = c * t;
+                double c, s;
+                jacobi_rotation(a, b, g, c, s);
 #pragma unroll
                 for (int r = 0; r < RPL; r++) {
-                    cp[r * kLanesPerPair] = c * xp[r] - s * xq[r];
-                    cq[r * kLanesPerPair] = s * xp[r] + c * xq[r];
+                    cp[r * LP] = c * xp[r] - s * xq[r];
+                    cq[r * LP] = s * xp[r] + c * xq[r];
                 }
                 if (sub == 0) s_rot = 1;
             }
@@ -139,7 +158,7 @@ void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sw
     }
     for (int k = tid; k < n; k += nthr) {
         double acc = 0.0;
-        for (int i = 0; i < NPC; i++) acc += C[k * NPC + i] * C[k * NPC + i];
+        for (int i = 0; i < NPC; i++) acc += C[k * LDC + i] * C[k * LDC + i];
         sv[k] = sqrt(acc);
     }
     __syncthreads();
@@ -159,23 +178,204 @@ template <int NPC>
 hipError_t launch_npc(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                       int32_t *sweeps_out, hipStream_t s)
 {
-    int threads = NPC * kLanesPerPair / 2;
-    if (threads < 64) threads = 64;
-    k_jacobi_lds<NPC><<<1, threads, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+    k_jacobi_lds<NPC><<<1, JacobiGeom<NPC>::THREADS, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ block Jacobi (n up to 512)
+//
+// For wider R the columns live in global memory (column-major, NPC x NPC) and
+// are split into blocks of 16.  A persistent grid of NPC / 32 workgroups runs
+// a round-robin over block pairs: in each round every workgroup loads one pair
+// of blocks (32 columns) into LDS, applies one sweep of the same pair rotations
+// over its 32 columns, writes them back, and meets the others at a grid
+// barrier.  nb - 1 rounds make an outer sweep in which every column pair meets
+// at least once; the iteration stops after an outer sweep without rotations.
+// Every wait is bounded: a barrier that does not complete within the spin limit
+// marks the run as timed out and every workgroup leaves.
+
+constexpr int kBlk = 16;            // columns per block
+constexpr int kBlkThreads = 256;    // 16 pairs x 16 lanes
+enum : int { CTRL_SWEEPS = 0, CTRL_BAR = 1, CTRL_FLAG = 2, CTRL_TIMEOUT = 5, CTRL_WORDS = 8 };
+constexpr int kSpinLimit = 1 << 22;
+
+__global__ void k_jacobi_blk_init(const double *R, int n, int64_t ldr, double *C, int npc, int32_t *ctrl)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < CTRL_WORDS) ctrl[e] = 0;
+    if (e >= (int64_t)npc * npc) return;
+    const int k = (int)(e / npc), i = (int)(e - (int64_t)k * npc);
+    C[e] = (k < n && i < n) ? R[(int64_t)i * ldr + k] : 0.0;
+}
+
+// All workgroups of the grid meet; false if the wait timed out (then every caller leaves).
+__device__ inline bool grid_barrier(int32_t *ctrl, int target)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(&ctrl[CTRL_BAR], 1);
+        int ok = 1, spins = 0;
+        while (atomicAdd(&ctrl[CTRL_BAR], 0) < target) {
+            if (atomicAdd(&ctrl[CTRL_TIMEOUT], 0) != 0 || ++spins > kSpinLimit) {
+                atomicExch(&ctrl[CTRL_TIMEOUT], 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <int NPC>
+__global__ __launch_bounds__(kBlkThreads) void k_jacobi_blk(double *C, int n, int max_sweeps, int32_t *ctrl)
+{
+    constexpr int LP = 16, RPL = NPC / LP, LOC = 2 * kBlk, LDC = NPC + 16;
+    __shared__ double Cs[LOC * LDC];
+    __shared__ int s_rot;
+    const int tid = threadIdx.x, pair = tid / LP, sub = tid % LP;
+    const int P = gridDim.x, w = blockIdx.x;
+    const int nb = 2 * P, M = nb - 1;
+    const double tol2 = ((double)n * 0x1p-53) * ((double)n * 0x1p-53);
+    int epoch = 0, sweeps = 0;
+    bool alive = true;
+    for (int sweep = 0; sweep < max_sweeps && alive; sweep++) {
+        if (w == 0 && tid == 0) ctrl[CTRL_FLAG + (sweep + 1) % 3] = 0;
+        for (int round = 0; round < M; round++) {
+            const int bp = w == 0 ? round : (round + w) % M;
+            const int bq = w == 0 ? nb - 1 : (round - w + M) % M;
+            for (int e = tid; e < LOC * NPC; e += kBlkThreads) {
+                const int l = e / NPC, i = e - l * NPC;
+                const int col = (l < kBlk ? bp * kBlk + l : bq * kBlk + (l - kBlk));
+                Cs[l * LDC + i] = C[(int64_t)col * NPC + i];
+            }
+            if (tid == 0) s_rot = 0;
+            __syncthreads();
+            for (int step = 0; step < LOC - 1; step++) {
+                int p, q;
+                if (pair == 0) {
+                    p = step;
+                    q = LOC - 1;
+                } else {
+                    p = (step + pair) % (LOC - 1);
+                    q = (step - pair + LOC - 1) % (LOC - 1);
+                }
+                if (p > q) { const int t = p; p = q; q = t; }
+                double *cp = Cs + p * LDC + sub, *cq = Cs + q * LDC + sub;
+                double xp[RPL], xq[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; r++) {
+                    xp[r] = cp[r * LP];
+                    xq[r] = cq[r * LP];
+                }
+                double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, g0 = 0.0, g1 = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPL; r += 2) {
+                    a0 = fma(xp[r], xp[r], a0);
+                    b0 = fma(xq[r], xq[r], b0);
+                    g0 = fma(xp[r], xq[r], g0);
+                    a1 = fma(xp[r + 1], xp[r + 1], a1);
+                    b1 = fma(xq[r + 1], xq[r + 1], b1);
+                    g1 = fma(xp[r + 1], xq[r + 1], g1);
+                }
+                const double a = group_sum<LP>(a0 + a1);
+                const double b = group_sum<LP>(b0 + b1);
+                const double g = group_sum<LP>(g0 + g1);
+                if (g * g > tol2 * a * b) {
+                    double c, sn;
+                    jacobi_rotation(a, b, g, c, sn);
+#pragma unroll
+                    for (int r = 0; r < RPL; r++) {
+                        cp[r * LP] = c * xp[r] - sn * xq[r];
+                        cq[r * LP] = sn * xp[r] + c * xq[r];
+                    }
+                    if (sub == 0) s_rot = 1;
+                }
+                __syncthreads();
+            }
+            for (int e = tid; e < LOC * NPC; e += kBlkThreads) {
+                const int l = e / NPC, i = e - l * NPC;
+                const int col = (l < kBlk ? bp * kBlk + l : bq * kBlk + (l - kBlk));
+                C[(int64_t)col * NPC + i] = Cs[l * LDC + i];
+            }
+            if (tid == 0 && s_rot) atomicExch(&ctrl[CTRL_FLAG + sweep % 3], 1);
+            epoch++;
+            if (!grid_barrier(ctrl, epoch * P)) {
+                alive = false;
+                break;
+            }
+        }
+        if (!alive) break;
+        sweeps++;
+        if (atomicAdd(&ctrl[CTRL_FLAG + sweep % 3], 0) == 0) break;
+    }
+    if (w == 0 && tid == 0) ctrl[CTRL_SWEEPS] = alive ? sweeps : -1;
+}
+
+// sigma_k = |column k|, sorted descending (NaN everywhere after a timed-out run).
+__global__ __launch_bounds__(1024) void k_jacobi_blk_finish(const double *C, int n, int npc, const int32_t *ctrl,
+                                                            double *sigma)
+{
+    __shared__ double sv[512];
+    const bool bad = ctrl[CTRL_SWEEPS] < 0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < npc; i++) acc = fma(C[(int64_t)k * npc + i], C[(int64_t)k * npc + i], acc);
+        sv[k] = sqrt(acc);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const double v = sv[k];
+        int rank = 0;
+        for (int j = 0; j < n; j++) {
+            const double u = sv[j];
+            rank += (u > v) || (u == v && j < k);
+        }
+        sigma[rank] = bad ? __builtin_nan("") : v;
+    }
+}
+
+template <int NPC>
+hipError_t launch_blk(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps, int32_t *ctrl,
+                      double *C, hipStream_t s)
+{
+    const int64_t total = (int64_t)NPC * NPC;
+    k_jacobi_blk_init<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(R, n, ldr, C, NPC, ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_jacobi_blk<NPC><<<NPC / (2 * kBlk), kBlkThreads, 0, s>>>(C, n, max_sweeps, ctrl);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_jacobi_blk_finish<<<1, 1024, 0, s>>>(C, n, NPC, ctrl, sigma);
     return hipGetLastError();
 }
 
 }  // namespace
 
+int64_t jacobi_scratch_doubles(int n)
+{
+    if (n <= 128) return 0;
+    const int64_t npc = n <= 256 ? 256 : 512;
+    return npc * npc;
+}
+
 hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
-                         int32_t *sweeps_out, hipStream_t s)
+                         int32_t *ctrl, double *scratch, hipStream_t s)
 {
     if (n <= 0) return hipErrorInvalidValue;
-    if (n <= 8) return launch_npc<8>(R, n, ldr, sigma, max_sweeps, sweeps_out, s);
-    if (n <= 16) return launch_npc<16>(R, n, ldr, sigma, max_sweeps, sweeps_out, s);
-    if (n <= 32) return launch_npc<32>(R, n, ldr, sigma, max_sweeps, sweeps_out, s);
-    if (n <= 64) return launch_npc<64>(R, n, ldr, sigma, max_sweeps, sweeps_out, s);
-    if (n <= 128) return launch_npc<128>(R, n, ldr, sigma, max_sweeps, sweeps_out, s);
+    if (n <= 8) return launch_npc<8>(R, n, ldr, sigma, max_sweeps, ctrl, s);
+    if (n <= 16) return launch_npc<16>(R, n, ldr, sigma, max_sweeps, ctrl, s);
+    if (n <= 32) return launch_npc<32>(R, n, ldr, sigma, max_sweeps, ctrl, s);
+    if (n <= 64) return launch_npc<64>(R, n, ldr, sigma, max_sweeps, ctrl, s);
+    if (n <= 128) return launch_npc<128>(R, n, ldr, sigma, max_sweeps, ctrl, s);
+    if (!scratch) return hipErrorInvalidValue;
+    if (n <= 256) return launch_blk<256>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, s);
+    if (n <= 512) return launch_blk<512>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, s);
     return hipErrorInvalidValue;
 }
 

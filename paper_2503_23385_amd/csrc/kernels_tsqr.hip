@@ -15,14 +15,14 @@
 // keeps RPT rows of column k of X in registers for row set h, column j is
 // broadcast through a per-wave LDS slot, and every reduction stays inside the
 // wave -- no workgroup barrier.  A region is reduced in one launch: each wave
-// reduces its rows to a leaf triangle, then the waves climb a binary tree;
-// at each node the second of the two children to arrive (per-node atomic
-// counter) combines them, always as left absorbing right, so results do not
-// depend on timing; the first to arrive exits.  Nothing waits on anything.
+// reduces its rows to a leaf triangle, then the waves climb a tree whose arity
+// is set so that one block of rows holds all siblings of a node; at each node
+// the last child to arrive (per-node atomic counter) combines them, always as
+// the first child absorbing the others in child order, so results do not
+// depend on timing; the others exit.  Nothing waits on anything.
 //
-// Widths 128 and 256: a workgroup owns the triangle; wave w owns a slab of
-// columns and the reflector is exchanged through LDS with one barrier per
-// column.  Tree levels are separate launches there.
+// Wider rows (padded widths 128 to 512) go to the blocked panel kernel
+// (kernels_panel.hip); its tree levels are separate launches.
 #include <float.h>
 
 #include "common.h"
@@ -30,7 +30,6 @@
 namespace figaro {
 namespace {
 
-constexpr int kTsqrThreads = 256;
 constexpr int kWavesPerBlock = 4;
 
 __host__ __device__ constexpr int packed_size(int np) { return np * (np + 1) / 2; }
@@ -73,128 +72,17 @@ __device__ inline double rsq_refined(double x)
     return y;
 }
 
-// ------------------------------------------------------------------ workgroup kernel (NP 128, 256)
-
-template <int NP, typename Tin, typename Tacc>
-__global__ __launch_bounds__(kTsqrThreads) void k_tsqr_stream(const double *init, int64_t init_ld,
-                                                              RowSrc s0, RowSrc s1, int nsrc,
-                                                              int width, int tri_rows,
-                                                              double *tri_out, int64_t tri_stride)
-{
-    constexpr int CW = NP / 4 > 0 ? NP / 4 : 1;  // columns per wave
-    constexpr int Q = 64 / CW;                   // row groups per column
-    constexpr int RPT = 16;                      // rows per thread per block
-    constexpr int BR = Q * RPT;                  // rows per block
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int k = wave * CW + (lane % CW);
-    const int q = lane / CW;
-
-    __shared__ Tacc Rp[packed_size(NP)];
-    __shared__ Tacc vbuf[2][BR];
-    __shared__ double sc[2][2];
-
-    for (int e = tid; e < width * NP; e += kTsqrThreads) {
-        const int j = e / NP, kk = e - j * NP;
-        if (kk >= j) Rp[pidx(NP, j, kk)] = (init && kk < width) ? (Tacc)init[(int64_t)j * init_ld + kk] : Tacc(0);
-    }
-
-    const int64_t rows0 = src_rows(s0);
-    const int64_t total = rows0 + (nsrc > 1 ? src_rows(s1) : 0);
-    int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
-    chunk = ((chunk + BR - 1) / BR) * BR;
-    const int64_t r_begin = (int64_t)blockIdx.x * chunk;
-    const int64_t r_end = min(total, r_begin + chunk);
-    __syncthreads();
-
-    int it = 0;  // global column-step counter: parity of the LDS buffers
-    for (int64_t rb = r_begin; rb < r_end; rb += BR) {
-        Tacc x[RPT];
-#pragma unroll
-        for (int i = 0; i < RPT; i++) {
-            const int64_t r = rb + q * RPT + i;
-            Tacc v = Tacc(0);
-            if (r < r_end && k < width) {
-                if (r < rows0) v = load_src<Tin, Tacc>(s0, r, k);
-                else v = load_src<Tin, Tacc>(s1, r - rows0, k);
-            }
-            x[i] = v;
-        }
-        // Leading columns known to be zero in this block: source column offset, and
-        // for stacked triangles the row index inside its triangle.
-        int jstart = 0;
-        const int64_t rlast = min(r_end, rb + BR) - 1;
-        if (rlast < rows0) jstart = s0.col_off;
-        else if (rb >= rows0) jstart = s1.col_off;
-        if (tri_rows > 0 && jstart == (rb < rows0 ? s0.col_off : s1.col_off)) {
-            const int64_t lr = rb < rows0 ? rb : rb - rows0;
-            const int64_t off = lr % tri_rows;
-            if (off + BR <= tri_rows) jstart += (int)off;
-        }
-        for (int j = jstart; j < width; j++, it++) {
-            const int buf = it & 1;
-            if (wave == j / CW) {
-                double pn = 0.0;
-#pragma unroll
-                for (int i = 0; i < RPT; i++) pn += (double)x[i] * (double)x[i];
-#pragma unroll
-                for (int off = CW; off < 64; off <<= 1) pn += shfl_xor_t(pn, off);
-                const double s = __shfl(pn, j % CW, 64);
-                const double alpha = (double)Rp[pidx(NP, j, j)];
-                double tau = 0.0, beta = alpha, scl = 0.0;
-                if (s > 0.0) {
-                    const double nrm = sqrt(alpha * alpha + s);
-                    beta = alpha >= 0.0 ? -nrm : nrm;
-                    tau = (beta - alpha) / beta;
-                    scl = 1.0 / (alpha - beta);
-                }
-                if (k == j) {
-#pragma unroll
-                    for (int i = 0; i < RPT; i++) vbuf[buf][q * RPT + i] = (Tacc)((double)x[i] * scl);
-                }
-                if (lane == 0) {
-                    sc[buf][0] = tau;
-                    sc[buf][1] = beta;
-                }
-            }
-            __syncthreads();
-            const double tau = sc[buf][0];
-            if (tau != 0.0) {
-                const Tacc rjk = (k > j && k < width) ? Rp[pidx(NP, j, k)] : Tacc(0);
-                Tacc dot = Tacc(0);
-#pragma unroll
-                for (int i = 0; i < RPT; i++) dot += vbuf[buf][q * RPT + i] * x[i];
-#pragma unroll
-                for (int off = CW; off < 64; off <<= 1) dot += shfl_xor_t(dot, off);
-                if (k > j && k < width) {
-                    const Tacc w = rjk + dot;
-                    const Tacc tw = (Tacc)tau * w;
-#pragma unroll
-                    for (int i = 0; i < RPT; i++) x[i] -= vbuf[buf][q * RPT + i] * tw;
-                    if (q == 0) Rp[pidx(NP, j, k)] = rjk - tw;
-                }
-                if (k == j && q == 0) Rp[pidx(NP, j, j)] = (Tacc)sc[buf][1];
-            }
-        }
-    }
-    __syncthreads();
-    // Triangle out: `width` rows of NP columns (zeros left of the diagonal).
-    double *out = tri_out + (int64_t)blockIdx.x * tri_stride;
-    for (int e = tid; e < width * NP; e += kTsqrThreads) {
-        const int j = e / NP, kk = e - j * NP;
-        out[e] = (kk >= j && kk < width) ? (double)Rp[pidx(NP, j, kk)] : 0.0;
-    }
-}
-
 // ------------------------------------------------------------------ one wave per triangle (NP <= 64)
 
 template <int NP>
 struct WaveGeom {
     static constexpr int H = NP >= 64 ? 1 : 64 / NP;    // row sets per wave
-    static constexpr int RPT = NP >= 64 ? 32 : 16;      // rows per lane per block
+    static constexpr int RPT = 32;                      // rows per lane per block
     static constexpr int BR = H * RPT;                  // rows per block
     static constexpr int PS = packed_size(NP);
 };
+
+__host__ __device__ constexpr int wave_block_rows(int np) { return (np >= 64 ? 1 : 64 / np) * 32; }
 
 // Absorb one block (RPT rows per lane, already in x) into R for columns [jstart, width).
 template <int NP, typename Tacc>
@@ -381,7 +269,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_tree(TreeRegion re
     __shared__ Tacc Rs[kWavesPerBlock][Gm::PS];
     __shared__ __align__(16) Tacc Xs[kWavesPerBlock][Gm::BR];
     const bool second = gw >= reg0.nleaves;
-    const TreeRegion &rg = second ? reg1 : reg0;
+    const TreeRegion rg = second ? reg1 : reg0;
     if (second) gw -= reg0.nleaves;
     if (gw >= rg.nleaves) return;
     const int width = rg.width, nleaves = rg.nleaves;
@@ -396,29 +284,33 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_tree(TreeRegion re
     wave_absorb_rows<NP, Tin, Tacc>(Rp, xb, rg.src, none, rows, r0, r1, 0, width, k, h);
 
     const int64_t tsz = (int64_t)width * NP;
+    const int A = rg.arity;
     int node = gw, n = nleaves;
     int64_t soff = 0, coff = 0;
     while (n > 1) {
-        const int sib = node ^ 1;
-        if (sib < n) {
+        const int parent = node / A, first = parent * A;
+        const int nchild = min(A, n - first);
+        if (nchild > 1) {
             wave_store<NP, Tacc>(Rp, rg.slots + (soff + node) * tsz, width, lane);
             __threadfence();
             int old = 0;
             if (lane == 0)
-                old = __hip_atomic_fetch_add(&rg.counters[coff + (node >> 1)], 1, __ATOMIC_ACQ_REL,
+                old = __hip_atomic_fetch_add(&rg.counters[coff + parent], 1, __ATOMIC_ACQ_REL,
                                              __HIP_MEMORY_SCOPE_AGENT);
             old = __builtin_amdgcn_readfirstlane(old);
-            if (old == 0) return;  // the sibling finishes this node
+            if (old != nchild - 1) return;  // the last child to arrive combines this node
             __threadfence();
-            const int left = node & ~1;
-            wave_init_tri<NP, Tacc>(Rp, rg.slots + (soff + left) * tsz, NP, width, lane);
-            wave_absorb_tri<NP, Tacc>(Rp, xb, rg.slots + (soff + left + 1) * tsz, NP, width, 0, width,
-                                      width, k, h);
+            // R <- first child; absorb the others, stacked in child order.
+            wave_init_tri<NP, Tacc>(Rp, rg.slots + (soff + first) * tsz, NP, width, lane);
+            const RowSrc sib{rg.slots + (soff + first + 1) * tsz, nullptr, (int64_t)(nchild - 1) * width, NP,
+                             0, width};
+            wave_absorb_rows<NP, double, Tacc>(Rp, xb, sib, none, sib.rows_host, 0, sib.rows_host, width,
+                                               width, k, h);
         }
-        node >>= 1;
+        node = parent;
         soff += n;
-        coff += (n + 1) / 2;
-        n = (n + 1) / 2;
+        coff += (n + A - 1) / A;
+        n = (n + A - 1) / A;
     }
     wave_store<NP, Tacc>(Rp, rg.root, width, lane);
 }
@@ -466,22 +358,8 @@ hipError_t launch_np(int acc_f64, int in_f64, const double *init, int64_t init_l
 #undef FIGARO_WAVE
         return hipGetLastError();
     } else {
-#define FIGARO_WG(TI, TA)                                                                      \
-    k_tsqr_stream<NP, TI, TA><<<nwg, kTsqrThreads, 0, s>>>(init, init_ld, s0, s1, nsrc, width,  \
-                                                          tri_rows, tri, stride)
-        if (acc_f64) {
-            if constexpr (packed_size(NP) * 8 + 2 * 16 * (256 / NP) * 8 <= 160 * 1024) {
-                if (in_f64) FIGARO_WG(double, double);
-                else FIGARO_WG(float, double);
-            } else {
-                return hipErrorInvalidValue;
-            }
-        } else {
-            if (in_f64) FIGARO_WG(double, float);
-            else FIGARO_WG(float, float);
-        }
-#undef FIGARO_WG
-        return hipGetLastError();
+        return launch_tsqr_panel(NP, acc_f64, in_f64, init, init_ld, s0, s1, nsrc, width, tri_rows, nwg, tri,
+                                 stride, s);
     }
 }
 
@@ -511,23 +389,29 @@ int tsqr_padded_width(int n)
     if (n <= 0) return 0;
     int np = 4;
     while (np < n) np <<= 1;
-    return np <= 256 ? np : 0;
+    return np <= 512 ? np : 0;
 }
 
-int tsqr_block_rows(int np)
+int tsqr_block_rows(int np, int acc_f64)
 {
-    if (np <= 64) return np >= 64 ? 32 : (64 / np) * 16;  // wave kernel: row sets x rows per lane
-    return (256 / np) * 16;                               // workgroup kernel
+    if (np <= 64) return wave_block_rows(np);  // wave kernel: row sets x rows per lane
+    return tsqr_panel_rows(np, acc_f64);      // workgroup panel kernel
 }
 
-void tsqr_tree_sizes(int nleaves, int64_t *slots, int64_t *counters)
+int tsqr_tree_arity(int np, int width)
+{
+    const int a = 1 + wave_block_rows(np) / (width > 0 ? width : 1);
+    return a < 2 ? 2 : (a > 32 ? 32 : a);
+}
+
+void tsqr_tree_sizes(int nleaves, int arity, int64_t *slots, int64_t *counters)
 {
     int64_t s = 0, c = 0;
     int n = nleaves;
     while (n > 1) {
         s += n;
-        c += (n + 1) / 2;
-        n = (n + 1) / 2;
+        c += (n + arity - 1) / arity;
+        n = (n + arity - 1) / arity;
     }
     *slots = s + 1;
     *counters = c + 1;
@@ -541,6 +425,7 @@ hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *ini
 #define FIGARO_CASE(NPV) \
     case NPV: return launch_np<NPV>(acc_f64, in_f64, init, init_ld, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
     FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64) FIGARO_CASE(128) FIGARO_CASE(256)
+    FIGARO_CASE(512)
 #undef FIGARO_CASE
     default: return hipErrorInvalidValue;
     }
@@ -557,6 +442,27 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
 #undef FIGARO_CASE
     default: return hipErrorInvalidValue;
     }
+}
+
+__global__ void k_block_diag(const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
+                             double *out, int64_t ldo)
+{
+    const int n = na + nb;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * ldo) return;
+    const int i = (int)(e / ldo), k = (int)(e - (int64_t)i * ldo);
+    double v = 0.0;
+    if (i < na && k >= i && k < na) v = Ta[(int64_t)i * lda + k];
+    else if (i >= na && k >= i && k < n) v = Tb[(int64_t)(i - na) * ldb + (k - na)];
+    out[e] = v;
+}
+
+hipError_t launch_block_diag(const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
+                             double *out, int64_t ldo, hipStream_t s)
+{
+    const int64_t total = (int64_t)(na + nb) * ldo;
+    k_block_diag<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(Ta, lda, na, Tb, ldb, nb, out, ldo);
+    return hipGetLastError();
 }
 
 hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,

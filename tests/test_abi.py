@@ -56,7 +56,6 @@ def test_workspace_size_ok_and_monotone():
     (table(dtype=7), table(dtype=7), 0),                  # bad dtype
     (table(), table(), 9),                                # bad precision
     (table(cols=300), table(cols=300), 1),                # N > 512
-    (table(cols=100), table(cols=100), 0),                # N = 200 > FP64 limit of this build
     (table(), table(), 0x200),                            # unknown flag
     (table(), table(), 0x101 | 0x400),                    # unknown flag beside a valid one
 ])
@@ -65,6 +64,14 @@ def test_invalid_arguments_rejected_on_host(A, B, prec):
     assert rc == fg.FIGARO_EINVAL
     msg = fg.lib().figaro_last_error().decode()
     assert msg
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 0x100, 0x102])
+def test_wide_rows_accepted(prec):
+    """Widths up to FIGARO_MAX_N in every precision and form (blocked panel kernel)."""
+    for n1, n2 in ((100, 100), (256, 256), (1, 511)):
+        rc, n = ws_size(table(1000, n1, keys=8), table(900, n2, keys=8), prec)
+        assert rc == 0 and n > 0, (n1, n2, prec)
 
 
 def test_two_sided_flag_accepted_and_sized():

@@ -64,6 +64,10 @@ def small_cases():
         # A tail leaf with a single row: its rank-deficient residual columns shrink
         # geometrically (regression case for reflector scalars that must not underflow).
         "cart_tail_leaf": W.random_instance(rng(14), 4097, 5, 2000, 59),
+        # wide rows: blocked panel TSQR (padded widths 256 and 512) and block Jacobi
+        "cart_n192_ragged": W.random_instance(rng(15), 1500, 70, 900, 122),
+        "keyed_n256": W.random_instance(rng(16), 3000, 128, 2600, 128, n_values=60),
+        "keyed_n512": W.random_instance(rng(17), 2500, 256, 2200, 256, n_values=30),
     }
     # every group has one B row: no tails at all
     inst = W.random_instance(rng(11), 3000, 6, 1, 5)
@@ -234,7 +238,7 @@ def test_strided_inputs():
 
 def refine_cases():
     c = {k: CASES[k] for k in ("cart_ragged", "keyed_zipf_n64", "keyed_uniform_sparse",
-                               "keyed_singleton_B", "cart_tail_leaf", "keyed_n128")}
+                               "keyed_singleton_B", "cart_tail_leaf", "keyed_n128", "keyed_n256")}
     # the wide workload's value recipe at a small size: columns scaled by 10^U(-3,0), kappa ~ 1e3
     c["keyed_scaled_small"] = W.config5(m=1 << 13, n=32, n_values=256)
     return c
@@ -325,6 +329,31 @@ def test_full_config3(prec, two_sided):
     er = relF(R.cpu().numpy(), L.T)
     say(f"    relF(R vs chol(Gram))={er:.3e}")
     assert er <= TOL_R[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_refine"])
+def test_full_config5(prec):
+    """Wide natural join (2^18 x 256 per table, N = 512, kappa ~ 1e3), two-sided form.
+
+    At this size R is checked against the Cholesky factor of the closed-form Gram
+    matrix (a property that holds at any size), and sigma against the singular
+    values of that factor.  The Gram reference itself carries an error of about
+    kappa^2 * 2^-53 (~1e-10), which bounds the tolerance of the refined form."""
+    inst = W.config5()
+    say(f"[full] config 5 {prec} shape={inst.shape}")
+    A, B, kA, kB = to_dev(inst)
+    R, ws = fg().r(A, B, kA, kB, prec, two_sided=True)
+    S = fg().sigma(R)
+    torch.cuda.synchronize()
+    assert fg().status(ws) == 0
+    L = np.linalg.cholesky(gram_closed_form(inst))
+    Rg = R.cpu().numpy()
+    er = relF(Rg, L.T)
+    Sref = np.linalg.svd(L.T, compute_uv=False)
+    es = np.linalg.norm(S.cpu().numpy() - Sref) / np.linalg.norm(Sref)
+    say(f"    relF(R vs chol(Gram))={er:.3e} rel2(sigma)={es:.3e}")
+    tol = 1e-5 if prec == "fp32" else 1e-9
+    assert er <= tol and es <= tol
 
 
 # ------------------------------------------------------------------ batched plan (graph)
