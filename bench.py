@@ -2,14 +2,23 @@
 
 One step = the whole path on one batch of synthetic input already resident in
 HBM: key grouping, head/tail scans, compact-matrix assembly, Householder TSQR
-(leaves, tree, merge, sign) -> R, then one-sided Jacobi -> sigma.
+(leaves, tree, merge, sign) -> R, the FP64 refinement sweep when the form asks
+for it, then one-sided Jacobi -> sigma.
 
-Workload: Cartesian product of two 1e5 x 32 FP64 N(0,1) tables (a 1e10 x 64
-join that is never materialised).  Six forms are timed: the Claim 1 compact
-matrix and the two-sided form, each with an FP64 reduction, an FP32 one, and
-an FP32 one followed by the FP64 refinement sweep.  `value`
-is the fastest form whose R and sigma are within 1e-5 of the oracle; every
-form is listed under "forms".  Prints one JSON line.
+Default workload (the headline line): Cartesian product of two 1e5 x 32 FP64
+N(0,1) tables (a 1e10 x 64 join that is never materialised).  Six forms are
+timed: the Claim 1 compact matrix and the two-sided form, each with an FP64
+reduction, an FP32 one, and an FP32 one followed by the FP64 refinement sweep.
+`value` is the fastest form whose R and sigma are within 1e-5 of the oracle;
+every form is listed under "forms".
+
+Other workloads (--workload): cfg1 (1000 x 4 U[0,1) Cartesian), cfg3 (2^20 x 64
+per table, Zipf(1.1) keys over 1e4 values), cfg5 (2^18 x 256 FP32 per table,
+scaled columns, 4096 uniform keys, N = 512) and cfg4 (256 Cartesian FP32
+instances with log-uniform sizes, all in one captured graph).  For cfg3/cfg5
+the error columns compare with the Cholesky factor of the closed-form Gram
+matrix, and the CPU baseline times the oracle on a prefix of both tables.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -29,6 +38,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 TOL = 1e-5
+ALL_FORMS = "claim1:fp64,two_sided:fp64,claim1:fp32,two_sided:fp32,claim1:fp32_refine,two_sided:fp32_refine"
 
 
 def parse():
@@ -36,11 +46,247 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--forms", default="claim1:fp64,two_sided:fp64,claim1:fp32,two_sided:fp32,"
-                                       "claim1:fp32_refine,two_sided:fp32_refine")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--forms", default=None, help="comma list of layout:precision (default: all six)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+# ------------------------------------------------------------------ host-side bookkeeping (no method arithmetic)
+
+def group_sizes(inst):
+    """Per-group (m1_g, m2_g) of the natural join, by counting equal keys."""
+    if inst.keys_A is None:
+        return np.array([inst.A.shape[0]]), np.array([inst.B.shape[0]])
+    ua, ca = np.unique(inst.keys_A, return_counts=True)
+    ub, cb = np.unique(inst.keys_B, return_counts=True)
+    _, ia, ib = np.intersect1d(ua, ub, return_indices=True)
+    return ca[ia].astype(np.int64), cb[ib].astype(np.int64)
+
+
+def gram_reference(inst):
+    """Cholesky factor of J^T J from the per-group closed form (FP64, numpy)."""
+    A = np.asarray(inst.A, dtype=np.float64)
+    B = np.asarray(inst.B, dtype=np.float64)
+    n1 = A.shape[1]
+    N = n1 + B.shape[1]
+    Gm = np.zeros((N, N))
+    if inst.keys_A is None:
+        groups = [(0, A.shape[0], 0, B.shape[0])]
+    else:
+        ua, sa, ca = np.unique(inst.keys_A, return_index=True, return_counts=True)
+        ub, sb, cb = np.unique(inst.keys_B, return_index=True, return_counts=True)
+        _, ia, ib = np.intersect1d(ua, ub, return_indices=True)
+        groups = zip(sa[ia], ca[ia], sb[ib], cb[ib])
+    for oa, ma, ob, mb in groups:
+        Ag, Bg = A[oa:oa + ma], B[ob:ob + mb]
+        a, b = Ag.sum(axis=0), Bg.sum(axis=0)
+        Gm[:n1, :n1] += mb * (Ag.T @ Ag)
+        Gm[n1:, n1:] += ma * (Bg.T @ Bg)
+        Gm[:n1, n1:] += np.outer(a, b)
+        Gm[n1:, :n1] += np.outer(b, a)
+    return np.linalg.cholesky(Gm).T
+
+
+def prefix_instance(inst, frac):
+    from paper_2503_23385_amd import workloads as W
+    m1 = max(1, int(inst.A.shape[0] * frac))
+    m2 = max(1, int(inst.B.shape[0] * frac))
+    kA = None if inst.keys_A is None else inst.keys_A[:m1]
+    kB = None if inst.keys_B is None else inst.keys_B[:m2]
+    return W.Instance(np.ascontiguousarray(inst.A[:m1]), np.ascontiguousarray(inst.B[:m2]), kA, kB)
+
+
+def stage_work(inst, two_sided, precision, sweeps):
+    """Algorithmic work of each single-kernel stage: (bound, amount in GB or TFLOP)."""
+    m1g, m2g = group_sizes(inst)
+    n1, n2 = inst.A.shape[1], inst.B.shape[1]
+    N = n1 + n2
+    R1, R2, TA, G = int(m1g.sum()), int((m2g - 1).sum()), int((m1g - 1).sum()), len(m1g)
+    flops = lambda rows, w: 2.0 * rows * w * w / 1e12  # noqa: E731  (streaming rows into a w x w triangle)
+    work = {
+        "tsqr_m1": ("alu", flops(R1, N)),
+        "tsqr_m2": ("alu", flops(R2, n2)),
+        "tsqr_ta": ("alu", flops(TA, n1)),
+        "tsqr_tb": ("alu", flops(R2, n2)),
+        "tsqr_heads": ("alu", flops(G, N)),
+        "tsqr_tails": ("alu", flops(TA, n1) + flops(R2, n2)),
+        # one sweep: n(n-1)/2 pairs, 3 dot products and a rotation of two n-vectors (12 n flops)
+        "jacobi": ("alu", 6.0 * N * N * (N - 1) * sweeps / 1e12),
+    }
+    return work
+
+
+# Kernel source and symbol behind each single-kernel stage.
+STAGE_KERNELS = {
+    "tsqr_tails": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
+    "tsqr_m1": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
+    "tsqr_m2": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
+    "jacobi": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_jacobi_lds"),
+}
+
+
+def measured_traffic(workload, stage):
+    """HBM bytes per launch of the stage's kernel from the committed counter summary, if the
+    kernel source is unchanged since the counters were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.md")
+    if stage not in STAGE_KERNELS or not os.path.exists(path):
+        return None
+    src, _ = STAGE_KERNELS[stage]
+    with open(os.path.join(ROOT, src), "rb") as fh:
+        sha = hashlib.sha1(fh.read()).hexdigest()
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("TRAFFIC "):
+                rec = json.loads(line[len("TRAFFIC "):])
+                if rec.get("stage") == stage and rec.get("source_sha1") == sha:
+                    return rec["bytes_per_launch"]
+    return None
+
+
+def roofline(form, work, precision):
+    stage_ms, launches = form["stage_ms"], form["launches_per_step"]
+    dom = max((k for k in stage_ms if k in work), key=lambda k: stage_ms[k])
+    per_launch_ms = stage_ms[dom] / max(1.0, launches[dom])
+    bound, amount = work[dom]
+    t = per_launch_ms / 1e3
+    if bound == "hbm":
+        return {"kernel": dom, "bound": "hbm", "achieved": amount / t, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": amount / t / PEAK_HBM_GBS, "traffic": None, "launch_ms": per_launch_ms}
+    # the FP32 forms' TSQR runs in FP32; Jacobi always runs in FP64
+    peak = PEAK_FP64_TFLOPS if (dom == "jacobi" or precision == "fp64") else PEAK_FP32_TFLOPS
+    return {"kernel": dom, "bound": "alu", "achieved": amount / t, "peak": peak, "unit": "TFLOP/s",
+            "frac": amount / t / peak, "traffic": None, "launch_ms": per_launch_ms}
+
+
+# ------------------------------------------------------------------ timing
+
+def time_steps(step, steps, warmup, stream, torch):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref):
+    A = torch.from_numpy(inst.A).to(dev)
+    B = torch.from_numpy(inst.B).to(dev)
+    kA = None if inst.keys_A is None else torch.from_numpy(inst.keys_A).to(dev)
+    kB = None if inst.keys_B is None else torch.from_numpy(inst.keys_B).to(dev)
+    N = inst.A.shape[1] + inst.B.shape[1]
+    m1g, m2g = group_sizes(inst)
+    join_rows = int((m1g * m2g).sum())
+    forms = {}
+    for spec in forms_spec.split(","):
+        layout, prec = spec.split(":")
+        two = layout == "two_sided"
+        ws = fg.alloc_workspace(fg.r_workspace_size(A, B, kA, kB, prec, two), dev)
+        R = torch.empty((N, N), dtype=torch.float64, device=dev)
+        S = torch.empty(N, dtype=torch.float64, device=dev)
+        sws = fg.alloc_workspace(fg.sigma_workspace_size(N), dev)
+
+        def step():
+            fg.r(A, B, kA, kB, prec, ws=ws, out=R, two_sided=two)
+            fg.sigma(R, out=S, ws=sws)
+
+        ms = time_steps(step, args.steps, args.warmup, stream, torch)
+        assert fg.status(ws) == 0
+        # The same K steps again with per-stage events (library stage timing).
+        fg.timing_enable(True)
+        fg.timing_read()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        stages = fg.timing_read()
+        fg.timing_enable(False)
+        sweeps = int(sws[:4].view(torch.int32)[0].item())
+        errs = None
+        if ref is not None:
+            Rref, Sref, kind = ref
+            Rg, Sg = R.cpu().numpy(), S.cpu().numpy()
+            errs = {"R_relF": float(np.linalg.norm(Rg - Rref) / np.linalg.norm(Rref)),
+                    "sigma_rel2": float(np.linalg.norm(Sg - Sref) / np.linalg.norm(Sref)), "reference": kind}
+        forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3),
+                       "stage_ms": {k: v[0] / args.steps for k, v in stages.items()},
+                       "launches_per_step": {k: v[1] / args.steps for k, v in stages.items()},
+                       "errors_vs_reference": errs, "jacobi_sweeps": sweeps, "layout": layout, "precision": prec}
+        del ws, R, S
+    ok = [k for k, f in forms.items()
+          if f["errors_vs_reference"] is None
+          or (f["errors_vs_reference"]["R_relF"] <= TOL and f["errors_vs_reference"]["sigma_rel2"] <= TOL)]
+    chosen = min(ok, key=lambda k: forms[k]["ms_per_step"])
+    f = forms[chosen]
+    work = stage_work(inst, f["layout"] == "two_sided", f["precision"], f["jacobi_sweeps"])
+    return {"value": f["value"], "ms_per_step": f["ms_per_step"], "chosen": chosen, "precision": f["precision"],
+            "roofline": roofline(f, work, f["precision"]), "forms": forms, "join_rows": join_rows,
+            "config": {"workload": desc, "join_rows": join_rows, "form": chosen}}
+
+
+def bench_batch(args, insts, desc, forms_spec, torch, fg, dev, stream, refs):
+    tens = []
+    for inst in insts:
+        tens.append((torch.from_numpy(inst.A).to(dev), torch.from_numpy(inst.B).to(dev), None, None))
+    join_rows = int(sum(i.A.shape[0] * i.B.shape[0] for i in insts))
+    forms = {}
+    for spec in forms_spec.split(","):
+        layout, prec = spec.split(":")
+        plan = fg.Plan(tens, prec, two_sided=(layout == "two_sided"))
+        ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=dev)
+        R = torch.zeros(plan.r_total, dtype=torch.float64, device=dev)
+        S = torch.zeros(plan.s_total, dtype=torch.float64, device=dev)
+        ms = time_steps(lambda: plan.execute(ws, R, S), args.steps, args.warmup, stream, torch)
+        errs = None
+        if refs:
+            Rh, Sh = R.cpu().numpy(), S.cpu().numpy()
+            er = es = 0.0
+            for i, (Ro, So) in refs.items():
+                n = Ro.shape[0]
+                Rg = Rh[plan.r_off[i]:plan.r_off[i] + n * n].reshape(n, n)
+                Sg = Sh[plan.s_off[i]:plan.s_off[i] + n]
+                er = max(er, float(np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)))
+                es = max(es, float(np.linalg.norm(Sg - So) / np.linalg.norm(So)))
+            errs = {"R_relF": er, "sigma_rel2": es, "reference": f"oracle, max over {len(refs)} instances"}
+        forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3), "errors_vs_reference": errs,
+                       "layout": layout, "precision": prec}
+        del plan, ws, R, S
+    ok = [k for k, f in forms.items()
+          if f["errors_vs_reference"] is None
+          or (f["errors_vs_reference"]["R_relF"] <= TOL and f["errors_vs_reference"]["sigma_rel2"] <= TOL)]
+    chosen = min(ok, key=lambda k: forms[k]["ms_per_step"])
+    f = forms[chosen]
+    return {"value": f["value"], "ms_per_step": f["ms_per_step"], "chosen": chosen, "precision": f["precision"],
+            "roofline": None, "forms": forms, "join_rows": join_rows,
+            "config": {"workload": desc, "join_rows": join_rows, "instances": len(insts), "form": chosen}}
+
+
+def cpu_baseline(oracle, insts, join_rows_per_rep, seconds, what):
+    t0 = time.perf_counter()
+    reps = 0
+    out = None
+    while True:
+        res = []
+        for inst in insts:
+            Ro = oracle.r(inst)
+            res.append((Ro, oracle.sigma(Ro)))
+        out = out or res
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or reps >= 20:
+            break
+    return out, {"value": join_rows_per_rep * reps / el, "unit": "join rows/s", "cores": oracle.num_threads(),
+                 "kind": "oracle", "sample": f"{reps} run(s) of the FP64 CPU oracle (groups, compact matrix, "
+                                             f"Householder QR, Jacobi) on {what}, {el:.1f} s"}
 
 
 def main():
@@ -59,140 +305,87 @@ def main():
         from paper_2503_23385_amd import build as hb
         hb.build()
     dev = torch.device("cuda:0")
-    inst = W.config2()
-    m1, n1 = inst.A.shape
-    m2, n2 = inst.B.shape
-    N = n1 + n2
-    join_rows = m1 * m2
-    A = torch.from_numpy(inst.A).to(dev)
-    B = torch.from_numpy(inst.B).to(dev)
     stream = torch.cuda.current_stream()
-
-    # Oracle: reference result for the error columns, and the CPU baseline timing.
-    Ro = So = None
-    cpu = None
+    oracle = None
     if not args.no_cpu_baseline:
         import oracle
         if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
             oracle.build()
-        t0 = time.perf_counter()
-        reps = 0
-        while True:
-            Ro = oracle.r(inst)
-            So = oracle.sigma(Ro)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= args.cpu_seconds or reps >= 20:
-                break
-        cpu = {"value": join_rows * reps / el, "unit": "join rows/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"{reps} full run(s) of the FP64 CPU oracle (groups, compact matrix, Householder QR, "
-                         f"Jacobi) on the same 1e5x32 + 1e5x32 workload, {el:.1f} s"}
 
-    forms = {}
-    for spec in args.forms.split(","):
-        layout, prec = spec.split(":")
-        two = layout == "two_sided"
-        ws = fg.alloc_workspace(fg.r_workspace_size(A, B, None, None, prec, two), dev)
-        R = torch.empty((N, N), dtype=torch.float64, device=dev)
-        S = torch.empty(N, dtype=torch.float64, device=dev)
-        sws = fg.alloc_workspace(256, dev)
-
-        def step():
-            fg.r(A, B, None, None, prec, ws=ws, out=R, two_sided=two)
-            fg.sigma(R, out=S, ws=sws)
-
-        for _ in range(args.warmup):
-            step()
+    if args.copy_calibration:
+        # A plain copy of known size: 256 MiB read, 256 MiB written per launch.
+        a = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
         torch.cuda.synchronize()
-        assert fg.status(ws) == 0
-        # Timed region: K steps bracketed by synchronisation, HIP events on the launch stream.
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            step()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        # The same K steps again with per-stage events (library stage timing).
-        fg.timing_enable(True)
-        fg.timing_read()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        stages = fg.timing_read()
-        fg.timing_enable(False)
-        stage_ms = {k: v[0] / args.steps for k, v in stages.items()}
-        launches = {k: v[1] / args.steps for k, v in stages.items()}
-        sweeps = int(sws[:4].view(torch.int32)[0].item())
-        errs = None
-        if Ro is not None:
-            Rg, Sg = R.cpu().numpy(), S.cpu().numpy()
-            errs = {"R_relF": float(np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)),
-                    "sigma_rel2": float(np.linalg.norm(Sg - So) / np.linalg.norm(So))}
-        forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3), "stage_ms": stage_ms,
-                       "launches_per_step": launches, "errors_vs_oracle": errs, "jacobi_sweeps": sweeps,
-                       "layout": layout, "precision": prec}
-        del ws, R, S
+        print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 8, "copy_bytes_written_per_launch": b.numel() * 8,
+                          "launches": 5}))
+        return
 
-    ok = [k for k, f in forms.items()
-          if f["errors_vs_oracle"] is None
-          or (f["errors_vs_oracle"]["R_relF"] <= TOL and f["errors_vs_oracle"]["sigma_rel2"] <= TOL)]
-    chosen = min(ok, key=lambda k: forms[k]["ms_per_step"])
-    f = forms[chosen]
-
-    # Dominant kernel of the chosen form and its algorithmic work per launch.
-    esz = 8 if f["precision"] == "fp64" else 4
-    peak_tsqr = PEAK_FP64_TFLOPS if f["precision"] == "fp64" else PEAK_FP32_TFLOPS
-    two = f["layout"] == "two_sided"
-    work = {
-        # B read once per pass of the scan (FP64) + region 2 written once
-        "scan": ("hbm", (m2 * n2 * 8 + (m2 - 1) * n2 * esz + (m1 * n1 * 8 + (m1 - 1) * n1 * esz if two else 0)) / 1e9),
-        "assemble": ("hbm", (m1 * n1 * 8 + m1 * N * esz) / 1e9 if not two else (N * esz) / 1e9),
-        # streaming `rows` rows of width w into a w x w triangle costs 2 w^2 flops per row
-        "tsqr_m1": ("alu", 2.0 * m1 * N * N / 1e12),
-        "tsqr_m2": ("alu", 2.0 * (m2 - 1) * n2 * n2 / 1e12),
-        "tsqr_ta": ("alu", 2.0 * (m1 - 1) * n1 * n1 / 1e12),
-        "tsqr_tb": ("alu", 2.0 * (m2 - 1) * n2 * n2 / 1e12),
-        # both tail regions of the two-sided form in one launch
-        "tsqr_tails": ("alu", 2.0 * ((m1 - 1) * n1 * n1 + (m2 - 1) * n2 * n2) / 1e12),
-        # one sweep: n(n-1)/2 pairs, 3 dot products and a rotation of two n-vectors (12 n flops)
-        "jacobi": ("alu", 6.0 * N * N * (N - 1) * f["jacobi_sweeps"] / 1e12),
-    }
-    stage_ms = f["stage_ms"]
-    dom = max((k for k in stage_ms if k in work), key=lambda k: stage_ms[k])
-    per_launch_ms = stage_ms[dom] / max(1.0, f["launches_per_step"][dom])
-    bound, amount = work[dom]
-    t = per_launch_ms / 1e3
-    if bound == "hbm":
-        roof = {"kernel": dom, "bound": "hbm", "achieved": amount / t, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": amount / t / PEAK_HBM_GBS, "traffic": None}
+    wl = args.workload
+    cpu = None
+    if wl in ("cfg1", "cfg2"):
+        inst = W.config1() if wl == "cfg1" else W.config2()
+        desc = ("cartesian product, A and B 1000 x 4 FP64 U[0,1), join 1e6 x 8, R 8x8 + sigma" if wl == "cfg1" else
+                "cartesian product, A and B 1e5 x 32 FP64 N(0,1), join 1e10 x 64 (never materialised), R 64x64 + sigma")
+        ref = None
+        if oracle is not None:
+            res, cpu = cpu_baseline(oracle, [inst], inst.A.shape[0] * inst.B.shape[0], args.cpu_seconds,
+                                    "the same workload")
+            ref = (res[0][0], res[0][1], "oracle")
+        out = bench_single(args, inst, desc, args.forms or ALL_FORMS, torch, fg, dev, stream, ref)
+    elif wl in ("cfg3", "cfg5"):
+        inst = W.config3() if wl == "cfg3" else W.config5()
+        desc = ("natural join, A and B 2^20 x 64 FP64 N(0,1), int32 keys Zipf(1.1) over 1e4 values, R 128x128 + sigma"
+                if wl == "cfg3" else
+                "natural join, A and B 2^18 x 256 FP32 N(0,1) with column scales 10^U(-3,0), int32 keys uniform "
+                "over 4096 values, R 512x512 + sigma")
+        Rref = gram_reference(inst)
+        ref = (Rref, np.linalg.svd(Rref, compute_uv=False), "Cholesky factor of the closed-form Gram matrix")
+        if oracle is not None:
+            frac = 1.0 / 8
+            sub = prefix_instance(inst, frac)
+            a, b = group_sizes(sub)
+            _, cpu = cpu_baseline(oracle, [sub], int((a * b).sum()), args.cpu_seconds,
+                                  f"the first 1/8 of the rows of both tables (a sub-join of the same workload)")
+        forms = args.forms or ("claim1:fp64,two_sided:fp64,claim1:fp32,two_sided:fp32,two_sided:fp32_refine"
+                               if wl == "cfg3" else "two_sided:fp32,two_sided:fp32_refine,two_sided:fp64")
+        out = bench_single(args, inst, desc, forms, torch, fg, dev, stream, ref)
     else:
-        # the FP32 forms' TSQR updates run in FP32; Jacobi always runs in FP64
-        peak_alu = PEAK_FP64_TFLOPS if dom == "jacobi" else peak_tsqr
-        roof = {"kernel": dom, "bound": "alu", "achieved": amount / t, "peak": peak_alu,
-                "unit": "TFLOP/s", "frac": amount / t / peak_alu, "traffic": None}
+        insts = W.config4()
+        desc = ("batch of 256 cartesian instances, m1 and m2 = floor(10^U(3,5)), n1 = n2 in {8,16,32,64}, "
+                "FP32 U(-1,1), one captured graph")
+        refs = {}
+        if oracle is not None:
+            idx = list(range(0, len(insts), 16))
+            sample = [insts[i] for i in idx]
+            res, cpu = cpu_baseline(oracle, sample, sum(i.A.shape[0] * i.B.shape[0] for i in sample),
+                                    args.cpu_seconds, f"every 16th instance of the batch ({len(sample)} instances)")
+            refs = {i: r for i, r in zip(idx, res)}
+        out = bench_batch(args, insts, desc, args.forms or "two_sided:fp32,two_sided:fp64", torch, fg, dev,
+                          stream, refs)
+
+    if out["roofline"] is not None:
+        out["roofline"]["traffic"] = measured_traffic(wl, out["roofline"]["kernel"])
 
     line = {
         "metric": METRIC,
-        "value": f["value"],
+        "value": out["value"],
         "unit": "join rows/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": f["ms_per_step"],
+        "ms_per_step": out["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp32_refine": "f32+f64"}[f["precision"]],
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32_refine": "f32+f64"}[out["precision"]],
         "data": "synthetic",
-        "config": {"workload": "cartesian product, A and B 1e5 x 32 FP64 N(0,1), join 1e10 x 64 "
-                               "(never materialised), R 64x64 + sigma",
-                   "join_rows": join_rows, "form": chosen},
-        "roofline": roof,
+        "config": out["config"],
+        "roofline": out["roofline"],
         "cpu_baseline": cpu,
-        "forms": forms,
+        "forms": out["forms"],
     }
     print(json.dumps(line))
 

@@ -219,7 +219,10 @@ int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
  * Enqueue the whole batch on `stream`.  The first call with a given
  * (ws, R, sigma) captures the launch sequence into a HIP graph on a private
  * stream; every call (the first included) launches that graph on `stream`.
- * Instances need n1 + n2 <= 128.
+ * Inside the graph the instances run as up to 8 parallel branches (largest
+ * instances first, each to the least-loaded branch); each branch owns one
+ * slice of `ws` and runs its instances in order.  Instances need
+ * n1 + n2 <= 128.  Calls that share `ws` must not overlap.
  */
 int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
                         void *stream);

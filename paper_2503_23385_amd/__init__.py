@@ -169,6 +169,12 @@ def r(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, out=None, strea
     return out, ws
 
 
+def sigma_workspace_size(n) -> int:
+    nb = ctypes.c_size_t(0)
+    _check(lib().figaro_sigma_workspace_size(n, ctypes.byref(nb)))
+    return nb.value
+
+
 def sigma(R, out=None, ws=None, stream=None):
     """Singular values (descending, FP64) of a square device matrix R."""
     torch = _torch()
@@ -176,9 +182,7 @@ def sigma(R, out=None, ws=None, stream=None):
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=R.device)
     if ws is None:
-        nb = ctypes.c_size_t(0)
-        _check(lib().figaro_sigma_workspace_size(n, ctypes.byref(nb)))
-        ws = alloc_workspace(nb.value, R.device)
+        ws = alloc_workspace(sigma_workspace_size(n), R.device)
     _check(lib().figaro_sigma(ctypes.c_void_p(R.data_ptr()), n, R.stride(0),
                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                               ws.numel(), _stream_ptr(stream)))

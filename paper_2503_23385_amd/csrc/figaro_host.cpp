@@ -105,6 +105,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kPrecMask = 0xff;
 constexpr int kMaxTreeLeaves = 2048;
 constexpr int kTreeArityWG = 4;
+constexpr int kPlanLanes = 8;  // parallel branches of a batched plan's graph
 
 struct Shape {
     int64_t m1, n1, lda, m2, n2, ldb;
@@ -213,7 +214,7 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     r.wave = r.np <= 64;
     const int br = tsqr_block_rows(r.np, acc_f64);
     // Leaves of a few blocks each (tunable through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS).
-    static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 8);
+    static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 2);
     static const int wg_blocks = env_int("FIGARO_WG_LEAF_BLOCKS", 4);
     const int64_t per = (r.wave ? wave_blocks : wg_blocks) * (int64_t)br;
     const int64_t leaves = (r.rows_cap + per - 1) / per;
@@ -723,25 +724,40 @@ struct figaro_plan {
     std::vector<int64_t> r_off, s_off;
     int64_t r_total = 0, s_total = 0;
     size_t ws_bytes = 0;
+    size_t lane_bytes = 0;          // workspace slice of one lane
+    std::vector<int> lane;          // lane of each instance
+    int nlanes = 1;
     hipStream_t cap_stream = nullptr;
+    std::vector<hipStream_t> lane_streams;
+    std::vector<hipEvent_t> lane_events;  // [0]: fork, [1 + l]: join of lane l
     // One captured graph per (ws, R, sigma) triple.
     std::map<std::tuple<void *, double *, double *>, hipGraphExec_t> graphs;
 };
 
 namespace {
 
+// Instances run as nlanes parallel branches: lane l owns workspace slice l and runs its
+// instances in order; the branches fork from and join back into s.
 int plan_enqueue(figaro_plan *plan, void *ws, double *R, double *sigma, hipStream_t s)
 {
+    HIPCHK(hipEventRecord(plan->lane_events[0], s), "fork");
+    for (int l = 0; l < plan->nlanes; l++)
+        HIPCHK(hipStreamWaitEvent(plan->lane_streams[l], plan->lane_events[0], 0), "fork wait");
     for (size_t i = 0; i < plan->inst.size(); i++) {
         const Shape &sh = plan->shapes[i];
         const int64_t N = sh.N();
-        int rc = run_r(&plan->inst[i].A, &plan->inst[i].B, sh, plan->layouts[i],
-                       R + plan->r_off[i], N, ws, s);
+        const int l = plan->lane[i];
+        hipStream_t ls = plan->lane_streams[l];
+        void *lws = (char *)ws + (size_t)l * plan->lane_bytes;
+        int rc = run_r(&plan->inst[i].A, &plan->inst[i].B, sh, plan->layouts[i], R + plan->r_off[i], N, lws, ls);
         if (rc) return rc;
-        Stage st("jacobi", s);
         hipError_t e = launch_jacobi(R + plan->r_off[i], (int)N, N, sigma + plan->s_off[i], 60,
-                                     nullptr, nullptr, s);
+                                     nullptr, nullptr, ls);
         if (e != hipSuccess) return hip_fail(e, "jacobi");
+    }
+    for (int l = 0; l < plan->nlanes; l++) {
+        HIPCHK(hipEventRecord(plan->lane_events[1 + l], plan->lane_streams[l]), "join");
+        HIPCHK(hipStreamWaitEvent(s, plan->lane_events[1 + l], 0), "join wait");
     }
     return FIGARO_OK;
 }
@@ -775,9 +791,27 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
         p->s_off.push_back(p->s_total);
         p->r_total += sh.N() * sh.N();
         p->s_total += sh.N();
-        wsmax = std::max(wsmax, L.total);
+        wsmax = std::max(wsmax, align_up(L.total));
     }
-    p->ws_bytes = wsmax;
+    // Lanes: largest instances first, each to the lane with the least work so far
+    // (work ~ rows x N^2; ties to the lower lane, so the assignment is deterministic).
+    p->nlanes = std::min(count, kPlanLanes);
+    p->lane.assign(count, 0);
+    std::vector<int> order(count);
+    for (int i = 0; i < count; i++) order[i] = i;
+    auto work = [&](int i) {
+        const Shape &sh = p->shapes[i];
+        return (double)(sh.m1 + sh.m2) * (double)(sh.N() * sh.N());
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::vector<double> load(p->nlanes, 0.0);
+    for (int i : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        p->lane[i] = l;
+        load[l] += work(i);
+    }
+    p->lane_bytes = wsmax;
+    p->ws_bytes = wsmax * p->nlanes;
     *out = p;
     return FIGARO_OK;
 }
@@ -812,8 +846,15 @@ int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R,
     auto key = std::make_tuple(ws, R, sigma);
     auto it = plan->graphs.find(key);
     if (it == plan->graphs.end()) {
-        if (!plan->cap_stream)
+        if (!plan->cap_stream) {
             HIPCHK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking), "plan stream");
+            plan->lane_streams.assign(plan->nlanes, nullptr);
+            for (auto &ls : plan->lane_streams)
+                HIPCHK(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking), "plan lane stream");
+            plan->lane_events.assign(plan->nlanes + 1, nullptr);
+            for (auto &ev : plan->lane_events)
+                HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "plan event");
+        }
         hipGraph_t graph = nullptr;
         HIPCHK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal),
                "begin capture");
@@ -841,6 +882,10 @@ void figaro_plan_destroy(figaro_plan *plan)
 {
     if (!plan) return;
     for (auto &kv : plan->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto ev : plan->lane_events)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto ls : plan->lane_streams)
+        if (ls) (void)hipStreamDestroy(ls);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
 }

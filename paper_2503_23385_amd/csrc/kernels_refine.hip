@@ -200,6 +200,90 @@ __global__ void k_lt_times_r(const double *__restrict__ L, int ldl, const double
     R[(int64_t)i * ldr + j] = s;
 }
 
+// The whole N x N part in one workgroup for N <= 128: R~ and the lower triangle of X
+// live in LDS (packed), Y = Gram R~^-1 goes through global scratch.
+//   1. row i (one thread each): y = g_i R~^-1 by forward substitution;
+//   2. column j (one thread each, in place over Y): x = R~^-T y_:,j; keep k >= j;
+//   3. right-looking Cholesky of X in LDS;
+//   4. R = L^T R~.
+constexpr int kSmallMax = 128;
+__device__ inline int lpk(int i, int j) { return i * (i + 1) / 2 + j; }       // lower packed, j <= i
+__device__ inline int upk(int n, int i, int j) { return i * n - i * (i - 1) / 2 + (j - i); }  // upper, j >= i
+
+__global__ __launch_bounds__(1024) void k_refine_small(const double *__restrict__ gram, const double *__restrict__ Rt,
+                                                       int ldt, int n, double *__restrict__ Y,
+                                                       int32_t *failed, double *__restrict__ R, int64_t ldr)
+{
+    __shared__ double Ru[kSmallMax * (kSmallMax + 1) / 2];
+    __shared__ double Xl[kSmallMax * (kSmallMax + 1) / 2];
+    __shared__ double piv;
+    __shared__ int bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e / n, j = e - i * n;
+        if (j >= i) Ru[upk(n, i, j)] = Rt[(int64_t)i * ldt + j];
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    if (tid < n) {  // row tid of Y: y_k = (g_k - sum_{l<k} y_l R_lk) / R_kk
+        const int i = tid;
+        for (int k = 0; k < n; k++) {
+            double acc = gram[(int64_t)i * n + k];
+            for (int l = 0; l < k; l++) acc = fma(-Y[(int64_t)i * n + l], Ru[upk(n, l, k)], acc);
+            Y[(int64_t)i * n + k] = acc / Ru[upk(n, k, k)];
+        }
+    }
+    __syncthreads();
+    if (tid < n) {  // column tid of X, in place over Y: x_k = (y_kj - sum_{l<k} R_lk x_l) / R_kk
+        const int j = tid;
+        for (int k = 0; k < n; k++) {
+            double acc = Y[(int64_t)k * n + j];
+            for (int l = 0; l < k; l++) acc = fma(-Ru[upk(n, l, k)], Y[(int64_t)l * n + j], acc);
+            const double xk = acc / Ru[upk(n, k, k)];
+            Y[(int64_t)k * n + j] = xk;
+            if (k >= j) Xl[lpk(k, j)] = xk;
+        }
+    }
+    __syncthreads();
+    // X is symmetric in exact arithmetic; its lower triangle (from the column solves) is used.
+    for (int k = 0; k < n; k++) {
+        if (tid == 0) {
+            const double d = Xl[lpk(k, k)];
+            const bool ok = d > 0.0 && d <= DBL_MAX;
+            piv = ok ? sqrt(d) : 1.0;
+            if (!ok) bad = 1;
+            Xl[lpk(k, k)] = piv;
+        }
+        __syncthreads();
+        const double p = piv;
+        for (int i = k + 1 + tid; i < n; i += nt) Xl[lpk(i, k)] /= p;
+        __syncthreads();
+        const int rem = n - k - 1;
+        for (int e = tid; e < rem * (rem + 1) / 2; e += nt) {
+            // e -> (i, j) with k < j <= i < n
+            int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+            while ((i + 1) * (i + 2) / 2 <= e) i++;
+            while (i * (i + 1) / 2 > e) i--;
+            const int j = e - i * (i + 1) / 2;
+            const int ii = k + 1 + i, jj = k + 1 + j;
+            Xl[lpk(ii, jj)] -= Xl[lpk(ii, k)] * Xl[lpk(jj, k)];
+        }
+        __syncthreads();
+    }
+    const bool fail = bad != 0;
+    if (tid == 0) *failed = bad;
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e / n, j = e - i * n;
+        double s = 0.0;
+        if (fail) {
+            s = j >= i ? Ru[upk(n, i, j)] : 0.0;
+        } else if (j >= i) {
+            for (int k = i; k <= j; k++) s = fma(Xl[lpk(k, i)], Ru[upk(n, k, j)], s);
+        }
+        R[(int64_t)i * ldr + j] = s;
+    }
+}
+
 template <typename Tin>
 hipError_t gram_blocks(const void *A, int64_t lda, int64_t m1, int n1, const void *B, int64_t ldb,
                        int64_t m2, int n2, Groups g, int cartesian, const double *hB, double *partial,
@@ -263,6 +347,10 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
                           : gram_blocks<float>(A, lda, m1, n1, B, ldb, m2, n2, g, cartesian, hB, partial,
                                                partial_cap, gram, s);
     if (e != hipSuccess) return e;
+    if (N <= kSmallMax) {
+        k_refine_small<<<1, 1024, 0, s>>>(gram, Rt, ldt, N, Y, failed, R, ldr);
+        return hipGetLastError();
+    }
     const size_t shm = sizeof(double) * N;
     // Y = Gram Rt^-1 ; then X^T = Y^T Rt^-1 (X symmetric), written over gram
     k_right_solve<<<N, 256, shm, s>>>(gram, N, Rt, ldt, N, Y, N, 0);

@@ -255,64 +255,219 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_wave(const double 
     wave_store<NP, Tacc>(Rp, tri_out + (int64_t)gw * tri_stride, width, lane);
 }
 
-// Up to two regions (same width class) in one launch: waves [0, leaves0) reduce region 0,
-// the rest region 1; each region runs its own leaves and binary tree (see the file comment).
-// slots: sum over levels of the node count, each width x NP doubles; counters: one int per
-// parent node (zero on entry).
+// ------------------------------------------------------------------ one workgroup per triangle (tree)
+//
+// The four waves of a workgroup share one triangle R and each holds a quarter
+// of the current block (BR rows per wave, so a block has 4 BR rows).  Column
+// step j: every wave forms its partial dot products d_k over its own rows, the
+// partials meet in LDS (one barrier; summed in wave order, so the result does
+// not depend on timing), every wave computes the same reflector scalars and
+// updates its own rows.  Row j of R is read by every wave during step j, so its
+// new values are written one step later, after the next barrier.
+
+constexpr int kTreeWaves = 4;
+
+template <int NP, typename Tacc>
+struct WgState {
+    Tacc *R;             // packed triangle (LDS)
+    Tacc *xb;            // this wave's broadcast slot, offset by the row set h
+    double (*red)[kTreeWaves][NP];
+    int k, h, wv, par;
+    int pend_row;        // row of R whose new values are still in pend_val (-1: none)
+    Tacc pend_val;
+};
+
+template <int NP, typename Tacc>
+__device__ inline void wg_flush(WgState<NP, Tacc> &st, int width)
+{
+    if (st.pend_row >= 0 && st.wv == 0 && st.h == 0 && st.k >= st.pend_row && st.k < width)
+        st.R[pidx(NP, st.pend_row, st.k)] = st.pend_val;
+    st.pend_row = -1;
+}
+
+// Absorb one block (this wave's RPT rows per lane in x) for columns [jstart, width).
+template <int NP, typename Tacc>
+__device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> &st, int jstart, int width)
+{
+    constexpr int RPT = WaveGeom<NP>::RPT;
+    const int k = st.k;
+    const bool col_ok = k < width;
+    for (int j = jstart; j < width; j++) {
+        __builtin_amdgcn_wave_barrier();
+        if (k == j) {
+#pragma unroll
+            for (int i = 0; i < RPT; i++) st.xb[i] = x[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        Tacc xj[RPT];
+#pragma unroll
+        for (int i = 0; i < RPT; i++) xj[i] = st.xb[i];
+        double dp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < RPT; i++) dp[i & 3] += (double)xj[i] * (double)x[i];
+        double d = (dp[0] + dp[1]) + (dp[2] + dp[3]);
+#pragma unroll
+        for (int off = NP; off < 64; off <<= 1) d += __shfl_xor(d, off, 64);
+        if (st.h == 0) st.red[st.par][st.wv][k] = d;
+        __syncthreads();
+        wg_flush(st, width);
+        double dk = 0.0, s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kTreeWaves; w++) {
+            dk += st.red[st.par][w][k];
+            s += st.red[st.par][w][j];
+        }
+        st.par ^= 1;
+        const double alpha = (double)st.R[pidx(NP, j, j)];
+        const Tacc rjk = (k > j && col_ok) ? st.R[pidx(NP, j, k)] : Tacc(0);
+        const double q = fma(alpha, alpha, s);
+        // A column whose norm is below the normal range is left untouched (tau = 0).
+        if (s > 0.0 && q >= DBL_MIN) {
+            const double r = rsq_refined(q);
+            const double sg = alpha >= 0.0 ? 1.0 : -1.0;
+            const double nrm = q * r;
+            const double beta = -sg * nrm;
+            const double inv_beta = -sg * r;
+            const double scl = rcp_refined(alpha + sg * nrm);
+            const double tau = 1.0 - alpha * inv_beta;
+            if (k > j && col_ok) {
+                const double w = (double)rjk + scl * dk;
+                st.pend_val = (Tacc)((double)rjk - tau * w);
+                const Tacc c = (Tacc)(w * inv_beta);
+#pragma unroll
+                for (int i = 0; i < RPT; i++) x[i] += c * xj[i];
+            } else if (k == j) {
+                st.pend_val = (Tacc)beta;
+            } else {
+                st.pend_val = Tacc(0);
+            }
+            st.pend_row = j;
+        }
+    }
+}
+
+// Absorb rows [r0, r1) of src in blocks of 4 BR rows (wave wv takes the wv-th quarter).
 template <int NP, typename Tin, typename Tacc>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_tree(TreeRegion reg0, TreeRegion reg1)
+__device__ inline void wg_absorb_rows(WgState<NP, Tacc> &st, const RowSrc &src, int64_t r0, int64_t r1,
+                                      int tri_rows, int width)
+{
+    constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR, BG = kTreeWaves * BR;
+    for (int64_t rb = r0; rb < r1; rb += BG) {
+        if (st.pend_row >= 0) {  // the block may start at the pending row: write it first
+            __syncthreads();
+            wg_flush(st, width);
+            __syncthreads();
+        }
+        Tacc x[RPT];
+#pragma unroll
+        for (int i = 0; i < RPT; i++) {
+            const int64_t r = rb + st.wv * BR + st.h * RPT + i;
+            x[i] = (r < r1 && st.k < width) ? load_src<Tin, Tacc>(src, r, st.k) : Tacc(0);
+        }
+        int jstart = src.col_off;
+        if (tri_rows > 0) {
+            const int64_t off = rb % tri_rows;
+            if (off + BG <= tri_rows) jstart += (int)off;
+        }
+        wg_block<NP, Tacc>(x, st, jstart, width);
+    }
+}
+
+template <int NP, typename Tacc>
+__device__ inline void wg_store(WgState<NP, Tacc> &st, double *out, int width)
+{
+    __syncthreads();
+    wg_flush(st, width);
+    __syncthreads();
+    for (int e = threadIdx.x; e < width * NP; e += 64 * kTreeWaves) {
+        const int j = e / NP, kk = e - j * NP;
+        out[e] = (kk >= j && kk < width) ? (double)st.R[pidx(NP, j, kk)] : 0.0;
+    }
+}
+
+template <int NP, typename Tacc>
+__device__ inline void wg_load_tri(WgState<NP, Tacc> &st, const double *T, int width)
+{
+    for (int e = threadIdx.x; e < WaveGeom<NP>::PS; e += 64 * kTreeWaves) st.R[e] = Tacc(0);
+    __syncthreads();
+    if (T) {
+        for (int e = threadIdx.x; e < width * NP; e += 64 * kTreeWaves) {
+            const int j = e / NP, kk = e - j * NP;
+            if (kk >= j && kk < width) st.R[pidx(NP, j, kk)] = (Tacc)T[e];
+        }
+    }
+    __syncthreads();
+}
+
+// Up to two regions (same width class) in one launch: workgroups [0, leaves0) reduce
+// region 0, the rest region 1.  Each region: one leaf triangle per workgroup, then a
+// tree of the region's arity; at each node the last child to arrive (per-node atomic
+// counter) combines all children in child order.  slots: the node triangles of every
+// level (width x NP doubles each); counters: one int per parent node, zero on entry.
+template <int NP, typename Tin, typename Tacc>
+__global__ __launch_bounds__(64 * kTreeWaves) void k_tsqr_tree(TreeRegion reg0, TreeRegion reg1)
 {
     using Gm = WaveGeom<NP>;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int gw = blockIdx.x * kWavesPerBlock + wv;
-    const int k = lane % NP, h = lane / NP;
-    __shared__ Tacc Rs[kWavesPerBlock][Gm::PS];
-    __shared__ __align__(16) Tacc Xs[kWavesPerBlock][Gm::BR];
-    const bool second = gw >= reg0.nleaves;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ Tacc Rs[Gm::PS];
+    __shared__ __align__(16) Tacc Xs[kTreeWaves][Gm::BR];
+    __shared__ double red[2][kTreeWaves][NP];
+    __shared__ int s_old;
+    int g = blockIdx.x;
+    const bool second = g >= reg0.nleaves;
     const TreeRegion rg = second ? reg1 : reg0;
-    if (second) gw -= reg0.nleaves;
-    if (gw >= rg.nleaves) return;
+    if (second) g -= reg0.nleaves;
     const int width = rg.width, nleaves = rg.nleaves;
-    Tacc *Rp = Rs[wv];
-    Tacc *xb = Xs[wv] + h * Gm::RPT;
-    wave_zero<NP, Tacc>(Rp, lane);
+    WgState<NP, Tacc> st;
+    st.R = Rs;
+    st.k = lane % NP;
+    st.h = lane / NP;
+    st.wv = wv;
+    st.xb = Xs[wv] + st.h * Gm::RPT;
+    st.red = red;
+    st.par = 0;
+    st.pend_row = -1;
+    st.pend_val = Tacc(0);
+    wg_load_tri<NP, Tacc>(st, nullptr, width);
+    constexpr int BG = kTreeWaves * Gm::BR;
     const int64_t rows = src_rows(rg.src);
     int64_t chunk = (rows + nleaves - 1) / nleaves;
-    chunk = ((chunk + Gm::BR - 1) / Gm::BR) * Gm::BR;
-    const int64_t r0 = (int64_t)gw * chunk, r1 = min(rows, r0 + chunk);
-    RowSrc none{};
-    wave_absorb_rows<NP, Tin, Tacc>(Rp, xb, rg.src, none, rows, r0, r1, 0, width, k, h);
+    chunk = ((chunk + BG - 1) / BG) * BG;
+    const int64_t r0 = (int64_t)g * chunk, r1 = min(rows, r0 + chunk);
+    wg_absorb_rows<NP, Tin, Tacc>(st, rg.src, r0, r1, 0, width);
 
     const int64_t tsz = (int64_t)width * NP;
     const int A = rg.arity;
-    int node = gw, n = nleaves;
+    int node = g, n = nleaves;
     int64_t soff = 0, coff = 0;
     while (n > 1) {
         const int parent = node / A, first = parent * A;
         const int nchild = min(A, n - first);
         if (nchild > 1) {
-            wave_store<NP, Tacc>(Rp, rg.slots + (soff + node) * tsz, width, lane);
-            __threadfence();
-            int old = 0;
-            if (lane == 0)
-                old = __hip_atomic_fetch_add(&rg.counters[coff + parent], 1, __ATOMIC_ACQ_REL,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-            old = __builtin_amdgcn_readfirstlane(old);
-            if (old != nchild - 1) return;  // the last child to arrive combines this node
-            __threadfence();
+            wg_store<NP, Tacc>(st, rg.slots + (soff + node) * tsz, width);
+            __syncthreads();
+            if (tid == 0) {
+                __threadfence();
+                s_old = __hip_atomic_fetch_add(&rg.counters[coff + parent], 1, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                __threadfence();
+            }
+            __syncthreads();
+            if (s_old != nchild - 1) return;  // the last child to arrive combines this node
             // R <- first child; absorb the others, stacked in child order.
-            wave_init_tri<NP, Tacc>(Rp, rg.slots + (soff + first) * tsz, NP, width, lane);
-            const RowSrc sib{rg.slots + (soff + first + 1) * tsz, nullptr, (int64_t)(nchild - 1) * width, NP,
-                             0, width};
-            wave_absorb_rows<NP, double, Tacc>(Rp, xb, sib, none, sib.rows_host, 0, sib.rows_host, width,
-                                               width, k, h);
+            wg_load_tri<NP, Tacc>(st, rg.slots + (soff + first) * tsz, width);
+            const RowSrc sib{rg.slots + (soff + first + 1) * tsz, nullptr, (int64_t)(nchild - 1) * width, NP, 0,
+                             width};
+            wg_absorb_rows<NP, double, Tacc>(st, sib, 0, sib.rows_host, width, width);
         }
         node = parent;
         soff += n;
         coff += (n + A - 1) / A;
         n = (n + A - 1) / A;
     }
-    wave_store<NP, Tacc>(Rp, rg.root, width, lane);
+    wg_store<NP, Tacc>(st, rg.root, width);
 }
 
 __global__ void k_sign_normalise(const double *Rin, int64_t ldin, int n, double *R, int64_t ldr)
@@ -368,9 +523,8 @@ hipError_t launch_tree_np(int acc_f64, int in_f64, const TreeRegion *regs, int n
 {
     TreeRegion r0 = regs[0];
     TreeRegion r1 = nreg > 1 ? regs[1] : TreeRegion{};
-    const int waves = r0.nleaves + r1.nleaves;
-    const unsigned grid = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-#define FIGARO_TREE(TI, TA) k_tsqr_tree<NP, TI, TA><<<grid, 64 * kWavesPerBlock, 0, s>>>(r0, r1)
+    const unsigned grid = (unsigned)(r0.nleaves + r1.nleaves);
+#define FIGARO_TREE(TI, TA) k_tsqr_tree<NP, TI, TA><<<grid, 64 * kTreeWaves, 0, s>>>(r0, r1)
     if (acc_f64) {
         if (in_f64) FIGARO_TREE(double, double);
         else FIGARO_TREE(float, double);
@@ -394,13 +548,13 @@ int tsqr_padded_width(int n)
 
 int tsqr_block_rows(int np, int acc_f64)
 {
-    if (np <= 64) return wave_block_rows(np);  // wave kernel: row sets x rows per lane
-    return tsqr_panel_rows(np, acc_f64);      // workgroup panel kernel
+    if (np <= 64) return kTreeWaves * wave_block_rows(np);  // tree kernel: 4 waves x row sets x rows per lane
+    return tsqr_panel_rows(np, acc_f64);                   // workgroup panel kernel
 }
 
 int tsqr_tree_arity(int np, int width)
 {
-    const int a = 1 + wave_block_rows(np) / (width > 0 ? width : 1);
+    const int a = 1 + kTreeWaves * wave_block_rows(np) / (width > 0 ? width : 1);
     return a < 2 ? 2 : (a > 32 ? 32 : a);
 }
 
