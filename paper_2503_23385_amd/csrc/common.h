@@ -107,7 +107,8 @@ hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *ini
 // counters (zero on entry) live in `counters`; the region's triangle lands in root.
 struct TreeRegion {
     RowSrc src;
-    int32_t width, nleaves, arity;
+    int32_t width, nleaves, arity;  // nleaves: the most leaves (slots and counters are sized for it)
+    int64_t rows_per_leaf;          // leaves used = min(nleaves, ceil(rows / rows_per_leaf)), at least 1
     double *slots;
     int32_t *counters;
     double *root;
@@ -118,6 +119,10 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
 // out (na + nb rows, ld ldo) <- the upper triangular block diagonal [Ta 0; 0 Tb].
 hipError_t launch_block_diag(const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
                              double *out, int64_t ldo, hipStream_t s);
+// Wide regions (padded widths 128..512): in-kernel binary tree over panel-kernel leaves,
+// one or two regions of the same padded width per launch.
+hipError_t launch_tsqr_panel_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s);
+void tsqr_panel_tree_sizes(int nleaves, int64_t *slots, int64_t *counters);
 hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,
                                  int64_t ldr, hipStream_t s);
 

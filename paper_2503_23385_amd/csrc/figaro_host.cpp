@@ -104,7 +104,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kPrecMask = 0xff;
 constexpr int kMaxTreeLeaves = 2048;
-constexpr int kTreeArityWG = 4;
+constexpr int kMaxPanelLeaves = 128;
 constexpr int kPlanLanes = 8;  // parallel branches of a batched plan's graph
 
 struct Shape {
@@ -124,11 +124,11 @@ struct Region {
     int64_t rows_cap;
     int cnt;
     int width, col_off, np;
-    bool wave;                // in-kernel tree (np <= 64)
+    bool wave;                // narrow tree kernel (np <= 64); else the panel tree kernel
     bool skip;                // rows absorbed directly by the root merge (no tree of its own)
-    int leaves, arity;
-    std::vector<int> levels;  // workgroup tree levels (wave == false)
-    size_t slots, counters, root, tri[2];
+    int leaves, arity;        // most leaves; tree arity
+    int64_t rows_per_leaf;    // leaves follow the device row count: ceil(rows / rows_per_leaf)
+    size_t slots, counters, root;
     int64_t ncounters;
 };
 
@@ -213,22 +213,16 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     r.np = tsqr_padded_width(width);
     r.wave = r.np <= 64;
     const int br = tsqr_block_rows(r.np, acc_f64);
-    // Leaves of a few blocks each (tunable through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS).
+    // Leaves of a few blocks each (tunable through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS);
+    // the wide tree keeps at most one leaf per compute unit and a half.
     static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 2);
     static const int wg_blocks = env_int("FIGARO_WG_LEAF_BLOCKS", 4);
-    const int64_t per = (r.wave ? wave_blocks : wg_blocks) * (int64_t)br;
-    const int64_t leaves = (r.rows_cap + per - 1) / per;
-    r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxTreeLeaves));
+    r.rows_per_leaf = (int64_t)(r.wave ? wave_blocks : wg_blocks) * br;
+    const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+    r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, r.wave ? kMaxTreeLeaves : kMaxPanelLeaves));
     r.ncounters = 0;
     r.skip = false;
-    r.arity = r.wave ? tsqr_tree_arity(r.np, width) : kTreeArityWG;
-    if (!r.wave) {
-        int cur = r.leaves;
-        while (cur > 1) {
-            cur = (cur + kTreeArityWG - 1) / kTreeArityWG;
-            r.levels.push_back(cur);
-        }
-    }
+    r.arity = r.wave ? tsqr_tree_arity(r.np, width) : 2;
     return r;
 }
 
@@ -297,20 +291,13 @@ Layout make_layout(const Shape &s)
     int64_t ctot = 0;
     for (Region &r : L.regions) {
         const size_t tsz = sizeof(double) * (size_t)r.width * r.np;
-        if (r.wave) {
-            int64_t ns, nc;
-            tsqr_tree_sizes(r.leaves, r.arity, &ns, &nc);
-            r.slots = take(tsz * ns);
-            r.ncounters = nc;
-            r.counters = (size_t)ctot;  // index into the shared counter block
-            ctot += nc;
-            r.tri[0] = r.tri[1] = 0;
-        } else {
-            r.slots = 0;
-            r.counters = 0;
-            r.tri[0] = take(tsz * r.leaves);
-            r.tri[1] = take(tsz * (r.levels.empty() ? 1 : r.levels[0]));
-        }
+        int64_t ns = 0, nc = 0;
+        if (r.wave) tsqr_tree_sizes(r.leaves, r.arity, &ns, &nc);
+        else tsqr_panel_tree_sizes(r.leaves, &ns, &nc);
+        r.slots = take(tsz * ns);
+        r.ncounters = nc;
+        r.counters = (size_t)ctot;  // index into the shared counter block
+        ctot += nc;
         r.root = take(tsz);
     }
     L.counters_total = ctot;
@@ -429,42 +416,14 @@ TreeRegion tree_region(const Region &r, const Layout &L, void *ws)
     t.width = r.width;
     t.nleaves = r.leaves;
     t.arity = r.arity;
+    t.rows_per_leaf = r.rows_per_leaf;
     t.slots = at<double>(ws, r.slots);
     t.counters = at<int32_t>(ws, L.counters_base) + r.counters;
     t.root = at<double>(ws, r.root);
     return t;
 }
 
-// Reduce one region to its triangle (FP64, width rows x np at r.root) with the workgroup
-// kernel: leaves, then levels of kTreeArityWG, the last level into root.
-int run_region_wg(const Region &r, const Layout &L, int acc_f64, void *ws, hipStream_t s)
-{
-    Groups g = groups_of(ws, L);
-    RowSrc src{at<void>(ws, r.buf), g.counts + r.cnt, 0, r.width, 0, r.width};
-    RowSrc none{};
-    double *root = at<double>(ws, r.root);
-    const int64_t tsz = (int64_t)r.width * r.np;
-    Stage st(r.name, s);
-    double *cur = r.levels.empty() ? root : at<double>(ws, r.tri[0]);
-    HIPCHK(launch_tsqr_stream(r.np, acc_f64, L.m_f64, nullptr, 0, src, none, 1, r.width, 0,
-                              r.leaves, cur, tsz, s),
-           "tsqr leaves");
-    int count = r.leaves, which = 0;
-    for (size_t i = 0; i < r.levels.size(); i++) {
-        const int nwg = r.levels[i];
-        double *nxt = (i + 1 == r.levels.size()) ? root : at<double>(ws, r.tri[which ^ 1]);
-        RowSrc lv{cur, nullptr, (int64_t)count * r.width, r.np, 0, r.width};
-        HIPCHK(launch_tsqr_stream(r.np, acc_f64, 1, nullptr, 0, lv, none, 1, r.width, r.width, nwg,
-                                  nxt, tsz, s),
-               "tsqr tree level");
-        cur = nxt;
-        which ^= 1;
-        count = nwg;
-    }
-    return FIGARO_OK;
-}
-
-// All regions: wave-tree regions of equal padded width share one launch.
+// All regions, each by its in-kernel tree; regions of equal padded width share a launch.
 int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
 {
     const size_t nr = L.regions.size();
@@ -474,23 +433,19 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
         const Region &r = L.regions[i];
         done[i] = true;
         if (r.skip) continue;
-        if (!r.wave) {
-            int rc = run_region_wg(r, L, acc_f64, ws, s);
-            if (rc) return rc;
-            continue;
-        }
         TreeRegion tr[2] = {tree_region(r, L, ws), TreeRegion{}};
         int n = 1;
         const char *name = r.name;
         for (size_t j = i + 1; j < nr && n < 2; j++) {
-            if (!done[j] && !L.regions[j].skip && L.regions[j].wave && L.regions[j].np == r.np) {
+            if (!done[j] && !L.regions[j].skip && L.regions[j].np == r.np) {
                 tr[n++] = tree_region(L.regions[j], L, ws);
                 done[j] = true;
                 name = "tsqr_tails";
             }
         }
         Stage st(name, s);
-        HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr tree");
+        if (r.wave) HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr tree");
+        else HIPCHK(launch_tsqr_panel_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr panel tree");
     }
     return FIGARO_OK;
 }

@@ -107,43 +107,50 @@ struct PanelGeom {
     static constexpr int RPL = RPW / 4;  // rows per lane in the panel step (4 row quarters per wave)
 };
 
+// LDS of one workgroup of the panel kernels.
+template <int NP, typename Tacc>
+struct PanelLds {
+    using Gm = PanelGeom<NP, Tacc>;
+    Tacc X[Gm::B * Gm::LDX];
+    double Rpan[KB][KB + 1];  // the panel's diagonal block of R on entry (read only)
+    double Rfin[KB][KB + 1];  // its rows once final (row j is final after column j)
+    double red[2][4][KB];
+    double tau[KB];
+    double T[KB][KB + 1];
+    double zb[4][KB][KB + 1];
+    Tacc wb[4][KB][KB + 1];
+    int flag;
+};
+
+// R (width rows x NP, FP64, global) <- init (or zero).
+template <int NP>
+__device__ inline void panel_set(double *R, const double *init, int64_t init_ld, int width)
+{
+    for (int e = threadIdx.x; e < width * NP; e += kPanelThreads) {
+        const int j = e / NP, k = e - j * NP;
+        R[e] = (init && k >= j && k < width) ? init[(int64_t)j * init_ld + k] : 0.0;
+    }
+}
+
+// R absorbs rows [r_begin, r_end) of s0 then s1 (rows0 rows in s0), blocks of B rows.
 template <int NP, typename Tin, typename Tacc>
-__global__ __launch_bounds__(kPanelThreads) void k_tsqr_panel(const double *init, int64_t init_ld, RowSrc s0,
-                                                              RowSrc s1, int nsrc, int width, int tri_rows,
-                                                              double *tri_out, int64_t tri_stride)
+__device__ void panel_absorb(PanelLds<NP, Tacc> &L, double *R, const RowSrc &s0, const RowSrc &s1, int64_t rows0,
+                             int64_t r_begin, int64_t r_end, int tri_rows, int width)
 {
     using Gm = PanelGeom<NP, Tacc>;
     using V4 = typename Vec4<Tacc>::type;
     constexpr int B = Gm::B, LDX = Gm::LDX, RPW = Gm::RPW, RPL = Gm::RPL;
-    __shared__ Tacc X[B * LDX];
-    __shared__ double Rpan[KB][KB + 1];  // the panel's diagonal block of R on entry (read only)
-    __shared__ double Rfin[KB][KB + 1];  // its rows once final (row j is final after column j)
-    __shared__ double red[2][4][KB];
-    __shared__ double tau[KB];
-    __shared__ double T[KB][KB + 1];
-    __shared__ double zb[4][KB][KB + 1];
-    __shared__ Tacc wb[4][KB][KB + 1];
-    static_assert(sizeof(X) + sizeof(Rpan) + sizeof(Rfin) + sizeof(red) + sizeof(tau) + sizeof(T) + sizeof(zb) + sizeof(wb) <=
-                      160 * 1024,
-                  "LDS budget");
-
+    Tacc *X = L.X;
+    auto &Rpan = L.Rpan;
+    auto &Rfin = L.Rfin;
+    auto &red = L.red;
+    auto &tau = L.tau;
+    auto &T = L.T;
+    auto &zb = L.zb;
+    auto &wb = L.wb;
+    int par = 0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
-    double *R = tri_out + (int64_t)blockIdx.x * tri_stride;  // width rows x NP
-
-    for (int e = tid; e < width * NP; e += kPanelThreads) {
-        const int j = e / NP, k = e - j * NP;
-        R[e] = (init && k >= j && k < width) ? init[(int64_t)j * init_ld + k] : 0.0;
-    }
-    const int64_t rows0 = rows_of(s0);
-    const int64_t total = rows0 + (nsrc > 1 ? rows_of(s1) : 0);
-    int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
-    chunk = ((chunk + B - 1) / B) * B;
-    const int64_t r_begin = (int64_t)blockIdx.x * chunk;
-    const int64_t r_end = min(total, r_begin + chunk);
-    __syncthreads();
-
-    int par = 0;
     for (int64_t rb = r_begin; rb < r_end; rb += B) {
         for (int e = tid; e < B * NP; e += kPanelThreads) {
             const int i = e / NP, c = e - i * NP;
@@ -308,6 +315,90 @@ __global__ __launch_bounds__(kPanelThreads) void k_tsqr_panel(const double *init
     }
 }
 
+template <int NP, typename Tin, typename Tacc>
+__global__ __launch_bounds__(kPanelThreads) void k_tsqr_panel(const double *init, int64_t init_ld, RowSrc s0,
+                                                              RowSrc s1, int nsrc, int width, int tri_rows,
+                                                              double *tri_out, int64_t tri_stride)
+{
+    __shared__ PanelLds<NP, Tacc> L;
+    static_assert(sizeof(PanelLds<NP, Tacc>) <= 160 * 1024, "LDS budget");
+    double *R = tri_out + (int64_t)blockIdx.x * tri_stride;  // width rows x NP
+    panel_set<NP>(R, init, init_ld, width);
+    const int64_t rows0 = rows_of(s0);
+    const int64_t total = rows0 + (nsrc > 1 ? rows_of(s1) : 0);
+    int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+    chunk = ((chunk + PanelGeom<NP, Tacc>::B - 1) / PanelGeom<NP, Tacc>::B) * PanelGeom<NP, Tacc>::B;
+    const int64_t r_begin = (int64_t)blockIdx.x * chunk;
+    const int64_t r_end = min(total, r_begin + chunk);
+    __syncthreads();
+    panel_absorb<NP, Tin, Tacc>(L, R, s0, s1, rows0, r_begin, r_end, tri_rows, width);
+}
+
+// Up to two regions of the same padded width in one launch, each reduced by an in-kernel
+// binary tree.  The number of leaves follows the region's row count on the device:
+// min(nleaves, ceil(rows / rows_per_leaf)); the remaining workgroups leave at once.
+// Leaf g reduces its rows into slot g of level 0; at each node the last child to arrive
+// (per-node atomic counter) writes the parent: the first child's triangle absorbing the
+// second's.  A lone child is copied up.  The last level's triangle is copied to root.
+template <int NP, typename Tin, typename Tacc>
+__global__ __launch_bounds__(kPanelThreads) void k_tsqr_panel_tree(TreeRegion reg0, TreeRegion reg1)
+{
+    __shared__ PanelLds<NP, Tacc> L;
+    static_assert(sizeof(PanelLds<NP, Tacc>) <= 160 * 1024, "LDS budget");
+    constexpr int B = PanelGeom<NP, Tacc>::B;
+    int g = blockIdx.x;
+    const bool second = g >= reg0.nleaves;
+    const TreeRegion rg = second ? reg1 : reg0;
+    if (second) g -= reg0.nleaves;
+    const int width = rg.width;
+    const int64_t rows = rows_of(rg.src);
+    const int64_t want = (rows + rg.rows_per_leaf - 1) / rg.rows_per_leaf;
+    const int nleaves = (int)max((int64_t)1, min((int64_t)rg.nleaves, want));
+    if (g >= nleaves) return;
+    const int64_t tsz = (int64_t)width * NP;
+    int64_t chunk = (rows + nleaves - 1) / nleaves;
+    chunk = ((chunk + B - 1) / B) * B;
+    const int64_t r_begin = (int64_t)g * chunk, r_end = min(rows, r_begin + chunk);
+    double *R = rg.slots + (int64_t)g * tsz;
+    panel_set<NP>(R, nullptr, 0, width);
+    __syncthreads();
+    const RowSrc none{};
+    panel_absorb<NP, Tin, Tacc>(L, R, rg.src, none, rows, r_begin, r_end, 0, width);
+
+    int node = g, n = nleaves;
+    int64_t soff = 0, coff = 0;
+    while (n > 1) {
+        const int parent = node >> 1, first = parent << 1;
+        const int nchild = min(2, n - first);
+        double *P = rg.slots + (soff + n + parent) * tsz;
+        if (nchild > 1) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __threadfence();
+                L.flag = __hip_atomic_fetch_add(&rg.counters[coff + parent], 1, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                __threadfence();
+            }
+            __syncthreads();
+            if (L.flag != 1) return;  // the last child to arrive combines this node
+            panel_set<NP>(P, rg.slots + (soff + first) * tsz, NP, width);
+            __syncthreads();
+            const RowSrc sib{rg.slots + (soff + first + 1) * tsz, nullptr, width, NP, 0, width};
+            panel_absorb<NP, double, Tacc>(L, P, sib, none, width, 0, width, width, width);
+        } else {
+            __syncthreads();
+            for (int e = threadIdx.x; e < tsz; e += kPanelThreads) P[e] = R[e];
+        }
+        R = P;
+        node = parent;
+        soff += n;
+        coff += (n + 1) / 2;
+        n = (n + 1) / 2;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < tsz; e += kPanelThreads) rg.root[e] = R[e];
+}
+
 template <int NP>
 hipError_t launch_panel_np(int acc_f64, int in_f64, const double *init, int64_t init_ld, RowSrc s0, RowSrc s1,
                            int nsrc, int width, int tri_rows, int nwg, double *tri, int64_t stride, hipStream_t s)
@@ -325,7 +416,49 @@ hipError_t launch_panel_np(int acc_f64, int in_f64, const double *init, int64_t 
     return hipGetLastError();
 }
 
+template <int NP>
+hipError_t launch_panel_tree_np(int acc_f64, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s)
+{
+    TreeRegion r0 = regs[0];
+    TreeRegion r1 = nreg > 1 ? regs[1] : TreeRegion{};
+    const unsigned grid = (unsigned)(r0.nleaves + r1.nleaves);
+#define FIGARO_PTREE(TI, TA) k_tsqr_panel_tree<NP, TI, TA><<<grid, kPanelThreads, 0, s>>>(r0, r1)
+    if (acc_f64) {
+        if (in_f64) FIGARO_PTREE(double, double);
+        else FIGARO_PTREE(float, double);
+    } else {
+        if (in_f64) FIGARO_PTREE(double, float);
+        else FIGARO_PTREE(float, float);
+    }
+#undef FIGARO_PTREE
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_tsqr_panel_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s)
+{
+    if (nreg < 1 || nreg > 2) return hipErrorInvalidValue;
+    switch (np) {
+    case 128: return launch_panel_tree_np<128>(acc_f64, in_f64, regs, nreg, s);
+    case 256: return launch_panel_tree_np<256>(acc_f64, in_f64, regs, nreg, s);
+    case 512: return launch_panel_tree_np<512>(acc_f64, in_f64, regs, nreg, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+void tsqr_panel_tree_sizes(int nleaves, int64_t *slots, int64_t *counters)
+{
+    int64_t sl = 0, c = 0;
+    int n = nleaves;
+    while (n > 1) {
+        sl += n;
+        c += (n + 1) / 2;
+        n = (n + 1) / 2;
+    }
+    *slots = sl + 1;  // every level's nodes plus the last level's single node
+    *counters = c + 1;
+}
 
 int tsqr_panel_rows(int np, int acc_f64)
 {

@@ -419,7 +419,12 @@ __global__ __launch_bounds__(64 * kTreeWaves) void k_tsqr_tree(TreeRegion reg0, 
     const bool second = g >= reg0.nleaves;
     const TreeRegion rg = second ? reg1 : reg0;
     if (second) g -= reg0.nleaves;
-    const int width = rg.width, nleaves = rg.nleaves;
+    const int width = rg.width;
+    const int64_t rows = src_rows(rg.src);
+    // leaves follow the device-side row count; surplus workgroups leave at once
+    const int64_t want = (rows + rg.rows_per_leaf - 1) / rg.rows_per_leaf;
+    const int nleaves = (int)max((int64_t)1, min((int64_t)rg.nleaves, want));
+    if (g >= nleaves) return;
     WgState<NP, Tacc> st;
     st.R = Rs;
     st.k = lane % NP;
@@ -432,7 +437,6 @@ __global__ __launch_bounds__(64 * kTreeWaves) void k_tsqr_tree(TreeRegion reg0, 
     st.pend_val = Tacc(0);
     wg_load_tri<NP, Tacc>(st, nullptr, width);
     constexpr int BG = kTreeWaves * Gm::BR;
-    const int64_t rows = src_rows(rg.src);
     int64_t chunk = (rows + nleaves - 1) / nleaves;
     chunk = ((chunk + BG - 1) / BG) * BG;
     const int64_t r0 = (int64_t)g * chunk, r1 = min(rows, r0 + chunk);
