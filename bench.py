@@ -100,6 +100,18 @@ def prefix_instance(inst, frac):
     return W.Instance(np.ascontiguousarray(inst.A[:m1]), np.ascontiguousarray(inst.B[:m2]), kA, kB)
 
 
+def sigma_lanes(n):
+    npc = 8
+    while npc < n:
+        npc *= 2
+    return min(16, 1024 // npc)
+
+
+def sigma_rounds(n):
+    t = sigma_lanes(n)
+    return 14 if t >= 16 else 18 if t >= 8 else 24 if t >= 4 else 56
+
+
 def stage_work(inst, two_sided, precision, sweeps):
     """Algorithmic work of each single-kernel stage: (bound, amount in GB or TFLOP)."""
     m1g, m2g = group_sizes(inst)
@@ -116,6 +128,9 @@ def stage_work(inst, two_sided, precision, sweeps):
         "tsqr_tails": ("alu", flops(TA, n1) + flops(R2, n2)),
         # one sweep: n(n-1)/2 pairs, 3 dot products and a rotation of two n-vectors (12 n flops)
         "jacobi": ("alu", 6.0 * N * N * (N - 1) * sweeps / 1e12),
+        # bidiagonalisation (8 n^3 / 3) + Sturm counts (n values x lanes x rounds x 2n steps x 3 flops)
+        "sigma": ("alu", (8.0 * N ** 3 / 3 + N * sigma_lanes(N) * sigma_rounds(N) * 2 * N * 3) / 1e12
+                  if N <= 128 else 6.0 * N * N * (N - 1) * sweeps / 1e12),
     }
     return work
 
@@ -126,6 +141,7 @@ STAGE_KERNELS = {
     "tsqr_m1": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
     "tsqr_m2": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
     "jacobi": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_jacobi_lds"),
+    "sigma": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_sigma_gk"),
 }
 
 
@@ -157,8 +173,8 @@ def roofline(form, work, precision):
     if bound == "hbm":
         return {"kernel": dom, "bound": "hbm", "achieved": amount / t, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": amount / t / PEAK_HBM_GBS, "traffic": None, "launch_ms": per_launch_ms}
-    # the FP32 forms' TSQR runs in FP32; Jacobi always runs in FP64
-    peak = PEAK_FP64_TFLOPS if (dom == "jacobi" or precision == "fp64") else PEAK_FP32_TFLOPS
+    # the FP32 forms' TSQR runs in FP32; sigma always runs in FP64
+    peak = PEAK_FP64_TFLOPS if (dom in ("jacobi", "sigma") or precision == "fp64") else PEAK_FP32_TFLOPS
     return {"kernel": dom, "bound": "alu", "achieved": amount / t, "peak": peak, "unit": "TFLOP/s",
             "frac": amount / t / peak, "traffic": None, "launch_ms": per_launch_ms}
 

@@ -153,13 +153,14 @@ int figaro_inspect(const figaro_table *A, const figaro_table *B, int32_t precisi
 int figaro_sigma_workspace_size(int64_t n, size_t *bytes);
 
 /*
- * Singular values of an upper-triangular R (equal to those of the join
- * matrix; Related Works: SVD through QR) by one-sided Jacobi in FP64:
- * Hestenes rotations on column pairs in a parallel (round-robin) order until
- * a sweep finds every pair orthogonal to |c_p . c_q| <= n 2^-53 |c_p||c_q|
- * (at most 60 sweeps).  n <= 128: one workgroup with R in LDS; 128 < n <= 512:
- * block Jacobi over blocks of 16 columns, one workgroup per block pair, with
- * bounded grid-wide waits between rounds.
+ * Singular values of R (equal to those of the join matrix; Related Works: SVD
+ * through QR) by one-sided (Hestenes) Jacobi in FP64: rotations on column
+ * pairs in a parallel (round-robin) order until a sweep finds every pair
+ * orthogonal to |c_p . c_q| <= n 2^-53 |c_p||c_q| (at most 60 sweeps).
+ * n <= 128: one workgroup with R in LDS; 128 < n <= 512: block Jacobi over
+ * blocks of 16 columns, one workgroup per block pair, with bounded grid-wide
+ * waits between rounds.  R is scaled by a power of two first (exact), so
+ * squared norms stay in range.
  *   R      device, FP64, n x n, leading dimension ldr (any square matrix is accepted).
  *   sigma  device, FP64, n values, descending (NaN if a bounded wait expired).
  *   ws     device workspace of figaro_sigma_workspace_size() bytes, 256-byte
@@ -168,6 +169,19 @@ int figaro_sigma_workspace_size(int64_t n, size_t *bytes);
  */
 int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma,
                  void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The same singular values by the route of a dense SVD (the paper's SVD of R):
+ * Householder bidiagonalisation B = U^T R V in one workgroup (R in LDS;
+ * reflector j on column j, then on row j, with the TSQR's reflector
+ * conventions), then the singular values of the bidiagonal as the positive
+ * eigenvalues of its Golub-Kahan tridiagonal (zero diagonal, off-diagonals
+ * d1, e1, d2, ...) by multisection on Sturm counts, to an interval below
+ * 2^-53 of the Gershgorin bound.  n <= 128 (FIGARO_EINVAL above).  Arguments,
+ * workspace and errors as figaro_sigma (the sweep count is set to 0).
+ */
+int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma,
+                        void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Synchronous: waits for `stream`, then reads the device status word left in

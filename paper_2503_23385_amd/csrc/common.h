@@ -116,6 +116,10 @@ struct TreeRegion {
 // One launch for one or two regions of the same padded width np (np <= 64).
 hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
                             hipStream_t s);
+// One wave absorbs the (few) rows of src into the triangle init (width rows, ld init_ld);
+// padded width np <= 64; the result (width x np, FP64) goes to out.
+hipError_t launch_tsqr_few(int np, const double *init, int64_t init_ld, RowSrc src, int in_f64, int width,
+                           double *out, hipStream_t s);
 // out (na + nb rows, ld ldo) <- the upper triangular block diagonal [Ta 0; 0 Tb].
 hipError_t launch_block_diag(const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
                              double *out, int64_t ldo, hipStream_t s);
@@ -143,5 +147,7 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
 int64_t jacobi_scratch_doubles(int n);
 hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                          int32_t *ctrl, double *scratch, hipStream_t s);
+// The bidiagonal route for n <= 128: bidiagonalisation + multisection (ctrl[0] = 0 sweeps).
+hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, double *sigma, int32_t *ctrl, hipStream_t s);
 
 }  // namespace figaro

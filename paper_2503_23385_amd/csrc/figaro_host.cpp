@@ -478,9 +478,12 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
         Groups g = groups_of(ws, L);
         const RowSrc heads = r0.skip ? RowSrc{at<void>(ws, r0.buf), g.counts + CNT_G, 0, N, 0, N}
                                      : RowSrc{cur, nullptr, N, r0.np, 0, N};
-        HIPCHK(launch_tsqr_stream(L.np_root, 1, r0.skip ? L.m_f64 : 1, init, L.np_root, heads, none, 1, N,
-                                  r0.skip ? 0 : N, 1, out, (int64_t)N * L.np_root, s),
-               "tsqr merge");
+        if (r0.skip && L.np_root <= 64)  // a Cartesian product has a single head row
+            HIPCHK(launch_tsqr_few(L.np_root, init, L.np_root, heads, L.m_f64, N, out, s), "tsqr merge");
+        else
+            HIPCHK(launch_tsqr_stream(L.np_root, 1, r0.skip ? L.m_f64 : 1, init, L.np_root, heads, none, 1, N,
+                                      r0.skip ? 0 : N, 1, out, (int64_t)N * L.np_root, s),
+                   "tsqr merge");
         cur = out;
         cur_ld = L.np_root;
     } else {
@@ -596,8 +599,9 @@ int figaro_sigma_workspace_size(int64_t n, size_t *bytes)
     return FIGARO_OK;
 }
 
-int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,
-                 void *stream)
+namespace {
+
+int sigma_common(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes)
 {
     if (n < 1 || n > FIGARO_MAX_N) return fail(FIGARO_EINVAL, "n out of range");
     if (!R || !sigma) return fail(FIGARO_EINVAL, "R or sigma is NULL");
@@ -607,10 +611,32 @@ int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma, void *w
     size_t need = 0;
     figaro_sigma_workspace_size(n, &need);
     if (ws_bytes < need) return fail(FIGARO_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    return FIGARO_OK;
+}
+
+}  // namespace
+
+int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,
+                 void *stream)
+{
+    int rc = sigma_common(R, n, ldr, sigma, ws, ws_bytes);
+    if (rc) return rc;
     Stage st("jacobi", (hipStream_t)stream);
     double *scratch = jacobi_scratch_doubles((int)n) ? at<double>(ws, kAlign) : nullptr;
     hipError_t e = launch_jacobi(R, (int)n, ldr, sigma, 60, (int32_t *)ws, scratch, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "jacobi");
+    return FIGARO_OK;
+}
+
+int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    int rc = sigma_common(R, n, ldr, sigma, ws, ws_bytes);
+    if (rc) return rc;
+    if (n > 128) return fail(FIGARO_EINVAL, "the bidiagonal route takes n <= 128");
+    Stage st("sigma_bidiag", (hipStream_t)stream);
+    hipError_t e = launch_sigma_bidiag(R, (int)n, ldr, sigma, (int32_t *)ws, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sigma (bidiagonal route)");
     return FIGARO_OK;
 }
 
@@ -706,8 +732,7 @@ int plan_enqueue(figaro_plan *plan, void *ws, double *R, double *sigma, hipStrea
         void *lws = (char *)ws + (size_t)l * plan->lane_bytes;
         int rc = run_r(&plan->inst[i].A, &plan->inst[i].B, sh, plan->layouts[i], R + plan->r_off[i], N, lws, ls);
         if (rc) return rc;
-        hipError_t e = launch_jacobi(R + plan->r_off[i], (int)N, N, sigma + plan->s_off[i], 60,
-                                     nullptr, nullptr, ls);
+        hipError_t e = launch_jacobi(R + plan->r_off[i], (int)N, N, sigma + plan->s_off[i], 60, nullptr, nullptr, ls);
         if (e != hipSuccess) return hip_fail(e, "jacobi");
     }
     for (int l = 0; l < plan->nlanes; l++) {

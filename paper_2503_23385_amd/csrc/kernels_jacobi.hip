@@ -19,6 +19,9 @@
 // its two columns in registers for the whole step; the three dot products are
 // reduced with DPP moves inside the group; one workgroup barrier separates the
 // steps.  The width is a template parameter so every loop over rows is unrolled.
+#include <float.h>
+#include <limits.h>
+
 #include "common.h"
 
 namespace figaro {
@@ -108,6 +111,21 @@ void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sw
     const double tol2 = ((double)n * 0x1p-53) * ((double)n * 0x1p-53);
     constexpr int M = NPC - 1;
     int sweeps = 0;
+    // Scale by a power of two so that the largest |entry| lies in [1, 2): squared norms stay in range.
+    __shared__ int s_exp;
+    if (tid == 0) s_exp = INT_MIN;
+    __syncthreads();
+    {
+        double m = 0.0;
+        for (int e = tid; e < NPC * NPC; e += nthr) m = fmax(m, fabs(C[(e / NPC) * LDC + e % NPC]));
+        if (m > 0.0) atomicMax(&s_exp, ilogb(m));
+    }
+    __syncthreads();
+    const int ex = s_exp == INT_MIN ? 0 : s_exp;
+    for (int e = tid; e < NPC * NPC; e += nthr) {
+        double &x = C[(e / NPC) * LDC + e % NPC];
+        x = ldexp(x, -ex);
+    }
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; sweep++) {
         if (tid == 0) s_rot = 0;
@@ -159,7 +177,7 @@ void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sw
     for (int k = tid; k < n; k += nthr) {
         double acc = 0.0;
         for (int i = 0; i < NPC; i++) acc += C[k * LDC + i] * C[k * LDC + i];
-        sv[k] = sqrt(acc);
+        sv[k] = ldexp(sqrt(acc), ex);
     }
     __syncthreads();
     for (int k = tid; k < n; k += nthr) {
@@ -196,7 +214,7 @@ hipError_t launch_npc(const double *R, int n, int64_t ldr, double *sigma, int ma
 
 constexpr int kBlk = 16;            // columns per block
 constexpr int kBlkThreads = 256;    // 16 pairs x 16 lanes
-enum : int { CTRL_SWEEPS = 0, CTRL_BAR = 1, CTRL_FLAG = 2, CTRL_TIMEOUT = 5, CTRL_WORDS = 8 };
+enum : int { CTRL_SWEEPS = 0, CTRL_BAR = 1, CTRL_FLAG = 2, CTRL_TIMEOUT = 5, CTRL_EXP = 6, CTRL_WORDS = 8 };
 constexpr int kSpinLimit = 1 << 22;
 
 __global__ void k_jacobi_blk_init(const double *R, int n, int64_t ldr, double *C, int npc, int32_t *ctrl)
@@ -244,6 +262,22 @@ __global__ __launch_bounds__(kBlkThreads) void k_jacobi_blk(double *C, int n, in
     const double tol2 = ((double)n * 0x1p-53) * ((double)n * 0x1p-53);
     int epoch = 0, sweeps = 0;
     bool alive = true;
+    // Power-of-two scale (largest |entry| into [1, 2)), the same in every workgroup; each
+    // block is scaled by the workgroup that loads it in the first round.
+    __shared__ int s_exp;
+    if (tid == 0) s_exp = INT_MIN;
+    __syncthreads();
+    {
+        double m = 0.0;
+        for (int64_t e = tid; e < (int64_t)NPC * NPC; e += kBlkThreads) m = fmax(m, fabs(C[e]));
+        if (m > 0.0) atomicMax(&s_exp, ilogb(m));
+    }
+    __syncthreads();
+    const int ex = s_exp == INT_MIN ? 0 : s_exp;
+    if (w == 0 && tid == 0) ctrl[CTRL_EXP] = ex;
+    // every workgroup has read the unscaled columns before any is written back
+    epoch++;
+    alive = grid_barrier(ctrl, epoch * P);
     for (int sweep = 0; sweep < max_sweeps && alive; sweep++) {
         if (w == 0 && tid == 0) ctrl[CTRL_FLAG + (sweep + 1) % 3] = 0;
         for (int round = 0; round < M; round++) {
@@ -252,7 +286,8 @@ __global__ __launch_bounds__(kBlkThreads) void k_jacobi_blk(double *C, int n, in
             for (int e = tid; e < LOC * NPC; e += kBlkThreads) {
                 const int l = e / NPC, i = e - l * NPC;
                 const int col = (l < kBlk ? bp * kBlk + l : bq * kBlk + (l - kBlk));
-                Cs[l * LDC + i] = C[(int64_t)col * NPC + i];
+                const double x = C[(int64_t)col * NPC + i];
+                Cs[l * LDC + i] = (sweep == 0 && round == 0) ? ldexp(x, -ex) : x;
             }
             if (tid == 0) s_rot = 0;
             __syncthreads();
@@ -336,7 +371,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_blk_finish(const double *C, int
             const double u = sv[j];
             rank += (u > v) || (u == v && j < k);
         }
-        sigma[rank] = bad ? __builtin_nan("") : v;
+        sigma[rank] = bad ? __builtin_nan("") : ldexp(v, ctrl[CTRL_EXP]);
     }
 }
 
@@ -376,6 +411,273 @@ hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int
     if (!scratch) return hipErrorInvalidValue;
     if (n <= 256) return launch_blk<256>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, s);
     if (n <= 512) return launch_blk<512>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace figaro
+
+// ------------------------------------------------------------------ sigma via bidiagonalisation (n <= 128)
+//
+// The route of a dense SVD of R (Related Works: SVD through QR): Householder
+// bidiagonalisation B = U^T R V (alternating a left reflector on column k and
+// a right reflector on row k), then the singular values of the bidiagonal
+// B = bidiag(d, e) as the positive eigenvalues of its Golub-Kahan tridiagonal
+// (zero diagonal, off-diagonals d1, e1, d2, e2, ...), located by multisection
+// on Sturm counts: the number of eigenvalues below x is the number of negative
+// pivots of the LDL^T factorisation of T - x I.  Reflector conventions are the
+// TSQR ones (beta = -sign(alpha) |(alpha, x)|, tau = 1 - alpha / beta).
+
+namespace figaro {
+namespace {
+
+constexpr int kGkThreads = 1024;  // all of them run the multisection
+constexpr int kGkBidiag = 256;    // the first four waves run the bidiagonalisation
+
+template <int NPC>
+struct GkGeom {
+    static constexpr int TPC = (kGkBidiag / NPC) < 16 ? (kGkBidiag / NPC) : 16;  // bidiag threads per column / row
+    static constexpr int LDA = NPC + 1;
+    static constexpr int RPT = (NPC + TPC - 1) / TPC;  // elements per thread along a column / row
+    static constexpr int LPS = (kGkThreads / NPC) < 16 ? (kGkThreads / NPC) : 16;  // multisection lanes per value
+    // multisection rounds: (LPS + 1)^ITERS > 2^55, so the final interval is below 2^-53 of the bound
+    static constexpr int ITERS = LPS >= 16 ? 14 : LPS >= 8 ? 18 : LPS >= 4 ? 24 : 56;
+};
+
+// Reflector scalars for (alpha, s = |x|^2): tau, beta, scl = 1 / (alpha - beta); tau = 0 if s is 0.
+__device__ inline void gk_reflector(double alpha, double s, double &tau, double &beta, double &scl)
+{
+    const double q = fma(alpha, alpha, s);
+    tau = 0.0;
+    beta = alpha;
+    scl = 0.0;
+    if (s > 0.0 && q >= DBL_MIN) {
+        const double r = rsq_refined(q);
+        const double sg = alpha >= 0.0 ? 1.0 : -1.0;
+        const double nrm = q * r;
+        beta = -sg * nrm;
+        scl = rcp_refined(alpha + sg * nrm);
+        tau = 1.0 - alpha * (-sg * r);
+    }
+}
+
+__device__ inline double readlane_f64(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over an aligned group of G lanes (G a power of two <= 16) with DPP moves.
+template <int G>
+__device__ inline double dpp_group_sum(double v)
+{
+    if constexpr (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    if constexpr (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    if constexpr (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+    if constexpr (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
+    return v;
+}
+
+// Sum over the whole wave, the same value in every lane: rows of 16 by DPP, then the
+// four row sums read back by lane.
+__device__ inline double wave_sum(double v)
+{
+    v = dpp_group_sum<16>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+template <int NPC>
+__global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n, int64_t ldr, double *sigma)
+{
+    using Gm = GkGeom<NPC>;
+    constexpr int TPC = Gm::TPC, LDA = Gm::LDA, RPT = Gm::RPT, LPS = Gm::LPS;
+    __shared__ double A[NPC * LDA];
+    __shared__ double v[NPC];
+    __shared__ double dd[NPC], ee[NPC];
+    __shared__ double bb[2 * NPC];
+    __shared__ double sc[2];
+    __shared__ double hi_s;
+    __shared__ int s_exp;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) s_exp = INT_MIN;
+    for (int e = tid; e < NPC * NPC; e += kGkThreads) {
+        const int i = e / NPC, j = e - i * NPC;
+        A[i * LDA + j] = (i < n && j < n) ? R[(int64_t)i * ldr + j] : 0.0;
+    }
+    __syncthreads();
+    // Scale by a power of two so that the largest |entry| lies in [1, 2) (exact): the
+    // reflector norms and the recurrence below stay in range.
+    {
+        double m = 0.0;
+        for (int e = tid; e < NPC * NPC; e += kGkThreads) m = fmax(m, fabs(A[(e / NPC) * LDA + e % NPC]));
+        if (m > 0.0) atomicMax(&s_exp, ilogb(m));
+    }
+    __syncthreads();
+    const int ex0 = s_exp == INT_MIN ? 0 : s_exp;
+    for (int e = tid; e < NPC * NPC; e += kGkThreads) {
+        double &x = A[(e / NPC) * LDA + e % NPC];
+        x = ldexp(x, -ex0);
+    }
+    __syncthreads();
+    const bool bid = tid < kGkBidiag;
+    const int c = tid / TPC, p = tid % TPC;  // column (or row) handled, part of it
+    for (int k = 0; k < n; k++) {
+        // ---- left reflector on column k, rows k..n-1
+        if (wv == 0) {
+            double s = 0.0;
+            for (int i = k + 1 + lane; i < n; i += 64) s = fma(A[i * LDA + k], A[i * LDA + k], s);
+            s = wave_sum(s);
+            double tau, beta, scl;
+            gk_reflector(A[k * LDA + k], s, tau, beta, scl);
+            for (int i = k + 1 + lane; i < n; i += 64) v[i] = A[i * LDA + k] * scl;
+            if (lane == 0) {
+                v[k] = 1.0;
+                sc[0] = tau;
+                dd[k] = beta;
+            }
+        }
+        __syncthreads();
+        if (bid) {
+            const double tau = sc[0];
+            const int j = c;
+            if (tau != 0.0 && j > k && j < n) {
+                double w = 0.0;
+#pragma unroll 8
+                for (int r = 0; r < RPT; r++) {
+                    const int i = k + p + r * TPC;
+                    if (i < n) w = fma(v[i], A[i * LDA + j], w);
+                }
+                w = dpp_group_sum<TPC>(w) * tau;
+#pragma unroll 8
+                for (int r = 0; r < RPT; r++) {
+                    const int i = k + p + r * TPC;
+                    if (i < n) A[i * LDA + j] = fma(-w, v[i], A[i * LDA + j]);
+                }
+            }
+        }
+        __syncthreads();
+        if (k + 1 >= n) break;
+        // ---- right reflector on row k, columns k+1..n-1
+        if (wv == 0) {
+            double s = 0.0;
+            for (int j = k + 2 + lane; j < n; j += 64) s = fma(A[k * LDA + j], A[k * LDA + j], s);
+            s = wave_sum(s);
+            double tau, beta, scl;
+            gk_reflector(A[k * LDA + k + 1], s, tau, beta, scl);
+            for (int j = k + 2 + lane; j < n; j += 64) v[j] = A[k * LDA + j] * scl;
+            if (lane == 0) {
+                v[k + 1] = 1.0;
+                sc[1] = tau;
+                ee[k] = beta;
+            }
+        }
+        __syncthreads();
+        if (bid) {
+            const double tau = sc[1];
+            const int i = c;
+            if (tau != 0.0 && i > k && i < n) {
+                double w = 0.0;
+#pragma unroll 8
+                for (int r = 0; r < RPT; r++) {
+                    const int j = k + 1 + p + r * TPC;
+                    if (j < n) w = fma(A[i * LDA + j], v[j], w);
+                }
+                w = dpp_group_sum<TPC>(w) * tau;
+#pragma unroll 8
+                for (int r = 0; r < RPT; r++) {
+                    const int j = k + 1 + p + r * TPC;
+                    if (j < n) A[i * LDA + j] = fma(-w, v[j], A[i * LDA + j]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // ---- multisection on the Golub-Kahan tridiagonal T (zero diagonal, off-diagonals
+    // d1, e1, d2, ...): sigma_k (k-th largest) by LPS lanes.  The number of eigenvalues of
+    // T below x is the number of sign changes of its characteristic sequence
+    // p_0 = 1, p_1 = -x, p_i = -x p_{i-1} - b_{i-1}^2 p_{i-2} (a zero p_i counts as a change,
+    // like a zero pivot taken negative).  d and e are scaled once more so that the
+    // Gershgorin bound lies in [1, 2); the pair (p_{i-1}, p_i) is rescaled by a power of
+    // two every 16 steps, which keeps it in range and does not change any sign.
+    if (tid == 0) {
+        double h = 0.0;
+        for (int i = 0; i < n; i++) {
+            const double a = fabs(dd[i]) + (i + 1 < n ? fabs(ee[i]) : 0.0) + (i > 0 ? fabs(ee[i - 1]) : 0.0);
+            h = fmax(h, a);
+        }
+        hi_s = h;
+        sc[0] = h > 0.0 ? (double)ilogb(h) : 0.0;
+    }
+    __syncthreads();
+    const int ex = (int)sc[0];
+    for (int i = tid; i < 2 * n - 1; i += kGkThreads) {
+        const double b = ldexp((i & 1) ? ee[i >> 1] : dd[i >> 1], -ex);
+        bb[i] = b * b;
+    }
+    __syncthreads();
+    const double hi = ldexp(hi_s, -ex);
+    const int k = tid / LPS, q = tid % LPS;
+    const bool act = k < n;
+    const int m = 2 * n - 1;  // off-diagonals of the 2n x 2n tridiagonal
+    double lo = 0.0, up = hi;
+    const int target = 2 * n - k;  // sigma_k < x  <=>  count(x) >= 2n - k
+    for (int it = 0; it < Gm::ITERS; it++) {
+        const double x = lo + (up - lo) * (double)(q + 1) / (double)(LPS + 1);
+        int cnt = 0;
+        if (act) {
+            double p0 = 1.0, p1 = -x;
+            cnt = p1 < 0.0;
+            for (int i0 = 0; i0 < m; i0 += 16) {
+#pragma unroll
+                for (int u = 0; u < 16; u++) {
+                    const int i = i0 + u;
+                    if (i < m) {
+                        double p2 = fma(-x, p1, -bb[i] * p0);
+                        if (p2 == 0.0) p2 = p1 < 0.0 ? DBL_MIN : -DBL_MIN;
+                        cnt += (p2 < 0.0) != (p1 < 0.0);
+                        p0 = p1;
+                        p1 = p2;
+                    }
+                }
+                const int e2 = ilogb(fmax(fabs(p0), fabs(p1)));
+                p0 = ldexp(p0, -e2);
+                p1 = ldexp(p1, -e2);
+            }
+        }
+        // new interval: the largest point whose count is below target and the next one
+        const bool below = cnt < target;
+        double lo_new = below ? x : lo, up_new = below ? up : x;
+#pragma unroll
+        for (int off = 1; off < LPS; off <<= 1) {
+            lo_new = fmax(lo_new, __shfl_xor(lo_new, off, 64));
+            up_new = fmin(up_new, __shfl_xor(up_new, off, 64));
+        }
+        lo = lo_new;
+        up = up_new;
+    }
+    if (act && q == 0) sigma[k] = ldexp(0.5 * (lo + up), ex + ex0);
+}
+
+template <int NPC>
+hipError_t launch_gk(const double *R, int n, int64_t ldr, double *sigma, int32_t *ctrl, hipStream_t s)
+{
+    k_sigma_gk<NPC><<<1, kGkThreads, 0, s>>>(R, n, ldr, sigma);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !ctrl) return e;
+    k_jacobi_blk_init<<<1, 64, 0, s>>>(nullptr, 0, 0, nullptr, 0, ctrl);  // sweeps = 0
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, double *sigma, int32_t *ctrl, hipStream_t s)
+{
+    if (n <= 0) return hipErrorInvalidValue;
+    if (n <= 8) return launch_gk<8>(R, n, ldr, sigma, ctrl, s);
+    if (n <= 16) return launch_gk<16>(R, n, ldr, sigma, ctrl, s);
+    if (n <= 32) return launch_gk<32>(R, n, ldr, sigma, ctrl, s);
+    if (n <= 64) return launch_gk<64>(R, n, ldr, sigma, ctrl, s);
+    if (n <= 128) return launch_gk<128>(R, n, ldr, sigma, ctrl, s);
     return hipErrorInvalidValue;
 }
 

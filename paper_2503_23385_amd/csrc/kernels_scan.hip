@@ -8,8 +8,8 @@
 // accumulated in FP64 whatever the input or storage type.  Three launches:
 //   1. tile reduce: each tile of rows produces its segmented aggregate
 //      (F = "a group starts in the tile", S = column sums since the last start);
-//   2. carry scan: one workgroup scans the tile aggregates in a fixed order and
-//      writes, per tile, the sums carried into its first (continuing) group;
+//   2. carry scan: one workgroup per column scans the tile aggregates in a fixed
+//      order and writes, per tile, the sums carried into its first (continuing) group;
 //   3. tile write: each tile rescans its rows with the carry and writes tail
 //      row i of group g to region-2 row r2_g + i - 1, scaled by sqrt(m1_g), and
 //      the head of a group that ends in the tile to heads[g].
@@ -230,51 +230,54 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_tile(
     }
 }
 
-// Exclusive segmented scan of the tile aggregates, per column, in a fixed order:
-// carry[t] = sums carried into tile t.  One workgroup: columns x tile segments.
+// Exclusive segmented scan of the tile aggregates, per column: carry[t] = the sums
+// carried into tile t.  One workgroup per column: each thread reduces a run of
+// consecutive tiles, the thread aggregates are scanned in LDS (Hillis-Steele with the
+// segmented operator (f1, s1) + (f2, s2) = (f1 | f2, f2 ? s2 : s1 + s2)), and each thread
+// rescans its run with the carry it receives.  The combination order is fixed, so the
+// result does not depend on timing.
 __global__ __launch_bounds__(kCarryThreads) void k_carry_scan(const int32_t *__restrict__ tileF,
                                                               const double *__restrict__ tileS,
                                                               double *__restrict__ carry, int T,
                                                               int n2)
 {
-    const int CT = min(n2, kCarryThreads);
-    const int NS = kCarryThreads / CT;
-    const int tid = threadIdx.x;
-    const int c0 = tid % CT, sg = tid / CT;
-    const bool active = sg < NS;
-    const int L = (T + NS - 1) / NS;
-    const int tb = sg * L, te = min(T, tb + L);
-    __shared__ int segF[kCarryThreads];
-    __shared__ double segS[kCarryThreads];
-    for (int c = c0; c < n2; c += CT) {
-        int F = 0;
-        double S = 0.0;
-        if (active) {
-            for (int t = tb; t < te; t++) {
-                const int ft = tileF[t];
-                const double st = tileS[(int64_t)t * n2 + c];
-                S = ft ? st : S + st;
-                F |= ft;
-            }
-            segF[sg * CT + c0] = F;
-            segS[sg * CT + c0] = S;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int L = (T + kCarryThreads - 1) / kCarryThreads;
+    const int tb = min(T, tid * L), te = min(T, tb + L);
+    __shared__ int sf[2][kCarryThreads];
+    __shared__ double ss[2][kCarryThreads];
+    int F = 0;
+    double S = 0.0;
+    for (int t = tb; t < te; t++) {
+        const int ft = tileF[t];
+        const double st = tileS[(int64_t)t * n2 + c];
+        S = ft ? st : S + st;
+        F |= ft;
+    }
+    int cur = 0;
+    sf[0][tid] = F;
+    ss[0][tid] = S;
+    __syncthreads();
+    for (int off = 1; off < kCarryThreads; off <<= 1) {
+        int f = sf[cur][tid];
+        double v = ss[cur][tid];
+        if (tid >= off) {
+            const int fp = sf[cur][tid - off];
+            const double vp = ss[cur][tid - off];
+            v = f ? v : vp + v;
+            f |= fp;
         }
+        sf[cur ^ 1][tid] = f;
+        ss[cur ^ 1][tid] = v;
+        cur ^= 1;
         __syncthreads();
-        if (active) {
-            double run = 0.0;
-            for (int s = 0; s < sg; s++) {
-                const int fs = segF[s * CT + c0];
-                const double ss = segS[s * CT + c0];
-                run = fs ? ss : run + ss;
-            }
-            for (int t = tb; t < te; t++) {
-                carry[(int64_t)t * n2 + c] = run;
-                const int ft = tileF[t];
-                const double st = tileS[(int64_t)t * n2 + c];
-                run = ft ? st : run + st;
-            }
-        }
-        __syncthreads();
+    }
+    double run = tid > 0 ? ss[cur][tid - 1] : 0.0;  // inclusive aggregate of the threads before
+    for (int t = tb; t < te; t++) {
+        carry[(int64_t)t * n2 + c] = run;
+        const int ft = tileF[t];
+        const double st = tileS[(int64_t)t * n2 + c];
+        run = ft ? st : run + st;
     }
 }
 
@@ -395,7 +398,7 @@ hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, i
     FIGARO_TILE_ALL(false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_carry_scan<<<1, kCarryThreads, 0, s>>>(tileF, tileS, carry, (int)sp.ntiles, (int)n2);
+    k_carry_scan<<<(unsigned)n2, kCarryThreads, 0, s>>>(tileF, tileS, carry, (int)sp.ntiles, (int)n2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     FIGARO_TILE_ALL(true);

@@ -265,13 +265,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_wave(const double 
 // updates its own rows.  Row j of R is read by every wave during step j, so its
 // new values are written one step later, after the next barrier.
 
-constexpr int kTreeWaves = 4;
+// Waves per workgroup of the tree kernel (8 at padded width 64 measured slower than 4).
+__host__ __device__ constexpr int tree_waves(int) { return 4; }
 
 template <int NP, typename Tacc>
 struct WgState {
     Tacc *R;             // packed triangle (LDS)
     Tacc *xb;            // this wave's broadcast slot, offset by the row set h
-    double (*red)[kTreeWaves][NP];
+    double (*red)[tree_waves(NP)][NP];
     int k, h, wv, par;
     int pend_row;        // row of R whose new values are still in pend_val (-1: none)
     Tacc pend_val;
@@ -315,7 +316,7 @@ __device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> 
         wg_flush(st, width);
         double dk = 0.0, s = 0.0;
 #pragma unroll
-        for (int w = 0; w < kTreeWaves; w++) {
+        for (int w = 0; w < tree_waves(NP); w++) {
             dk += st.red[st.par][w][k];
             s += st.red[st.par][w][j];
         }
@@ -353,7 +354,7 @@ template <int NP, typename Tin, typename Tacc>
 __device__ inline void wg_absorb_rows(WgState<NP, Tacc> &st, const RowSrc &src, int64_t r0, int64_t r1,
                                       int tri_rows, int width)
 {
-    constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR, BG = kTreeWaves * BR;
+    constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR, BG = tree_waves(NP) * BR;
     for (int64_t rb = r0; rb < r1; rb += BG) {
         if (st.pend_row >= 0) {  // the block may start at the pending row: write it first
             __syncthreads();
@@ -381,7 +382,7 @@ __device__ inline void wg_store(WgState<NP, Tacc> &st, double *out, int width)
     __syncthreads();
     wg_flush(st, width);
     __syncthreads();
-    for (int e = threadIdx.x; e < width * NP; e += 64 * kTreeWaves) {
+    for (int e = threadIdx.x; e < width * NP; e += 64 * tree_waves(NP)) {
         const int j = e / NP, kk = e - j * NP;
         out[e] = (kk >= j && kk < width) ? (double)st.R[pidx(NP, j, kk)] : 0.0;
     }
@@ -390,10 +391,10 @@ __device__ inline void wg_store(WgState<NP, Tacc> &st, double *out, int width)
 template <int NP, typename Tacc>
 __device__ inline void wg_load_tri(WgState<NP, Tacc> &st, const double *T, int width)
 {
-    for (int e = threadIdx.x; e < WaveGeom<NP>::PS; e += 64 * kTreeWaves) st.R[e] = Tacc(0);
+    for (int e = threadIdx.x; e < WaveGeom<NP>::PS; e += 64 * tree_waves(NP)) st.R[e] = Tacc(0);
     __syncthreads();
     if (T) {
-        for (int e = threadIdx.x; e < width * NP; e += 64 * kTreeWaves) {
+        for (int e = threadIdx.x; e < width * NP; e += 64 * tree_waves(NP)) {
             const int j = e / NP, kk = e - j * NP;
             if (kk >= j && kk < width) st.R[pidx(NP, j, kk)] = (Tacc)T[e];
         }
@@ -407,13 +408,14 @@ __device__ inline void wg_load_tri(WgState<NP, Tacc> &st, const double *T, int w
 // counter) combines all children in child order.  slots: the node triangles of every
 // level (width x NP doubles each); counters: one int per parent node, zero on entry.
 template <int NP, typename Tin, typename Tacc>
-__global__ __launch_bounds__(64 * kTreeWaves) void k_tsqr_tree(TreeRegion reg0, TreeRegion reg1)
+__global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion reg0, TreeRegion reg1)
 {
     using Gm = WaveGeom<NP>;
+    constexpr int WV = tree_waves(NP);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     __shared__ Tacc Rs[Gm::PS];
-    __shared__ __align__(16) Tacc Xs[kTreeWaves][Gm::BR];
-    __shared__ double red[2][kTreeWaves][NP];
+    __shared__ __align__(16) Tacc Xs[WV][Gm::BR];
+    __shared__ double red[2][WV][NP];
     __shared__ int s_old;
     int g = blockIdx.x;
     const bool second = g >= reg0.nleaves;
@@ -436,7 +438,7 @@ __global__ __launch_bounds__(64 * kTreeWaves) void k_tsqr_tree(TreeRegion reg0, 
     st.pend_row = -1;
     st.pend_val = Tacc(0);
     wg_load_tri<NP, Tacc>(st, nullptr, width);
-    constexpr int BG = kTreeWaves * Gm::BR;
+    constexpr int BG = WV * Gm::BR;
     int64_t chunk = (rows + nleaves - 1) / nleaves;
     chunk = ((chunk + BG - 1) / BG) * BG;
     const int64_t r0 = (int64_t)g * chunk, r1 = min(rows, r0 + chunk);
@@ -528,7 +530,7 @@ hipError_t launch_tree_np(int acc_f64, int in_f64, const TreeRegion *regs, int n
     TreeRegion r0 = regs[0];
     TreeRegion r1 = nreg > 1 ? regs[1] : TreeRegion{};
     const unsigned grid = (unsigned)(r0.nleaves + r1.nleaves);
-#define FIGARO_TREE(TI, TA) k_tsqr_tree<NP, TI, TA><<<grid, 64 * kTreeWaves, 0, s>>>(r0, r1)
+#define FIGARO_TREE(TI, TA) k_tsqr_tree<NP, TI, TA><<<grid, 64 * tree_waves(NP), 0, s>>>(r0, r1)
     if (acc_f64) {
         if (in_f64) FIGARO_TREE(double, double);
         else FIGARO_TREE(float, double);
@@ -552,13 +554,13 @@ int tsqr_padded_width(int n)
 
 int tsqr_block_rows(int np, int acc_f64)
 {
-    if (np <= 64) return kTreeWaves * wave_block_rows(np);  // tree kernel: 4 waves x row sets x rows per lane
+    if (np <= 64) return tree_waves(np) * wave_block_rows(np);  // tree kernel: waves x row sets x rows per lane
     return tsqr_panel_rows(np, acc_f64);                   // workgroup panel kernel
 }
 
 int tsqr_tree_arity(int np, int width)
 {
-    const int a = 1 + kTreeWaves * wave_block_rows(np) / (width > 0 ? width : 1);
+    const int a = 1 + tree_waves(np) * wave_block_rows(np) / (width > 0 ? width : 1);
     return a < 2 ? 2 : (a > 32 ? 32 : a);
 }
 
@@ -598,6 +600,94 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
     case NPV: return launch_tree_np<NPV>(acc_f64, in_f64, regs, nreg, s);
     FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64)
 #undef FIGARO_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ a few rows into one triangle
+//
+// The merge of the two-sided form of a Cartesian product absorbs a single head row.
+// One wave, lane k = column k (no row sets), up to kFewRows rows per block in
+// registers: the column step needs no cross-lane reduction.
+constexpr int kFewRows = 4;
+
+template <int NP>
+__global__ __launch_bounds__(64) void k_tsqr_few(const double *init, int64_t init_ld, RowSrc src, int in_f64,
+                                                 int width, double *out)
+{
+    __shared__ double Rp[packed_size(NP)];
+    __shared__ double xb[kFewRows];
+    const int k = threadIdx.x;
+    for (int e = k; e < width * NP; e += 64) {
+        const int j = e / NP, kk = e - j * NP;
+        if (kk >= j) Rp[pidx(NP, j, kk)] = (init && kk < width) ? init[(int64_t)j * init_ld + kk] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int64_t rows = src_rows(src);
+    const bool col_ok = k < width;
+    for (int64_t rb = 0; rb < rows; rb += kFewRows) {
+        double x[kFewRows];
+#pragma unroll
+        for (int i = 0; i < kFewRows; i++) {
+            const int64_t r = rb + i;
+            x[i] = (r < rows && col_ok) ? (in_f64 ? load_src<double, double>(src, r, k) : load_src<float, double>(src, r, k))
+                                        : 0.0;
+        }
+        for (int j = src.col_off; j < width; j++) {
+            __builtin_amdgcn_wave_barrier();
+            if (k == j) {
+#pragma unroll
+                for (int i = 0; i < kFewRows; i++) xb[i] = x[i];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            double xj[kFewRows], d = 0.0, s = 0.0;
+#pragma unroll
+            for (int i = 0; i < kFewRows; i++) {
+                xj[i] = xb[i];
+                d = fma(xj[i], x[i], d);
+                s = fma(xj[i], xj[i], s);
+            }
+            const double alpha = Rp[pidx(NP, j, j)];
+            const double rjk = (k > j && col_ok) ? Rp[pidx(NP, j, k)] : 0.0;
+            const double q = fma(alpha, alpha, s);
+            if (s > 0.0 && q >= DBL_MIN) {
+                const double r = rsq_refined(q);
+                const double sg = alpha >= 0.0 ? 1.0 : -1.0;
+                const double nrm = q * r;
+                const double beta = -sg * nrm;
+                const double inv_beta = -sg * r;
+                const double scl = rcp_refined(alpha + sg * nrm);
+                const double tau = 1.0 - alpha * inv_beta;
+                if (k > j && col_ok) {
+                    const double w = rjk + scl * d;
+                    Rp[pidx(NP, j, k)] = rjk - tau * w;
+                    const double c = w * inv_beta;
+#pragma unroll
+                    for (int i = 0; i < kFewRows; i++) x[i] = fma(c, xj[i], x[i]);
+                }
+                if (k == j) Rp[pidx(NP, j, j)] = beta;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int e = k; e < width * NP; e += 64) {
+        const int j = e / NP, kk = e - j * NP;
+        out[e] = (kk >= j && kk < width) ? Rp[pidx(NP, j, kk)] : 0.0;
+    }
+}
+
+hipError_t launch_tsqr_few(int np, const double *init, int64_t init_ld, RowSrc src, int in_f64, int width,
+                           double *out, hipStream_t s)
+{
+    switch (np) {
+#define FIGARO_FEW(NPV) \
+    case NPV: k_tsqr_few<NPV><<<1, 64, 0, s>>>(init, init_ld, src, in_f64, width, out); return hipGetLastError();
+    FIGARO_FEW(4) FIGARO_FEW(8) FIGARO_FEW(16) FIGARO_FEW(32) FIGARO_FEW(64)
+#undef FIGARO_FEW
     default: return hipErrorInvalidValue;
     }
 }

@@ -234,6 +234,45 @@ def test_strided_inputs():
     assert relF(R.cpu().numpy(), oracle.r(inst)) <= 1e-12
 
 
+# ------------------------------------------------------------------ the two sigma routes
+
+def special_matrices():
+    rng = np.random.default_rng(7)
+    out = {
+        "zero_8": np.zeros((8, 8)),
+        "identity_16": np.eye(16),
+        "diag_known_32": np.diag(np.linspace(1.0, 32.0, 32)[::-1].copy()),
+        "repeated_64": np.triu(np.linalg.qr(rng.standard_normal((64, 64)))[1] * 0 + np.diag(np.r_[np.full(32, 3.0), np.full(32, 1e-3)])),
+        "graded_48": np.triu(rng.standard_normal((48, 48))) * (10.0 ** -np.arange(48) / 4)[None, :],
+        "huge_64": np.triu(rng.standard_normal((64, 64))) * 2.0 ** 600,
+        "tiny_64": np.triu(rng.standard_normal((64, 64))) * 2.0 ** -600,
+        "rank3_100": np.triu(rng.standard_normal((100, 3)) @ rng.standard_normal((3, 100))),
+        "random_128": np.triu(rng.standard_normal((128, 128))),
+        "random_5": rng.standard_normal((5, 5)),
+    }
+    return out
+
+
+SPECIAL = special_matrices()
+
+
+@pytest.mark.parametrize("name", list(SPECIAL))
+@pytest.mark.parametrize("method", ["jacobi", "bidiag"])
+def test_sigma_routes_match_lapack(name, method):
+    """Both sigma routes (one-sided Jacobi; bidiagonalisation + multisection) on special
+    matrices against LAPACK's singular values (numpy.linalg.svd), normwise rel2 <= 1e-12."""
+    M = SPECIAL[name]
+    d = dev()
+    R = torch.from_numpy(np.ascontiguousarray(M)).to(d)
+    S = fg().sigma(R, method=method).cpu().numpy()
+    ref = np.linalg.svd(M, compute_uv=False)
+    top = ref[0] if ref.size and ref[0] > 0 else 1.0  # normalise first: norms of 2^600-sized values overflow
+    err = np.linalg.norm((S - ref) / top) / max(np.linalg.norm(ref / top), 1e-300) if ref[0] > 0 else np.abs(S).max()
+    say(f"[sigma] {name} {method} rel2={err:.3e}")
+    assert np.all(np.diff(S) <= 0)
+    assert err <= 1e-12
+
+
 # ------------------------------------------------------------------ refinement sweep
 
 def refine_cases():
