@@ -147,6 +147,12 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
 int64_t jacobi_scratch_doubles(int n);
 hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                          int32_t *ctrl, double *scratch, hipStream_t s);
+// Width class (padded n: 8..128) of the LDS Jacobi; 0 above 128.
+int jacobi_class(int n);
+// Independent problems of one width class in one launch; tab (device): 3 int64 per problem
+// (element offset of its R in R, of its sigma in sigma, n), R packed n x n (ld n).
+hipError_t launch_jacobi_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count,
+                               hipStream_t s);
 // The bidiagonal route for n <= 128: bidiagonalisation + multisection (ctrl[0] = 0 sweeps).
 hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, double *sigma, int32_t *ctrl, hipStream_t s);
 

@@ -709,6 +709,11 @@ struct figaro_plan {
     std::vector<int> lane;          // lane of each instance
     int nlanes = 1;
     hipStream_t cap_stream = nullptr;
+    // Batched Jacobi: per width class, a contiguous run of (r_off, s_off, n) entries in the
+    // device table `jtab` (owned by the plan).
+    int64_t *jtab = nullptr;           // uploaded at the first execution (creation is host-only)
+    std::vector<int64_t> jtab_host;
+    std::vector<std::pair<int, std::pair<int, int>>> jclass;  // (class, (first entry, count))
     std::vector<hipStream_t> lane_streams;
     std::vector<hipEvent_t> lane_events;  // [0]: fork, [1 + l]: join of lane l
     // One captured graph per (ws, R, sigma) triple.
@@ -732,13 +737,15 @@ int plan_enqueue(figaro_plan *plan, void *ws, double *R, double *sigma, hipStrea
         void *lws = (char *)ws + (size_t)l * plan->lane_bytes;
         int rc = run_r(&plan->inst[i].A, &plan->inst[i].B, sh, plan->layouts[i], R + plan->r_off[i], N, lws, ls);
         if (rc) return rc;
-        hipError_t e = launch_jacobi(R + plan->r_off[i], (int)N, N, sigma + plan->s_off[i], 60, nullptr, nullptr, ls);
-        if (e != hipSuccess) return hip_fail(e, "jacobi");
     }
     for (int l = 0; l < plan->nlanes; l++) {
         HIPCHK(hipEventRecord(plan->lane_events[1 + l], plan->lane_streams[l]), "join");
         HIPCHK(hipStreamWaitEvent(s, plan->lane_events[1 + l], 0), "join wait");
     }
+    // sigma of every instance: one launch per width class, one workgroup per instance
+    for (const auto &c : plan->jclass)
+        HIPCHK(launch_jacobi_batch(c.first, R, sigma, plan->jtab + 3 * (int64_t)c.second.first, c.second.second, s),
+               "batched jacobi");
     return FIGARO_OK;
 }
 
@@ -792,6 +799,20 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
     }
     p->lane_bytes = wsmax;
     p->ws_bytes = wsmax * p->nlanes;
+    // instance table of the batched Jacobi, grouped by width class
+    std::vector<int64_t> tab;
+    for (int c = 8; c <= 128; c *= 2) {
+        const int first = (int)(tab.size() / 3);
+        for (int i = 0; i < count; i++) {
+            if (jacobi_class((int)p->shapes[i].N()) != c) continue;
+            tab.push_back(p->r_off[i]);
+            tab.push_back(p->s_off[i]);
+            tab.push_back(p->shapes[i].N());
+        }
+        const int n = (int)(tab.size() / 3) - first;
+        if (n > 0) p->jclass.push_back({c, {first, n}});
+    }
+    p->jtab_host = std::move(tab);
     *out = p;
     return FIGARO_OK;
 }
@@ -825,6 +846,13 @@ int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R,
     hipStream_t s = (hipStream_t)stream;
     auto key = std::make_tuple(ws, R, sigma);
     auto it = plan->graphs.find(key);
+    if (!plan->jtab) {
+        const size_t nb = sizeof(int64_t) * std::max<size_t>(1, plan->jtab_host.size());
+        HIPCHK(hipMalloc((void **)&plan->jtab, nb), "plan instance table");
+        HIPCHK(hipMemcpy(plan->jtab, plan->jtab_host.data(), sizeof(int64_t) * plan->jtab_host.size(),
+                         hipMemcpyHostToDevice),
+               "plan instance table");
+    }
     if (it == plan->graphs.end()) {
         if (!plan->cap_stream) {
             HIPCHK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking), "plan stream");
@@ -867,6 +895,7 @@ void figaro_plan_destroy(figaro_plan *plan)
     for (auto ls : plan->lane_streams)
         if (ls) (void)hipStreamDestroy(ls);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    if (plan->jtab) (void)hipFree(plan->jtab);
     delete plan;
 }
 

@@ -91,9 +91,8 @@ struct JacobiGeom {
 };
 
 template <int NPC>
-__global__ __launch_bounds__(JacobiGeom<NPC>::THREADS)
-void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
-                  int32_t *sweeps_out)
+__device__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
+                                int32_t *sweeps_out)
 {
     using Gm = JacobiGeom<NPC>;
     constexpr int LP = Gm::LP, RPL = Gm::RPL, PAIRS = Gm::PAIRS, LDC = Gm::LDC;
@@ -190,6 +189,24 @@ void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sw
         sigma[rank] = v;
     }
     if (tid == 0 && sweeps_out) *sweeps_out = sweeps;
+}
+
+template <int NPC>
+__global__ __launch_bounds__(JacobiGeom<NPC>::THREADS)
+void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps, int32_t *sweeps_out)
+{
+    jacobi_lds_body<NPC>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+}
+
+// Many independent problems of one width class in one launch: workgroup b takes entry
+// b of tab (3 int64 each: element offset of its n x n R in R, offset of its sigma, n).
+template <int NPC>
+__global__ __launch_bounds__(JacobiGeom<NPC>::THREADS)
+void k_jacobi_batch(const double *R, double *sigma, const int64_t *tab, int max_sweeps)
+{
+    const int64_t *e = tab + 3 * (int64_t)blockIdx.x;
+    const int n = (int)e[2];
+    jacobi_lds_body<NPC>(R + e[0], n, n, sigma + e[1], max_sweeps, nullptr);
 }
 
 template <int NPC>
@@ -390,7 +407,36 @@ hipError_t launch_blk(const double *R, int n, int64_t ldr, double *sigma, int ma
     return hipGetLastError();
 }
 
+template <int NPC>
+hipError_t launch_batch_npc(const double *R, double *sigma, const int64_t *tab, int count, int max_sweeps,
+                            hipStream_t s)
+{
+    k_jacobi_batch<NPC><<<count, JacobiGeom<NPC>::THREADS, 0, s>>>(R, sigma, tab, max_sweeps);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int jacobi_class(int n)
+{
+    int npc = 8;
+    while (npc < n) npc *= 2;
+    return npc <= 128 ? npc : 0;
+}
+
+hipError_t launch_jacobi_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count,
+                               hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    switch (npc) {
+    case 8: return launch_batch_npc<8>(R, sigma, tab, count, 60, s);
+    case 16: return launch_batch_npc<16>(R, sigma, tab, count, 60, s);
+    case 32: return launch_batch_npc<32>(R, sigma, tab, count, 60, s);
+    case 64: return launch_batch_npc<64>(R, sigma, tab, count, 60, s);
+    case 128: return launch_batch_npc<128>(R, sigma, tab, count, 60, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 int64_t jacobi_scratch_doubles(int n)
 {
