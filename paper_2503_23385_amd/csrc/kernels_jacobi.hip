@@ -44,11 +44,12 @@ __device__ inline double rsq_refined(double x)
     return y;
 }
 
+// DPP move of a double (every lane reads an in-range source for the patterns used here).
 template <int CTRL>
 __device__ inline double dpp_f64(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 // Sum over an aligned group of LP (8 or 16) lanes with DPP: xor 1, xor 2, the
@@ -129,16 +130,14 @@ __device__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sig
     for (int sweep = 0; sweep < max_sweeps; sweep++) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
+        // pair slots of the circle order: (step, NPC-1) for pair 0, else
+        // ((step + pair) mod M, (step - pair) mod M), advanced by one step at a time
+        int pa = pair == 0 ? 0 : pair % M, qa = pair == 0 ? NPC - 1 : (M - pair % M) % M;
         for (int step = 0; step < M; step++) {
-            int p = 0, q = 0;
-            if (pair == 0) {
-                p = step;
-                q = NPC - 1;
-            } else if (active) {
-                p = (step + pair) % M;
-                q = (step - pair + M) % M;
-            }
+            int p = active ? pa : 0, q = active ? qa : 0;
             if (p > q) { const int t = p; p = q; q = t; }
+            pa = pa + 1 == M ? 0 : pa + 1;
+            if (pair != 0) qa = qa + 1 == M ? 0 : qa + 1;
             double *cp = C + p * LDC + sub, *cq = C + q * LDC + sub;
             double xp[RPL], xq[RPL];
 #pragma unroll
@@ -308,16 +307,13 @@ __global__ __launch_bounds__(kBlkThreads) void k_jacobi_blk(double *C, int n, in
             }
             if (tid == 0) s_rot = 0;
             __syncthreads();
-            for (int step = 0; step < LOC - 1; step++) {
-                int p, q;
-                if (pair == 0) {
-                    p = step;
-                    q = LOC - 1;
-                } else {
-                    p = (step + pair) % (LOC - 1);
-                    q = (step - pair + LOC - 1) % (LOC - 1);
-                }
+            constexpr int ML = LOC - 1;
+            int pa = pair == 0 ? 0 : pair % ML, qa = pair == 0 ? LOC - 1 : (ML - pair % ML) % ML;
+            for (int step = 0; step < ML; step++) {
+                int p = pa, q = qa;
                 if (p > q) { const int t = p; p = q; q = t; }
+                pa = pa + 1 == ML ? 0 : pa + 1;
+                if (pair != 0) qa = qa + 1 == ML ? 0 : qa + 1;
                 double *cp = Cs + p * LDC + sub, *cq = Cs + q * LDC + sub;
                 double xp[RPL], xq[RPL];
 #pragma unroll
