@@ -15,12 +15,14 @@
 // zeta = u / v, written with two reciprocal square roots and no division).
 // sigma_k = |c_k| after convergence, sorted descending.
 //
-// A lane group (16 lanes, 8 for the narrowest widths) shares a pair and keeps
+// A lane group (4 to 16 lanes, so that a step fits four waves) shares a pair and keeps
 // its two columns in registers for the whole step; the three dot products are
 // reduced with DPP moves inside the group; one workgroup barrier separates the
 // steps.  The width is a template parameter so every loop over rows is unrolled.
 #include <float.h>
 #include <limits.h>
+
+#include <cstdlib>
 
 #include "common.h"
 
@@ -52,15 +54,16 @@ __device__ inline double dpp_f64(double v)
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
-// Sum over an aligned group of LP (8 or 16) lanes with DPP: xor 1, xor 2, the
-// half-row mirror (lane i <-> 7 - i, swapping the quads of 8 lanes) and, for 16,
-// the row mirror (lane i <-> 15 - i, swapping the halves of the row).
+// Sum over an aligned group of LP (4, 8 or 16) lanes with DPP: xor 1, xor 2,
+// then for 8 and 16 the half-row mirror (lane i <-> 7 - i, swapping the quads of
+// 8 lanes) and for 16 the row mirror (lane i <-> 15 - i, swapping the halves).
 template <int LP>
 __device__ inline double group_sum(double v)
 {
+    static_assert(LP == 4 || LP == 8 || LP == 16, "group of 4, 8 or 16 lanes");
     v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141>(v);  // row_half_mirror
+    if constexpr (LP >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
     if constexpr (LP == 16) v += dpp_f64<0x140>(v);  // row_mirror
     return v;
 }
@@ -82,21 +85,28 @@ __device__ inline void jacobi_rotation(double alpha, double beta, double gamma, 
 }
 
 // NPC: padded (even, power of two) column count; columns n..NPC-1 are zero.
-template <int NPC>
+// LP: lanes per pair (4, 8 or 16, at most NPC).  Fewer lanes per pair issue the
+// per-pair reductions and the rotation, which every lane of a group repeats, on
+// fewer waves; more lanes give more waves to hide latency with.
+template <int NPC, int LP>
 struct JacobiGeom {
-    static constexpr int LP = NPC >= 16 ? 16 : 8;   // lanes per pair
-    static constexpr int RPL = NPC / LP;           // rows per lane (NPC >= LP)
+    static_assert(LP == 4 || LP == 8 || LP == 16, "lanes per pair");
+    static_assert(LP <= NPC, "at least one row per lane");
+    static constexpr int RPL = NPC / LP;           // rows per lane
     static constexpr int PAIRS = NPC / 2;
     static constexpr int THREADS = PAIRS * LP < 64 ? 64 : PAIRS * LP;
-    static constexpr int LDC = NPC + (NPC >= 16 ? 16 : 0);  // column stride (bank spread)
+    // Column stride: column k starts LP doubles further along the 32-double bank
+    // window than column k - 1, so the pairs of one wave, whose columns are
+    // consecutive in the circle order, read disjoint banks.
+    static constexpr int LDC = NPC + LP;
 };
 
-template <int NPC>
-__device__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
+template <int NPC, int LP>
+__device__ __forceinline__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                                 int32_t *sweeps_out)
 {
-    using Gm = JacobiGeom<NPC>;
-    constexpr int LP = Gm::LP, RPL = Gm::RPL, PAIRS = Gm::PAIRS, LDC = Gm::LDC;
+    using Gm = JacobiGeom<NPC, LP>;
+    constexpr int RPL = Gm::RPL, PAIRS = Gm::PAIRS, LDC = Gm::LDC;
     __shared__ double C[NPC * LDC];  // column k at C[k * LDC]
     __shared__ double sv[NPC];
     __shared__ int s_rot;
@@ -107,7 +117,8 @@ __device__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sig
         C[k * LDC + i] = (k < n && i < n) ? R[(int64_t)i * ldr + k] : 0.0;
     }
     const int pair = tid / LP, sub = tid % LP;
-    const bool active = pair < PAIRS;
+    // every lane has a pair unless the pairs fill less than one wave
+    const bool active = PAIRS * LP >= Gm::THREADS || pair < PAIRS;
     const double tol2 = ((double)n * 0x1p-53) * ((double)n * 0x1p-53);
     constexpr int M = NPC - 1;
     int sweeps = 0;
@@ -134,8 +145,8 @@ __device__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sig
         // ((step + pair) mod M, (step - pair) mod M), advanced by one step at a time
         int pa = pair == 0 ? 0 : pair % M, qa = pair == 0 ? NPC - 1 : (M - pair % M) % M;
         for (int step = 0; step < M; step++) {
-            int p = active ? pa : 0, q = active ? qa : 0;
-            if (p > q) { const int t = p; p = q; q = t; }
+            // (p, q) and (q, p) give the same rotated pair, so slots are not reordered
+            const int p = active ? pa : 0, q = active ? qa : 0;
             pa = pa + 1 == M ? 0 : pa + 1;
             if (pair != 0) qa = qa + 1 == M ? 0 : qa + 1;
             double *cp = C + p * LDC + sub, *cq = C + q * LDC + sub;
@@ -145,16 +156,29 @@ __device__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sig
                 xp[r] = active ? cp[r * LP] : 0.0;
                 xq[r] = active ? cq[r * LP] : 0.0;
             }
-            double a = 0.0, b = 0.0, g = 0.0;
+            // up to four independent partial sums per dot product (short FMA chains)
+            constexpr int NA = RPL >= 4 ? 4 : RPL;
+            double pa_[NA], pb_[NA], pg_[NA];
+#pragma unroll
+            for (int t = 0; t < NA; t++) pa_[t] = pb_[t] = pg_[t] = 0.0;
 #pragma unroll
             for (int r = 0; r < RPL; r++) {
-                a = fma(xp[r], xp[r], a);
-                b = fma(xq[r], xq[r], b);
-                g = fma(xp[r], xq[r], g);
+                pa_[r % NA] = fma(xp[r], xp[r], pa_[r % NA]);
+                pb_[r % NA] = fma(xq[r], xq[r], pb_[r % NA]);
+                pg_[r % NA] = fma(xp[r], xq[r], pg_[r % NA]);
             }
-            a = group_sum<LP>(a);
-            b = group_sum<LP>(b);
-            g = group_sum<LP>(g);
+#pragma unroll
+            for (int t = NA / 2; t >= 1; t /= 2) {
+#pragma unroll
+                for (int u = 0; u < t; u++) {
+                    pa_[u] += pa_[u + t];
+                    pb_[u] += pb_[u + t];
+                    pg_[u] += pg_[u + t];
+                }
+            }
+            double a = group_sum<LP>(pa_[0]);
+            double b = group_sum<LP>(pb_[0]);
+            double g = group_sum<LP>(pg_[0]);
             if (active && g * g > tol2 * a * b) {
                 double c, s;
                 jacobi_rotation(a, b, g, c, s);
@@ -190,29 +214,52 @@ __device__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sig
     if (tid == 0 && sweeps_out) *sweeps_out = sweeps;
 }
 
-template <int NPC>
-__global__ __launch_bounds__(JacobiGeom<NPC>::THREADS)
+template <int NPC, int LP>
+__global__ __launch_bounds__((JacobiGeom<NPC, LP>::THREADS))
 void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps, int32_t *sweeps_out)
 {
-    jacobi_lds_body<NPC>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+    jacobi_lds_body<NPC, LP>(R, n, ldr, sigma, max_sweeps, sweeps_out);
 }
 
 // Many independent problems of one width class in one launch: workgroup b takes entry
 // b of tab (3 int64 each: element offset of its n x n R in R, offset of its sigma, n).
-template <int NPC>
-__global__ __launch_bounds__(JacobiGeom<NPC>::THREADS)
+template <int NPC, int LP>
+__global__ __launch_bounds__((JacobiGeom<NPC, LP>::THREADS))
 void k_jacobi_batch(const double *R, double *sigma, const int64_t *tab, int max_sweeps)
 {
     const int64_t *e = tab + 3 * (int64_t)blockIdx.x;
     const int n = (int)e[2];
-    jacobi_lds_body<NPC>(R + e[0], n, n, sigma + e[1], max_sweeps, nullptr);
+    jacobi_lds_body<NPC, LP>(R + e[0], n, n, sigma + e[1], max_sweeps, nullptr);
+}
+
+// Lanes per pair for a width class: FIGARO_JACOBI_LP (4, 8 or 16) when it is set and
+// valid for the class, else the measured default.
+int jacobi_lanes(int npc)
+{
+    static const int forced = [] {
+        const char *v = std::getenv("FIGARO_JACOBI_LP");
+        return v ? std::atoi(v) : 0;
+    }();
+    if ((forced == 4 || forced == 8 || forced == 16) && forced <= npc) return forced;
+    return npc <= 8 ? npc : 16;
 }
 
 template <int NPC>
 hipError_t launch_npc(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                       int32_t *sweeps_out, hipStream_t s)
 {
-    k_jacobi_lds<NPC><<<1, JacobiGeom<NPC>::THREADS, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+    const int lp = jacobi_lanes(NPC);
+    if constexpr (NPC >= 16) {
+        if (lp == 16) {
+            k_jacobi_lds<NPC, 16><<<1, JacobiGeom<NPC, 16>::THREADS, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+            return hipGetLastError();
+        }
+    }
+    if (lp == 8) {
+        k_jacobi_lds<NPC, 8><<<1, JacobiGeom<NPC, 8>::THREADS, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+        return hipGetLastError();
+    }
+    k_jacobi_lds<NPC, 4><<<1, JacobiGeom<NPC, 4>::THREADS, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
     return hipGetLastError();
 }
 
@@ -407,7 +454,18 @@ template <int NPC>
 hipError_t launch_batch_npc(const double *R, double *sigma, const int64_t *tab, int count, int max_sweeps,
                             hipStream_t s)
 {
-    k_jacobi_batch<NPC><<<count, JacobiGeom<NPC>::THREADS, 0, s>>>(R, sigma, tab, max_sweeps);
+    const int lp = jacobi_lanes(NPC);
+    if constexpr (NPC >= 16) {
+        if (lp == 16) {
+            k_jacobi_batch<NPC, 16><<<count, JacobiGeom<NPC, 16>::THREADS, 0, s>>>(R, sigma, tab, max_sweeps);
+            return hipGetLastError();
+        }
+    }
+    if (lp == 8) {
+        k_jacobi_batch<NPC, 8><<<count, JacobiGeom<NPC, 8>::THREADS, 0, s>>>(R, sigma, tab, max_sweeps);
+        return hipGetLastError();
+    }
+    k_jacobi_batch<NPC, 4><<<count, JacobiGeom<NPC, 4>::THREADS, 0, s>>>(R, sigma, tab, max_sweeps);
     return hipGetLastError();
 }
 

@@ -55,6 +55,12 @@ __device__ inline double readlane_f64(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
+__device__ inline double readlane_t(double v, int l) { return readlane_f64(v, l); }
+__device__ inline float readlane_t(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // Hardware reciprocal / reciprocal square root refined by two Newton steps.
 __device__ inline double rcp_refined(double x)
 {
@@ -290,21 +296,29 @@ __device__ inline void wg_flush(WgState<NP, Tacc> &st, int width)
 template <int NP, typename Tacc>
 __device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> &st, int jstart, int width)
 {
-    constexpr int RPT = WaveGeom<NP>::RPT;
+    constexpr int RPT = WaveGeom<NP>::RPT, H = WaveGeom<NP>::H;
     const int k = st.k;
     const bool col_ok = k < width;
     for (int j = jstart; j < width; j++) {
-        __builtin_amdgcn_wave_barrier();
-        if (k == j) {
-#pragma unroll
-            for (int i = 0; i < RPT; i++) st.xb[i] = x[i];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // Column j of this wave's rows.  With one row set per wave it is read from lane j
+        // into scalar registers (no LDS traffic); with several, lane j of each row set
+        // stages it in LDS (a per-row-set select of lane reads costs more than that).
         Tacc xj[RPT];
+        if constexpr (H == 1) {
 #pragma unroll
-        for (int i = 0; i < RPT; i++) xj[i] = st.xb[i];
+            for (int i = 0; i < RPT; i++) xj[i] = readlane_t(x[i], j);
+        } else {
+            __builtin_amdgcn_wave_barrier();
+            if (k == j) {
+#pragma unroll
+                for (int i = 0; i < RPT; i++) st.xb[i] = x[i];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int i = 0; i < RPT; i++) xj[i] = st.xb[i];
+        }
         double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < RPT; i++) dp[i & 3] += (double)xj[i] * (double)x[i];
