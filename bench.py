@@ -100,16 +100,8 @@ def prefix_instance(inst, frac):
     return W.Instance(np.ascontiguousarray(inst.A[:m1]), np.ascontiguousarray(inst.B[:m2]), kA, kB)
 
 
-def sigma_lanes(n):
-    npc = 8
-    while npc < n:
-        npc *= 2
-    return min(16, 1024 // npc)
-
-
-def sigma_rounds(n):
-    t = sigma_lanes(n)
-    return 14 if t >= 16 else 18 if t >= 8 else 24 if t >= 4 else 56
+# multisection of the bidiagonal route: points per round and rounds per singular value
+MSECT_POINTS, MSECT_ROUNDS = 256, 7
 
 
 def stage_work(inst, two_sided, precision, sweeps):
@@ -128,9 +120,10 @@ def stage_work(inst, two_sided, precision, sweeps):
         "tsqr_tails": ("alu", flops(TA, n1) + flops(R2, n2)),
         # one sweep: n(n-1)/2 pairs, 3 dot products and a rotation of two n-vectors (12 n flops)
         "jacobi": ("alu", 6.0 * N * N * (N - 1) * sweeps / 1e12),
-        # bidiagonalisation (8 n^3 / 3) + Sturm counts (n values x lanes x rounds x 2n steps x 3 flops)
-        "sigma": ("alu", (8.0 * N ** 3 / 3 + N * sigma_lanes(N) * sigma_rounds(N) * 2 * N * 3) / 1e12
-                  if N <= 128 else 6.0 * N * N * (N - 1) * sweeps / 1e12),
+        # Householder bidiagonalisation of an n x n matrix: 8 n^3 / 3
+        "sigma_bidiag": ("alu", 8.0 * N ** 3 / 3 / 1e12),
+        # Sturm counts: n values x points x rounds x (2n - 1) steps x 3 flops
+        "sigma_msect": ("alu", N * MSECT_POINTS * MSECT_ROUNDS * (2 * N - 1) * 3.0 / 1e12),
     }
     return work
 
@@ -141,7 +134,8 @@ STAGE_KERNELS = {
     "tsqr_m1": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
     "tsqr_m2": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
     "jacobi": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_jacobi_lds"),
-    "sigma": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_sigma_gk"),
+    "sigma_bidiag": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_sigma_gk"),
+    "sigma_msect": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_sigma_msect"),
 }
 
 
@@ -174,7 +168,8 @@ def roofline(form, work, precision):
         return {"kernel": dom, "bound": "hbm", "achieved": amount / t, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": amount / t / PEAK_HBM_GBS, "traffic": None, "launch_ms": per_launch_ms}
     # the FP32 forms' TSQR runs in FP32; sigma always runs in FP64
-    peak = PEAK_FP64_TFLOPS if (dom in ("jacobi", "sigma") or precision == "fp64") else PEAK_FP32_TFLOPS
+    peak = PEAK_FP64_TFLOPS if (dom in ("jacobi", "sigma_bidiag", "sigma_msect") or precision == "fp64") \
+        else PEAK_FP32_TFLOPS
     return {"kernel": dom, "bound": "alu", "achieved": amount / t, "peak": peak, "unit": "TFLOP/s",
             "frac": amount / t / peak, "traffic": None, "launch_ms": per_launch_ms}
 

@@ -148,14 +148,24 @@ int figaro_inspect(const figaro_table *A, const figaro_table *B, int32_t precisi
                    void *ws, size_t ws_bytes, figaro_view *out);
 
 /*
- * Workspace bytes needed by figaro_sigma for an n x n R.
+ * Workspace bytes needed by figaro_sigma, figaro_sigma_jacobi and
+ * figaro_sigma_bidiag for an n x n R.
  */
 int figaro_sigma_workspace_size(int64_t n, size_t *bytes);
 
 /*
  * Singular values of R (equal to those of the join matrix; Related Works: SVD
- * through QR) by one-sided (Hestenes) Jacobi in FP64: rotations on column
- * pairs in a parallel (round-robin) order until a sweep finds every pair
+ * through QR), descending, in FP64: by the bidiagonal route of
+ * figaro_sigma_bidiag for n <= 128 and by the block one-sided Jacobi of
+ * figaro_sigma_jacobi for 128 < n <= 512.  Arguments, workspace and errors as
+ * those two.
+ */
+int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The singular values by one-sided (Hestenes) Jacobi in FP64: rotations on
+ * column pairs in a parallel (round-robin) order until a sweep finds every pair
  * orthogonal to |c_p . c_q| <= n 2^-53 |c_p||c_q| (at most 60 sweeps).
  * n <= 128: one workgroup with R in LDS; 128 < n <= 512: block Jacobi over
  * blocks of 16 columns, one workgroup per block pair, with bounded grid-wide
@@ -166,19 +176,23 @@ int figaro_sigma_workspace_size(int64_t n, size_t *bytes);
  *   ws     device workspace of figaro_sigma_workspace_size() bytes, 256-byte
  *          aligned; afterwards its first int32 holds the number of sweeps
  *          (-1 if a bounded wait expired).
+ * FIGARO_EINVAL for n outside [1, 512], NULL pointers, ldr < n or a misaligned
+ * workspace; FIGARO_EWORKSPACE if ws_bytes is too small.
  */
-int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma,
-                 void *ws, size_t ws_bytes, void *stream);
+int figaro_sigma_jacobi(const double *R, int64_t n, int64_t ldr, double *sigma,
+                        void *ws, size_t ws_bytes, void *stream);
 
 /*
- * The same singular values by the route of a dense SVD (the paper's SVD of R):
- * Householder bidiagonalisation B = U^T R V in one workgroup (R in LDS;
- * reflector j on column j, then on row j, with the TSQR's reflector
+ * The singular values by the route of a dense SVD (the paper's SVD of R):
+ * Householder bidiagonalisation B = U^T R V by one wavefront (R in LDS;
+ * reflector k on column k, then on row k, with the TSQR's reflector
  * conventions), then the singular values of the bidiagonal as the positive
  * eigenvalues of its Golub-Kahan tridiagonal (zero diagonal, off-diagonals
- * d1, e1, d2, ...) by multisection on Sturm counts, to an interval below
- * 2^-53 of the Gershgorin bound.  n <= 128 (FIGARO_EINVAL above).  Arguments,
- * workspace and errors as figaro_sigma (the sweep count is set to 0).
+ * d1, e1, d2, ...) by multisection on Sturm counts, one workgroup per value
+ * and 256 points per round, to an interval below 2^-53 of the Gershgorin
+ * bound.  n <= 128 (FIGARO_EINVAL above).  Arguments, workspace and errors as
+ * figaro_sigma_jacobi (the sweep count is set to 0); the workspace also
+ * carries the multisection inputs between the two kernels.
  */
 int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma,
                         void *ws, size_t ws_bytes, void *stream);
@@ -197,7 +211,8 @@ const char *figaro_last_error(void);
  * Per-stage device timing, for measurement.  Off by default.  When on, every
  * kernel launch of the library is bracketed by two hipEventRecord calls on
  * its stream, under a stage name ("group", "scan", "assemble", "tsqr_leaf_m1",
- * "tsqr_leaf_m2", "tsqr_tree", "tsqr_root", "sign", "jacobi").
+ * "tsqr_leaf_m2", "tsqr_tree", "tsqr_root", "sign", "jacobi", "sigma_bidiag",
+ * "sigma_msect").
  * figaro_timing_read is synchronous: it waits for the recorded events, writes
  * up to `cap` entries (stage name, total milliseconds, number of launches)
  * accumulated since the previous read, sets *count and clears the record.

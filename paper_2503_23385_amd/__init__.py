@@ -57,7 +57,7 @@ class Instance(ctypes.Structure):
 
 EXPORTS = [
     "figaro_r_workspace_size", "figaro_r", "figaro_compact", "figaro_inspect",
-    "figaro_sigma_workspace_size", "figaro_sigma", "figaro_sigma_bidiag", "figaro_status", "figaro_last_error",
+    "figaro_sigma_workspace_size", "figaro_sigma", "figaro_sigma_jacobi", "figaro_sigma_bidiag", "figaro_status", "figaro_last_error",
     "figaro_plan_create", "figaro_plan_workspace_size", "figaro_plan_offsets",
     "figaro_plan_execute", "figaro_plan_destroy", "figaro_timing_enable", "figaro_timing_read",
 ]
@@ -82,6 +82,7 @@ def lib():
     L.figaro_inspect.argtypes = [TP, TP, I32, P, SZ, ctypes.POINTER(View)]
     L.figaro_sigma_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
     L.figaro_sigma.argtypes = [P, I64, I64, P, P, SZ, P]
+    L.figaro_sigma_jacobi.argtypes = [P, I64, I64, P, P, SZ, P]
     L.figaro_sigma_bidiag.argtypes = [P, I64, I64, P, P, SZ, P]
     L.figaro_status.argtypes = [P, P, ctypes.POINTER(I32)]
     L.figaro_last_error.argtypes = []
@@ -176,18 +177,21 @@ def sigma_workspace_size(n) -> int:
     return nb.value
 
 
-def sigma(R, out=None, ws=None, stream=None, method="jacobi"):
+def sigma(R, out=None, ws=None, stream=None, method="default"):
     """Singular values (descending, FP64) of a square device matrix R.
 
-    method: "jacobi" (one-sided Jacobi, any n <= 512) or "bidiag" (bidiagonalisation +
-    multisection, n <= 128)."""
+    method: "default" (bidiagonal route for n <= 128, Jacobi above), "jacobi" (one-sided
+    Jacobi, any n <= 512) or "bidiag" (bidiagonalisation + multisection, n <= 128)."""
     torch = _torch()
     n = R.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=R.device)
     if ws is None:
         ws = alloc_workspace(sigma_workspace_size(n), R.device)
-    fn = lib().figaro_sigma_bidiag if method == "bidiag" else lib().figaro_sigma
+    fns = {"default": lib().figaro_sigma, "jacobi": lib().figaro_sigma_jacobi, "bidiag": lib().figaro_sigma_bidiag}
+    if method not in fns:
+        raise ValueError(f"unknown sigma method {method!r}")
+    fn = fns[method]
     _check(fn(ctypes.c_void_p(R.data_ptr()), n, R.stride(0),
                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                               ws.numel(), _stream_ptr(stream)))

@@ -154,6 +154,10 @@ int jacobi_class(int n);
 hipError_t launch_jacobi_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count,
                                hipStream_t s);
 // The bidiagonal route for n <= 128: bidiagonalisation + multisection (ctrl[0] = 0 sweeps).
-hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, double *sigma, int32_t *ctrl, hipStream_t s);
+int64_t sigma_bidiag_scratch_doubles(int n);  // multisection inputs of the bidiagonal route (n <= 128)
+// bidiagonalisation of R (one workgroup), leaving the multisection inputs in msin
+hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s);
+// multisection: one workgroup per singular value
+hipError_t launch_sigma_msect(const double *msin, int n, double *sigma, hipStream_t s);
 
 }  // namespace figaro

@@ -595,7 +595,8 @@ int figaro_sigma_workspace_size(int64_t n, size_t *bytes)
 {
     if (n < 1 || n > FIGARO_MAX_N) return fail(FIGARO_EINVAL, "n out of range");
     if (!bytes) return fail(FIGARO_EINVAL, "bytes is NULL");
-    *bytes = kAlign + sizeof(double) * (size_t)jacobi_scratch_doubles((int)n);
+    *bytes = kAlign + sizeof(double) * (size_t)std::max(jacobi_scratch_doubles((int)n),
+                                                        sigma_bidiag_scratch_doubles((int)n));
     return FIGARO_OK;
 }
 
@@ -616,16 +617,48 @@ int sigma_common(const double *R, int64_t n, int64_t ldr, double *sigma, void *w
 
 }  // namespace
 
+namespace {
+
+int sigma_jacobi(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, hipStream_t stream)
+{
+    Stage st("jacobi", stream);
+    double *scratch = jacobi_scratch_doubles((int)n) ? at<double>(ws, kAlign) : nullptr;
+    hipError_t e = launch_jacobi(R, (int)n, ldr, sigma, 60, (int32_t *)ws, scratch, stream);
+    if (e != hipSuccess) return hip_fail(e, "jacobi");
+    return FIGARO_OK;
+}
+
+int sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, hipStream_t stream)
+{
+    double *msin = at<double>(ws, kAlign);
+    {
+        Stage st("sigma_bidiag", stream);
+        hipError_t e = launch_sigma_bidiag(R, (int)n, ldr, (int32_t *)ws, msin, stream);
+        if (e != hipSuccess) return hip_fail(e, "sigma bidiagonalisation");
+    }
+    Stage st("sigma_msect", stream);
+    hipError_t e = launch_sigma_msect(msin, (int)n, sigma, stream);
+    if (e != hipSuccess) return hip_fail(e, "sigma multisection");
+    return FIGARO_OK;
+}
+
+}  // namespace
+
 int figaro_sigma(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,
                  void *stream)
 {
     int rc = sigma_common(R, n, ldr, sigma, ws, ws_bytes);
     if (rc) return rc;
-    Stage st("jacobi", (hipStream_t)stream);
-    double *scratch = jacobi_scratch_doubles((int)n) ? at<double>(ws, kAlign) : nullptr;
-    hipError_t e = launch_jacobi(R, (int)n, ldr, sigma, 60, (int32_t *)ws, scratch, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "jacobi");
-    return FIGARO_OK;
+    if (n <= 128) return sigma_bidiag(R, n, ldr, sigma, ws, (hipStream_t)stream);
+    return sigma_jacobi(R, n, ldr, sigma, ws, (hipStream_t)stream);
+}
+
+int figaro_sigma_jacobi(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    int rc = sigma_common(R, n, ldr, sigma, ws, ws_bytes);
+    if (rc) return rc;
+    return sigma_jacobi(R, n, ldr, sigma, ws, (hipStream_t)stream);
 }
 
 int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,
@@ -634,10 +667,7 @@ int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, 
     int rc = sigma_common(R, n, ldr, sigma, ws, ws_bytes);
     if (rc) return rc;
     if (n > 128) return fail(FIGARO_EINVAL, "the bidiagonal route takes n <= 128");
-    Stage st("sigma_bidiag", (hipStream_t)stream);
-    hipError_t e = launch_sigma_bidiag(R, (int)n, ldr, sigma, (int32_t *)ws, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "sigma (bidiagonal route)");
-    return FIGARO_OK;
+    return sigma_bidiag(R, n, ldr, sigma, ws, (hipStream_t)stream);
 }
 
 int figaro_timing_enable(int32_t on)

@@ -530,17 +530,15 @@ hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int
 namespace figaro {
 namespace {
 
-constexpr int kGkThreads = 1024;  // all of them run the multisection
-constexpr int kGkBidiag = 256;    // the first four waves run the bidiagonalisation
+constexpr int kGkThreads = 256;   // load and scale; wave 0 bidiagonalises
+constexpr int kMsThreads = 256;   // multisection points per round (one workgroup per value)
+constexpr int kMsRounds = 7;      // 257^7 > 2^55: the final interval is below 2^-53 of the bound
 
 template <int NPC>
 struct GkGeom {
-    static constexpr int TPC = (kGkBidiag / NPC) < 16 ? (kGkBidiag / NPC) : 16;  // bidiag threads per column / row
-    static constexpr int LDA = NPC + 1;
-    static constexpr int RPT = (NPC + TPC - 1) / TPC;  // elements per thread along a column / row
-    static constexpr int LPS = (kGkThreads / NPC) < 16 ? (kGkThreads / NPC) : 16;  // multisection lanes per value
-    // multisection rounds: (LPS + 1)^ITERS > 2^55, so the final interval is below 2^-53 of the bound
-    static constexpr int ITERS = LPS >= 16 ? 14 : LPS >= 8 ? 18 : LPS >= 4 ? 24 : 56;
+    static constexpr int LDA = NPC + 1;                 // row stride of A in LDS (odd: spreads banks)
+    static constexpr int CPL = NPC > 64 ? NPC / 64 : 1; // rows / columns per lane in the bidiagonalisation
+    static constexpr int CH = NPC < 16 ? NPC : 16;      // rows per chunk of the reflector loops
 };
 
 // Reflector scalars for (alpha, s = |x|^2): tau, beta, scl = 1 / (alpha - beta); tau = 0 if s is 0.
@@ -586,19 +584,168 @@ __device__ inline double wave_sum(double v)
     return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// Order the LDS accesses of the lanes of one wave (the only wave at work).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Householder bidiagonalisation of the n x n matrix A (LDS, row stride LDA) by one wave:
+// d receives the diagonal, e the superdiagonal of B = U^T A V.  Lane l owns rows and
+// columns l + 64 c.  Step k: the left reflector of column k (its entries are in
+// registers, left there by the previous step) is reduced with a wave sum and applied to
+// the columns j > k by their owners (a dot product and an update over rows k..n-1);
+// the updated row k comes back in registers, gives the right reflector, which the row
+// owners apply to the rows i > k, leaving column k + 1 in registers for step k + 1.
+// No workgroup barrier: the wave orders its own LDS accesses.
 template <int NPC>
-__global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n, int64_t ldr, double *sigma)
+__device__ void gk_bidiag_wave(double *A, double *vl, double *vr, double *dd, double *ee, int n, int lane)
+{
+    constexpr int LDA = GkGeom<NPC>::LDA, CPL = GkGeom<NPC>::CPL, CH = GkGeom<NPC>::CH;
+    double a[CPL];  // A[i][k] for this lane's rows i
+#pragma unroll
+    for (int c = 0; c < CPL; c++) {
+        const int i = lane + 64 * c;
+        a[c] = i < n ? A[i * LDA] : 0.0;
+    }
+    for (int k = 0; k < n; k++) {
+        // ---- left reflector from column k, rows k..n-1
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPL; c++) {
+            const int i = lane + 64 * c;
+            if (i > k && i < n) s = fma(a[c], a[c], s);
+        }
+        s = wave_sum(s);
+        double alpha = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPL; c++)
+            if (k / 64 == c) alpha = readlane_f64(a[c], k % 64);
+        double tau, beta, scl;
+        gk_reflector(alpha, s, tau, beta, scl);
+#pragma unroll
+        for (int c = 0; c < CPL; c++) {
+            const int i = lane + 64 * c;
+            if (i < NPC) vl[i] = i > k && i < n ? a[c] * scl : (i == k ? 1.0 : 0.0);
+        }
+        if (lane == 0) dd[k] = beta;
+        wave_sync();
+        double rk[CPL];  // A[k][j] for this lane's columns j, after the left reflector
+#pragma unroll
+        for (int c = 0; c < CPL; c++) {
+            const int j = lane + 64 * c;
+            if (tau != 0.0 && j > k && j < n) {
+                // whole chunks of CH rows from the one holding row k: vl is zero outside
+                // rows k..n-1 and rows n..NPC-1 of A are zero, so the extra rows add nothing
+                // and are written back unchanged
+                const int i0 = k - k % CH, i1 = n + (CH - n % CH) % CH;
+                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+                for (int i = i0; i < i1; i += CH) {
+                    double x[CH], u[CH];
+#pragma unroll
+                    for (int r = 0; r < CH; r++) {
+                        x[r] = A[(i + r) * LDA + j];
+                        u[r] = vl[i + r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < CH; r += 4) {
+                        w0 = fma(u[r], x[r], w0);
+                        if (r + 1 < CH) w1 = fma(u[r + 1], x[r + 1], w1);
+                        if (r + 2 < CH) w2 = fma(u[r + 2], x[r + 2], w2);
+                        if (r + 3 < CH) w3 = fma(u[r + 3], x[r + 3], w3);
+                    }
+                }
+                const double w = ((w0 + w1) + (w2 + w3)) * tau;
+                for (int i = i0; i < i1; i += CH) {
+                    double x[CH], u[CH];
+#pragma unroll
+                    for (int r = 0; r < CH; r++) {
+                        x[r] = A[(i + r) * LDA + j];
+                        u[r] = vl[i + r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < CH; r++) A[(i + r) * LDA + j] = fma(-w, u[r], x[r]);
+                }
+            }
+            rk[c] = j > k && j < n ? A[k * LDA + j] : 0.0;
+        }
+        if (k + 1 >= n) break;
+        // ---- right reflector from row k, columns k+1..n-1
+        s = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPL; c++) {
+            const int j = lane + 64 * c;
+            if (j > k + 1 && j < n) s = fma(rk[c], rk[c], s);
+        }
+        s = wave_sum(s);
+        alpha = 0.0;
+#pragma unroll
+        for (int c = 0; c < CPL; c++)
+            if ((k + 1) / 64 == c) alpha = readlane_f64(rk[c], (k + 1) % 64);
+        gk_reflector(alpha, s, tau, beta, scl);
+#pragma unroll
+        for (int c = 0; c < CPL; c++) {
+            const int j = lane + 64 * c;
+            if (j < NPC) vr[j] = j > k + 1 && j < n ? rk[c] * scl : (j == k + 1 ? 1.0 : 0.0);
+        }
+        if (lane == 0) ee[k] = beta;
+        wave_sync();
+#pragma unroll
+        for (int c = 0; c < CPL; c++) {
+            const int i = lane + 64 * c;
+            if (tau != 0.0 && i > k && i < n) {
+                // whole chunks of CH columns, as for the left reflector (vr is zero outside
+                // columns k+1..n-1, columns n..NPC-1 of A are zero)
+                const int j0 = (k + 1) - (k + 1) % CH, j1 = n + (CH - n % CH) % CH;
+                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+                for (int j = j0; j < j1; j += CH) {
+                    double x[CH], u[CH];
+#pragma unroll
+                    for (int r = 0; r < CH; r++) {
+                        x[r] = A[i * LDA + j + r];
+                        u[r] = vr[j + r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < CH; r += 4) {
+                        w0 = fma(x[r], u[r], w0);
+                        if (r + 1 < CH) w1 = fma(x[r + 1], u[r + 1], w1);
+                        if (r + 2 < CH) w2 = fma(x[r + 2], u[r + 2], w2);
+                        if (r + 3 < CH) w3 = fma(x[r + 3], u[r + 3], w3);
+                    }
+                }
+                const double w = ((w0 + w1) + (w2 + w3)) * tau;
+                for (int j = j0; j < j1; j += CH) {
+                    double x[CH], u[CH];
+#pragma unroll
+                    for (int r = 0; r < CH; r++) {
+                        x[r] = A[i * LDA + j + r];
+                        u[r] = vr[j + r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < CH; r++) A[i * LDA + j + r] = fma(-w, u[r], x[r]);
+                }
+            }
+            a[c] = i > k && i < n ? A[i * LDA + k + 1] : 0.0;
+        }
+        wave_sync();
+    }
+}
+
+template <int NPC>
+__global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n, int64_t ldr, double *msin,
+                                                         int32_t *ctrl)
 {
     using Gm = GkGeom<NPC>;
-    constexpr int TPC = Gm::TPC, LDA = Gm::LDA, RPT = Gm::RPT, LPS = Gm::LPS;
+    constexpr int LDA = Gm::LDA;
     __shared__ double A[NPC * LDA];
-    __shared__ double v[NPC];
+    __shared__ double vl[NPC], vr[NPC];
     __shared__ double dd[NPC], ee[NPC];
-    __shared__ double bb[2 * NPC];
     __shared__ double sc[2];
-    __shared__ double hi_s;
     __shared__ int s_exp;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (ctrl && tid < CTRL_WORDS) ctrl[tid] = 0;  // no sweeps: this route does not iterate
     if (tid == 0) s_exp = INT_MIN;
     for (int e = tid; e < NPC * NPC; e += kGkThreads) {
         const int i = e / NPC, j = e - i * NPC;
@@ -619,166 +766,143 @@ __global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n,
         x = ldexp(x, -ex0);
     }
     __syncthreads();
-    const bool bid = tid < kGkBidiag;
-    const int c = tid / TPC, p = tid % TPC;  // column (or row) handled, part of it
-    for (int k = 0; k < n; k++) {
-        // ---- left reflector on column k, rows k..n-1
-        if (wv == 0) {
-            double s = 0.0;
-            for (int i = k + 1 + lane; i < n; i += 64) s = fma(A[i * LDA + k], A[i * LDA + k], s);
-            s = wave_sum(s);
-            double tau, beta, scl;
-            gk_reflector(A[k * LDA + k], s, tau, beta, scl);
-            for (int i = k + 1 + lane; i < n; i += 64) v[i] = A[i * LDA + k] * scl;
-            if (lane == 0) {
-                v[k] = 1.0;
-                sc[0] = tau;
-                dd[k] = beta;
-            }
-        }
-        __syncthreads();
-        if (bid) {
-            const double tau = sc[0];
-            const int j = c;
-            if (tau != 0.0 && j > k && j < n) {
-                double w = 0.0;
-#pragma unroll 8
-                for (int r = 0; r < RPT; r++) {
-                    const int i = k + p + r * TPC;
-                    if (i < n) w = fma(v[i], A[i * LDA + j], w);
-                }
-                w = dpp_group_sum<TPC>(w) * tau;
-#pragma unroll 8
-                for (int r = 0; r < RPT; r++) {
-                    const int i = k + p + r * TPC;
-                    if (i < n) A[i * LDA + j] = fma(-w, v[i], A[i * LDA + j]);
-                }
-            }
-        }
-        __syncthreads();
-        if (k + 1 >= n) break;
-        // ---- right reflector on row k, columns k+1..n-1
-        if (wv == 0) {
-            double s = 0.0;
-            for (int j = k + 2 + lane; j < n; j += 64) s = fma(A[k * LDA + j], A[k * LDA + j], s);
-            s = wave_sum(s);
-            double tau, beta, scl;
-            gk_reflector(A[k * LDA + k + 1], s, tau, beta, scl);
-            for (int j = k + 2 + lane; j < n; j += 64) v[j] = A[k * LDA + j] * scl;
-            if (lane == 0) {
-                v[k + 1] = 1.0;
-                sc[1] = tau;
-                ee[k] = beta;
-            }
-        }
-        __syncthreads();
-        if (bid) {
-            const double tau = sc[1];
-            const int i = c;
-            if (tau != 0.0 && i > k && i < n) {
-                double w = 0.0;
-#pragma unroll 8
-                for (int r = 0; r < RPT; r++) {
-                    const int j = k + 1 + p + r * TPC;
-                    if (j < n) w = fma(A[i * LDA + j], v[j], w);
-                }
-                w = dpp_group_sum<TPC>(w) * tau;
-#pragma unroll 8
-                for (int r = 0; r < RPT; r++) {
-                    const int j = k + 1 + p + r * TPC;
-                    if (j < n) A[i * LDA + j] = fma(-w, v[j], A[i * LDA + j]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // ---- multisection on the Golub-Kahan tridiagonal T (zero diagonal, off-diagonals
-    // d1, e1, d2, ...): sigma_k (k-th largest) by LPS lanes.  The number of eigenvalues of
-    // T below x is the number of sign changes of its characteristic sequence
-    // p_0 = 1, p_1 = -x, p_i = -x p_{i-1} - b_{i-1}^2 p_{i-2} (a zero p_i counts as a change,
-    // like a zero pivot taken negative).  d and e are scaled once more so that the
-    // Gershgorin bound lies in [1, 2); the pair (p_{i-1}, p_i) is rescaled by a power of
-    // two every 16 steps, which keeps it in range and does not change any sign.
+    if (wv == 0) gk_bidiag_wave<NPC>(A, vl, vr, dd, ee, n, lane);
+    __syncthreads();
+    // ---- inputs of the multisection: the Golub-Kahan tridiagonal T (zero diagonal,
+    // off-diagonals d1, e1, d2, ...) scaled once more so that its Gershgorin bound lies in
+    // [1, 2); msin = {bound, total binary exponent, squared off-diagonals}.
     if (tid == 0) {
         double h = 0.0;
         for (int i = 0; i < n; i++) {
             const double a = fabs(dd[i]) + (i + 1 < n ? fabs(ee[i]) : 0.0) + (i > 0 ? fabs(ee[i - 1]) : 0.0);
             h = fmax(h, a);
         }
-        hi_s = h;
-        sc[0] = h > 0.0 ? (double)ilogb(h) : 0.0;
+        const int ex = h > 0.0 ? ilogb(h) : 0;
+        sc[0] = (double)ex;
+        msin[0] = ldexp(h, -ex);
+        msin[1] = (double)(ex + ex0);
     }
     __syncthreads();
     const int ex = (int)sc[0];
     for (int i = tid; i < 2 * n - 1; i += kGkThreads) {
         const double b = ldexp((i & 1) ? ee[i >> 1] : dd[i >> 1], -ex);
-        bb[i] = b * b;
+        msin[2 + i] = b * b;
     }
-    __syncthreads();
-    const double hi = ldexp(hi_s, -ex);
-    const int k = tid / LPS, q = tid % LPS;
-    const bool act = k < n;
-    const int m = 2 * n - 1;  // off-diagonals of the 2n x 2n tridiagonal
-    double lo = 0.0, up = hi;
-    const int target = 2 * n - k;  // sigma_k < x  <=>  count(x) >= 2n - k
-    for (int it = 0; it < Gm::ITERS; it++) {
-        const double x = lo + (up - lo) * (double)(q + 1) / (double)(LPS + 1);
-        int cnt = 0;
-        if (act) {
-            double p0 = 1.0, p1 = -x;
-            cnt = p1 < 0.0;
-            for (int i0 = 0; i0 < m; i0 += 16) {
+}
+
+// Number of eigenvalues of the Golub-Kahan tridiagonal (zero diagonal, squared
+// off-diagonals bb[0..m-1]) below x: the sign changes of its characteristic sequence
+// p_0 = 1, p_1 = -x, p_i = -x p_{i-1} - bb_{i-2} p_{i-2} (a zero p_i counts as a change,
+// like a zero pivot taken negative).  The pair (p_{i-1}, p_i) is rescaled by a power of
+// two every 16 steps, which keeps it in range and changes no sign.
+__device__ inline int gk_sturm_count(const double *bb, int m, double x)
+{
+    double p0 = 1.0, p1 = -x;
+    int cnt = p1 < 0.0;
+    // whole chunks of 16 steps with their coefficients loaded up front (the recurrence
+    // does not wait on LDS), then the remaining steps
+    const int mfull = m - m % 16;
+    for (int i0 = 0; i0 < m; i0 += 16) {
+        if (i0 < mfull) {
+            double b[16];
 #pragma unroll
-                for (int u = 0; u < 16; u++) {
-                    const int i = i0 + u;
-                    if (i < m) {
-                        double p2 = fma(-x, p1, -bb[i] * p0);
-                        if (p2 == 0.0) p2 = p1 < 0.0 ? DBL_MIN : -DBL_MIN;
-                        cnt += (p2 < 0.0) != (p1 < 0.0);
-                        p0 = p1;
-                        p1 = p2;
-                    }
-                }
-                const int e2 = ilogb(fmax(fabs(p0), fabs(p1)));
-                p0 = ldexp(p0, -e2);
-                p1 = ldexp(p1, -e2);
+            for (int u = 0; u < 16; u++) b[u] = bb[i0 + u];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                double p2 = fma(-x, p1, -b[u] * p0);
+                if (p2 == 0.0) p2 = p1 < 0.0 ? DBL_MIN : -DBL_MIN;
+                cnt += (p2 < 0.0) != (p1 < 0.0);
+                p0 = p1;
+                p1 = p2;
+            }
+        } else {
+            for (int i = i0; i < m; i++) {
+                double p2 = fma(-x, p1, -bb[i] * p0);
+                if (p2 == 0.0) p2 = p1 < 0.0 ? DBL_MIN : -DBL_MIN;
+                cnt += (p2 < 0.0) != (p1 < 0.0);
+                p0 = p1;
+                p1 = p2;
             }
         }
-        // new interval: the largest point whose count is below target and the next one
-        const bool below = cnt < target;
-        double lo_new = below ? x : lo, up_new = below ? up : x;
-#pragma unroll
-        for (int off = 1; off < LPS; off <<= 1) {
-            lo_new = fmax(lo_new, __shfl_xor(lo_new, off, 64));
-            up_new = fmin(up_new, __shfl_xor(up_new, off, 64));
-        }
-        lo = lo_new;
-        up = up_new;
+        const int e2 = ilogb(fmax(fabs(p0), fabs(p1)));
+        p0 = ldexp(p0, -e2);
+        p1 = ldexp(p1, -e2);
     }
-    if (act && q == 0) sigma[k] = ldexp(0.5 * (lo + up), ex + ex0);
+    return cnt;
+}
+
+// Multisection for the singular values of the bidiagonal: workgroup k locates sigma_k
+// (the k-th largest), which lies in [0, bound].  sigma_k < x exactly when at least 2n - k
+// eigenvalues of T lie below x.  Each round evaluates the count at kMsThreads points
+// evenly inside the current interval and keeps the gap between the last point whose count
+// is below 2n - k and the first point whose count is not.
+__global__ __launch_bounds__(kMsThreads) void k_sigma_msect(const double *msin, int n, double *sigma)
+{
+    constexpr int NW = kMsThreads / 64;
+    __shared__ double bb[255];
+    __shared__ int s_lo[2][NW], s_up[2][NW];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int k = blockIdx.x, m = 2 * n - 1;
+    for (int i = tid; i < m; i += kMsThreads) bb[i] = msin[2 + i];
+    const double bound = msin[0];
+    const int ex = (int)msin[1];
+    __syncthreads();
+    const int target = 2 * n - k;
+    const double step = 1.0 / (double)(kMsThreads + 1);
+    double lo = 0.0, up = bound;
+    for (int it = 0; it < kMsRounds; it++) {
+        const double w = up - lo;
+        const double x = lo + w * ((double)(tid + 1) * step);
+        const bool below = gk_sturm_count(bb, m, x) < target;
+        const unsigned long long mask = __ballot(below);
+        if (lane == 0) {
+            // last point of this wave below the target, first one not below
+            s_lo[it & 1][wv] = mask ? wv * 64 + 63 - __builtin_clzll(mask) : -1;
+            s_up[it & 1][wv] = ~mask ? wv * 64 + __builtin_ctzll(~mask) : kMsThreads;
+        }
+        __syncthreads();
+        int ilo = -1, iup = kMsThreads;
+#pragma unroll
+        for (int q = 0; q < NW; q++) {
+            ilo = max(ilo, s_lo[it & 1][q]);
+            iup = min(iup, s_up[it & 1][q]);
+        }
+        // every thread recomputes the two points exactly as their lanes did
+        const double xlo = ilo >= 0 ? lo + w * ((double)(ilo + 1) * step) : lo;
+        const double xup = iup < kMsThreads ? lo + w * ((double)(iup + 1) * step) : up;
+        lo = xlo;
+        up = xup;
+    }
+    if (tid == 0) sigma[k] = ldexp(0.5 * (lo + up), ex);
 }
 
 template <int NPC>
-hipError_t launch_gk(const double *R, int n, int64_t ldr, double *sigma, int32_t *ctrl, hipStream_t s)
+hipError_t launch_gk(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s)
 {
-    k_sigma_gk<NPC><<<1, kGkThreads, 0, s>>>(R, n, ldr, sigma);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !ctrl) return e;
-    k_jacobi_blk_init<<<1, 64, 0, s>>>(nullptr, 0, 0, nullptr, 0, ctrl);  // sweeps = 0
+    k_sigma_gk<NPC><<<1, kGkThreads, 0, s>>>(R, n, ldr, msin, ctrl);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, double *sigma, int32_t *ctrl, hipStream_t s)
+int64_t sigma_bidiag_scratch_doubles(int n) { return n <= 128 ? 2 * (int64_t)n + 2 : 0; }
+
+hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s)
 {
-    if (n <= 0) return hipErrorInvalidValue;
-    if (n <= 8) return launch_gk<8>(R, n, ldr, sigma, ctrl, s);
-    if (n <= 16) return launch_gk<16>(R, n, ldr, sigma, ctrl, s);
-    if (n <= 32) return launch_gk<32>(R, n, ldr, sigma, ctrl, s);
-    if (n <= 64) return launch_gk<64>(R, n, ldr, sigma, ctrl, s);
-    if (n <= 128) return launch_gk<128>(R, n, ldr, sigma, ctrl, s);
+    if (n <= 0 || !msin) return hipErrorInvalidValue;
+    if (n <= 8) return launch_gk<8>(R, n, ldr, ctrl, msin, s);
+    if (n <= 16) return launch_gk<16>(R, n, ldr, ctrl, msin, s);
+    if (n <= 32) return launch_gk<32>(R, n, ldr, ctrl, msin, s);
+    if (n <= 64) return launch_gk<64>(R, n, ldr, ctrl, msin, s);
+    if (n <= 128) return launch_gk<128>(R, n, ldr, ctrl, msin, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_sigma_msect(const double *msin, int n, double *sigma, hipStream_t s)
+{
+    if (n <= 0 || n > 128 || !msin) return hipErrorInvalidValue;
+    k_sigma_msect<<<n, kMsThreads, 0, s>>>(msin, n, sigma);
+    return hipGetLastError();
 }
 
 }  // namespace figaro

@@ -109,8 +109,32 @@ def test_sigma_host_checks():
     n = ctypes.c_size_t(0)
     assert L.figaro_sigma_workspace_size(0, ctypes.byref(n)) == fg.FIGARO_EINVAL
     assert L.figaro_sigma_workspace_size(8, ctypes.byref(n)) == 0 and n.value > 0
-    assert L.figaro_sigma(None, 8, 8, ctypes.c_void_p(256), ctypes.c_void_p(256), n.value, None) == fg.FIGARO_EINVAL
-    assert L.figaro_sigma(ctypes.c_void_p(256), 8, 4, ctypes.c_void_p(256), ctypes.c_void_p(256), n.value, None) == fg.FIGARO_EINVAL
+    p = ctypes.c_void_p(256)
+    for fn in (L.figaro_sigma, L.figaro_sigma_jacobi, L.figaro_sigma_bidiag):
+        assert fn(None, 8, 8, p, p, n.value, None) == fg.FIGARO_EINVAL          # R is NULL
+        assert fn(p, 8, 4, p, p, n.value, None) == fg.FIGARO_EINVAL             # ldr < n
+        assert fn(p, 8, 8, p, ctypes.c_void_p(264), n.value, None) == fg.FIGARO_EINVAL  # misaligned
+        assert fn(p, 8, 8, p, p, n.value - 1, None) == fg.FIGARO_EWORKSPACE    # workspace too small
+        assert fn(p, 513, 513, p, p, 1 << 30, None) == fg.FIGARO_EINVAL         # n above 512
+
+
+def test_sigma_workspace_covers_both_routes():
+    """The workspace holds the multisection inputs of the bidiagonal route (2n + 2 doubles
+    after the 256-byte control block) up to n = 128 and the block-Jacobi columns above."""
+    L = fg.lib()
+    for k, want in ((8, 256 + 8 * 18), (64, 256 + 8 * 130), (128, 256 + 8 * 258), (200, 256 + 8 * 256 * 256),
+                    (512, 256 + 8 * 512 * 512)):
+        n = ctypes.c_size_t(0)
+        assert L.figaro_sigma_workspace_size(k, ctypes.byref(n)) == 0
+        assert n.value == want, (k, n.value, want)
+
+
+def test_sigma_bidiag_rejects_wide():
+    L = fg.lib()
+    n = ctypes.c_size_t(0)
+    assert L.figaro_sigma_workspace_size(200, ctypes.byref(n)) == 0
+    p = ctypes.c_void_p(256)
+    assert L.figaro_sigma_bidiag(p, 200, 200, p, p, n.value, None) == fg.FIGARO_EINVAL
 
 
 def test_plan_host_checks():
