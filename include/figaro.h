@@ -246,15 +246,17 @@ int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
                         int64_t *r_total, int64_t *s_total);
 /*
  * Enqueue the whole batch on `stream`.  The first call uploads a small device
- * table (24 bytes per instance, synchronous; freed by figaro_plan_destroy).
+ * table (32 bytes per instance, synchronous; freed by figaro_plan_destroy).
  * The first call with a given (ws, R, sigma) captures the launch sequence into
  * a HIP graph on a private stream; every call (the first included) launches
  * that graph on `stream`.
  * Inside the graph the instances' R pipelines run as up to 8 parallel
  * branches (largest instances first, each to the least-loaded branch); each
  * branch owns one slice of `ws` and runs its instances in order.  After the
- * branches join, sigma of all instances is computed by one-sided Jacobi in one
- * launch per width class (one workgroup per instance).  Instances need
+ * branches join, sigma of all instances is computed by the bidiagonal route of
+ * figaro_sigma_bidiag, two launches per width class (one bidiagonalisation
+ * workgroup per instance, then one multisection workgroup per singular value);
+ * its inputs sit in `ws` after the branches' slices.  Instances need
  * n1 + n2 <= 128.  Calls that share `ws` must not overlap.
  */
 int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,

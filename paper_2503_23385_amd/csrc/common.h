@@ -147,17 +147,18 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
 int64_t jacobi_scratch_doubles(int n);
 hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                          int32_t *ctrl, double *scratch, hipStream_t s);
-// Width class (padded n: 8..128) of the LDS Jacobi; 0 above 128.
-int jacobi_class(int n);
-// Independent problems of one width class in one launch; tab (device): 3 int64 per problem
-// (element offset of its R in R, of its sigma in sigma, n), R packed n x n (ld n).
-hipError_t launch_jacobi_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count,
-                               hipStream_t s);
 // The bidiagonal route for n <= 128: bidiagonalisation + multisection (ctrl[0] = 0 sweeps).
 int64_t sigma_bidiag_scratch_doubles(int n);  // multisection inputs of the bidiagonal route (n <= 128)
 // bidiagonalisation of R (one workgroup), leaving the multisection inputs in msin
 hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s);
 // multisection: one workgroup per singular value
 hipError_t launch_sigma_msect(const double *msin, int n, double *sigma, hipStream_t s);
+// Width class (padded n: 8..128) of the bidiagonal route; 0 above 128.
+int sigma_width_class(int n);
+// Independent problems of one width class by the bidiagonal route, two launches; tab
+// (device): 4 int64 per problem (element offset of its R in R, of its sigma in sigma, n,
+// of its 2n + 2 multisection doubles in msin), R packed n x n (ld n).
+hipError_t launch_sigma_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count, double *msin,
+                              hipStream_t s);
 
 }  // namespace figaro

@@ -478,7 +478,7 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
         Groups g = groups_of(ws, L);
         const RowSrc heads = r0.skip ? RowSrc{at<void>(ws, r0.buf), g.counts + CNT_G, 0, N, 0, N}
                                      : RowSrc{cur, nullptr, N, r0.np, 0, N};
-        if (r0.skip && L.np_root <= 64)  // a Cartesian product has a single head row
+        if (r0.skip && L.np_root <= 128)  // a Cartesian product has a single head row
             HIPCHK(launch_tsqr_few(L.np_root, init, L.np_root, heads, L.m_f64, N, out, s), "tsqr merge");
         else
             HIPCHK(launch_tsqr_stream(L.np_root, 1, r0.skip ? L.m_f64 : 1, init, L.np_root, heads, none, 1, N,
@@ -739,11 +739,13 @@ struct figaro_plan {
     std::vector<int> lane;          // lane of each instance
     int nlanes = 1;
     hipStream_t cap_stream = nullptr;
-    // Batched Jacobi: per width class, a contiguous run of (r_off, s_off, n) entries in the
-    // device table `jtab` (owned by the plan).
-    int64_t *jtab = nullptr;           // uploaded at the first execution (creation is host-only)
-    std::vector<int64_t> jtab_host;
-    std::vector<std::pair<int, std::pair<int, int>>> jclass;  // (class, (first entry, count))
+    // Batched sigma: per width class, a contiguous run of (r_off, s_off, n, msin offset)
+    // entries in the device table `stab` (owned by the plan); the multisection inputs of
+    // every instance sit after the lanes' workspace slices.
+    int64_t *stab = nullptr;           // uploaded at the first execution (creation is host-only)
+    std::vector<int64_t> stab_host;
+    std::vector<std::pair<int, std::pair<int, int>>> sclass;  // (class, (first entry, count))
+    size_t msin_off = 0;               // byte offset of the multisection inputs in the workspace
     std::vector<hipStream_t> lane_streams;
     std::vector<hipEvent_t> lane_events;  // [0]: fork, [1 + l]: join of lane l
     // One captured graph per (ws, R, sigma) triple.
@@ -772,10 +774,13 @@ int plan_enqueue(figaro_plan *plan, void *ws, double *R, double *sigma, hipStrea
         HIPCHK(hipEventRecord(plan->lane_events[1 + l], plan->lane_streams[l]), "join");
         HIPCHK(hipStreamWaitEvent(s, plan->lane_events[1 + l], 0), "join wait");
     }
-    // sigma of every instance: one launch per width class, one workgroup per instance
-    for (const auto &c : plan->jclass)
-        HIPCHK(launch_jacobi_batch(c.first, R, sigma, plan->jtab + 3 * (int64_t)c.second.first, c.second.second, s),
-               "batched jacobi");
+    // sigma of every instance: per width class, one bidiagonalisation workgroup per instance,
+    // then one multisection workgroup per singular value
+    double *msin = at<double>(ws, plan->msin_off);
+    for (const auto &c : plan->sclass)
+        HIPCHK(launch_sigma_batch(c.first, R, sigma, plan->stab + 4 * (int64_t)c.second.first, c.second.second, msin,
+                                  s),
+               "batched sigma");
     return FIGARO_OK;
 }
 
@@ -828,21 +833,24 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
         load[l] += work(i);
     }
     p->lane_bytes = wsmax;
-    p->ws_bytes = wsmax * p->nlanes;
-    // instance table of the batched Jacobi, grouped by width class
+    p->msin_off = wsmax * p->nlanes;
+    // multisection inputs: 2 N + 2 doubles per instance
+    p->ws_bytes = p->msin_off + align_up(sizeof(double) * (size_t)(2 * p->s_total + 2 * (int64_t)count));
+    // instance table of the batched sigma, grouped by width class
     std::vector<int64_t> tab;
     for (int c = 8; c <= 128; c *= 2) {
-        const int first = (int)(tab.size() / 3);
+        const int first = (int)(tab.size() / 4);
         for (int i = 0; i < count; i++) {
-            if (jacobi_class((int)p->shapes[i].N()) != c) continue;
+            if (sigma_width_class((int)p->shapes[i].N()) != c) continue;
             tab.push_back(p->r_off[i]);
             tab.push_back(p->s_off[i]);
             tab.push_back(p->shapes[i].N());
+            tab.push_back(2 * p->s_off[i] + 2 * (int64_t)i);
         }
-        const int n = (int)(tab.size() / 3) - first;
-        if (n > 0) p->jclass.push_back({c, {first, n}});
+        const int n = (int)(tab.size() / 4) - first;
+        if (n > 0) p->sclass.push_back({c, {first, n}});
     }
-    p->jtab_host = std::move(tab);
+    p->stab_host = std::move(tab);
     *out = p;
     return FIGARO_OK;
 }
@@ -876,10 +884,10 @@ int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R,
     hipStream_t s = (hipStream_t)stream;
     auto key = std::make_tuple(ws, R, sigma);
     auto it = plan->graphs.find(key);
-    if (!plan->jtab) {
-        const size_t nb = sizeof(int64_t) * std::max<size_t>(1, plan->jtab_host.size());
-        HIPCHK(hipMalloc((void **)&plan->jtab, nb), "plan instance table");
-        HIPCHK(hipMemcpy(plan->jtab, plan->jtab_host.data(), sizeof(int64_t) * plan->jtab_host.size(),
+    if (!plan->stab) {
+        const size_t nb = sizeof(int64_t) * std::max<size_t>(1, plan->stab_host.size());
+        HIPCHK(hipMalloc((void **)&plan->stab, nb), "plan instance table");
+        HIPCHK(hipMemcpy(plan->stab, plan->stab_host.data(), sizeof(int64_t) * plan->stab_host.size(),
                          hipMemcpyHostToDevice),
                "plan instance table");
     }
@@ -925,7 +933,7 @@ void figaro_plan_destroy(figaro_plan *plan)
     for (auto ls : plan->lane_streams)
         if (ls) (void)hipStreamDestroy(ls);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
-    if (plan->jtab) (void)hipFree(plan->jtab);
+    if (plan->stab) (void)hipFree(plan->stab);
     delete plan;
 }
 

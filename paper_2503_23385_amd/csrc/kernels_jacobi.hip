@@ -221,17 +221,6 @@ void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sw
     jacobi_lds_body<NPC, LP>(R, n, ldr, sigma, max_sweeps, sweeps_out);
 }
 
-// Many independent problems of one width class in one launch: workgroup b takes entry
-// b of tab (3 int64 each: element offset of its n x n R in R, offset of its sigma, n).
-template <int NPC, int LP>
-__global__ __launch_bounds__((JacobiGeom<NPC, LP>::THREADS))
-void k_jacobi_batch(const double *R, double *sigma, const int64_t *tab, int max_sweeps)
-{
-    const int64_t *e = tab + 3 * (int64_t)blockIdx.x;
-    const int n = (int)e[2];
-    jacobi_lds_body<NPC, LP>(R + e[0], n, n, sigma + e[1], max_sweeps, nullptr);
-}
-
 // Lanes per pair for a width class: FIGARO_JACOBI_LP (4, 8 or 16) when it is set and
 // valid for the class, else the measured default.
 int jacobi_lanes(int npc)
@@ -450,47 +439,7 @@ hipError_t launch_blk(const double *R, int n, int64_t ldr, double *sigma, int ma
     return hipGetLastError();
 }
 
-template <int NPC>
-hipError_t launch_batch_npc(const double *R, double *sigma, const int64_t *tab, int count, int max_sweeps,
-                            hipStream_t s)
-{
-    const int lp = jacobi_lanes(NPC);
-    if constexpr (NPC >= 16) {
-        if (lp == 16) {
-            k_jacobi_batch<NPC, 16><<<count, JacobiGeom<NPC, 16>::THREADS, 0, s>>>(R, sigma, tab, max_sweeps);
-            return hipGetLastError();
-        }
-    }
-    if (lp == 8) {
-        k_jacobi_batch<NPC, 8><<<count, JacobiGeom<NPC, 8>::THREADS, 0, s>>>(R, sigma, tab, max_sweeps);
-        return hipGetLastError();
-    }
-    k_jacobi_batch<NPC, 4><<<count, JacobiGeom<NPC, 4>::THREADS, 0, s>>>(R, sigma, tab, max_sweeps);
-    return hipGetLastError();
-}
-
 }  // namespace
-
-int jacobi_class(int n)
-{
-    int npc = 8;
-    while (npc < n) npc *= 2;
-    return npc <= 128 ? npc : 0;
-}
-
-hipError_t launch_jacobi_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count,
-                               hipStream_t s)
-{
-    if (count <= 0) return hipSuccess;
-    switch (npc) {
-    case 8: return launch_batch_npc<8>(R, sigma, tab, count, 60, s);
-    case 16: return launch_batch_npc<16>(R, sigma, tab, count, 60, s);
-    case 32: return launch_batch_npc<32>(R, sigma, tab, count, 60, s);
-    case 64: return launch_batch_npc<64>(R, sigma, tab, count, 60, s);
-    case 128: return launch_batch_npc<128>(R, sigma, tab, count, 60, s);
-    default: return hipErrorInvalidValue;
-    }
-}
 
 int64_t jacobi_scratch_doubles(int n)
 {
@@ -584,12 +533,43 @@ __device__ inline double wave_sum(double v)
     return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
-// Order the LDS accesses of the lanes of one wave (the only wave at work).
-__device__ inline void wave_sync()
+// Order the LDS accesses of the lanes of one wave (the only wave at work).  The LDS
+// executes the instructions of one wave in issue order, so a read issued after a write
+// of another lane sees it; the wave barrier keeps the compiler from moving LDS accesses
+// across this point.
+__device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+// Reflector applied to one vector x of this lane (a column of A for a left reflector,
+// a row for a right one): x <- x - tau (v . x) v over the active entries [lo, n), in
+// whole chunks of CH entries (v is zero outside [lo, n) and A is zero beyond n, so the
+// extra entries add nothing and are written back unchanged).  X(e) addresses entry e
+// of x in LDS.
+template <int CH, typename Addr>
+__device__ inline void reflect_vector(double *A, const double *v, double tau, int lo, int n, Addr X)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int c0 = lo / CH, c1 = (n + CH - 1) / CH;
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = c0; c < c1; c++) {
+        double x[CH], u[CH];
+#pragma unroll
+        for (int r = 0; r < CH; r++) {
+            x[r] = A[X(c * CH + r)];
+            u[r] = v[c * CH + r];
+        }
+#pragma unroll
+        for (int r = 0; r < CH; r++) w[r & 3] = fma(u[r], x[r], w[r & 3]);
+    }
+    const double t = ((w[0] + w[1]) + (w[2] + w[3])) * tau;
+    for (int c = c0; c < c1; c++) {
+        double x[CH], u[CH];
+#pragma unroll
+        for (int r = 0; r < CH; r++) {
+            x[r] = A[X(c * CH + r)];
+            u[r] = v[c * CH + r];
+        }
+#pragma unroll
+        for (int r = 0; r < CH; r++) A[X(c * CH + r)] = fma(-t, u[r], x[r]);
+    }
 }
 
 // Householder bidiagonalisation of the n x n matrix A (LDS, row stride LDA) by one wave:
@@ -636,39 +616,8 @@ __device__ void gk_bidiag_wave(double *A, double *vl, double *vr, double *dd, do
 #pragma unroll
         for (int c = 0; c < CPL; c++) {
             const int j = lane + 64 * c;
-            if (tau != 0.0 && j > k && j < n) {
-                // whole chunks of CH rows from the one holding row k: vl is zero outside
-                // rows k..n-1 and rows n..NPC-1 of A are zero, so the extra rows add nothing
-                // and are written back unchanged
-                const int i0 = k - k % CH, i1 = n + (CH - n % CH) % CH;
-                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-                for (int i = i0; i < i1; i += CH) {
-                    double x[CH], u[CH];
-#pragma unroll
-                    for (int r = 0; r < CH; r++) {
-                        x[r] = A[(i + r) * LDA + j];
-                        u[r] = vl[i + r];
-                    }
-#pragma unroll
-                    for (int r = 0; r < CH; r += 4) {
-                        w0 = fma(u[r], x[r], w0);
-                        if (r + 1 < CH) w1 = fma(u[r + 1], x[r + 1], w1);
-                        if (r + 2 < CH) w2 = fma(u[r + 2], x[r + 2], w2);
-                        if (r + 3 < CH) w3 = fma(u[r + 3], x[r + 3], w3);
-                    }
-                }
-                const double w = ((w0 + w1) + (w2 + w3)) * tau;
-                for (int i = i0; i < i1; i += CH) {
-                    double x[CH], u[CH];
-#pragma unroll
-                    for (int r = 0; r < CH; r++) {
-                        x[r] = A[(i + r) * LDA + j];
-                        u[r] = vl[i + r];
-                    }
-#pragma unroll
-                    for (int r = 0; r < CH; r++) A[(i + r) * LDA + j] = fma(-w, u[r], x[r]);
-                }
-            }
+            if (tau != 0.0 && j > k && j < n)
+                reflect_vector<CH>(A, vl, tau, k, n, [j](int e) { return e * LDA + j; });
             rk[c] = j > k && j < n ? A[k * LDA + j] : 0.0;
         }
         if (k + 1 >= n) break;
@@ -695,38 +644,8 @@ __device__ void gk_bidiag_wave(double *A, double *vl, double *vr, double *dd, do
 #pragma unroll
         for (int c = 0; c < CPL; c++) {
             const int i = lane + 64 * c;
-            if (tau != 0.0 && i > k && i < n) {
-                // whole chunks of CH columns, as for the left reflector (vr is zero outside
-                // columns k+1..n-1, columns n..NPC-1 of A are zero)
-                const int j0 = (k + 1) - (k + 1) % CH, j1 = n + (CH - n % CH) % CH;
-                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-                for (int j = j0; j < j1; j += CH) {
-                    double x[CH], u[CH];
-#pragma unroll
-                    for (int r = 0; r < CH; r++) {
-                        x[r] = A[i * LDA + j + r];
-                        u[r] = vr[j + r];
-                    }
-#pragma unroll
-                    for (int r = 0; r < CH; r += 4) {
-                        w0 = fma(x[r], u[r], w0);
-                        if (r + 1 < CH) w1 = fma(x[r + 1], u[r + 1], w1);
-                        if (r + 2 < CH) w2 = fma(x[r + 2], u[r + 2], w2);
-                        if (r + 3 < CH) w3 = fma(x[r + 3], u[r + 3], w3);
-                    }
-                }
-                const double w = ((w0 + w1) + (w2 + w3)) * tau;
-                for (int j = j0; j < j1; j += CH) {
-                    double x[CH], u[CH];
-#pragma unroll
-                    for (int r = 0; r < CH; r++) {
-                        x[r] = A[i * LDA + j + r];
-                        u[r] = vr[j + r];
-                    }
-#pragma unroll
-                    for (int r = 0; r < CH; r++) A[i * LDA + j + r] = fma(-w, u[r], x[r]);
-                }
-            }
+            if (tau != 0.0 && i > k && i < n)
+                reflect_vector<CH>(A, vr, tau, k + 1, n, [i](int e) { return i * LDA + e; });
             a[c] = i > k && i < n ? A[i * LDA + k + 1] : 0.0;
         }
         wave_sync();
@@ -734,8 +653,7 @@ __device__ void gk_bidiag_wave(double *A, double *vl, double *vr, double *dd, do
 }
 
 template <int NPC>
-__global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n, int64_t ldr, double *msin,
-                                                         int32_t *ctrl)
+__device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ldr, double *msin, int32_t *ctrl)
 {
     using Gm = GkGeom<NPC>;
     constexpr int LDA = Gm::LDA;
@@ -790,6 +708,22 @@ __global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n,
     }
 }
 
+template <int NPC>
+__global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n, int64_t ldr, double *msin, int32_t *ctrl)
+{
+    sigma_gk_body<NPC>(R, n, ldr, msin, ctrl);
+}
+
+// Many independent problems of one width class: workgroup b takes entry b of tab (4 int64
+// each: element offset of its n x n R, offset of its sigma, n, offset of its msin).
+template <int NPC>
+__global__ __launch_bounds__(kGkThreads) void k_sigma_gk_batch(const double *R, const int64_t *tab, double *msin)
+{
+    const int64_t *e = tab + 4 * (int64_t)blockIdx.x;
+    const int n = (int)e[2];
+    sigma_gk_body<NPC>(R + e[0], n, n, msin + e[3], nullptr);
+}
+
 // Number of eigenvalues of the Golub-Kahan tridiagonal (zero diagonal, squared
 // off-diagonals bb[0..m-1]) below x: the sign changes of its characteristic sequence
 // p_0 = 1, p_1 = -x, p_i = -x p_{i-1} - bb_{i-2} p_{i-2} (a zero p_i counts as a change,
@@ -836,13 +770,13 @@ __device__ inline int gk_sturm_count(const double *bb, int m, double x)
 // eigenvalues of T lie below x.  Each round evaluates the count at kMsThreads points
 // evenly inside the current interval and keeps the gap between the last point whose count
 // is below 2n - k and the first point whose count is not.
-__global__ __launch_bounds__(kMsThreads) void k_sigma_msect(const double *msin, int n, double *sigma)
+__device__ __forceinline__ void sigma_msect_body(const double *msin, int n, int k, double *sigma)
 {
     constexpr int NW = kMsThreads / 64;
     __shared__ double bb[255];
     __shared__ int s_lo[2][NW], s_up[2][NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int k = blockIdx.x, m = 2 * n - 1;
+    const int m = 2 * n - 1;
     for (int i = tid; i < m; i += kMsThreads) bb[i] = msin[2 + i];
     const double bound = msin[0];
     const int ex = (int)msin[1];
@@ -876,6 +810,22 @@ __global__ __launch_bounds__(kMsThreads) void k_sigma_msect(const double *msin, 
     if (tid == 0) sigma[k] = ldexp(0.5 * (lo + up), ex);
 }
 
+__global__ __launch_bounds__(kMsThreads) void k_sigma_msect(const double *msin, int n, double *sigma)
+{
+    sigma_msect_body(msin, n, blockIdx.x, sigma);
+}
+
+// Batched: workgroup (k, b) locates value k of entry b of tab (entries as k_sigma_gk_batch);
+// workgroups with k >= n leave at once.
+__global__ __launch_bounds__(kMsThreads) void k_sigma_msect_batch(const int64_t *tab, const double *msin,
+                                                                  double *sigma)
+{
+    const int64_t *e = tab + 4 * (int64_t)blockIdx.y;
+    const int n = (int)e[2], k = blockIdx.x;
+    if (k >= n) return;
+    sigma_msect_body(msin + e[3], n, k, sigma + e[1]);
+}
+
 template <int NPC>
 hipError_t launch_gk(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s)
 {
@@ -902,6 +852,31 @@ hipError_t launch_sigma_msect(const double *msin, int n, double *sigma, hipStrea
 {
     if (n <= 0 || n > 128 || !msin) return hipErrorInvalidValue;
     k_sigma_msect<<<n, kMsThreads, 0, s>>>(msin, n, sigma);
+    return hipGetLastError();
+}
+
+int sigma_width_class(int n)
+{
+    int npc = 8;
+    while (npc < n) npc *= 2;
+    return npc <= 128 ? npc : 0;
+}
+
+hipError_t launch_sigma_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count, double *msin,
+                              hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    switch (npc) {
+    case 8: k_sigma_gk_batch<8><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
+    case 16: k_sigma_gk_batch<16><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
+    case 32: k_sigma_gk_batch<32><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
+    case 64: k_sigma_gk_batch<64><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
+    case 128: k_sigma_gk_batch<128><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_sigma_msect_batch<<<dim3(npc, count), kMsThreads, 0, s>>>(tab, msin, sigma);
     return hipGetLastError();
 }
 

@@ -621,51 +621,63 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
 // ------------------------------------------------------------------ a few rows into one triangle
 //
 // The merge of the two-sided form of a Cartesian product absorbs a single head row.
-// One wave, lane k = column k (no row sets), up to kFewRows rows per block in
-// registers: the column step needs no cross-lane reduction.
+// One wave, lane l = columns l + 64 c (one column for NP <= 64, two for NP = 128), up
+// to kFewRows rows per block in registers: the column step needs no cross-lane
+// reduction.  The packed triangle lives in LDS (66 KB at NP = 128).
 constexpr int kFewRows = 4;
 
 template <int NP>
 __global__ __launch_bounds__(64) void k_tsqr_few(const double *init, int64_t init_ld, RowSrc src, int in_f64,
                                                  int width, double *out)
 {
+    constexpr int CPL = NP > 64 ? NP / 64 : 1;
     __shared__ double Rp[packed_size(NP)];
     __shared__ double xb[kFewRows];
-    const int k = threadIdx.x;
-    for (int e = k; e < width * NP; e += 64) {
+    const int lane = threadIdx.x;
+    for (int e = lane; e < width * NP; e += 64) {
         const int j = e / NP, kk = e - j * NP;
         if (kk >= j) Rp[pidx(NP, j, kk)] = (init && kk < width) ? init[(int64_t)j * init_ld + kk] : 0.0;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int64_t rows = src_rows(src);
-    const bool col_ok = k < width;
     for (int64_t rb = 0; rb < rows; rb += kFewRows) {
-        double x[kFewRows];
+        double x[CPL][kFewRows];
 #pragma unroll
-        for (int i = 0; i < kFewRows; i++) {
-            const int64_t r = rb + i;
-            x[i] = (r < rows && col_ok) ? (in_f64 ? load_src<double, double>(src, r, k) : load_src<float, double>(src, r, k))
-                                        : 0.0;
+        for (int c = 0; c < CPL; c++) {
+            const int col = lane + 64 * c;
+#pragma unroll
+            for (int i = 0; i < kFewRows; i++) {
+                const int64_t r = rb + i;
+                x[c][i] = (r < rows && col < width)
+                              ? (in_f64 ? load_src<double, double>(src, r, col) : load_src<float, double>(src, r, col))
+                              : 0.0;
+            }
         }
         for (int j = src.col_off; j < width; j++) {
             __builtin_amdgcn_wave_barrier();
-            if (k == j) {
 #pragma unroll
-                for (int i = 0; i < kFewRows; i++) xb[i] = x[i];
-            }
+            for (int c = 0; c < CPL; c++)
+                if (lane + 64 * c == j) {
+#pragma unroll
+                    for (int i = 0; i < kFewRows; i++) xb[i] = x[c][i];
+                }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            double xj[kFewRows], d = 0.0, s = 0.0;
+            double xj[kFewRows], s = 0.0;
 #pragma unroll
             for (int i = 0; i < kFewRows; i++) {
                 xj[i] = xb[i];
-                d = fma(xj[i], x[i], d);
                 s = fma(xj[i], xj[i], s);
             }
             const double alpha = Rp[pidx(NP, j, j)];
-            const double rjk = (k > j && col_ok) ? Rp[pidx(NP, j, k)] : 0.0;
+            double rjk[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; c++) {
+                const int col = lane + 64 * c;
+                rjk[c] = (col > j && col < width) ? Rp[pidx(NP, j, col)] : 0.0;
+            }
             const double q = fma(alpha, alpha, s);
             if (s > 0.0 && q >= DBL_MIN) {
                 const double r = rsq_refined(q);
@@ -675,20 +687,27 @@ __global__ __launch_bounds__(64) void k_tsqr_few(const double *init, int64_t ini
                 const double inv_beta = -sg * r;
                 const double scl = rcp_refined(alpha + sg * nrm);
                 const double tau = 1.0 - alpha * inv_beta;
-                if (k > j && col_ok) {
-                    const double w = rjk + scl * d;
-                    Rp[pidx(NP, j, k)] = rjk - tau * w;
-                    const double c = w * inv_beta;
 #pragma unroll
-                    for (int i = 0; i < kFewRows; i++) x[i] = fma(c, xj[i], x[i]);
+                for (int c = 0; c < CPL; c++) {
+                    const int col = lane + 64 * c;
+                    if (col > j && col < width) {
+                        double d = 0.0;
+#pragma unroll
+                        for (int i = 0; i < kFewRows; i++) d = fma(xj[i], x[c][i], d);
+                        const double w = rjk[c] + scl * d;
+                        Rp[pidx(NP, j, col)] = rjk[c] - tau * w;
+                        const double cc = w * inv_beta;
+#pragma unroll
+                        for (int i = 0; i < kFewRows; i++) x[c][i] = fma(cc, xj[i], x[c][i]);
+                    }
+                    if (col == j) Rp[pidx(NP, j, j)] = beta;
                 }
-                if (k == j) Rp[pidx(NP, j, j)] = beta;
             }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (int e = k; e < width * NP; e += 64) {
+    for (int e = lane; e < width * NP; e += 64) {
         const int j = e / NP, kk = e - j * NP;
         out[e] = (kk >= j && kk < width) ? Rp[pidx(NP, j, kk)] : 0.0;
     }
@@ -700,7 +719,7 @@ hipError_t launch_tsqr_few(int np, const double *init, int64_t init_ld, RowSrc s
     switch (np) {
 #define FIGARO_FEW(NPV) \
     case NPV: k_tsqr_few<NPV><<<1, 64, 0, s>>>(init, init_ld, src, in_f64, width, out); return hipGetLastError();
-    FIGARO_FEW(4) FIGARO_FEW(8) FIGARO_FEW(16) FIGARO_FEW(32) FIGARO_FEW(64)
+    FIGARO_FEW(4) FIGARO_FEW(8) FIGARO_FEW(16) FIGARO_FEW(32) FIGARO_FEW(64) FIGARO_FEW(128)
 #undef FIGARO_FEW
     default: return hipErrorInvalidValue;
     }

@@ -64,6 +64,8 @@ def small_cases():
         # A tail leaf with a single row: its rank-deficient residual columns shrink
         # geometrically (regression case for reflector scalars that must not underflow).
         "cart_tail_leaf": W.random_instance(rng(14), 4097, 5, 2000, 59),
+        # a Cartesian root of padded width 128: the single head row merged by one wave
+        "cart_n125_ragged": W.random_instance(rng(18), 2100, 64, 1700, 61),
         # wide rows: blocked panel TSQR (padded widths 256 and 512) and block Jacobi
         "cart_n192_ragged": W.random_instance(rng(15), 1500, 70, 900, 122),
         "keyed_n256": W.random_instance(rng(16), 3000, 128, 2600, 128, n_values=60),
