@@ -45,6 +45,29 @@ struct RowSrc {
     int32_t width;
 };
 
+// Copies count elements through registers with U loads in flight: v = ld(e) for
+// e = first, first + stride, ..., then st(e, v).  A plain loop whose body loads and
+// then stores waits for every load in turn; here the U loads of a round are issued
+// together.  ld is also called with e = count - 1 in place of indices past the end, so
+// it must be safe (and is only used) for e < count.
+template <int U, typename T, typename Ld, typename St>
+__device__ inline void staged_copy(int count, int first, int stride, Ld ld, St st)
+{
+    for (int e0 = first; e0 < count; e0 += U * stride) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int e = e0 + u * stride;
+            v[u] = ld(e < count ? e : count - 1);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int e = e0 + u * stride;
+            if (e < count) st(e, v[u]);
+        }
+    }
+}
+
 // Elements handled per block by the grouping kernels.
 constexpr int kGroupBlock = 2048;
 constexpr int kGroupThreads = 256;

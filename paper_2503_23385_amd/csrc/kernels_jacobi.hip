@@ -112,10 +112,16 @@ __device__ __forceinline__ void jacobi_lds_body(const double *R, int n, int64_t 
     __shared__ int s_rot;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    for (int e = tid; e < NPC * NPC; e += nthr) {
-        const int k = e / NPC, i = e - k * NPC;
-        C[k * LDC + i] = (k < n && i < n) ? R[(int64_t)i * ldr + k] : 0.0;
-    }
+    staged_copy<8, double>(
+        NPC * NPC, tid, nthr,
+        [&](int e) {
+            const int k = e / NPC, i = e - k * NPC;
+            return R[(int64_t)(i < n ? i : n - 1) * ldr + (k < n ? k : n - 1)];
+        },
+        [&](int e, double v) {
+            const int k = e / NPC, i = e - k * NPC;
+            C[k * LDC + i] = (k < n && i < n) ? v : 0.0;
+        });
     const int pair = tid / LP, sub = tid % LP;
     // every lane has a pair unless the pairs fill less than one wave
     const bool active = PAIRS * LP >= Gm::THREADS || pair < PAIRS;
@@ -665,10 +671,16 @@ __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ld
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (ctrl && tid < CTRL_WORDS) ctrl[tid] = 0;  // no sweeps: this route does not iterate
     if (tid == 0) s_exp = INT_MIN;
-    for (int e = tid; e < NPC * NPC; e += kGkThreads) {
-        const int i = e / NPC, j = e - i * NPC;
-        A[i * LDA + j] = (i < n && j < n) ? R[(int64_t)i * ldr + j] : 0.0;
-    }
+    staged_copy<16, double>(
+        NPC * NPC, tid, kGkThreads,
+        [&](int e) {
+            const int i = e / NPC, j = e - i * NPC;
+            return R[(int64_t)(i < n ? i : n - 1) * ldr + (j < n ? j : n - 1)];
+        },
+        [&](int e, double v) {
+            const int i = e / NPC, j = e - i * NPC;
+            A[i * LDA + j] = (i < n && j < n) ? v : 0.0;
+        });
     __syncthreads();
     // Scale by a power of two so that the largest |entry| lies in [1, 2) (exact): the
     // reflector norms and the recurrence below stay in range.

@@ -83,15 +83,24 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename Tin, typename Tacc>
-__device__ inline Tacc load_col(const RowSrc &s, int64_t lr, int k)
-{
-    const int c = k - s.col_off;
-    if (c < 0 || c >= s.width) return Tacc(0);
-    return (Tacc)((const Tin *)s.p)[lr * s.ld + c];
-}
-
 __device__ inline int64_t rows_of(const RowSrc &s) { return s.rows_dev ? *s.rows_dev : s.rows_host; }
+
+// Row r of the stacked sources (rows [0, rows0) of s0, then s1), column k of the virtual
+// row, or 0 where the element is not real.  r must be a row of the stacked sources; the
+// source column is clamped into range, so the load is always valid and can be issued
+// without a branch.
+template <typename Tin, typename Tacc>
+__device__ inline Tacc load_stacked(const RowSrc &s0, const RowSrc &s1, int64_t rows0, int64_t r, int k, bool real)
+{
+    const bool first = r < rows0;
+    const Tin *p = (const Tin *)(first ? s0.p : s1.p);
+    const int64_t lr = first ? r : r - rows0, ld = first ? s0.ld : s1.ld;
+    const int off = first ? s0.col_off : s1.col_off, w = first ? s0.width : s1.width;
+    const int c = k - off;
+    const int cc = c < 0 ? 0 : (c >= w ? w - 1 : c);
+    const Tacc v = (Tacc)p[lr * ld + cc];
+    return (real && c >= 0 && c < w) ? v : Tacc(0);
+}
 
 template <int NP, typename Tacc>
 struct PanelGeom {
@@ -126,10 +135,20 @@ struct PanelLds {
 template <int NP>
 __device__ inline void panel_set(double *R, const double *init, int64_t init_ld, int width)
 {
-    for (int e = threadIdx.x; e < width * NP; e += kPanelThreads) {
-        const int j = e / NP, k = e - j * NP;
-        R[e] = (init && k >= j && k < width) ? init[(int64_t)j * init_ld + k] : 0.0;
+    if (!init) {
+        for (int e = threadIdx.x; e < width * NP; e += kPanelThreads) R[e] = 0.0;
+        return;
     }
+    staged_copy<8, double>(
+        width * NP, threadIdx.x, kPanelThreads,
+        [&](int e) {
+            const int j = e / NP, k = e - j * NP;
+            return init[(int64_t)j * init_ld + (k < width ? k : width - 1)];
+        },
+        [&](int e, double v) {
+            const int j = e / NP, k = e - j * NP;
+            R[e] = (k >= j && k < width) ? v : 0.0;
+        });
 }
 
 // R absorbs rows [r_begin, r_end) of s0 then s1 (rows0 rows in s0), blocks of B rows.
@@ -152,13 +171,18 @@ __device__ void panel_absorb(PanelLds<NP, Tacc> &L, double *R, const RowSrc &s0,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
     for (int64_t rb = r_begin; rb < r_end; rb += B) {
-        for (int e = tid; e < B * NP; e += kPanelThreads) {
-            const int i = e / NP, c = e - i * NP;
-            const int64_t r = rb + i;
-            Tacc v = Tacc(0);
-            if (r < r_end && c < width) v = r < rows0 ? load_col<Tin, Tacc>(s0, r, c) : load_col<Tin, Tacc>(s1, r - rows0, c);
-            X[i * LDX + c] = v;
-        }
+        // rows past r_end read row r_end - 1 and are stored as zeros
+        staged_copy<16, Tacc>(
+            B * NP, tid, kPanelThreads,
+            [&](int e) {
+                const int i = e / NP, c = e - i * NP;
+                const int64_t r = rb + i;
+                return load_stacked<Tin, Tacc>(s0, s1, rows0, r < r_end ? r : r_end - 1, c, r < r_end && c < width);
+            },
+            [&](int e, Tacc v) {
+                const int i = e / NP, c = e - i * NP;
+                X[i * LDX + c] = v;
+            });
         // Leading columns known to be zero in this block.
         int jstart = 0;
         const int64_t rlast = min(r_end, rb + B) - 1;

@@ -63,6 +63,7 @@ __global__ __launch_bounds__(256) void k_gram_tile(const Tin *__restrict__ X, in
         }
         __syncthreads();
         // stage rows: i-columns of X, j-columns of X (weighted) or of the group's B sum
+#pragma unroll 4
         for (int e = tid; e < kRowsPerStage * kTile; e += 256) {
             const int rr = e / kTile, c = e - rr * kTile;
             const int64_t s = rb + rr;

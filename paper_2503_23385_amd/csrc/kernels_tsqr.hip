@@ -156,10 +156,16 @@ __device__ inline void wave_block(Tacc (&x)[WaveGeom<NP>::RPT], Tacc *Rp, Tacc *
 template <int NP, typename Tacc>
 __device__ inline void wave_init_tri(Tacc *Rp, const double *T, int64_t ld, int width, int lane)
 {
-    for (int e = lane; e < width * NP; e += 64) {
-        const int j = e / NP, kk = e - j * NP;
-        if (kk >= j) Rp[pidx(NP, j, kk)] = kk < width ? (Tacc)T[(int64_t)j * ld + kk] : Tacc(0);
-    }
+    staged_copy<16, double>(
+        width * NP, lane, 64,
+        [&](int e) {
+            const int j = e / NP, kk = e - j * NP;
+            return T[(int64_t)j * ld + (kk < width ? kk : width - 1)];
+        },
+        [&](int e, double v) {
+            const int j = e / NP, kk = e - j * NP;
+            if (kk >= j) Rp[pidx(NP, j, kk)] = kk < width ? (Tacc)v : Tacc(0);
+        });
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
@@ -408,10 +414,12 @@ __device__ inline void wg_load_tri(WgState<NP, Tacc> &st, const double *T, int w
     for (int e = threadIdx.x; e < WaveGeom<NP>::PS; e += 64 * tree_waves(NP)) st.R[e] = Tacc(0);
     __syncthreads();
     if (T) {
-        for (int e = threadIdx.x; e < width * NP; e += 64 * tree_waves(NP)) {
-            const int j = e / NP, kk = e - j * NP;
-            if (kk >= j && kk < width) st.R[pidx(NP, j, kk)] = (Tacc)T[e];
-        }
+        staged_copy<8, double>(
+            width * NP, threadIdx.x, 64 * tree_waves(NP), [&](int e) { return T[e]; },
+            [&](int e, double v) {
+                const int j = e / NP, kk = e - j * NP;
+                if (kk >= j && kk < width) st.R[pidx(NP, j, kk)] = (Tacc)v;
+            });
     }
     __syncthreads();
 }
@@ -620,93 +628,87 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
 
 // ------------------------------------------------------------------ a few rows into one triangle
 //
-// The merge of the two-sided form of a Cartesian product absorbs a single head row.
-// One wave, lane l = columns l + 64 c (one column for NP <= 64, two for NP = 128), up
-// to kFewRows rows per block in registers: the column step needs no cross-lane
-// reduction.  The packed triangle lives in LDS (66 KB at NP = 128).
-constexpr int kFewRows = 4;
-
+// The merge of the two-sided form of a Cartesian product absorbs a single head row h
+// into the upper triangle R.  With one row, the reflector of column j acts on the pair
+// (R_jj, h_j) only: a plane rotation that zeroes h_j and rotates row j of R with h.
+// It leaves rows j+1.. of R untouched, so row j+1 is read from LDS while step j runs.
+// One wave; lane l owns columns l + 64 c (one column for NP <= 64, two for NP = 128) and
+// keeps its entries of h and of the current row of R in registers; the two scalars of
+// a step come from lane j by lane reads.  Rows are absorbed one after another.  The
+// packed triangle lives in LDS (66 KB at NP = 128).
 template <int NP>
 __global__ __launch_bounds__(64) void k_tsqr_few(const double *init, int64_t init_ld, RowSrc src, int in_f64,
                                                  int width, double *out)
 {
     constexpr int CPL = NP > 64 ? NP / 64 : 1;
     __shared__ double Rp[packed_size(NP)];
-    __shared__ double xb[kFewRows];
     const int lane = threadIdx.x;
-    for (int e = lane; e < width * NP; e += 64) {
-        const int j = e / NP, kk = e - j * NP;
-        if (kk >= j) Rp[pidx(NP, j, kk)] = (init && kk < width) ? init[(int64_t)j * init_ld + kk] : 0.0;
+    if (init) {
+        staged_copy<16, double>(
+            width * NP, lane, 64,
+            [&](int e) {
+                const int j = e / NP, kk = e - j * NP;
+                return init[(int64_t)j * init_ld + (kk < width ? kk : width - 1)];
+            },
+            [&](int e, double v) {
+                const int j = e / NP, kk = e - j * NP;
+                if (kk >= j) Rp[pidx(NP, j, kk)] = kk < width ? v : 0.0;
+            });
+    } else {
+        for (int e = lane; e < packed_size(NP); e += 64) Rp[e] = 0.0;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int64_t rows = src_rows(src);
-    for (int64_t rb = 0; rb < rows; rb += kFewRows) {
-        double x[CPL][kFewRows];
+    const int j0 = src.col_off;
+    for (int64_t r = 0; r < rows; r++) {
+        double h[CPL], rj[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; c++) {
             const int col = lane + 64 * c;
-#pragma unroll
-            for (int i = 0; i < kFewRows; i++) {
-                const int64_t r = rb + i;
-                x[c][i] = (r < rows && col < width)
-                              ? (in_f64 ? load_src<double, double>(src, r, col) : load_src<float, double>(src, r, col))
-                              : 0.0;
-            }
+            h[c] = col < width ? (in_f64 ? load_src<double, double>(src, r, col) : load_src<float, double>(src, r, col))
+                               : 0.0;
+            rj[c] = (col >= j0 && col < width) ? Rp[pidx(NP, j0, col)] : 0.0;
         }
-        for (int j = src.col_off; j < width; j++) {
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int c = 0; c < CPL; c++)
-                if (lane + 64 * c == j) {
-#pragma unroll
-                    for (int i = 0; i < kFewRows; i++) xb[i] = x[c][i];
-                }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            double xj[kFewRows], s = 0.0;
-#pragma unroll
-            for (int i = 0; i < kFewRows; i++) {
-                xj[i] = xb[i];
-                s = fma(xj[i], xj[i], s);
-            }
-            const double alpha = Rp[pidx(NP, j, j)];
-            double rjk[CPL];
+        for (int j = j0; j < width; j++) {
+            // row j + 1 of R, which step j does not change
+            double rn[CPL];
 #pragma unroll
             for (int c = 0; c < CPL; c++) {
                 const int col = lane + 64 * c;
-                rjk[c] = (col > j && col < width) ? Rp[pidx(NP, j, col)] : 0.0;
+                rn[c] = (col > j && col < width) ? Rp[pidx(NP, j + 1, col)] : 0.0;
             }
-            const double q = fma(alpha, alpha, s);
-            if (s > 0.0 && q >= DBL_MIN) {
-                const double r = rsq_refined(q);
-                const double sg = alpha >= 0.0 ? 1.0 : -1.0;
-                const double nrm = q * r;
-                const double beta = -sg * nrm;
-                const double inv_beta = -sg * r;
-                const double scl = rcp_refined(alpha + sg * nrm);
-                const double tau = 1.0 - alpha * inv_beta;
+            double alpha = 0.0, hj = 0.0;
+#pragma unroll
+            for (int c = 0; c < CPL; c++)
+                if (j / 64 == c) {
+                    alpha = readlane_f64(rj[c], j % 64);
+                    hj = readlane_f64(h[c], j % 64);
+                }
+            const double q = fma(alpha, alpha, hj * hj);
+            // (a pair whose norm is below the normal range is left untouched)
+            if (hj != 0.0 && q >= DBL_MIN) {
+                const double rinv = rsq_refined(q);
+                const double cs = alpha * rinv, sn = hj * rinv;
 #pragma unroll
                 for (int c = 0; c < CPL; c++) {
                     const int col = lane + 64 * c;
                     if (col > j && col < width) {
-                        double d = 0.0;
-#pragma unroll
-                        for (int i = 0; i < kFewRows; i++) d = fma(xj[i], x[c][i], d);
-                        const double w = rjk[c] + scl * d;
-                        Rp[pidx(NP, j, col)] = rjk[c] - tau * w;
-                        const double cc = w * inv_beta;
-#pragma unroll
-                        for (int i = 0; i < kFewRows; i++) x[c][i] = fma(cc, xj[i], x[c][i]);
+                        const double a = rj[c], b = h[c];
+                        Rp[pidx(NP, j, col)] = fma(cs, a, sn * b);
+                        h[c] = fma(cs, b, -sn * a);
+                    } else if (col == j) {
+                        Rp[pidx(NP, j, j)] = q * rinv;
+                        h[c] = 0.0;
                     }
-                    if (col == j) Rp[pidx(NP, j, j)] = beta;
                 }
             }
+#pragma unroll
+            for (int c = 0; c < CPL; c++) rj[c] = rn[c];
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
     for (int e = lane; e < width * NP; e += 64) {
         const int j = e / NP, kk = e - j * NP;
         out[e] = (kk >= j && kk < width) ? Rp[pidx(NP, j, kk)] : 0.0;
