@@ -215,9 +215,11 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     const int br = tsqr_block_rows(r.np, acc_f64);
     // Leaves of a few blocks each (tunable through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS);
     // the wide tree keeps at most one leaf per compute unit and a half.
-    static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 4);
+    static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 0);
     static const int wg_blocks = env_int("FIGARO_WG_LEAF_BLOCKS", 4);
-    r.rows_per_leaf = (int64_t)(r.wave ? wave_blocks : wg_blocks) * br;
+    // narrow trees (measured): two blocks of 512 rows at width 32, four blocks elsewhere
+    const int narrow_blocks = wave_blocks > 0 ? wave_blocks : (r.np == 32 ? 2 : 4);
+    r.rows_per_leaf = (int64_t)(r.wave ? narrow_blocks : wg_blocks) * br;
     const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
     r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, r.wave ? kMaxTreeLeaves : kMaxPanelLeaves));
     r.ncounters = 0;

@@ -277,8 +277,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_wave(const double 
 // updates its own rows.  Row j of R is read by every wave during step j, so its
 // new values are written one step later, after the next barrier.
 
-// Waves per workgroup of the tree kernel (8 at padded width 64 measured slower than 4).
-__host__ __device__ constexpr int tree_waves(int) { return 4; }
+// Waves per workgroup of the tree kernel (measured): 8 at padded width 32, where the
+// blocks of 512 rows halve the sequential column steps of a leaf and two waves per SIMD
+// hide part of the LDS broadcast; 4 elsewhere (8 measured slower at widths 64 and below 32).
+__host__ __device__ constexpr int tree_waves(int np) { return np == 32 ? 8 : 4; }
 
 template <int NP, typename Tacc>
 struct WgState {
