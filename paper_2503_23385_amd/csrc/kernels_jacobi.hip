@@ -736,15 +736,29 @@ __global__ __launch_bounds__(kGkThreads) void k_sigma_gk_batch(const double *R, 
     sigma_gk_body<NPC>(R + e[0], n, n, msin + e[3], nullptr);
 }
 
+// One step of the Sturm sequence: p2 = -x p1 - b p0, then DBL_MIN with the sign opposite
+// to p1 added.  An exact zero becomes that tiny value (a zero term counts as a sign
+// change: a zero pivot taken negative); any term of magnitude above 2^-1020 is unchanged
+// by the addition, and the rescaling every 16 steps keeps the nonzero terms far above
+// it.  cnt counts the sign changes from the sign bits.
+__device__ inline void sturm_step(double x, double b, double &p0, double &p1, int &cnt)
+{
+    const int h1 = __double2hiint(p1);
+    const double bias = __hiloint2double((h1 & (int)0x80000000) ^ (int)0x80100000, 0);  // -sign(p1) DBL_MIN
+    const double p2 = fma(-x, p1, -b * p0) + bias;
+    cnt += (int)(((unsigned)(__double2hiint(p2) ^ h1)) >> 31);
+    p0 = p1;
+    p1 = p2;
+}
+
 // Number of eigenvalues of the Golub-Kahan tridiagonal (zero diagonal, squared
 // off-diagonals bb[0..m-1]) below x: the sign changes of its characteristic sequence
-// p_0 = 1, p_1 = -x, p_i = -x p_{i-1} - bb_{i-2} p_{i-2} (a zero p_i counts as a change,
-// like a zero pivot taken negative).  The pair (p_{i-1}, p_i) is rescaled by a power of
-// two every 16 steps, which keeps it in range and changes no sign.
+// p_0 = 1, p_1 = -x, p_i = -x p_{i-1} - bb_{i-2} p_{i-2}.  The pair (p_{i-1}, p_i) is
+// rescaled by a power of two every 16 steps, which keeps it in range and changes no sign.
 __device__ inline int gk_sturm_count(const double *bb, int m, double x)
 {
     double p0 = 1.0, p1 = -x;
-    int cnt = p1 < 0.0;
+    int cnt = (int)(((unsigned)__double2hiint(p1)) >> 31);  // signs are read from the sign bits throughout
     // whole chunks of 16 steps with their coefficients loaded up front (the recurrence
     // does not wait on LDS), then the remaining steps
     const int mfull = m - m % 16;
@@ -754,21 +768,9 @@ __device__ inline int gk_sturm_count(const double *bb, int m, double x)
 #pragma unroll
             for (int u = 0; u < 16; u++) b[u] = bb[i0 + u];
 #pragma unroll
-            for (int u = 0; u < 16; u++) {
-                double p2 = fma(-x, p1, -b[u] * p0);
-                if (p2 == 0.0) p2 = p1 < 0.0 ? DBL_MIN : -DBL_MIN;
-                cnt += (p2 < 0.0) != (p1 < 0.0);
-                p0 = p1;
-                p1 = p2;
-            }
+            for (int u = 0; u < 16; u++) sturm_step(x, b[u], p0, p1, cnt);
         } else {
-            for (int i = i0; i < m; i++) {
-                double p2 = fma(-x, p1, -bb[i] * p0);
-                if (p2 == 0.0) p2 = p1 < 0.0 ? DBL_MIN : -DBL_MIN;
-                cnt += (p2 < 0.0) != (p1 < 0.0);
-                p0 = p1;
-                p1 = p2;
-            }
+            for (int i = i0; i < m; i++) sturm_step(x, bb[i], p0, p1, cnt);
         }
         const int e2 = ilogb(fmax(fabs(p0), fabs(p1)));
         p0 = ldexp(p0, -e2);
