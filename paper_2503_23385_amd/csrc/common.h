@@ -139,10 +139,12 @@ struct TreeRegion {
 // One launch for one or two regions of the same padded width np (np <= 64).
 hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
                             hipStream_t s);
-// One wave absorbs the (few) rows of src into the triangle init (width rows, ld init_ld);
-// padded width np <= 64; the result (width x np, FP64) goes to out.
-hipError_t launch_tsqr_few(int np, const double *init, int64_t init_ld, RowSrc src, int in_f64, int width,
-                           double *out, hipStream_t s);
+// Root of the two-sided form of a Cartesian product (N = na + nb <= 128): diag(R_TA, R_TB)
+// absorbs the head row built from the head sums hA, hB; R (ld ldr) receives the result
+// with row signs normalised.
+hipError_t launch_merge_cartesian(int np, const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
+                                  Groups g, const double *hA, const double *hB, double *R, int64_t ldr,
+                                  hipStream_t s);
 // out (na + nb rows, ld ldo) <- the upper triangular block diagonal [Ta 0; 0 Tb].
 hipError_t launch_block_diag(const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
                              double *out, int64_t ldo, hipStream_t s);

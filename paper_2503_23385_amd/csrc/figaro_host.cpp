@@ -355,9 +355,10 @@ int check_ws(const Layout &L, void *ws, size_t ws_bytes)
         if (e_ != hipSuccess) return hip_fail(e_, where); \
     } while (0)
 
-// Grouping, head/tail scans and assembly: fills the regions' row buffers.
+// Grouping, head/tail scans and assembly: fills the regions' row buffers (the head rows
+// of the two-sided form only when head_rows is set).
 int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L,
-                void *ws, hipStream_t s)
+                void *ws, hipStream_t s, bool head_rows = true)
 {
     Groups g = groups_of(ws, L);
     int32_t *status = at<int32_t>(ws, L.status);
@@ -402,10 +403,12 @@ int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, c
                                    at<double>(ws, L.carry[0]), L.spA, s),
                    "head/tail scan of A");
         }
-        Stage st("assemble", s);
-        HIPCHK(launch_head_rows(g, L.gcap, hA, hB, sh.n1, sh.n2, at<void>(ws, L.regions[0].buf),
-                                L.m_f64, s),
-               "head rows");
+        if (head_rows) {
+            Stage st("assemble", s);
+            HIPCHK(launch_head_rows(g, L.gcap, hA, hB, sh.n1, sh.n2, at<void>(ws, L.regions[0].buf),
+                                    L.m_f64, s),
+                   "head rows");
+        }
     }
     return FIGARO_OK;
 }
@@ -452,15 +455,43 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
     return FIGARO_OK;
 }
 
+// Refinement sweep (mixed form): R <- refined R~ (R~ with normalised row signs in rt).
+int run_refine(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
+               int64_t ldr, void *ws, hipStream_t s)
+{
+    Stage st("refine", s);
+    HIPCHK(launch_refine(A->data, sh.in_f64, sh.lda, sh.m1, (int)sh.n1, B->data, sh.ldb, sh.m2, (int)sh.n2,
+                         groups_of(ws, L), !sh.keyed, at<double>(ws, L.headsB), at<double>(ws, L.rt), (int)sh.N(),
+                         at<double>(ws, L.gram), at<double>(ws, L.gy), at<double>(ws, L.partial),
+                         L.partial_cap, at<int32_t>(ws, L.failed), R, ldr, s),
+           "refinement sweep");
+    return FIGARO_OK;
+}
+
 int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
           int64_t ldr, void *ws, hipStream_t s)
 {
-    int rc = run_compact(A, B, sh, L, ws, s);
-    if (rc) return rc;
     const int N = (int)sh.N();
+    // A Cartesian product in the two-sided form has one head row: one kernel builds it,
+    // merges it into diag(R_TA, R_TB) and normalises the row signs.
+    const bool cart_root = sh.two_sided && L.regions[0].skip && L.np_root <= 128;
+    int rc = run_compact(A, B, sh, L, ws, s, !cart_root);
+    if (rc) return rc;
     const int acc = sh.precision == FIGARO_PLAIN_FP64;
     rc = run_regions(L, acc, ws, s);
     if (rc) return rc;
+    if (cart_root) {
+        const Region &ra = L.regions[1], &rb = L.regions[2];
+        {
+            Stage st("tsqr_root", s);
+            HIPCHK(launch_merge_cartesian(L.np_root, at<double>(ws, ra.root), ra.np, ra.width,
+                                          at<double>(ws, rb.root), rb.np, rb.width, groups_of(ws, L),
+                                          at<double>(ws, L.headsA), at<double>(ws, L.headsB),
+                                          L.refine ? at<double>(ws, L.rt) : R, L.refine ? N : ldr, s),
+                   "cartesian root merge");
+        }
+        return L.refine ? run_refine(A, B, sh, L, R, ldr, ws, s) : FIGARO_OK;
+    }
     // Merge in FP64.
     const Region &r0 = L.regions[0];
     const double *cur = at<double>(ws, r0.root);
@@ -480,10 +511,7 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
         Groups g = groups_of(ws, L);
         const RowSrc heads = r0.skip ? RowSrc{at<void>(ws, r0.buf), g.counts + CNT_G, 0, N, 0, N}
                                      : RowSrc{cur, nullptr, N, r0.np, 0, N};
-        if (r0.skip && L.np_root <= 128)  // a Cartesian product has a single head row
-            HIPCHK(launch_tsqr_few(L.np_root, init, L.np_root, heads, L.m_f64, N, out, s), "tsqr merge");
-        else
-            HIPCHK(launch_tsqr_stream(L.np_root, 1, r0.skip ? L.m_f64 : 1, init, L.np_root, heads, none, 1, N,
+        HIPCHK(launch_tsqr_stream(L.np_root, 1, r0.skip ? L.m_f64 : 1, init, L.np_root, heads, none, 1, N,
                                       r0.skip ? 0 : N, 1, out, (int64_t)N * L.np_root, s),
                    "tsqr merge");
         cur = out;
@@ -506,18 +534,11 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
         HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, R, ldr, s), "sign normalisation");
         return FIGARO_OK;
     }
-    double *rt = at<double>(ws, L.rt);
     {
         Stage st("sign", s);
-        HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, rt, N, s), "sign normalisation");
+        HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, at<double>(ws, L.rt), N, s), "sign normalisation");
     }
-    Stage st("refine", s);
-    HIPCHK(launch_refine(A->data, sh.in_f64, sh.lda, sh.m1, (int)sh.n1, B->data, sh.ldb, sh.m2, (int)sh.n2,
-                         groups_of(ws, L), !sh.keyed, at<double>(ws, L.headsB), rt, N,
-                         at<double>(ws, L.gram), at<double>(ws, L.gy), at<double>(ws, L.partial),
-                         L.partial_cap, at<int32_t>(ws, L.failed), R, ldr, s),
-           "refinement sweep");
-    return FIGARO_OK;
+    return run_refine(A, B, sh, L, R, ldr, ws, s);
 }
 
 }  // namespace

@@ -86,20 +86,26 @@ __device__ inline void wave_sync()
 __device__ inline int64_t rows_of(const RowSrc &s) { return s.rows_dev ? *s.rows_dev : s.rows_host; }
 
 // Row r of the stacked sources (rows [0, rows0) of s0, then s1), column k of the virtual
-// row, or 0 where the element is not real.  r must be a row of the stacked sources; the
-// source column is clamped into range, so the load is always valid and can be issued
-// without a branch.
+// row.  r must be a row of the stacked sources; the source column is clamped into range,
+// so the load is always valid and needs no branch.  stacked_real says whether the
+// element is real (else it counts as 0); keeping that test out of the load lets a round
+// of loads be issued together.
 template <typename Tin, typename Tacc>
-__device__ inline Tacc load_stacked(const RowSrc &s0, const RowSrc &s1, int64_t rows0, int64_t r, int k, bool real)
+__device__ inline Tacc load_stacked(const RowSrc &s0, const RowSrc &s1, int64_t rows0, int64_t r, int k)
 {
     const bool first = r < rows0;
     const Tin *p = (const Tin *)(first ? s0.p : s1.p);
     const int64_t lr = first ? r : r - rows0, ld = first ? s0.ld : s1.ld;
     const int off = first ? s0.col_off : s1.col_off, w = first ? s0.width : s1.width;
     const int c = k - off;
-    const int cc = c < 0 ? 0 : (c >= w ? w - 1 : c);
-    const Tacc v = (Tacc)p[lr * ld + cc];
-    return (real && c >= 0 && c < w) ? v : Tacc(0);
+    return (Tacc)p[lr * ld + (c < 0 ? 0 : (c >= w ? w - 1 : c))];
+}
+
+__device__ inline bool stacked_real(const RowSrc &s0, const RowSrc &s1, int64_t rows0, int64_t r, int k)
+{
+    const bool first = r < rows0;
+    const int c = k - (first ? s0.col_off : s1.col_off);
+    return c >= 0 && c < (first ? s0.width : s1.width);
 }
 
 template <int NP, typename Tacc>
@@ -177,11 +183,13 @@ __device__ void panel_absorb(PanelLds<NP, Tacc> &L, double *R, const RowSrc &s0,
             [&](int e) {
                 const int i = e / NP, c = e - i * NP;
                 const int64_t r = rb + i;
-                return load_stacked<Tin, Tacc>(s0, s1, rows0, r < r_end ? r : r_end - 1, c, r < r_end && c < width);
+                return load_stacked<Tin, Tacc>(s0, s1, rows0, r < r_end ? r : r_end - 1, c);
             },
             [&](int e, Tacc v) {
                 const int i = e / NP, c = e - i * NP;
-                X[i * LDX + c] = v;
+                const int64_t r = rb + i;
+                const bool real = r < r_end && c < width && stacked_real(s0, s1, rows0, r, c);
+                X[i * LDX + c] = real ? v : Tacc(0);
             });
         // Leading columns known to be zero in this block.
         int jstart = 0;

@@ -628,53 +628,58 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
     }
 }
 
-// ------------------------------------------------------------------ a few rows into one triangle
+// ------------------------------------------------------------------ Cartesian root
 //
-// The merge of the two-sided form of a Cartesian product absorbs a single head row h
-// into the upper triangle R.  With one row, the reflector of column j acts on the pair
-// (R_jj, h_j) only: a plane rotation that zeroes h_j and rotates row j of R with h.
-// It leaves rows j+1.. of R untouched, so row j+1 is read from LDS while step j runs.
-// One wave; lane l owns columns l + 64 c (one column for NP <= 64, two for NP = 128) and
-// keeps its entries of h and of the current row of R in registers; the two scalars of
-// a step come from lane j by lane reads.  Rows are absorbed one after another.  The
-// packed triangle lives in LDS (66 KB at NP = 128).
+// The root of the two-sided form of a Cartesian product in one wave.  R starts as
+// diag(R_TA, R_TB) (the upper triangles of the two tails' roots, widths na and nb) and
+// absorbs the single head row h = [sqrt(m2) H(A) | sqrt(m1) H(B)] of the one group.
+// With one row, the reflector of column j acts on the pair (R_jj, h_j) only: a plane
+// rotation that zeroes h_j and rotates row j of R with h.  It leaves rows j+1.. of R
+// untouched, so row j+1 is read from LDS while step j runs.  Lane l owns columns
+// l + 64 c (one for NP <= 64, two for NP = 128) and keeps its entries of h and of the
+// current row of R in registers; the two scalars of a step come from lane j by lane
+// reads.  The packed triangle lives in LDS (66 KB at NP = 128).  R is written out with
+// every row's sign normalised (diagonal >= 0; a zero diagonal takes the sign of the row's
+// first nonzero entry; -0.0 becomes +0.0).  With no group (an empty table) nothing is
+// absorbed.
 template <int NP>
-__global__ __launch_bounds__(64) void k_tsqr_few(const double *init, int64_t init_ld, RowSrc src, int in_f64,
-                                                 int width, double *out)
+__global__ __launch_bounds__(64) void k_merge_cartesian(const double *Ta, int64_t lda, int na, const double *Tb,
+                                                        int64_t ldb, int nb, Groups g, const double *hA,
+                                                        const double *hB, double *R, int64_t ldr)
 {
     constexpr int CPL = NP > 64 ? NP / 64 : 1;
     __shared__ double Rp[packed_size(NP)];
-    const int lane = threadIdx.x;
-    if (init) {
-        staged_copy<16, double>(
-            width * NP, lane, 64,
-            [&](int e) {
-                const int j = e / NP, kk = e - j * NP;
-                return init[(int64_t)j * init_ld + (kk < width ? kk : width - 1)];
-            },
-            [&](int e, double v) {
-                const int j = e / NP, kk = e - j * NP;
-                if (kk >= j) Rp[pidx(NP, j, kk)] = kk < width ? v : 0.0;
-            });
-    } else {
-        for (int e = lane; e < packed_size(NP); e += 64) Rp[e] = 0.0;
-    }
+    const int lane = threadIdx.x, width = na + nb;
+    // diag(Ta, Tb) into the packed triangle; every load is clamped into its source
+    staged_copy<16, double>(
+        width * NP, lane, 64,
+        [&](int e) {
+            // base pointer and clamped offset chosen first: one unconditional load
+            const int j = e / NP, kk = e - j * NP;
+            const bool top = j < na;
+            const double *p = top ? Ta + (int64_t)j * lda : Tb + (int64_t)(j - na) * ldb;
+            const int c = top ? (kk < na ? kk : na - 1) : (kk < na ? 0 : (kk < width ? kk - na : nb - 1));
+            return p[c];
+        },
+        [&](int e, double v) {
+            const int j = e / NP, kk = e - j * NP;
+            if (kk < j) return;
+            const bool in = j < na ? kk < na : (kk >= na && kk < width);
+            Rp[pidx(NP, j, kk)] = in ? v : 0.0;
+        });
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const int64_t rows = src_rows(src);
-    const int j0 = src.col_off;
-    for (int64_t r = 0; r < rows; r++) {
+    if (g.counts[CNT_G] > 0) {
+        const double s2 = sqrt((double)g.m2[0]), s1 = sqrt((double)g.m1[0]);
         double h[CPL], rj[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; c++) {
             const int col = lane + 64 * c;
-            h[c] = col < width ? (in_f64 ? load_src<double, double>(src, r, col) : load_src<float, double>(src, r, col))
-                               : 0.0;
-            rj[c] = (col >= j0 && col < width) ? Rp[pidx(NP, j0, col)] : 0.0;
+            h[c] = col < na ? s2 * hA[col] : (col < width ? s1 * hB[col - na] : 0.0);
+            rj[c] = col < width ? Rp[pidx(NP, 0, col)] : 0.0;
         }
-        for (int j = j0; j < width; j++) {
-            // row j + 1 of R, which step j does not change
-            double rn[CPL];
+        for (int j = 0; j < width; j++) {
+            double rn[CPL];  // row j + 1 of R, which step j does not change
 #pragma unroll
             for (int c = 0; c < CPL; c++) {
                 const int col = lane + 64 * c;
@@ -688,7 +693,6 @@ __global__ __launch_bounds__(64) void k_tsqr_few(const double *init, int64_t ini
                     hj = readlane_f64(h[c], j % 64);
                 }
             const double q = fma(alpha, alpha, hj * hj);
-            // (a pair whose norm is below the normal range is left untouched)
             if (hj != 0.0 && q >= DBL_MIN) {
                 const double rinv = rsq_refined(q);
                 const double cs = alpha * rinv, sn = hj * rinv;
@@ -708,23 +712,113 @@ __global__ __launch_bounds__(64) void k_tsqr_few(const double *init, int64_t ini
 #pragma unroll
             for (int c = 0; c < CPL; c++) rj[c] = rn[c];
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
-    for (int e = lane; e < width * NP; e += 64) {
-        const int j = e / NP, kk = e - j * NP;
-        out[e] = (kk >= j && kk < width) ? Rp[pidx(NP, j, kk)] : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int i = 0; i < width; i++) {
+        const double d = Rp[pidx(NP, i, i)];
+        bool neg = d < 0.0;
+        if (d == 0.0) {
+            int first = width;
+            for (int k = i + lane; k < width; k += 64)
+                if (Rp[pidx(NP, i, k)] != 0.0) {
+                    first = k;
+                    break;
+                }
+            for (int off = 32; off > 0; off >>= 1) first = min(first, __shfl_xor(first, off, 64));
+            neg = first < width && Rp[pidx(NP, i, first)] < 0.0;
+        }
+        for (int k = lane; k < width; k += 64) {
+            const double v = k < i ? 0.0 : Rp[pidx(NP, i, k)];
+            R[(int64_t)i * ldr + k] = (neg ? -v : v) + 0.0;
+        }
     }
 }
 
-hipError_t launch_tsqr_few(int np, const double *init, int64_t init_ld, RowSrc src, int in_f64, int width,
-                           double *out, hipStream_t s)
+// The same for NP <= 64 with R in registers: lane k holds column k of R (row j in r[j]),
+// and the column loop is unrolled so that every row index is static.  No LDS: the two
+// scalars of step j come from lane j by lane reads, and row i is written out by the
+// lanes straight from r[i].
+template <int NP>
+__global__ __launch_bounds__(64) void k_merge_cartesian_reg(const double *Ta, int64_t lda, int na, const double *Tb,
+                                                            int64_t ldb, int nb, Groups g, const double *hA,
+                                                            const double *hB, double *R, int64_t ldr)
 {
+    static_assert(NP <= 64, "one column per lane");
+    const int k = threadIdx.x, width = na + nb;
+    const bool col_ok = k < width;
+    // column k of diag(Ta, Tb): rows of Ta for k < na, rows of Tb below them otherwise
+    // (clamped loads: every address lies inside its triangle)
+    double r[NP];
+    const int kc = k < width ? k : width - 1;
+    const bool top = kc < na;
+    // one base pointer and stride per lane, so that every load is unconditional (a select
+    // between two loads compiles to a branch that waits for each load in turn)
+    const double *col = top ? Ta + kc : Tb + (kc - na);
+    const int64_t ld = top ? lda : ldb;
+    const int r0 = top ? 0 : na, rows = top ? na : nb;  // rows of this lane's triangle
+#pragma unroll
+    for (int j = 0; j < NP; j++) {
+        const int jr = j - r0;
+        r[j] = col[(int64_t)(jr < 0 ? 0 : (jr < rows ? jr : rows - 1)) * ld];
+    }
+#pragma unroll
+    for (int j = 0; j < NP; j++) {
+        const int jr = j - r0;
+        r[j] = (col_ok && j <= k && jr >= 0 && jr < rows) ? r[j] : 0.0;
+    }
+    if (g.counts[CNT_G] > 0) {
+        const double s2 = sqrt((double)g.m2[0]), s1 = sqrt((double)g.m1[0]);
+        double h = k < na ? s2 * hA[k] : (col_ok ? s1 * hB[kc - na] : 0.0);
+#pragma unroll
+        for (int j = 0; j < NP; j++) {
+            const double alpha = readlane_f64(r[j], j), hj = readlane_f64(h, j);
+            const double q = fma(alpha, alpha, hj * hj);
+            // (columns past the width hold zeros: hj = 0 leaves them alone)
+            if (hj != 0.0 && q >= DBL_MIN) {
+                const double rinv = rsq_refined(q);
+                const double cs = alpha * rinv, sn = hj * rinv;
+                if (k > j) {
+                    const double a = r[j];
+                    r[j] = fma(cs, a, sn * h);
+                    h = fma(cs, h, -sn * a);
+                } else if (k == j) {
+                    r[j] = q * rinv;
+                    h = 0.0;
+                }
+            }
+        }
+    }
+    // row i: sign from its diagonal (lane i), or from its first nonzero entry if that is 0
+#pragma unroll
+    for (int i = 0; i < NP; i++) {
+        if (i >= width) continue;
+        const double d = readlane_f64(r[i], i);
+        bool neg = d < 0.0;
+        if (d == 0.0) {
+            const unsigned long long nz = __ballot(col_ok && k >= i && r[i] != 0.0);
+            if (nz) neg = readlane_f64(r[i], __builtin_ctzll(nz)) < 0.0;
+        }
+        if (col_ok) {
+            const double v = k < i ? 0.0 : r[i];
+            R[(int64_t)i * ldr + k] = (neg ? -v : v) + 0.0;
+        }
+    }
+}
+
+hipError_t launch_merge_cartesian(int np, const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
+                                  Groups g, const double *hA, const double *hB, double *R, int64_t ldr,
+                                  hipStream_t s)
+{
+    if (na < 1 || nb < 1) return hipErrorInvalidValue;
     switch (np) {
-#define FIGARO_FEW(NPV) \
-    case NPV: k_tsqr_few<NPV><<<1, 64, 0, s>>>(init, init_ld, src, in_f64, width, out); return hipGetLastError();
-    FIGARO_FEW(4) FIGARO_FEW(8) FIGARO_FEW(16) FIGARO_FEW(32) FIGARO_FEW(64) FIGARO_FEW(128)
-#undef FIGARO_FEW
+#define FIGARO_MC(NPV) \
+    case NPV: k_merge_cartesian_reg<NPV><<<1, 64, 0, s>>>(Ta, lda, na, Tb, ldb, nb, g, hA, hB, R, ldr); return hipGetLastError();
+    FIGARO_MC(4) FIGARO_MC(8) FIGARO_MC(16) FIGARO_MC(32) FIGARO_MC(64)
+#undef FIGARO_MC
+    case 128:
+        k_merge_cartesian<128><<<1, 64, 0, s>>>(Ta, lda, na, Tb, ldb, nb, g, hA, hB, R, ldr);
+        return hipGetLastError();
     default: return hipErrorInvalidValue;
     }
 }
