@@ -68,6 +68,29 @@ __device__ inline void staged_copy(int count, int first, int stride, Ld ld, St s
     }
 }
 
+// Row r of the stacked sources (rows [0, rows0) of s0, then s1), column k of the virtual
+// row.  r must be a row of the stacked sources; the source column is clamped into range,
+// so the load is always valid and needs no branch.  stacked_real says whether the
+// element is real (else it counts as 0); keeping that test out of the load lets a round
+// of loads be issued together.
+template <typename Tin, typename Tacc>
+__device__ inline Tacc load_stacked(const RowSrc &s0, const RowSrc &s1, int64_t rows0, int64_t r, int k)
+{
+    const bool first = r < rows0;
+    const Tin *p = (const Tin *)(first ? s0.p : s1.p);
+    const int64_t lr = first ? r : r - rows0, ld = first ? s0.ld : s1.ld;
+    const int off = first ? s0.col_off : s1.col_off, w = first ? s0.width : s1.width;
+    const int c = k - off;
+    return (Tacc)p[lr * ld + (c < 0 ? 0 : (c >= w ? w - 1 : c))];
+}
+
+__device__ inline bool stacked_real(const RowSrc &s0, const RowSrc &s1, int64_t rows0, int64_t r, int k)
+{
+    const bool first = r < rows0;
+    const int c = k - (first ? s0.col_off : s1.col_off);
+    return c >= 0 && c < (first ? s0.width : s1.width);
+}
+
 // Elements handled per block by the grouping kernels.
 constexpr int kGroupBlock = 2048;
 constexpr int kGroupThreads = 256;

@@ -79,14 +79,19 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_tile(
     __shared__ double a_s[kMaxCols];
 
     // The tile's loads are issued first; they stay in flight during the metadata search.
+    // Each load is unconditional, with the row and column clamped into the table (a
+    // conditional load compiles to a branch that waits for it in turn).  Entries outside
+    // the table are never used: their rows belong to no group and their columns are
+    // never stored.
     double x[RPT][CPT];
 #pragma unroll
     for (int i = 0; i < RPT; i++) {
         const int64_t s = t0 + (int64_t)q * RPT + i;
+        const int64_t sc = s < m2 ? s : m2 - 1;
 #pragma unroll
         for (int cc = 0; cc < CPT; cc++) {
             const int col = c + cc * ncolthr;
-            x[i][cc] = (active && s < m2 && col < n2) ? to_f64(B[s * ldb + col]) : 0.0;
+            x[i][cc] = to_f64(B[sc * ldb + (col < n2 ? col : n2 - 1)]);
         }
     }
 

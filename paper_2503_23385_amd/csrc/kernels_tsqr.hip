@@ -196,13 +196,19 @@ __device__ inline void wave_absorb_tri(Tacc *Rp, Tacc *xb, const double *T, int6
                                        int off, int tw, int width, int k, int h)
 {
     constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR;
+    const int c = k - off, cc = c < 0 ? 0 : (c < tw ? c : tw - 1);
     for (int b0 = 0; b0 < trows; b0 += BR) {
+        // unconditional loads (row and column clamped into T), masked afterwards
         Tacc x[RPT];
 #pragma unroll
         for (int i = 0; i < RPT; i++) {
             const int r = b0 + h * RPT + i;
-            const int c = k - off;
-            x[i] = (r < trows && c >= 0 && c < tw) ? (Tacc)T[(int64_t)r * ld + c] : Tacc(0);
+            x[i] = (Tacc)T[(int64_t)(r < trows ? r : trows - 1) * ld + cc];
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; i++) {
+            const int r = b0 + h * RPT + i;
+            if (!(r < trows && c >= 0 && c < tw)) x[i] = Tacc(0);
         }
         wave_block<NP, Tacc>(x, Rp, xb, k, h, off + b0, width);
     }
@@ -216,16 +222,17 @@ __device__ inline void wave_absorb_rows(Tacc *Rp, Tacc *xb, const RowSrc &s0, co
 {
     constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR;
     for (int64_t rb = r0; rb < r1; rb += BR) {
+        // unconditional loads (clamped into the sources), masked afterwards
         Tacc x[RPT];
 #pragma unroll
         for (int i = 0; i < RPT; i++) {
             const int64_t r = rb + h * RPT + i;
-            Tacc v = Tacc(0);
-            if (r < r1 && k < width) {
-                if (r < rows0) v = load_src<Tin, Tacc>(s0, r, k);
-                else v = load_src<Tin, Tacc>(s1, r - rows0, k);
-            }
-            x[i] = v;
+            x[i] = load_stacked<Tin, Tacc>(s0, s1, rows0, r < r1 ? r : r1 - 1, k);
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; i++) {
+            const int64_t r = rb + h * RPT + i;
+            if (!(r < r1 && k < width && stacked_real(s0, s1, rows0, r, k))) x[i] = Tacc(0);
         }
         int jstart = 0;
         const int64_t rlast = min(r1, rb + BR) - 1;
@@ -372,11 +379,20 @@ __device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> 
 }
 
 // Absorb rows [r0, r1) of src in blocks of 4 BR rows (wave wv takes the wv-th quarter).
-template <int NP, typename Tin, typename Tacc>
+// STAGED: every row load is issued unconditionally (row and column clamped into the
+// source) and masked afterwards, so the loads of a block stay in flight together; more
+// registers, used when a launch has at most one leaf per compute unit (each leaf's
+// latency is the launch's).  Otherwise the loads are conditional and converted in a
+// second pass (fewer registers, more workgroups per compute unit to hide latency with).
+template <int NP, typename Tin, typename Tacc, bool STAGED>
 __device__ inline void wg_absorb_rows(WgState<NP, Tacc> &st, const RowSrc &src, int64_t r0, int64_t r1,
                                       int tri_rows, int width)
 {
     constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR, BG = tree_waves(NP) * BR;
+    // this lane's column of the source, clamped into range (col_in: whether it is real)
+    const int c = st.k - src.col_off;
+    const bool col_in = st.k < width && c >= 0 && c < src.width;
+    const Tin *col_base = (const Tin *)src.p + (c < 0 ? 0 : (c < src.width ? c : src.width - 1));
     for (int64_t rb = r0; rb < r1; rb += BG) {
         if (st.pend_row >= 0) {  // the block may start at the pending row: write it first
             __syncthreads();
@@ -384,10 +400,23 @@ __device__ inline void wg_absorb_rows(WgState<NP, Tacc> &st, const RowSrc &src, 
             __syncthreads();
         }
         Tacc x[RPT];
+        if constexpr (STAGED) {
 #pragma unroll
-        for (int i = 0; i < RPT; i++) {
-            const int64_t r = rb + st.wv * BR + st.h * RPT + i;
-            x[i] = (r < r1 && st.k < width) ? load_src<Tin, Tacc>(src, r, st.k) : Tacc(0);
+            for (int i = 0; i < RPT; i++) {
+                const int64_t r = rb + st.wv * BR + st.h * RPT + i;
+                x[i] = (Tacc)col_base[(r < r1 ? r : r1 - 1) * src.ld];
+            }
+#pragma unroll
+            for (int i = 0; i < RPT; i++) {
+                const int64_t r = rb + st.wv * BR + st.h * RPT + i;
+                if (!(r < r1 && col_in)) x[i] = Tacc(0);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPT; i++) {
+                const int64_t r = rb + st.wv * BR + st.h * RPT + i;
+                x[i] = (r < r1 && col_in) ? (Tacc)col_base[r * src.ld] : Tacc(0);
+            }
         }
         int jstart = src.col_off;
         if (tri_rows > 0) {
@@ -431,7 +460,7 @@ __device__ inline void wg_load_tri(WgState<NP, Tacc> &st, const double *T, int w
 // tree of the region's arity; at each node the last child to arrive (per-node atomic
 // counter) combines all children in child order.  slots: the node triangles of every
 // level (width x NP doubles each); counters: one int per parent node, zero on entry.
-template <int NP, typename Tin, typename Tacc>
+template <int NP, typename Tin, typename Tacc, bool STAGED>
 __global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion reg0, TreeRegion reg1)
 {
     using Gm = WaveGeom<NP>;
@@ -466,7 +495,7 @@ __global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion re
     int64_t chunk = (rows + nleaves - 1) / nleaves;
     chunk = ((chunk + BG - 1) / BG) * BG;
     const int64_t r0 = (int64_t)g * chunk, r1 = min(rows, r0 + chunk);
-    wg_absorb_rows<NP, Tin, Tacc>(st, rg.src, r0, r1, 0, width);
+    wg_absorb_rows<NP, Tin, Tacc, STAGED>(st, rg.src, r0, r1, 0, width);
 
     const int64_t tsz = (int64_t)width * NP;
     const int A = rg.arity;
@@ -490,7 +519,7 @@ __global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion re
             wg_load_tri<NP, Tacc>(st, rg.slots + (soff + first) * tsz, width);
             const RowSrc sib{rg.slots + (soff + first + 1) * tsz, nullptr, (int64_t)(nchild - 1) * width, NP, 0,
                              width};
-            wg_absorb_rows<NP, double, Tacc>(st, sib, 0, sib.rows_host, width, width);
+            wg_absorb_rows<NP, double, Tacc, STAGED>(st, sib, 0, sib.rows_host, width, width);
         }
         node = parent;
         soff += n;
@@ -554,7 +583,13 @@ hipError_t launch_tree_np(int acc_f64, int in_f64, const TreeRegion *regs, int n
     TreeRegion r0 = regs[0];
     TreeRegion r1 = nreg > 1 ? regs[1] : TreeRegion{};
     const unsigned grid = (unsigned)(r0.nleaves + r1.nleaves);
-#define FIGARO_TREE(TI, TA) k_tsqr_tree<NP, TI, TA><<<grid, 64 * tree_waves(NP), 0, s>>>(r0, r1)
+    // at most one leaf per compute unit: staged loads (see wg_absorb_rows)
+    const bool staged = grid <= 256;
+#define FIGARO_TREE(TI, TA)                                                                   \
+    do {                                                                                      \
+        if (staged) k_tsqr_tree<NP, TI, TA, true><<<grid, 64 * tree_waves(NP), 0, s>>>(r0, r1);  \
+        else k_tsqr_tree<NP, TI, TA, false><<<grid, 64 * tree_waves(NP), 0, s>>>(r0, r1);        \
+    } while (0)
     if (acc_f64) {
         if (in_f64) FIGARO_TREE(double, double);
         else FIGARO_TREE(float, double);
