@@ -491,7 +491,10 @@ constexpr int kMsRounds = 7;      // 257^7 > 2^55: the final interval is below 2
 
 template <int NPC>
 struct GkGeom {
-    static constexpr int LDA = NPC + 1;                 // row stride of A in LDS (odd: spreads banks)
+    // row stride of A in LDS: even, so that rows are 16-byte aligned and a lane reading
+    // its own row can use 128-bit reads; lane i then starts 4 i banks further, so 16
+    // lanes cover the 64 banks (the fewest passes a 128-bit read of 64 lanes can take)
+    static constexpr int LDA = NPC + 2;
     static constexpr int CPL = NPC > 64 ? NPC / 64 : 1; // rows / columns per lane in the bidiagonalisation
     static constexpr int CH = NPC < 16 ? NPC : 16;      // rows per chunk of the reflector loops
 };
