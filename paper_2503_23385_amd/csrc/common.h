@@ -116,10 +116,25 @@ struct ScanPlan {
 ScanPlan scan_plan(int64_t m, int64_t n, int in_bytes);
 // Three launches: tile reduce, carry scan, tile write (tileF: ntiles ints; tileS, carry:
 // ntiles x n doubles of scratch).  heads[g] receives H(X_g) = (sum of the group's rows) / sqrt(size).
-hipError_t launch_seg_scan(const void *X, int in_f64, int64_t ldx, int64_t m, int64_t n, Groups g,
-                           ScanSide side, int cartesian, void *out, int out_f64, double *heads,
-                           int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp,
-                           hipStream_t s);
+// One table's head/tail scan: its rows, output tails (out) and heads, and the tile scratch.
+struct ScanJob {
+    const void *in;
+    int64_t ld;
+    int32_t m, n, q;
+    ScanSide side;
+    void *out;
+    double *heads;
+    int32_t *tileF;
+    double *tileS;
+    double *carry;
+    int64_t ntiles;
+};
+ScanJob scan_job(const void *X, int64_t ldx, int64_t m, int64_t n, ScanSide side, void *out, double *heads,
+                 int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp);
+// Scans one or two jobs (an empty second job has ntiles = 0) in three launches (tile
+// reduce, carry scan, tile write); two jobs need the same cpt and storage types.
+hipError_t launch_seg_scan(const ScanJob &j0, const ScanJob &j1, int cpt, int in_f64, int out_f64, Groups g,
+                           int cartesian, hipStream_t s);
 // Claim 1 region 1: [sqrt(m2_g) A_r | H(B_g)].
 hipError_t launch_assemble_a(const void *A, int in_f64, int64_t lda, int64_t m1, int64_t n1,
                              int64_t n2, Groups g, int cartesian, const double *heads, void *M1,

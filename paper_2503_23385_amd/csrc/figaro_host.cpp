@@ -379,29 +379,39 @@ int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, c
     }
     double *hB = at<double>(ws, L.headsB);
     const Region &rb = L.regions.back();  // region of B's tails in both forms
-    {
-        Stage st("scan", s);
-        ScanSide sideB{g.offB, g.m2, g.m1, g.r2, 0};
-        HIPCHK(launch_seg_scan(B->data, sh.in_f64, sh.ldb, sh.m2, sh.n2, g, sideB, !sh.keyed,
-                               at<void>(ws, rb.buf), L.m_f64, hB, at<int32_t>(ws, L.tileF[1]),
-                               at<double>(ws, L.tileS[1]), at<double>(ws, L.carry[1]), L.spB, s),
-               "head/tail scan of B");
-    }
+    const ScanJob none{};
+    ScanSide sideB{g.offB, g.m2, g.m1, g.r2, 0};
+    const ScanJob jb = scan_job(B->data, sh.ldb, sh.m2, sh.n2, sideB, at<void>(ws, rb.buf), hB,
+                                at<int32_t>(ws, L.tileF[1]), at<double>(ws, L.tileS[1]),
+                                at<double>(ws, L.carry[1]), L.spB);
     if (!sh.two_sided) {
+        {
+            Stage st("scan", s);
+            HIPCHK(launch_seg_scan(jb, none, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+                   "head/tail scan of B");
+        }
         Stage st("assemble", s);
         HIPCHK(launch_assemble_a(A->data, sh.in_f64, sh.lda, sh.m1, sh.n1, sh.n2, g, !sh.keyed, hB,
                                  at<void>(ws, L.regions[0].buf), L.m_f64, s),
                "region-1 assembly");
     } else {
         double *hA = at<double>(ws, L.headsA);
+        ScanSide sideA{g.offA, g.m1, g.m2, g.r1, 1};
+        const ScanJob ja = scan_job(A->data, sh.lda, sh.m1, sh.n1, sideA, at<void>(ws, L.regions[1].buf), hA,
+                                    at<int32_t>(ws, L.tileF[0]), at<double>(ws, L.tileS[0]),
+                                    at<double>(ws, L.carry[0]), L.spA);
         {
+            // both tables in one launch per pass when their tiles have the same column layout
             Stage st("scan", s);
-            ScanSide sideA{g.offA, g.m1, g.m2, g.r1, 1};
-            HIPCHK(launch_seg_scan(A->data, sh.in_f64, sh.lda, sh.m1, sh.n1, g, sideA, !sh.keyed,
-                                   at<void>(ws, L.regions[1].buf), L.m_f64, hA,
-                                   at<int32_t>(ws, L.tileF[0]), at<double>(ws, L.tileS[0]),
-                                   at<double>(ws, L.carry[0]), L.spA, s),
-                   "head/tail scan of A");
+            if (L.spA.cpt == L.spB.cpt) {
+                HIPCHK(launch_seg_scan(jb, ja, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+                       "head/tail scans");
+            } else {
+                HIPCHK(launch_seg_scan(jb, none, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+                       "head/tail scan of B");
+                HIPCHK(launch_seg_scan(ja, none, L.spA.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+                       "head/tail scan of A");
+            }
         }
         if (head_rows) {
             Stage st("assemble", s);

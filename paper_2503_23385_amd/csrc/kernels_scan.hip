@@ -55,20 +55,30 @@ __device__ inline int first_end_gt(const int32_t *start, const int32_t *size, in
     return lo;
 }
 
-// One tile of B rows: reduce (WRITE = false) or write tails/heads (WRITE = true).
+// One tile of a table's rows: reduce (WRITE = false) or write tails/heads (WRITE = true).
+// The tiles of two jobs (the two tables of the two-sided form) share one launch: blocks
+// [0, j0.ntiles) take job 0, the rest job 1.
 template <typename Tin, typename Tout, int CPT, int RPT, bool WRITE>
-__global__ __launch_bounds__(kScanThreads) void k_seg_tile(
-    const Tin *__restrict__ B, int64_t ldb, int m2, int n2, int Q, Groups g, ScanSide side,
-    int cartesian, Tout *__restrict__ M2, double *__restrict__ heads, int32_t *__restrict__ tileF,
-    double *__restrict__ tileS, const double *__restrict__ carry)
+__global__ __launch_bounds__(kScanThreads) void k_seg_tile(ScanJob j0, ScanJob j1, Groups g, int cartesian)
 {
+    const bool second = (int64_t)blockIdx.x >= j0.ntiles;
+    const ScanJob &J = second ? j1 : j0;
+    const Tin *__restrict__ B = (const Tin *)J.in;
+    const int64_t ldb = J.ld;
+    const int m2 = J.m, n2 = J.n, Q = J.q;
+    const ScanSide side = J.side;
+    Tout *__restrict__ M2 = (Tout *)J.out;
+    double *__restrict__ heads = J.heads;
+    int32_t *__restrict__ tileF = J.tileF;
+    double *__restrict__ tileS = J.tileS;
+    const double *__restrict__ carry = J.carry;
     const int tid = threadIdx.x;
     const int ncolthr = (n2 + CPT - 1) / CPT;
     const int c = tid % ncolthr;
     const int q = tid / ncolthr;
     const bool active = q < Q;
     const int TR = Q * RPT;
-    const int t = blockIdx.x;
+    const int t = (int)(blockIdx.x - (second ? j0.ntiles : 0));
     const int64_t t0 = (int64_t)t * TR;
     const int G = (int)g.counts[CNT_G];
 
@@ -241,12 +251,16 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_tile(
 // segmented operator (f1, s1) + (f2, s2) = (f1 | f2, f2 ? s2 : s1 + s2)), and each thread
 // rescans its run with the carry it receives.  The combination order is fixed, so the
 // result does not depend on timing.
-__global__ __launch_bounds__(kCarryThreads) void k_carry_scan(const int32_t *__restrict__ tileF,
-                                                              const double *__restrict__ tileS,
-                                                              double *__restrict__ carry, int T,
-                                                              int n2)
+__global__ __launch_bounds__(kCarryThreads) void k_carry_scan(ScanJob j0, ScanJob j1)
 {
-    const int c = blockIdx.x, tid = threadIdx.x;
+    // blocks [0, j0.n) take the columns of job 0, the rest those of job 1
+    const bool second = (int)blockIdx.x >= j0.n;
+    const ScanJob &J = second ? j1 : j0;
+    const int32_t *__restrict__ tileF = J.tileF;
+    const double *__restrict__ tileS = J.tileS;
+    double *__restrict__ carry = J.carry;
+    const int T = (int)J.ntiles, n2 = J.n;
+    const int c = (int)blockIdx.x - (second ? j0.n : 0), tid = threadIdx.x;
     const int L = (T + kCarryThreads - 1) / kCarryThreads;
     const int tb = min(T, tid * L), te = min(T, tb + L);
     __shared__ int sf[2][kCarryThreads];
@@ -374,21 +388,37 @@ ScanPlan scan_plan(int64_t m2, int64_t n2, int in_bytes)
     return p;
 }
 
-hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, int64_t n2, Groups g,
-                           ScanSide side, int cartesian, void *M2, int out_f64, double *heads,
-                           int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp,
-                           hipStream_t s)
+ScanJob scan_job(const void *X, int64_t ldx, int64_t m, int64_t n, ScanSide side, void *out, double *heads,
+                 int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp)
 {
-    if (sp.ntiles == 0) return hipSuccess;
-    if (n2 > kMaxCols) return hipErrorInvalidValue;
-    const unsigned grid = (unsigned)sp.ntiles;
-#define FIGARO_TILE(TI, TO, CPT, WR)                                                              \
-    k_seg_tile<TI, TO, CPT, 16, WR><<<grid, kScanThreads, 0, s>>>(                               \
-        (const TI *)B, ldb, (int)m2, (int)n2, sp.q, g, side, cartesian, (TO *)M2, heads, tileF,   \
-        tileS, carry)
+    ScanJob j;
+    j.in = X;
+    j.ld = ldx;
+    j.m = (int)m;
+    j.n = (int)n;
+    j.q = sp.q;
+    j.side = side;
+    j.out = out;
+    j.heads = heads;
+    j.tileF = tileF;
+    j.tileS = tileS;
+    j.carry = carry;
+    j.ntiles = sp.ntiles;
+    return j;
+}
+
+hipError_t launch_seg_scan(const ScanJob &j0, const ScanJob &j1, int cpt, int in_f64, int out_f64, Groups g,
+                           int cartesian, hipStream_t s)
+{
+    const int64_t tiles = j0.ntiles + j1.ntiles;
+    if (tiles == 0) return hipSuccess;
+    if (j0.n > kMaxCols || j1.n > kMaxCols) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)tiles;
+#define FIGARO_TILE(TI, TO, CPT, WR) \
+    k_seg_tile<TI, TO, CPT, 16, WR><<<grid, kScanThreads, 0, s>>>(j0, j1, g, cartesian)
 #define FIGARO_TILE_ALL(WR)                                                                       \
     do {                                                                                          \
-        if (sp.cpt == 1) {                                                                        \
+        if (cpt == 1) {                                                                           \
             if (in_f64 && out_f64) FIGARO_TILE(double, double, 1, WR);                            \
             else if (in_f64) FIGARO_TILE(double, float, 1, WR);                                   \
             else if (out_f64) FIGARO_TILE(float, double, 1, WR);                                  \
@@ -403,7 +433,11 @@ hipError_t launch_seg_scan(const void *B, int in_f64, int64_t ldb, int64_t m2, i
     FIGARO_TILE_ALL(false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_carry_scan<<<(unsigned)n2, kCarryThreads, 0, s>>>(tileF, tileS, carry, (int)sp.ntiles, (int)n2);
+    // jobs without tiles have no columns to carry
+    ScanJob c0 = j0, c1 = j1;
+    if (c0.ntiles == 0) c0.n = 0;
+    if (c1.ntiles == 0) c1.n = 0;
+    k_carry_scan<<<(unsigned)(c0.n + c1.n), kCarryThreads, 0, s>>>(c0, c1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     FIGARO_TILE_ALL(true);
