@@ -139,9 +139,10 @@ STAGE_KERNELS = {
 }
 
 
-def measured_traffic(workload, stage):
-    """HBM bytes per launch of the stage's kernel from the committed counter summary, if the
-    kernel source is unchanged since the counters were taken (else None)."""
+def measured_traffic(workload, stage, form=None):
+    """HBM bytes per launch of the stage's kernel for this form (layout:precision) from the
+    committed counter summary, if the kernel source is unchanged since the counters were
+    taken (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.md")
     if stage not in STAGE_KERNELS or not os.path.exists(path):
@@ -153,7 +154,8 @@ def measured_traffic(workload, stage):
         for line in fh:
             if line.startswith("TRAFFIC "):
                 rec = json.loads(line[len("TRAFFIC "):])
-                if rec.get("stage") == stage and rec.get("source_sha1") == sha:
+                if (rec.get("stage") == stage and rec.get("source_sha1") == sha
+                        and rec.get("form") in (None, form)):
                     return rec["bytes_per_launch"]
     return None
 
@@ -378,7 +380,7 @@ def main():
                           stream, refs)
 
     if out["roofline"] is not None:
-        out["roofline"]["traffic"] = measured_traffic(wl, out["roofline"]["kernel"])
+        out["roofline"]["traffic"] = measured_traffic(wl, out["roofline"]["kernel"], out["config"].get("form"))
 
     line = {
         "metric": METRIC,

@@ -104,6 +104,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr int kPrecMask = 0xff;
 constexpr int kMaxTreeLeaves = 2048;
+constexpr int64_t kLeafTarget = 256;
 constexpr int kMaxPanelLeaves = 128;
 constexpr int kPlanLanes = 8;  // parallel branches of a batched plan's graph
 
@@ -213,13 +214,21 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     r.np = tsqr_padded_width(width);
     r.wave = r.np <= 64;
     const int br = tsqr_block_rows(r.np, acc_f64);
-    // Leaves of a few blocks each (tunable through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS);
-    // the wide tree keeps at most one leaf per compute unit and a half.
+    // Leaf sizes (fixed through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS).  Narrow trees
+    // (measured): leaves of two blocks, lengthened to keep a region at kLeafTarget leaves
+    // (two per compute unit when the two tails share a launch): shorter leaves add
+    // workgroups that wait for a compute unit, longer ones add sequential column steps.
+    // The wide tree keeps at most one leaf per compute unit and a half.
     static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 0);
     static const int wg_blocks = env_int("FIGARO_WG_LEAF_BLOCKS", 4);
-    // narrow trees (measured): two blocks of 512 rows at width 32, four blocks elsewhere
-    const int narrow_blocks = wave_blocks > 0 ? wave_blocks : (r.np == 32 ? 2 : 4);
-    r.rows_per_leaf = (int64_t)(r.wave ? narrow_blocks : wg_blocks) * br;
+    if (!r.wave) {
+        r.rows_per_leaf = (int64_t)wg_blocks * br;
+    } else if (wave_blocks > 0) {
+        r.rows_per_leaf = (int64_t)wave_blocks * br;
+    } else {
+        const int64_t per_leaf = (r.rows_cap + kLeafTarget - 1) / kLeafTarget;
+        r.rows_per_leaf = std::max<int64_t>(2 * br, (per_leaf + br - 1) / br * br);
+    }
     const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
     r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, r.wave ? kMaxTreeLeaves : kMaxPanelLeaves));
     r.ncounters = 0;
