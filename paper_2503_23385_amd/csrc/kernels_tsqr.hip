@@ -276,18 +276,28 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_tsqr_wave(const double 
 
 // ------------------------------------------------------------------ one workgroup per triangle (tree)
 //
-// The four waves of a workgroup share one triangle R and each holds a quarter
-// of the current block (BR rows per wave, so a block has 4 BR rows).  Column
-// step j: every wave forms its partial dot products d_k over its own rows, the
-// partials meet in LDS (one barrier; summed in wave order, so the result does
-// not depend on timing), every wave computes the same reflector scalars and
-// updates its own rows.  Row j of R is read by every wave during step j, so its
-// new values are written one step later, after the next barrier.
+// The waves of a workgroup share one triangle R and each holds its share of the
+// current block (BR rows per wave).  Column step j: every wave forms its partial dot
+// products d_k over its own rows, the partials meet in LDS (one barrier; summed in a
+// fixed order, so the result does not depend on timing), every wave computes the same
+// reflector scalars and updates its own rows.  Only step j changes row j of R; every wave reads it at the start of the
+// step, before the barrier, and its new values are written one step later, after the
+// next barrier.
 
 // Waves per workgroup of the tree kernel (measured): 8 at padded width 32, where the
 // blocks of 512 rows halve the sequential column steps of a leaf and two waves per SIMD
 // hide part of the LDS broadcast; 4 elsewhere (8 measured slower at widths 64 and below 32).
 __host__ __device__ constexpr int tree_waves(int np) { return np == 32 ? 8 : 4; }
+
+// Sum of the values of lanes l and l ^ 32, the same in both lanes: a swap of the wave's
+// halves (a VALU lane permutation, no LDS round trip) and one add.
+__device__ inline double half_swap_sum(double v)
+{
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
 
 template <int NP, typename Tacc>
 struct WgState {
@@ -312,9 +322,13 @@ template <int NP, typename Tacc>
 __device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> &st, int jstart, int width)
 {
     constexpr int RPT = WaveGeom<NP>::RPT, H = WaveGeom<NP>::H;
+    constexpr int NPART = tree_waves(NP);
     const int k = st.k;
     const bool col_ok = k < width;
     for (int j = jstart; j < width; j++) {
+        // Row j of R (changed by this step only), read before the barrier.
+        const double alpha = (double)st.R[pidx(NP, j, j)];
+        const Tacc rjk = st.R[pidx(NP, j, (k > j && col_ok) ? k : j)];
         // Column j of this wave's rows.  With one row set per wave it is read from lane j
         // into scalar registers (no LDS traffic); with several, lane j of each row set
         // stages it in LDS (a per-row-set select of lane reads costs more than that).
@@ -334,45 +348,56 @@ __device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> 
 #pragma unroll
             for (int i = 0; i < RPT; i++) xj[i] = st.xb[i];
         }
-        double dp[4] = {0.0, 0.0, 0.0, 0.0};
+        // Per-lane dot over RPT rows in the accumulation type (FP32 storage: FP32 sums of
+        // RPT products, in 8 chains of RPT / 8 fmas), then FP64 from the half-wave sums on.
+        Tacc dp[8];
 #pragma unroll
-        for (int i = 0; i < RPT; i++) dp[i & 3] += (double)xj[i] * (double)x[i];
-        double d = (dp[0] + dp[1]) + (dp[2] + dp[3]);
+        for (int i = 0; i < 8; i++) dp[i] = xj[i] * x[i];
 #pragma unroll
-        for (int off = NP; off < 64; off <<= 1) d += __shfl_xor(d, off, 64);
+        for (int i = 8; i < RPT; i++) dp[i & 7] = fma(xj[i], x[i], dp[i & 7]);
+        double d = (double)(((dp[0] + dp[1]) + (dp[2] + dp[3])) + ((dp[4] + dp[5]) + (dp[6] + dp[7])));
+#pragma unroll
+        for (int off = NP; off < 32; off <<= 1) d += __shfl_xor(d, off, 64);
+        if constexpr (H >= 2) d = half_swap_sum(d);
         if (st.h == 0) st.red[st.par][st.wv][k] = d;
         __syncthreads();
         wg_flush(st, width);
-        double dk = 0.0, s = 0.0;
+        double pk[NPART], pj[NPART];
 #pragma unroll
-        for (int w = 0; w < tree_waves(NP); w++) {
-            dk += st.red[st.par][w][k];
-            s += st.red[st.par][w][j];
+        for (int w = 0; w < NPART; w++) {
+            pk[w] = st.red[st.par][w][k];
+            pj[w] = st.red[st.par][w][j];
         }
-        st.par ^= 1;
-        const double alpha = (double)st.R[pidx(NP, j, j)];
-        const Tacc rjk = (k > j && col_ok) ? st.R[pidx(NP, j, k)] : Tacc(0);
-        const double q = fma(alpha, alpha, s);
-        // A column whose norm is below the normal range is left untouched (tau = 0).
-        if (s > 0.0 && q >= DBL_MIN) {
-            const double r = rsq_refined(q);
-            const double sg = alpha >= 0.0 ? 1.0 : -1.0;
-            const double nrm = q * r;
-            const double beta = -sg * nrm;
-            const double inv_beta = -sg * r;
-            const double scl = rcp_refined(alpha + sg * nrm);
-            const double tau = 1.0 - alpha * inv_beta;
-            if (k > j && col_ok) {
-                const double w = (double)rjk + scl * dk;
-                st.pend_val = (Tacc)((double)rjk - tau * w);
-                const Tacc c = (Tacc)(w * inv_beta);
 #pragma unroll
-                for (int i = 0; i < RPT; i++) x[i] += c * xj[i];
-            } else if (k == j) {
-                st.pend_val = (Tacc)beta;
-            } else {
-                st.pend_val = Tacc(0);
+        for (int w = 1; w < NPART; w <<= 1)
+#pragma unroll
+            for (int u = 0; u + w < NPART; u += 2 * w) {
+                pk[u] += pk[u + w];
+                pj[u] += pj[u + w];
             }
+        const double dk = pk[0], s = pj[0];
+        st.par ^= 1;
+        const double q = fma(alpha, alpha, s);
+        // A column whose norm is below the normal range is left untouched (tau = 0).  The
+        // scalars are formed without a branch (the same in every lane), so that the
+        // partials of both columns are read together right after the barrier.
+        const bool ok = s > 0.0 && q >= DBL_MIN;
+        const double r = rsq_refined(ok ? q : 1.0);
+        const double sg = alpha >= 0.0 ? 1.0 : -1.0;
+        const double nrm = q * r;
+        const double beta = -sg * nrm;
+        const double inv_beta = -sg * r;
+        const double scl = rcp_refined(ok ? alpha + sg * nrm : 1.0);
+        const double tau = 1.0 - alpha * inv_beta;
+        const double w = (double)rjk + scl * dk;
+        const bool upd = ok && k > j && col_ok;
+        const Tacc c = upd ? (Tacc)(w * inv_beta) : Tacc(0);
+        if (upd) {
+#pragma unroll
+            for (int i = 0; i < RPT; i++) x[i] += c * xj[i];
+        }
+        if (ok) {
+            st.pend_val = upd ? (Tacc)((double)rjk - tau * w) : (k == j ? (Tacc)beta : Tacc(0));
             st.pend_row = j;
         }
     }
