@@ -485,7 +485,7 @@ hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int
 namespace figaro {
 namespace {
 
-constexpr int kGkThreads = 256;   // load and scale; wave 0 bidiagonalises
+constexpr int kGkThreads = 256;   // load and scale; four waves bidiagonalise (wave 0 alone above width 64)
 constexpr int kMsThreads = 256;   // multisection points per round (one workgroup per value)
 constexpr int kMsRounds = 7;      // 257^7 > 2^55: the final interval is below 2^-53 of the bound
 
@@ -552,11 +552,15 @@ __device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 // a row for a right one): x <- x - tau (v . x) v over the active entries [lo, n), in
 // whole chunks of CH entries (v is zero outside [lo, n) and A is zero beyond n, so the
 // extra entries add nothing and are written back unchanged).  X(e) addresses entry e
-// of x in LDS.
+// of x in LDS.  Returns the new entry lo of x (v_lo = 1), which the caller needs next,
+// without reading it back.  (Keeping the chunks in registers between the two passes
+// measured slower: it exceeds the architectural registers and the compiler moves them
+// through accumulation registers.)
 template <int CH, typename Addr>
-__device__ inline void reflect_vector(double *A, const double *v, double tau, int lo, int n, Addr X)
+__device__ inline double reflect_vector(double *A, const double *v, double tau, int lo, int n, Addr X)
 {
     const int c0 = lo / CH, c1 = (n + CH - 1) / CH;
+    const double xlo = A[X(lo)];
     double w[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = c0; c < c1; c++) {
         double x[CH], u[CH];
@@ -579,6 +583,7 @@ __device__ inline void reflect_vector(double *A, const double *v, double tau, in
 #pragma unroll
         for (int r = 0; r < CH; r++) A[X(c * CH + r)] = fma(-t, u[r], x[r]);
     }
+    return fma(-t, 1.0, xlo);
 }
 
 // Householder bidiagonalisation of the n x n matrix A (LDS, row stride LDA) by one wave:
@@ -625,9 +630,8 @@ __device__ void gk_bidiag_wave(double *A, double *vl, double *vr, double *dd, do
 #pragma unroll
         for (int c = 0; c < CPL; c++) {
             const int j = lane + 64 * c;
-            if (tau != 0.0 && j > k && j < n)
-                reflect_vector<CH>(A, vl, tau, k, n, [j](int e) { return e * LDA + j; });
-            rk[c] = j > k && j < n ? A[k * LDA + j] : 0.0;
+            rk[c] = j > k && j < n ? reflect_vector<CH>(A, vl, tau, k, n, [j](int e) { return e * LDA + j; })
+                                   : 0.0;
         }
         if (k + 1 >= n) break;
         // ---- right reflector from row k, columns k+1..n-1
@@ -653,11 +657,83 @@ __device__ void gk_bidiag_wave(double *A, double *vl, double *vr, double *dd, do
 #pragma unroll
         for (int c = 0; c < CPL; c++) {
             const int i = lane + 64 * c;
-            if (tau != 0.0 && i > k && i < n)
-                reflect_vector<CH>(A, vr, tau, k + 1, n, [i](int e) { return i * LDA + e; });
-            a[c] = i > k && i < n ? A[i * LDA + k + 1] : 0.0;
+            a[c] = i > k && i < n ? reflect_vector<CH>(A, vr, tau, k + 1, n, [i](int e) { return i * LDA + e; })
+                                  : 0.0;
         }
         wave_sync();
+    }
+}
+
+// The same bidiagonalisation by the four waves of the workgroup (NPC <= 64).  Every wave
+// forms the reflector of a half-step itself, from the column (left) or row (right) it
+// reads from LDS, and applies it to its quarter of the rows (left: lane = column) or of
+// the columns (right: lane = row), entries [w RW, (w + 1) RW): the quarter is loaded
+// right after the barrier, the reflector entries of the quarter come from lane reads,
+// the per-lane partial dot products meet in LDS (one barrier), the wave updates its
+// quarter, and a second barrier publishes the matrix for the next half-step.
+template <int NPC>
+__device__ void gk_bidiag_wg(double *A, double (*red)[64], double *dd, double *ee, int n, int lane, int wv)
+{
+    constexpr int LDA = GkGeom<NPC>::LDA, RW = NPC / 4;
+    const int w = __builtin_amdgcn_readfirstlane(wv);
+    const int e0 = w * RW;                      // first entry of this wave's quarter
+    const int ln = lane < NPC ? lane : NPC - 1;  // this lane's column (row) of A, clamped
+    for (int k = 0; k < n; k++) {
+        // ---- left reflector from column k (rows k..n-1), applied to the columns j > k
+        {
+            double x[RW];  // A[e0 + r][lane]
+#pragma unroll
+            for (int r = 0; r < RW; r++) x[r] = A[(e0 + r) * LDA + ln];
+            const double a = A[ln * LDA + k];
+            const double s = wave_sum(lane > k && lane < n ? a * a : 0.0);
+            const double alpha = readlane_f64(a, k);
+            double tau, beta, scl;
+            gk_reflector(alpha, s, tau, beta, scl);
+            const double v = lane == k ? 1.0 : (lane > k && lane < n ? a * scl : 0.0);
+            double ve[RW], p[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < RW; r++) {
+                ve[r] = readlane_f64(v, e0 + r);
+                p[r & 3] = fma(ve[r], x[r], p[r & 3]);
+            }
+            red[w][lane] = (p[0] + p[1]) + (p[2] + p[3]);
+            __syncthreads();
+            const double t = ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) * tau;
+            if (lane > k && lane < n && e0 + RW > k) {
+#pragma unroll
+                for (int r = 0; r < RW; r++) A[(e0 + r) * LDA + lane] = fma(-t, ve[r], x[r]);
+            }
+            if (lane == 0 && w == 0) dd[k] = beta;
+            __syncthreads();
+        }
+        if (k + 1 >= n) break;
+        // ---- right reflector from row k (columns k+1..n-1), applied to the rows i > k
+        {
+            double x[RW];  // A[lane][e0 + r]
+#pragma unroll
+            for (int r = 0; r < RW; r++) x[r] = A[ln * LDA + e0 + r];
+            const double rk = A[k * LDA + ln];
+            const double s = wave_sum(lane > k + 1 && lane < n ? rk * rk : 0.0);
+            const double alpha = readlane_f64(rk, k + 1);
+            double tau, beta, scl;
+            gk_reflector(alpha, s, tau, beta, scl);
+            const double v = lane == k + 1 ? 1.0 : (lane > k + 1 && lane < n ? rk * scl : 0.0);
+            double ve[RW], p[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < RW; r++) {
+                ve[r] = readlane_f64(v, e0 + r);
+                p[r & 3] = fma(ve[r], x[r], p[r & 3]);
+            }
+            red[w][lane] = (p[0] + p[1]) + (p[2] + p[3]);
+            __syncthreads();
+            const double t = ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) * tau;
+            if (lane > k && lane < n && e0 + RW > k + 1) {
+#pragma unroll
+                for (int r = 0; r < RW; r++) A[lane * LDA + e0 + r] = fma(-t, ve[r], x[r]);
+            }
+            if (lane == 0 && w == 0) ee[k] = beta;
+            __syncthreads();
+        }
     }
 }
 
@@ -668,6 +744,7 @@ __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ld
     constexpr int LDA = Gm::LDA;
     __shared__ double A[NPC * LDA];
     __shared__ double vl[NPC], vr[NPC];
+    __shared__ double red[4][64];
     __shared__ double dd[NPC], ee[NPC];
     __shared__ double sc[2];
     __shared__ int s_exp;
@@ -699,7 +776,11 @@ __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ld
         x = ldexp(x, -ex0);
     }
     __syncthreads();
-    if (wv == 0) gk_bidiag_wave<NPC>(A, vl, vr, dd, ee, n, lane);
+    if constexpr (NPC <= 64) {
+        gk_bidiag_wg<NPC>(A, red, dd, ee, n, lane, wv);
+    } else {
+        if (wv == 0) gk_bidiag_wave<NPC>(A, vl, vr, dd, ee, n, lane);
+    }
     __syncthreads();
     // ---- inputs of the multisection: the Golub-Kahan tridiagonal T (zero diagonal,
     // off-diagonals d1, e1, d2, ...) scaled once more so that its Gershgorin bound lies in
