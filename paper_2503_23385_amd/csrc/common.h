@@ -99,7 +99,9 @@ constexpr int kGroupThreads = 256;
 // grouping (kernels_group.hip)
 hipError_t launch_group_init(int32_t *status, int64_t *counts, int32_t *ticket, int32_t *flags,
                              int64_t nflags, hipStream_t s);
-hipError_t launch_group_cartesian(Groups g, int64_t m1, int64_t m2, hipStream_t s);
+// Cartesian product: the initialisation of launch_group_init and the one-group table in one launch.
+hipError_t launch_group_cartesian(int32_t *status, int32_t *flags, int64_t nflags, Groups g, int64_t m1,
+                                  int64_t m2, hipStream_t s);
 hipError_t launch_group_keys(const int32_t *kA, int64_t m1, const int32_t *kB, int64_t m2,
                              Groups g, int32_t *blkA, int32_t *blkB, int32_t *runA, int32_t *runB,
                              int32_t *matchA, int32_t *blkM, int64_t *blkS, int32_t *status,

@@ -373,17 +373,19 @@ int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, c
     int32_t *status = at<int32_t>(ws, L.status);
     {
         Stage st("group", s);
-        HIPCHK(launch_group_init(status, g.counts, nullptr, at<int32_t>(ws, L.counters_base),
-                                 L.counters_total, s),
-               "init");
         if (sh.keyed) {
+            HIPCHK(launch_group_init(status, g.counts, nullptr, at<int32_t>(ws, L.counters_base),
+                                     L.counters_total, s),
+                   "init");
             HIPCHK(launch_group_keys(A->keys, sh.m1, B->keys, sh.m2, g, at<int32_t>(ws, L.blkA),
                                      at<int32_t>(ws, L.blkB), at<int32_t>(ws, L.runA),
                                      at<int32_t>(ws, L.runB), at<int32_t>(ws, L.matchA),
                                      at<int32_t>(ws, L.blkM), at<int64_t>(ws, L.blkS), status, s),
                    "grouping");
         } else {
-            HIPCHK(launch_group_cartesian(g, sh.m1, sh.m2, s), "grouping");
+            HIPCHK(launch_group_cartesian(status, at<int32_t>(ws, L.counters_base), L.counters_total, g, sh.m1,
+                                          sh.m2, s),
+                   "grouping");
         }
     }
     double *hB = at<double>(ws, L.headsB);

@@ -30,9 +30,16 @@ __global__ void k_init(int32_t *status, int64_t *counts, int32_t *ticket, int32_
     for (int64_t j = i; j < nflags; j += (int64_t)gridDim.x * blockDim.x) flags[j] = 0;
 }
 
-__global__ void k_cartesian(Groups g, int64_t m1, int64_t m2)
+// The whole grouping of a Cartesian product (one group) with the initialisation of
+// k_init in the same launch: node counters zeroed by every thread, the status, counts
+// and the one-group table written by thread 0.
+__global__ void k_cartesian(int32_t *status, int32_t *flags, int64_t nflags, Groups g, int64_t m1, int64_t m2)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t j = i; j < nflags; j += (int64_t)gridDim.x * blockDim.x) flags[j] = 0;
+    if (i != 0) return;
+    *status = kStatusOk;
+    for (int c = 0; c < CNT_SLOTS; c++) g.counts[c] = 0;
     const bool nonempty = m1 > 0 && m2 > 0;
     g.counts[CNT_G] = nonempty ? 1 : 0;
     g.counts[CNT_R1] = nonempty ? m1 : 0;
@@ -306,9 +313,13 @@ hipError_t launch_group_init(int32_t *status, int64_t *counts, int32_t *ticket, 
     return hipGetLastError();
 }
 
-hipError_t launch_group_cartesian(Groups g, int64_t m1, int64_t m2, hipStream_t s)
+hipError_t launch_group_cartesian(int32_t *status, int32_t *flags, int64_t nflags, Groups g, int64_t m1,
+                                  int64_t m2, hipStream_t s)
 {
-    k_cartesian<<<1, 64, 0, s>>>(g, m1, m2);
+    int64_t blocks = (nflags + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    k_cartesian<<<(unsigned)blocks, 256, 0, s>>>(status, flags, nflags, g, m1, m2);
     return hipGetLastError();
 }
 

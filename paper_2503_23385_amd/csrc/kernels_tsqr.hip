@@ -403,21 +403,43 @@ __device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> 
     }
 }
 
-// Absorb rows [r0, r1) of src in blocks of 4 BR rows (wave wv takes the wv-th quarter).
-// STAGED: every row load is issued unconditionally (row and column clamped into the
-// source) and masked afterwards, so the loads of a block stay in flight together; more
-// registers, used when a launch has at most one leaf per compute unit (each leaf's
-// latency is the launch's).  Otherwise the loads are conditional and converted in a
-// second pass (fewer registers, more workgroups per compute unit to hide latency with).
+// Absorb rows [r0, r1) of src in blocks of WV BR rows (wave wv takes the wv-th share).
+// STAGED: every row load is issued unconditionally (row clamped into the source: the
+// row pointer advances while the next row is still inside) and masked afterwards, so
+// the loads of a block stay in flight together; more registers, used when a launch has
+// at most one leaf per compute unit (each leaf's latency is the launch's).  With FP32
+// storage the next block's loads are also issued before the current block's column
+// steps, which hide them.  Otherwise the loads are conditional (fewer registers, more
+// workgroups per compute unit to hide latency with).
 template <int NP, typename Tin, typename Tacc, bool STAGED>
 __device__ inline void wg_absorb_rows(WgState<NP, Tacc> &st, const RowSrc &src, int64_t r0, int64_t r1,
                                       int tri_rows, int width)
 {
     constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR, BG = tree_waves(NP) * BR;
+    constexpr bool PREFETCH = STAGED && sizeof(Tin) == 4 && sizeof(Tacc) == 4;
     // this lane's column of the source, clamped into range (col_in: whether it is real)
     const int c = st.k - src.col_off;
     const bool col_in = st.k < width && c >= 0 && c < src.width;
     const Tin *col_base = (const Tin *)src.p + (c < 0 ? 0 : (c < src.width ? c : src.width - 1));
+    const int64_t roff = (int64_t)st.wv * BR + st.h * RPT;  // this lane's first row in a block
+    auto load_rows = [&](Tacc (&y)[RPT], int64_t rb) {
+        const int64_t rs = rb + roff, last = r1 - 1;
+        const Tin *p = col_base + (rs < last ? rs : last) * src.ld;
+#pragma unroll
+        for (int i = 0; i < RPT; i++) {
+            y[i] = (Tacc)*p;
+            if (rs + i < last) p += src.ld;
+        }
+    };
+    auto mask_rows = [&](Tacc (&y)[RPT], int64_t rb) {
+#pragma unroll
+        for (int i = 0; i < RPT; i++)
+            if (!(rb + roff + i < r1 && col_in)) y[i] = Tacc(0);
+    };
+    Tacc xn[PREFETCH ? RPT : 1];
+    if constexpr (PREFETCH) {
+        if (r0 < r1) load_rows(xn, r0);
+    }
     for (int64_t rb = r0; rb < r1; rb += BG) {
         if (st.pend_row >= 0) {  // the block may start at the pending row: write it first
             __syncthreads();
@@ -425,21 +447,18 @@ __device__ inline void wg_absorb_rows(WgState<NP, Tacc> &st, const RowSrc &src, 
             __syncthreads();
         }
         Tacc x[RPT];
-        if constexpr (STAGED) {
+        if constexpr (PREFETCH) {
 #pragma unroll
-            for (int i = 0; i < RPT; i++) {
-                const int64_t r = rb + st.wv * BR + st.h * RPT + i;
-                x[i] = (Tacc)col_base[(r < r1 ? r : r1 - 1) * src.ld];
-            }
-#pragma unroll
-            for (int i = 0; i < RPT; i++) {
-                const int64_t r = rb + st.wv * BR + st.h * RPT + i;
-                if (!(r < r1 && col_in)) x[i] = Tacc(0);
-            }
+            for (int i = 0; i < RPT; i++) x[i] = xn[i];
+            mask_rows(x, rb);
+            if (rb + BG < r1) load_rows(xn, rb + BG);
+        } else if constexpr (STAGED) {
+            load_rows(x, rb);
+            mask_rows(x, rb);
         } else {
 #pragma unroll
             for (int i = 0; i < RPT; i++) {
-                const int64_t r = rb + st.wv * BR + st.h * RPT + i;
+                const int64_t r = rb + roff + i;
                 x[i] = (r < r1 && col_in) ? (Tacc)col_base[r * src.ld] : Tacc(0);
             }
         }
