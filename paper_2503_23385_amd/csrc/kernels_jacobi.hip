@@ -843,18 +843,20 @@ __device__ inline int gk_sturm_count(const double *bb, int m, double x)
 {
     double p0 = 1.0, p1 = -x;
     int cnt = (int)(((unsigned)__double2hiint(p1)) >> 31);  // signs are read from the sign bits throughout
-    // whole chunks of 16 steps with their coefficients loaded up front (the recurrence
-    // does not wait on LDS), then the remaining steps
-    const int mfull = m - m % 16;
+    // chunks of 16 steps with their coefficients loaded up front (the recurrence does not
+    // wait on LDS; bb holds whole chunks, entries past m unused): full chunks, then the
+    // last one step by step under a uniform condition
     for (int i0 = 0; i0 < m; i0 += 16) {
-        if (i0 < mfull) {
-            double b[16];
+        double b[16];
 #pragma unroll
-            for (int u = 0; u < 16; u++) b[u] = bb[i0 + u];
+        for (int u = 0; u < 16; u++) b[u] = bb[i0 + u];
+        if (i0 + 16 <= m) {
 #pragma unroll
             for (int u = 0; u < 16; u++) sturm_step(x, b[u], p0, p1, cnt);
         } else {
-            for (int i = i0; i < m; i++) sturm_step(x, bb[i], p0, p1, cnt);
+#pragma unroll
+            for (int u = 0; u < 16; u++)
+                if (i0 + u < m) sturm_step(x, b[u], p0, p1, cnt);
         }
         const int e2 = ilogb(fmax(fabs(p0), fabs(p1)));
         p0 = ldexp(p0, -e2);
@@ -871,7 +873,7 @@ __device__ inline int gk_sturm_count(const double *bb, int m, double x)
 __device__ __forceinline__ void sigma_msect_body(const double *msin, int n, int k, double *sigma)
 {
     constexpr int NW = kMsThreads / 64;
-    __shared__ double bb[255];
+    __shared__ double bb[256];  // 2n - 1 <= 255 coefficients, read in chunks of 16
     __shared__ int s_lo[2][NW], s_up[2][NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = 2 * n - 1;
