@@ -299,11 +299,16 @@ __device__ inline double half_swap_sum(double v)
     return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
 }
 
+// Row stride (doubles) of the partial-sum table, one row per column with the waves'
+// partials side by side: a lane reads its column's partials with 128-bit reads; the two
+// extra doubles spread the rows over the LDS banks.
+__host__ __device__ constexpr int tree_red_stride(int np) { return tree_waves(np) + 2; }
+
 template <int NP, typename Tacc>
 struct WgState {
     Tacc *R;             // packed triangle (LDS)
     Tacc *xb;            // this wave's broadcast slot, offset by the row set h
-    double (*red)[tree_waves(NP)][NP];
+    double (*red)[NP][tree_red_stride(NP)];  // [parity][column][wave]
     int k, h, wv, par;
     int pend_row;        // row of R whose new values are still in pend_val (-1: none)
     Tacc pend_val;
@@ -359,14 +364,14 @@ __device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> 
 #pragma unroll
         for (int off = NP; off < 32; off <<= 1) d += __shfl_xor(d, off, 64);
         if constexpr (H >= 2) d = half_swap_sum(d);
-        if (st.h == 0) st.red[st.par][st.wv][k] = d;
+        if (st.h == 0) st.red[st.par][k][st.wv] = d;
         __syncthreads();
         wg_flush(st, width);
         double pk[NPART], pj[NPART];
 #pragma unroll
         for (int w = 0; w < NPART; w++) {
-            pk[w] = st.red[st.par][w][k];
-            pj[w] = st.red[st.par][w][j];
+            pk[w] = st.red[st.par][k][w];
+            pj[w] = st.red[st.par][j][w];
         }
 #pragma unroll
         for (int w = 1; w < NPART; w <<= 1)
@@ -512,7 +517,7 @@ __global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion re
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     __shared__ Tacc Rs[Gm::PS];
     __shared__ __align__(16) Tacc Xs[WV][Gm::BR];
-    __shared__ double red[2][WV][NP];
+    __shared__ __align__(16) double red[2][NP][tree_red_stride(NP)];
     __shared__ int s_old;
     int g = blockIdx.x;
     const bool second = g >= reg0.nleaves;
