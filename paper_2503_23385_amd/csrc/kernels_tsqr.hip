@@ -367,20 +367,16 @@ __device__ inline void wg_block(Tacc (&x)[WaveGeom<NP>::RPT], WgState<NP, Tacc> 
         if (st.h == 0) st.red[st.par][k][st.wv] = d;
         __syncthreads();
         wg_flush(st, width);
-        double pk[NPART], pj[NPART];
+        // this lane's column sum; the pivot column's (the same sum, formed the same way by
+        // lane j) comes by a lane read instead of another round of LDS reads
+        double pk[NPART];
 #pragma unroll
-        for (int w = 0; w < NPART; w++) {
-            pk[w] = st.red[st.par][k][w];
-            pj[w] = st.red[st.par][j][w];
-        }
+        for (int w = 0; w < NPART; w++) pk[w] = st.red[st.par][k][w];
 #pragma unroll
         for (int w = 1; w < NPART; w <<= 1)
 #pragma unroll
-            for (int u = 0; u + w < NPART; u += 2 * w) {
-                pk[u] += pk[u + w];
-                pj[u] += pj[u + w];
-            }
-        const double dk = pk[0], s = pj[0];
+            for (int u = 0; u + w < NPART; u += 2 * w) pk[u] += pk[u + w];
+        const double dk = pk[0], s = readlane_f64(dk, j);
         st.par ^= 1;
         const double q = fma(alpha, alpha, s);
         // A column whose norm is below the normal range is left untouched (tau = 0).  The
