@@ -101,7 +101,8 @@ int figaro_r_workspace_size(const figaro_table *A, const figaro_table *B, int32_
  *         256-byte aligned.  After the call it holds the group table and
  *         the device status word (read with figaro_status).
  * An empty join (no common key) gives R = 0.  Unsorted keys give
- * FIGARO_EUNSORTED from figaro_status and an unspecified R.
+ * FIGARO_EUNSORTED from figaro_status; no group is then formed (G = 0) and
+ * R = 0.
  */
 int figaro_r(const figaro_table *A, const figaro_table *B, int32_t precision,
              double *R, int64_t ldr, void *ws, size_t ws_bytes, void *stream);

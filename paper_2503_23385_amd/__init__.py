@@ -127,9 +127,22 @@ def _dtype_code(t):
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
+def require_device(name, t, device=None):
+    """Raise unless t is a GPU tensor (on `device` when given): the kernels dereference
+    its address, and a host address there faults the GPU."""
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor, got one on {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
 def make_table(X, keys=None) -> Table:
     """Describe a device tensor (rows x cols, unit column stride) and optional int32 keys."""
     torch = _torch()
+    require_device("table", X)
+    require_device("keys", keys, X.device)
     if X.dim() != 2 or X.stride(1) != 1:
         raise ValueError("table must be 2-D with unit column stride")
     if keys is not None:
@@ -160,11 +173,16 @@ def r(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, out=None, strea
     """R (N x N, FP64, diag >= 0) of the join of A and B on the device.  Returns (R, ws)."""
     torch = _torch()
     ta, tb = make_table(A, keys_A), make_table(B, keys_B)
+    require_device("B", B, A.device)
     N = A.shape[1] + B.shape[1]
     if ws is None:
         ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision, two_sided), A.device)
     if out is None:
         out = torch.empty((N, N), dtype=torch.float64, device=A.device)
+    require_device("ws", ws, A.device)
+    require_device("out", out, A.device)
+    if out.dtype != torch.float64 or out.dim() != 2 or out.shape[0] < N or out.shape[1] < N or out.stride(1) != 1:
+        raise ValueError("out must be an FP64 N x N (or larger) matrix with unit column stride")
     _check(lib().figaro_r(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided),
                           ctypes.c_void_p(out.data_ptr()), out.stride(0),
                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
@@ -183,11 +201,18 @@ def sigma(R, out=None, ws=None, stream=None, method="default"):
     method: "default" (bidiagonal route for n <= 128, Jacobi above), "jacobi" (one-sided
     Jacobi, any n <= 512) or "bidiag" (bidiagonalisation + multisection, n <= 128)."""
     torch = _torch()
+    require_device("R", R)
+    if R.dtype != torch.float64 or R.dim() != 2 or R.shape[0] != R.shape[1] or R.stride(1) != 1:
+        raise ValueError("R must be a square FP64 matrix with unit column stride")
     n = R.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=R.device)
     if ws is None:
         ws = alloc_workspace(sigma_workspace_size(n), R.device)
+    require_device("out", out, R.device)
+    require_device("ws", ws, R.device)
+    if out.dtype != torch.float64 or out.numel() < n:
+        raise ValueError("out must hold n FP64 values")
     fns = {"default": lib().figaro_sigma, "jacobi": lib().figaro_sigma_jacobi, "bidiag": lib().figaro_sigma_bidiag}
     if method not in fns:
         raise ValueError(f"unknown sigma method {method!r}")
@@ -210,6 +235,7 @@ def compact(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, stream=No
     code = precision_code(precision, two_sided)
     if ws is None:
         ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision, two_sided), A.device)
+    require_device("ws", ws, A.device)
     _check(lib().figaro_compact(ctypes.byref(ta), ctypes.byref(tb), code,
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
     return inspect(A, B, keys_A, keys_B, precision, ws, stream, two_sided)

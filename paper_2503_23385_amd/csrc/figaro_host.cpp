@@ -18,10 +18,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -47,6 +49,10 @@ int hip_fail(hipError_t e, const char *where)
 }
 
 // ------------------------------------------------------------ stage timing
+//
+// Process-wide record of stage events, guarded by a mutex: library calls may run on
+// several host threads.  A thread that is capturing a graph records no events (events
+// recorded into a capture would not measure replays).
 
 struct TimingRec {
     const char *name;
@@ -54,11 +60,11 @@ struct TimingRec {
 };
 
 struct Timing {
-    bool on = false;
-    bool capturing = false;
+    std::atomic<bool> on{false};
+    std::mutex mu;
     std::vector<TimingRec> recs;
     std::vector<hipEvent_t> pool;
-    hipEvent_t get()
+    hipEvent_t get()  // caller holds mu
     {
         if (!pool.empty()) {
             hipEvent_t e = pool.back();
@@ -72,6 +78,7 @@ struct Timing {
 };
 
 Timing g_timing;
+thread_local bool t_capturing = false;
 
 // Brackets the launches of one stage with events when timing is on.
 struct Stage {
@@ -80,21 +87,24 @@ struct Stage {
     hipEvent_t a = nullptr;
     Stage(const char *n, hipStream_t st) : name(n), s(st)
     {
-        if (g_timing.on && !g_timing.capturing) {
-            a = g_timing.get();
+        if (g_timing.on.load() && !t_capturing) {
+            {
+                std::lock_guard<std::mutex> lk(g_timing.mu);
+                a = g_timing.get();
+            }
             if (a) (void)hipEventRecord(a, s);
         }
     }
     ~Stage()
     {
-        if (a) {
-            hipEvent_t b = g_timing.get();
-            if (b) {
-                (void)hipEventRecord(b, s);
-                g_timing.recs.push_back({name, a, b});
-            } else {
-                g_timing.pool.push_back(a);
-            }
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        hipEvent_t b = g_timing.get();
+        if (b) {
+            (void)hipEventRecord(b, s);
+            g_timing.recs.push_back({name, a, b});
+        } else {
+            g_timing.pool.push_back(a);
         }
     }
 };
@@ -716,7 +726,7 @@ int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, 
 
 int figaro_timing_enable(int32_t on)
 {
-    g_timing.on = on != 0;
+    g_timing.on.store(on != 0);
     return FIGARO_OK;
 }
 
@@ -724,6 +734,7 @@ int figaro_timing_read(const char **names, double *ms, int32_t *launches, int32_
                        int32_t *count)
 {
     if (!count) return fail(FIGARO_EINVAL, "count is NULL");
+    std::lock_guard<std::mutex> lk(g_timing.mu);
     std::vector<const char *> nm;
     std::vector<double> tot;
     std::vector<int32_t> cnt;
@@ -948,9 +959,9 @@ int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R,
         hipGraph_t graph = nullptr;
         HIPCHK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal),
                "begin capture");
-        g_timing.capturing = true;
+        t_capturing = true;
         int rc = plan_enqueue(plan, ws, R, sigma, plan->cap_stream);
-        g_timing.capturing = false;
+        t_capturing = false;
         hipError_t e = hipStreamEndCapture(plan->cap_stream, &graph);
         if (rc) {
             if (graph) (void)hipGraphDestroy(graph);

@@ -166,12 +166,16 @@ __global__ __launch_bounds__(kGroupThreads) void k_run_scatter(const int32_t *kA
 }
 
 // Round 2a: match each run of A against the runs of B (binary search on run keys).
+// With unsorted keys (status set by round 1a) no run matches: a key may then recur in
+// several runs, and the sizes the later rounds derive from matches would no longer be
+// bounded by the group table's and the regions' capacities.  The join is taken as empty.
 __global__ __launch_bounds__(kGroupThreads) void k_match(const int32_t *kA, const int32_t *runA,
                                                          const int64_t *UAp, const int32_t *kB,
                                                          const int32_t *runB, const int64_t *UBp,
-                                                         int32_t *matchA, int32_t *blkM)
+                                                         const int32_t *status, int32_t *matchA,
+                                                         int32_t *blkM)
 {
-    const int64_t UA = *UAp, UB = *UBp;
+    const int64_t UA = *UAp, UB = *status == kStatusOk ? *UBp : 0;
     const int64_t u0 = (int64_t)blockIdx.x * kGroupBlock + (int64_t)threadIdx.x * EPT;
     int cnt = 0;
     for (int e = 0; e < EPT; e++) {
@@ -338,7 +342,7 @@ hipError_t launch_group_keys(const int32_t *kA, int64_t m1, const int32_t *kB, i
     k_run_scatter<<<nbA + nbB, kGroupThreads, 0, s>>>(kA, m1, kB, m2, nbA, blkA, blkB, runA, runB);
     if (nbA == 0 || nbB == 0) return hipGetLastError();
     k_match<<<nbA, kGroupThreads, 0, s>>>(kA, runA, counts + CNT_UA, kB, runB, counts + CNT_UB,
-                                          matchA, blkM);
+                                          status, matchA, blkM);
     // G lands in counts[CNT_G] via the scan total (CNT_TMP used as a temporary).
     k_scan_small<int32_t><<<1, 1024, 0, s>>>(blkM, nbA, counts + CNT_TMP, nullptr, 0, nullptr, nullptr, 0,
                                              nullptr, 0);

@@ -210,6 +210,10 @@ def test_unsorted_keys_reported():
     A, B, kA_d, kB_d = to_dev(bad)
     R, ws = fg().r(A, B, kA_d, kB_d, "fp64")
     assert fg().status(ws) == fg().FIGARO_EUNSORTED
+    # no group is formed from unsorted keys: the join is taken as empty and R = 0
+    assert torch.count_nonzero(R).item() == 0
+    out = fg().compact(A, B, kA_d, kB_d, "fp64")
+    assert out["status"] == fg().FIGARO_EUNSORTED and list(out["counts"]) == [0, 0, 0, 0]
 
 
 @pytest.mark.parametrize("two_sided", [False, True])
