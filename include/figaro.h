@@ -199,6 +199,20 @@ int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma,
                         void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * figaro_sigma without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is a static array of the library
+ * (256 bytes + 512 x 512 FP64 = 2 MiB + 256 bytes) of which every GPU holds its
+ * own copy until the process ends; its address on the current device is looked
+ * up on the first call there.  Same route, kernels and results as figaro_sigma;
+ * no allocation and no stage timing.  `stream` must belong to the current
+ * device.  Calls that overlap on one GPU race on the shared array.
+ * FIGARO_EINVAL for n outside [1, 512] (sizes beyond the static array), NULL
+ * pointers or ldr < n; FIGARO_EHIP if the array's address cannot be obtained.
+ */
+int figaro_sigma_noalloc(const double *R, int64_t n, int64_t ldr, double *sigma, void *stream);
+
+/*
  * Synchronous: waits for `stream`, then reads the device status word left in
  * `ws` by the last figaro_r / figaro_compact / plan execution that used it.
  * *code receives FIGARO_OK, FIGARO_EUNSORTED or FIGARO_ETIMEOUT.

@@ -60,6 +60,7 @@ EXPORTS = [
     "figaro_sigma_workspace_size", "figaro_sigma", "figaro_sigma_jacobi", "figaro_sigma_bidiag", "figaro_status", "figaro_last_error",
     "figaro_plan_create", "figaro_plan_workspace_size", "figaro_plan_offsets",
     "figaro_plan_execute", "figaro_plan_destroy", "figaro_timing_enable", "figaro_timing_read",
+    "figaro_sigma_noalloc",
 ]
 
 _lib = None
@@ -84,6 +85,7 @@ def lib():
     L.figaro_sigma.argtypes = [P, I64, I64, P, P, SZ, P]
     L.figaro_sigma_jacobi.argtypes = [P, I64, I64, P, P, SZ, P]
     L.figaro_sigma_bidiag.argtypes = [P, I64, I64, P, P, SZ, P]
+    L.figaro_sigma_noalloc.argtypes = [P, I64, I64, P, P]
     L.figaro_status.argtypes = [P, P, ctypes.POINTER(I32)]
     L.figaro_last_error.argtypes = []
     L.figaro_last_error.restype = ctypes.c_char_p
@@ -220,6 +222,25 @@ def sigma(R, out=None, ws=None, stream=None, method="default"):
     _check(fn(ctypes.c_void_p(R.data_ptr()), n, R.stride(0),
                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                               ws.numel(), _stream_ptr(stream)))
+    return out
+
+
+def sigma_noalloc(R, out=None, stream=None):
+    """Singular values of R by the route of sigma(method="default"), with no workspace: the
+    library's static per-GPU scratch serves instead (n <= 512; calls on one GPU must not
+    overlap).  Allocates nothing itself when `out` is given."""
+    torch = _torch()
+    require_device("R", R)
+    if R.dtype != torch.float64 or R.dim() != 2 or R.shape[0] != R.shape[1] or R.stride(1) != 1:
+        raise ValueError("R must be a square FP64 matrix with unit column stride")
+    n = R.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=R.device)
+    require_device("out", out, R.device)
+    if out.dtype != torch.float64 or out.numel() < n:
+        raise ValueError("out must hold n FP64 values")
+    _check(lib().figaro_sigma_noalloc(ctypes.c_void_p(R.data_ptr()), n, R.stride(0),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

@@ -87,7 +87,7 @@ struct Stage {
     hipEvent_t a = nullptr;
     Stage(const char *n, hipStream_t st) : name(n), s(st)
     {
-        if (g_timing.on.load() && !t_capturing) {
+        if (n && g_timing.on.load() && !t_capturing) {
             {
                 std::lock_guard<std::mutex> lk(g_timing.mu);
                 a = g_timing.get();
@@ -673,24 +673,28 @@ int sigma_common(const double *R, int64_t n, int64_t ldr, double *sigma, void *w
 
 namespace {
 
-int sigma_jacobi(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, hipStream_t stream)
+// `timed`: bracket the launches with stage events (figaro_timing_enable); off for the
+// allocation-free entry point, since creating events may allocate.
+int sigma_jacobi(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, hipStream_t stream,
+                 bool timed = true)
 {
-    Stage st("jacobi", stream);
+    Stage st(timed ? "jacobi" : nullptr, stream);
     double *scratch = jacobi_scratch_doubles((int)n) ? at<double>(ws, kAlign) : nullptr;
     hipError_t e = launch_jacobi(R, (int)n, ldr, sigma, 60, (int32_t *)ws, scratch, stream);
     if (e != hipSuccess) return hip_fail(e, "jacobi");
     return FIGARO_OK;
 }
 
-int sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, hipStream_t stream)
+int sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, hipStream_t stream,
+                 bool timed = true)
 {
     double *msin = at<double>(ws, kAlign);
     {
-        Stage st("sigma_bidiag", stream);
+        Stage st(timed ? "sigma_bidiag" : nullptr, stream);
         hipError_t e = launch_sigma_bidiag(R, (int)n, ldr, (int32_t *)ws, msin, stream);
         if (e != hipSuccess) return hip_fail(e, "sigma bidiagonalisation");
     }
-    Stage st("sigma_msect", stream);
+    Stage st(timed ? "sigma_msect" : nullptr, stream);
     hipError_t e = launch_sigma_msect(msin, (int)n, sigma, stream);
     if (e != hipSuccess) return hip_fail(e, "sigma multisection");
     return FIGARO_OK;
@@ -722,6 +726,66 @@ int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, 
     if (rc) return rc;
     if (n > 128) return fail(FIGARO_EINVAL, "the bidiagonal route takes n <= 128");
     return sigma_bidiag(R, n, ldr, sigma, ws, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------ sigma without allocation
+//
+// The workspace of figaro_sigma for every n <= FIGARO_MAX_N (a 256-byte control block and
+// at most 512 x 512 FP64 columns of the block Jacobi) as one device array of the library.
+// Every GPU holds its own copy until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress returns on that GPU (the array's name is a host-side
+// stand-in, not a device address).  Calls on one GPU share it and must not overlap; each
+// call clears what its kernels need cleared (the control block is zeroed in-stream by the
+// first kernel of either route, the rest is written before it is read).
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kNoAllocBytes = kAlign + sizeof(double) * (size_t)FIGARO_MAX_N * FIGARO_MAX_N;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this GPU's copy of `scratch`, looked up once per device with it current.
+int scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FIGARO_EINVAL, "device index beyond the supported 64");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p) % kAlign) return fail(FIGARO_EHIP, "static scratch address is null or misaligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FIGARO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int figaro_sigma_noalloc(const double *R, int64_t n, int64_t ldr, double *sigma, void *stream)
+{
+    if (n < 1 || n > FIGARO_MAX_N)
+        return fail(FIGARO_EINVAL, "n out of range [1, 512] (the static scratch holds the workspace of n <= 512)");
+    if (!R || !sigma) return fail(FIGARO_EINVAL, "R or sigma is NULL");
+    if (ldr < n) return fail(FIGARO_EINVAL, "ldr < n");
+    size_t need = 0;
+    figaro_sigma_workspace_size(n, &need);
+    if (need > kNoAllocBytes) return fail(FIGARO_EINVAL, "workspace of this n exceeds the static scratch");
+    void *ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    if (n <= 128) return sigma_bidiag(R, n, ldr, sigma, ws, (hipStream_t)stream, false);
+    return sigma_jacobi(R, n, ldr, sigma, ws, (hipStream_t)stream, false);
 }
 
 int figaro_timing_enable(int32_t on)
