@@ -3,21 +3,30 @@
 One step = the whole path on one batch of synthetic input already resident in
 HBM: key grouping, head/tail scans, compact-matrix assembly, Householder TSQR
 (leaves, tree, merge, sign) -> R, the FP64 refinement sweep when the form asks
-for it, then one-sided Jacobi -> sigma.
+for it, then the singular values of R.
 
-Default workload (the headline line): Cartesian product of two 1e5 x 32 FP64
-N(0,1) tables (a 1e10 x 64 join that is never materialised).  Six forms are
-timed: the Claim 1 compact matrix and the two-sided form, each with an FP64
-reduction, an FP32 one, and an FP32 one followed by the FP64 refinement sweep.
-`value` is the fastest form whose R and sigma are within 1e-5 of the oracle;
-every form is listed under "forms".
+Default workload (the headline line): the batch of 256 independent Cartesian
+two-table instances (m1, m2 = floor(10^U(3,5)), n1 = n2 in {8, 16, 32, 64},
+FP32 U(-1,1)).  Forms timed:
+  - batched (one captured graph, stage by stage over all instances): two-sided
+    compact matrix reduced in FP32, in FP32 + FP64 refinement sweep, and in FP64;
+  - the FP64 per-instance loop: figaro_r + figaro_sigma for one instance after
+    another on one stream (the baseline of the batched FP32 form).
+`value` is the effective join rows/s (sum of m1 m2 over the batch / latency) of
+the fastest batched form whose R and sigma are within 1e-5 of the FP64 oracle
+for every instance; every form is listed under "forms" with its speedup over
+the FP64 per-instance loop.
 
-Other workloads (--workload): cfg1 (1000 x 4 U[0,1) Cartesian), cfg3 (2^20 x 64
-per table, Zipf(1.1) keys over 1e4 values), cfg5 (2^18 x 256 FP32 per table,
-scaled columns, 4096 uniform keys, N = 512) and cfg4 (256 Cartesian FP32
-instances with log-uniform sizes, all in one captured graph).  For cfg3/cfg5
-the error columns compare with the Cholesky factor of the closed-form Gram
-matrix, and the CPU baseline times the oracle on a prefix of both tables.
+Other workloads (--workload): cfg1 (1000 x 4 U[0,1) Cartesian), cfg2 (1e5 x 32
+FP64 Cartesian), cfg3 (2^20 x 64 per table, Zipf(1.1) keys over 1e4 values),
+cfg5 (2^18 x 256 FP32 per table, scaled columns, 4096 uniform keys, N = 512).
+Errors are taken against the oracle's stored references (tests/golden, written
+by the oracle alone) when present, else against the oracle run in this process.
+
+Timing: `ms_per_step` is K back-to-back steps between two synchronisations
+(HIP events on the launch stream).  "flushed" repeats single steps with a 1 GiB
+write between them (outside the events) so that no input is served from the
+Infinity Cache, and reports their median and the mean of the first 4.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -39,15 +48,19 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 TOL = 1e-5
 ALL_FORMS = "claim1:fp64,two_sided:fp64,claim1:fp32,two_sided:fp32,claim1:fp32_refine,two_sided:fp32_refine"
+BATCH_FORMS = "batched:two_sided:fp32,batched:two_sided:fp32_refine,batched:two_sided:fp64,loop:two_sided:fp64"
+FLUSH_BYTES = 1 << 30
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
-    ap.add_argument("--forms", default=None, help="comma list of layout:precision (default: all six)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg4", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--forms", default=None,
+                    help="comma list: layout:precision (single workloads) or batched|loop:layout:precision (cfg4)")
+    ap.add_argument("--flush-reps", type=int, default=8, help="single steps timed after a cache flush")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -67,30 +80,6 @@ def group_sizes(inst):
     return ca[ia].astype(np.int64), cb[ib].astype(np.int64)
 
 
-def gram_reference(inst):
-    """Cholesky factor of J^T J from the per-group closed form (FP64, numpy)."""
-    A = np.asarray(inst.A, dtype=np.float64)
-    B = np.asarray(inst.B, dtype=np.float64)
-    n1 = A.shape[1]
-    N = n1 + B.shape[1]
-    Gm = np.zeros((N, N))
-    if inst.keys_A is None:
-        groups = [(0, A.shape[0], 0, B.shape[0])]
-    else:
-        ua, sa, ca = np.unique(inst.keys_A, return_index=True, return_counts=True)
-        ub, sb, cb = np.unique(inst.keys_B, return_index=True, return_counts=True)
-        _, ia, ib = np.intersect1d(ua, ub, return_indices=True)
-        groups = zip(sa[ia], ca[ia], sb[ib], cb[ib])
-    for oa, ma, ob, mb in groups:
-        Ag, Bg = A[oa:oa + ma], B[ob:ob + mb]
-        a, b = Ag.sum(axis=0), Bg.sum(axis=0)
-        Gm[:n1, :n1] += mb * (Ag.T @ Ag)
-        Gm[n1:, n1:] += ma * (Bg.T @ Bg)
-        Gm[:n1, n1:] += np.outer(a, b)
-        Gm[n1:, :n1] += np.outer(b, a)
-    return np.linalg.cholesky(Gm).T
-
-
 def prefix_instance(inst, frac):
     from paper_2503_23385_amd import workloads as W
     m1 = max(1, int(inst.A.shape[0] * frac))
@@ -100,17 +89,24 @@ def prefix_instance(inst, frac):
     return W.Instance(np.ascontiguousarray(inst.A[:m1]), np.ascontiguousarray(inst.B[:m2]), kA, kB)
 
 
+def padded(w):
+    p = 4
+    while p < w:
+        p *= 2
+    return p
+
+
 # multisection of the bidiagonal route: points per round and rounds per singular value
 MSECT_POINTS, MSECT_ROUNDS = 256, 7
+flops = lambda rows, w: 2.0 * rows * w * w / 1e12  # noqa: E731  (streaming rows into a w x w triangle)
 
 
 def stage_work(inst, two_sided, precision, sweeps):
-    """Algorithmic work of each single-kernel stage: (bound, amount in GB or TFLOP)."""
+    """Algorithmic work of each single-kernel stage of one instance: (bound, TFLOP or GB)."""
     m1g, m2g = group_sizes(inst)
     n1, n2 = inst.A.shape[1], inst.B.shape[1]
     N = n1 + n2
     R1, R2, TA, G = int(m1g.sum()), int((m2g - 1).sum()), int((m1g - 1).sum()), len(m1g)
-    flops = lambda rows, w: 2.0 * rows * w * w / 1e12  # noqa: E731  (streaming rows into a w x w triangle)
     work = {
         "tsqr_m1": ("alu", flops(R1, N)),
         "tsqr_m2": ("alu", flops(R2, n2)),
@@ -128,6 +124,24 @@ def stage_work(inst, two_sided, precision, sweeps):
     return work
 
 
+def batch_stage_work(insts, precision):
+    """Algorithmic work of the single-kernel stages of the batched two-sided form."""
+    work = {}
+    in_bytes = out_bytes = 0.0
+    esz = 8 if precision == "fp64" else 4
+    for inst in insts:
+        (m1, n1), (m2, n2) = inst.A.shape, inst.B.shape
+        for rows, w in ((m1 - 1, n1), (m2 - 1, n2)):
+            k = f"tsqr_np{padded(w)}"
+            work[k] = ("alu", work.get(k, ("alu", 0.0))[1] + flops(rows, w))
+        in_bytes += inst.A.nbytes + inst.B.nbytes
+        out_bytes += ((m1 - 1) * n1 + (m2 - 1) * n2) * esz
+    # the write pass reads every table and writes every tail row once; the reduce pass reads
+    work["scan_write"] = ("hbm", (in_bytes + out_bytes) / 1e9)
+    work["scan_reduce"] = ("hbm", in_bytes / 1e9)
+    return work
+
+
 # Kernel source and symbol behind each single-kernel stage.
 STAGE_KERNELS = {
     "tsqr_tails": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
@@ -136,13 +150,16 @@ STAGE_KERNELS = {
     "jacobi": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_jacobi_lds"),
     "sigma_bidiag": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_sigma_gk"),
     "sigma_msect": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_sigma_msect"),
+    "scan_write": ("paper_2503_23385_amd/csrc/kernels_scan.hip", "k_seg_tile_batch"),
+    "scan_reduce": ("paper_2503_23385_amd/csrc/kernels_scan.hip", "k_seg_tile_batch"),
 }
+for _np in (4, 8, 16, 32, 64):
+    STAGE_KERNELS[f"tsqr_np{_np}"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree_batch")
 
 
 def measured_traffic(workload, stage, form=None):
-    """HBM bytes per launch of the stage's kernel for this form (layout:precision) from the
-    committed counter summary, if the kernel source is unchanged since the counters were
-    taken (else None)."""
+    """HBM bytes per launch of the stage's kernel for this form from the committed counter
+    summary, if the kernel source is unchanged since the counters were taken (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.md")
     if stage not in STAGE_KERNELS or not os.path.exists(path):
@@ -160,39 +177,95 @@ def measured_traffic(workload, stage, form=None):
     return None
 
 
-def roofline(form, work, precision):
+def roofline_of(form, work, precision, bound=None):
+    """Roofline entry of the dominant single-kernel stage (of the given bound, if set)."""
     stage_ms, launches = form["stage_ms"], form["launches_per_step"]
-    dom = max((k for k in stage_ms if k in work), key=lambda k: stage_ms[k])
+    cand = [k for k in stage_ms if k in work and (bound is None or work[k][0] == bound)]
+    if not cand:
+        return None
+    dom = max(cand, key=lambda k: stage_ms[k] / max(1.0, launches[k]))
     per_launch_ms = stage_ms[dom] / max(1.0, launches[dom])
-    bound, amount = work[dom]
+    kind, amount = work[dom]
     t = per_launch_ms / 1e3
-    if bound == "hbm":
+    if kind == "hbm":
         return {"kernel": dom, "bound": "hbm", "achieved": amount / t, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": amount / t / PEAK_HBM_GBS, "traffic": None, "launch_ms": per_launch_ms}
+                "frac": amount / t / PEAK_HBM_GBS, "traffic": None, "launch_ms": per_launch_ms,
+                "algorithmic_GB_per_launch": amount}
     # the FP32 forms' TSQR runs in FP32; sigma always runs in FP64
     peak = PEAK_FP64_TFLOPS if (dom in ("jacobi", "sigma_bidiag", "sigma_msect") or precision == "fp64") \
         else PEAK_FP32_TFLOPS
     return {"kernel": dom, "bound": "alu", "achieved": amount / t, "peak": peak, "unit": "TFLOP/s",
-            "frac": amount / t / peak, "traffic": None, "launch_ms": per_launch_ms}
+            "frac": amount / t / peak, "traffic": None, "launch_ms": per_launch_ms,
+            "algorithmic_TFLOP_per_launch": amount}
 
 
 # ------------------------------------------------------------------ timing
 
-def time_steps(step, steps, warmup, stream, torch):
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / steps
+class Timer:
+    def __init__(self, torch, stream, dev):
+        self.torch, self.stream = torch, stream
+        self.flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+
+    def steps(self, step, steps, warmup):
+        """Mean ms of `steps` back-to-back steps after `warmup` untimed ones."""
+        torch = self.torch
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(self.stream)
+        for _ in range(steps):
+            step()
+        ev1.record(self.stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    def flushed(self, step, reps):
+        """Single steps, each after a 1 GiB write that evicts the inputs from every cache."""
+        torch = self.torch
+        out = []
+        for _ in range(reps):
+            self.flush_buf.fill_(1.0)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(self.stream)
+            step()
+            ev1.record(self.stream)
+            torch.cuda.synchronize()
+            out.append(ev0.elapsed_time(ev1))
+        return {"median_ms": float(np.median(out)), "mean_of_4_ms": float(np.mean(out[:4])), "reps": reps}
+
+    def stages(self, step, steps, fg):
+        """Per-stage device time of `steps` steps (library stage events)."""
+        fg.timing_enable(True)
+        fg.timing_read()
+        for _ in range(steps):
+            step()
+        self.torch.cuda.synchronize()
+        st = fg.timing_read()
+        fg.timing_enable(False)
+        return ({k: v[0] / steps for k, v in st.items()}, {k: v[1] / steps for k, v in st.items()})
 
 
-def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref):
+def error_vs(R, S, ref):
+    Ro, So = ref
+    return (float(np.linalg.norm(R - Ro) / np.linalg.norm(Ro)), float(np.linalg.norm(S - So) / np.linalg.norm(So)))
+
+
+def stored_references(name):
+    """The oracle's stored references for a workload (tests/golden), or None."""
+    path = os.path.join(ROOT, "tests", "golden")
+    if not os.path.exists(os.path.join(path, f"oracle_{name}.npz")):
+        return None
+    sys.path.insert(0, path)
+    import make_golden
+    refs, digest = make_golden.load(name)
+    insts = make_golden.instances(name)
+    if make_golden.input_digest(insts) != digest:
+        return None
+    return refs
+
+
+def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref, timer):
     A = torch.from_numpy(inst.A).to(dev)
     B = torch.from_numpy(inst.B).to(dev)
     kA = None if inst.keys_A is None else torch.from_numpy(inst.keys_A).to(dev)
@@ -213,74 +286,117 @@ def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref):
             fg.r(A, B, kA, kB, prec, ws=ws, out=R, two_sided=two)
             fg.sigma(R, out=S, ws=sws)
 
-        ms = time_steps(step, args.steps, args.warmup, stream, torch)
+        ms = timer.steps(step, args.steps, args.warmup)
         assert fg.status(ws) == 0
-        # The same K steps again with per-stage events (library stage timing).
-        fg.timing_enable(True)
-        fg.timing_read()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        stages = fg.timing_read()
-        fg.timing_enable(False)
+        flushed = timer.flushed(step, args.flush_reps)
+        stage_ms, launches = timer.stages(step, args.steps, fg)
         sweeps = int(sws[:4].view(torch.int32)[0].item())
         errs = None
         if ref is not None:
-            Rref, Sref, kind = ref
-            Rg, Sg = R.cpu().numpy(), S.cpu().numpy()
-            errs = {"R_relF": float(np.linalg.norm(Rg - Rref) / np.linalg.norm(Rref)),
-                    "sigma_rel2": float(np.linalg.norm(Sg - Sref) / np.linalg.norm(Sref)), "reference": kind}
-        forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3),
-                       "stage_ms": {k: v[0] / args.steps for k, v in stages.items()},
-                       "launches_per_step": {k: v[1] / args.steps for k, v in stages.items()},
-                       "errors_vs_reference": errs, "jacobi_sweeps": sweeps, "layout": layout, "precision": prec}
+            er, es = error_vs(R.cpu().numpy(), S.cpu().numpy(), ref)
+            errs = {"R_relF": er, "sigma_rel2": es, "reference": "FP64 oracle"}
+        forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3), "flushed": flushed,
+                       "stage_ms": stage_ms, "launches_per_step": launches,
+                       "errors_vs_oracle": errs, "jacobi_sweeps": sweeps, "layout": layout, "precision": prec}
         del ws, R, S
     ok = [k for k, f in forms.items()
-          if f["errors_vs_reference"] is None
-          or (f["errors_vs_reference"]["R_relF"] <= TOL and f["errors_vs_reference"]["sigma_rel2"] <= TOL)]
+          if f["errors_vs_oracle"] is None
+          or (f["errors_vs_oracle"]["R_relF"] <= TOL and f["errors_vs_oracle"]["sigma_rel2"] <= TOL)]
     chosen = min(ok, key=lambda k: forms[k]["ms_per_step"])
     f = forms[chosen]
     work = stage_work(inst, f["layout"] == "two_sided", f["precision"], f["jacobi_sweeps"])
     return {"value": f["value"], "ms_per_step": f["ms_per_step"], "chosen": chosen, "precision": f["precision"],
-            "roofline": roofline(f, work, f["precision"]), "forms": forms, "join_rows": join_rows,
+            "roofline": roofline_of(f, work, f["precision"]), "forms": forms, "join_rows": join_rows,
             "config": {"workload": desc, "join_rows": join_rows, "form": chosen}}
 
 
-def bench_batch(args, insts, desc, forms_spec, torch, fg, dev, stream, refs):
-    tens = []
-    for inst in insts:
-        tens.append((torch.from_numpy(inst.A).to(dev), torch.from_numpy(inst.B).to(dev), None, None))
+def instance_tables(fg, A, B):
+    """C-ABI table descriptors of one Cartesian instance (kept for direct calls)."""
+    return fg.make_table(A, None), fg.make_table(B, None)
+
+
+def bench_batch(args, insts, desc, forms_spec, torch, fg, dev, stream, refs, timer):
+    import ctypes
+    tens = [(torch.from_numpy(i.A).to(dev), torch.from_numpy(i.B).to(dev), None, None) for i in insts]
     join_rows = int(sum(i.A.shape[0] * i.B.shape[0] for i in insts))
     forms = {}
     for spec in forms_spec.split(","):
-        layout, prec = spec.split(":")
-        plan = fg.Plan(tens, prec, two_sided=(layout == "two_sided"))
-        ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=dev)
-        R = torch.zeros(plan.r_total, dtype=torch.float64, device=dev)
-        S = torch.zeros(plan.s_total, dtype=torch.float64, device=dev)
-        ms = time_steps(lambda: plan.execute(ws, R, S), args.steps, args.warmup, stream, torch)
+        kind, layout, prec = spec.split(":")
+        two = layout == "two_sided"
+        if kind == "batched":
+            plan = fg.Plan(tens, prec, two_sided=two)
+            ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=dev)
+            R = torch.zeros(plan.r_total, dtype=torch.float64, device=dev)
+            S = torch.zeros(plan.s_total, dtype=torch.float64, device=dev)
+            r_off, s_off = plan.r_off, plan.s_off
+            step = lambda: plan.execute(ws, R, S)  # noqa: E731
+            eager = lambda: plan.execute_eager(ws, R, S)  # noqa: E731
+        else:
+            # FP64 per-instance loop: figaro_r then figaro_sigma for each instance in turn,
+            # called straight through the C ABI on one stream
+            L = fg.lib()
+            code = fg.precision_code(prec, two)
+            sp = fg._stream_ptr(None)
+            calls = []
+            r_off, s_off, ro, so = [], [], 0, 0
+            for (A, B, _, _), inst in zip(tens, insts):
+                N = inst.A.shape[1] + inst.B.shape[1]
+                r_off.append(ro)
+                s_off.append(so)
+                ro += N * N
+                so += N
+            R = torch.zeros(ro, dtype=torch.float64, device=dev)
+            S = torch.zeros(so, dtype=torch.float64, device=dev)
+            keep = []
+            for i, ((A, B, _, _), inst) in enumerate(zip(tens, insts)):
+                N = inst.A.shape[1] + inst.B.shape[1]
+                ta, tb = fg.make_table(A, None), fg.make_table(B, None)
+                ws = fg.alloc_workspace(fg.r_workspace_size(A, B, None, None, prec, two), dev)
+                sws = fg.alloc_workspace(fg.sigma_workspace_size(N), dev)
+                keep += [ta, tb, ws, sws]
+                rp = ctypes.c_void_p(R.data_ptr() + 8 * r_off[i])
+                spp = ctypes.c_void_p(S.data_ptr() + 8 * s_off[i])
+                calls.append((ctypes.byref(ta), ctypes.byref(tb), rp, N, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                              spp, ctypes.c_void_p(sws.data_ptr()), sws.numel()))
+
+            def step(calls=calls, L=L, code=code, sp=sp):
+                for ta, tb, rp, N, wsp, wsn, spp, swsp, swsn in calls:
+                    fg._check(L.figaro_r(ta, tb, code, rp, N, wsp, wsn, sp))
+                    fg._check(L.figaro_sigma(rp, N, N, spp, swsp, swsn, sp))
+            eager = step
+        ms = timer.steps(step, args.steps, args.warmup)
+        flushed = timer.flushed(step, args.flush_reps)
+        stage_ms, launches = timer.stages(eager, max(2, args.steps // 2), fg)
         errs = None
         if refs:
             Rh, Sh = R.cpu().numpy(), S.cpu().numpy()
             er = es = 0.0
             for i, (Ro, So) in refs.items():
                 n = Ro.shape[0]
-                Rg = Rh[plan.r_off[i]:plan.r_off[i] + n * n].reshape(n, n)
-                Sg = Sh[plan.s_off[i]:plan.s_off[i] + n]
-                er = max(er, float(np.linalg.norm(Rg - Ro) / np.linalg.norm(Ro)))
-                es = max(es, float(np.linalg.norm(Sg - So) / np.linalg.norm(So)))
-            errs = {"R_relF": er, "sigma_rel2": es, "reference": f"oracle, max over {len(refs)} instances"}
-        forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3), "errors_vs_reference": errs,
-                       "layout": layout, "precision": prec}
-        del plan, ws, R, S
+                e1, e2 = error_vs(Rh[r_off[i]:r_off[i] + n * n].reshape(n, n), Sh[s_off[i]:s_off[i] + n], (Ro, So))
+                er, es = max(er, e1), max(es, e2)
+            errs = {"R_relF": er, "sigma_rel2": es,
+                    "reference": f"FP64 oracle, max over {len(refs)} of {len(insts)} instances"}
+        forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3), "flushed": flushed,
+                       "stage_ms": stage_ms, "launches_per_step": launches, "errors_vs_oracle": errs,
+                       "layout": layout, "precision": prec, "kind": kind}
+        del R, S
+    base = next((k for k in forms if k.startswith("loop:") and forms[k]["precision"] == "fp64"), None)
+    for k, f in forms.items():
+        f["speedup_vs_fp64_loop"] = forms[base]["ms_per_step"] / f["ms_per_step"] if base else None
     ok = [k for k, f in forms.items()
-          if f["errors_vs_reference"] is None
-          or (f["errors_vs_reference"]["R_relF"] <= TOL and f["errors_vs_reference"]["sigma_rel2"] <= TOL)]
+          if f["kind"] == "batched" and (f["errors_vs_oracle"] is None
+                                         or (f["errors_vs_oracle"]["R_relF"] <= TOL
+                                             and f["errors_vs_oracle"]["sigma_rel2"] <= TOL))]
     chosen = min(ok, key=lambda k: forms[k]["ms_per_step"])
     f = forms[chosen]
+    work = batch_stage_work(insts, f["precision"])
+    roof = roofline_of(f, work, f["precision"], bound="alu")
+    roof_hbm = roofline_of(f, work, f["precision"], bound="hbm")
     return {"value": f["value"], "ms_per_step": f["ms_per_step"], "chosen": chosen, "precision": f["precision"],
-            "roofline": None, "forms": forms, "join_rows": join_rows,
-            "config": {"workload": desc, "join_rows": join_rows, "instances": len(insts), "form": chosen}}
+            "roofline": roof, "roofline_hbm": roof_hbm, "forms": forms, "join_rows": join_rows,
+            "config": {"workload": desc, "join_rows": join_rows, "instances": len(insts), "form": chosen,
+                       "baseline_form": base}}
 
 
 def cpu_baseline(oracle, insts, join_rows_per_rep, seconds, what):
@@ -336,51 +452,53 @@ def main():
                           "launches": 5}))
         return
 
+    timer = Timer(torch, stream, dev)
     wl = args.workload
     cpu = None
-    if wl in ("cfg1", "cfg2"):
-        inst = W.config1() if wl == "cfg1" else W.config2()
-        desc = ("cartesian product, A and B 1000 x 4 FP64 U[0,1), join 1e6 x 8, R 8x8 + sigma" if wl == "cfg1" else
-                "cartesian product, A and B 1e5 x 32 FP64 N(0,1), join 1e10 x 64 (never materialised), R 64x64 + sigma")
-        ref = None
+    stored = stored_references(wl)
+    if wl != "cfg4":
+        inst = W.CONFIGS[int(wl[3:])]()
+        desc = {
+            "cfg1": "cartesian product, A and B 1000 x 4 FP64 U[0,1), join 1e6 x 8, R 8x8 + sigma",
+            "cfg2": "cartesian product, A and B 1e5 x 32 FP64 N(0,1), join 1e10 x 64 (never materialised), "
+                    "R 64x64 + sigma",
+            "cfg3": "natural join, A and B 2^20 x 64 FP64 N(0,1), int32 keys Zipf(1.1) over 1e4 values, "
+                    "R 128x128 + sigma",
+            "cfg5": "natural join, A and B 2^18 x 256 FP32 N(0,1) with column scales 10^U(-3,0), int32 keys "
+                    "uniform over 4096 values, R 512x512 + sigma",
+        }[wl]
+        ref = stored[0] if stored else None
         if oracle is not None:
-            res, cpu = cpu_baseline(oracle, [inst], inst.A.shape[0] * inst.B.shape[0], args.cpu_seconds,
-                                    "the same workload")
-            ref = (res[0][0], res[0][1], "oracle")
-        out = bench_single(args, inst, desc, args.forms or ALL_FORMS, torch, fg, dev, stream, ref)
-    elif wl in ("cfg3", "cfg5"):
-        inst = W.config3() if wl == "cfg3" else W.config5()
-        desc = ("natural join, A and B 2^20 x 64 FP64 N(0,1), int32 keys Zipf(1.1) over 1e4 values, R 128x128 + sigma"
-                if wl == "cfg3" else
-                "natural join, A and B 2^18 x 256 FP32 N(0,1) with column scales 10^U(-3,0), int32 keys uniform "
-                "over 4096 values, R 512x512 + sigma")
-        Rref = gram_reference(inst)
-        ref = (Rref, np.linalg.svd(Rref, compute_uv=False), "Cholesky factor of the closed-form Gram matrix")
-        if oracle is not None:
-            frac = 1.0 / 8
-            sub = prefix_instance(inst, frac)
-            a, b = group_sizes(sub)
-            _, cpu = cpu_baseline(oracle, [sub], int((a * b).sum()), args.cpu_seconds,
-                                  f"the first 1/8 of the rows of both tables (a sub-join of the same workload)")
-        forms = args.forms or ("claim1:fp64,two_sided:fp64,claim1:fp32,two_sided:fp32,two_sided:fp32_refine"
-                               if wl == "cfg3" else "two_sided:fp32,two_sided:fp32_refine,two_sided:fp64")
-        out = bench_single(args, inst, desc, forms, torch, fg, dev, stream, ref)
+            if wl in ("cfg1", "cfg2"):
+                res, cpu = cpu_baseline(oracle, [inst], inst.A.shape[0] * inst.B.shape[0], args.cpu_seconds,
+                                        "the same workload")
+                ref = ref or res[0]
+            else:
+                sub = prefix_instance(inst, 1.0 / 8)
+                a, b = group_sizes(sub)
+                _, cpu = cpu_baseline(oracle, [sub], int((a * b).sum()), args.cpu_seconds,
+                                      "the first 1/8 of the rows of both tables (a sub-join of the same workload)")
+        forms = args.forms or {"cfg1": ALL_FORMS, "cfg2": ALL_FORMS,
+                               "cfg3": "claim1:fp64,two_sided:fp64,claim1:fp32,two_sided:fp32,two_sided:fp32_refine",
+                               "cfg5": "two_sided:fp32,two_sided:fp32_refine,two_sided:fp64"}[wl]
+        out = bench_single(args, inst, desc, forms, torch, fg, dev, stream, ref, timer)
     else:
         insts = W.config4()
         desc = ("batch of 256 cartesian instances, m1 and m2 = floor(10^U(3,5)), n1 = n2 in {8,16,32,64}, "
                 "FP32 U(-1,1), one captured graph")
-        refs = {}
+        refs = {i: r for i, r in enumerate(stored)} if stored else {}
         if oracle is not None:
             idx = list(range(0, len(insts), 16))
             sample = [insts[i] for i in idx]
             res, cpu = cpu_baseline(oracle, sample, sum(i.A.shape[0] * i.B.shape[0] for i in sample),
                                     args.cpu_seconds, f"every 16th instance of the batch ({len(sample)} instances)")
-            refs = {i: r for i, r in zip(idx, res)}
-        out = bench_batch(args, insts, desc, args.forms or "two_sided:fp32,two_sided:fp64", torch, fg, dev,
-                          stream, refs)
+            if not refs:
+                refs = {i: r for i, r in zip(idx, res)}
+        out = bench_batch(args, insts, desc, args.forms or BATCH_FORMS, torch, fg, dev, stream, refs, timer)
 
-    if out["roofline"] is not None:
-        out["roofline"]["traffic"] = measured_traffic(wl, out["roofline"]["kernel"], out["config"].get("form"))
+    for key in ("roofline", "roofline_hbm"):
+        if out.get(key) is not None:
+            out[key]["traffic"] = measured_traffic(wl, out[key]["kernel"], out["config"].get("form"))
 
     line = {
         "metric": METRIC,
@@ -397,6 +515,7 @@ def main():
         "data": "synthetic",
         "config": out["config"],
         "roofline": out["roofline"],
+        "roofline_hbm": out.get("roofline_hbm"),
         "cpu_baseline": cpu,
         "forms": out["forms"],
     }

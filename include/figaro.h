@@ -13,7 +13,9 @@
  * Conventions shared by every entry point:
  *   - Pointers named "device" point to GPU memory; everything else is host.
  *   - All memory is allocated and owned by the caller.  The library never
- *     allocates on the compute path and never frees caller memory.
+ *     frees caller memory and allocates nothing on the compute path of
+ *     figaro_r and figaro_sigma; a plan allocates its launch tables (and its
+ *     graph) once per buffer triple, on that triple's first execution.
  *   - Calls enqueue work on `stream` (a hipStream_t passed as void*; NULL is
  *     the default stream) and return without waiting, except those marked
  *     "synchronous".
@@ -260,22 +262,34 @@ int figaro_plan_workspace_size(const figaro_plan *plan, size_t *bytes);
 int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
                         int64_t *r_total, int64_t *s_total);
 /*
- * Enqueue the whole batch on `stream`.  The first call uploads a small device
- * table (32 bytes per instance, synchronous; freed by figaro_plan_destroy).
- * The first call with a given (ws, R, sigma) captures the launch sequence into
- * a HIP graph on a private stream; every call (the first included) launches
- * that graph on `stream`.
- * Inside the graph the instances' R pipelines run as up to 8 parallel
- * branches (largest instances first, each to the least-loaded branch); each
- * branch owns one slice of `ws` and runs its instances in order.  After the
- * branches join, sigma of all instances is computed by the bidiagonal route of
- * figaro_sigma_bidiag, two launches per width class (one bidiagonalisation
- * workgroup per instance, then one multisection workgroup per singular value);
- * its inputs sit in `ws` after the branches' slices.  Instances need
- * n1 + n2 <= 128.  Calls that share `ws` must not overlap.
+ * Enqueue the whole batch on `stream`.  The batch runs stage by stage, each
+ * stage one launch (or a short sequence) over every instance, driven by device
+ * tables of per-instance descriptors:
+ *   grouping (one launch for all Cartesian instances; a keyed instance runs its
+ *   own grouping), head/tail scans (one tile-reduce / carry-scan / tile-write
+ *   sequence over the tiles of every table), the regions' TSQR (one tree launch
+ *   per padded width up to 64 over the leaves of every region of every instance,
+ *   each region with its own node counters and root; wider regions per region),
+ *   the roots (one launch per padded width for the Cartesian instances of the
+ *   two-sided form; the others, and the refinement sweep, per instance), and
+ *   sigma by the bidiagonal route of figaro_sigma_bidiag (two launches per width
+ *   class over all instances).  Each instance owns one slice of `ws`; the
+ *   multisection inputs sit after the slices.  Instances need n1 + n2 <= 128.
+ * The first call with a given (ws, R, sigma) allocates and uploads that
+ * triple's launch tables (synchronous; freed by figaro_plan_destroy) and
+ * captures the launch sequence into a HIP graph on a private stream; every call
+ * (the first included) launches that graph on `stream`.  Later calls with the
+ * same triple allocate nothing.  Calls that share `ws` must not overlap.
  */
 int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
                         void *stream);
+/*
+ * The same launches as figaro_plan_execute, enqueued one by one on `stream`
+ * without a graph (the launch tables of the triple are uploaded as there), so
+ * that the stage timing of figaro_timing_enable records every stage.
+ */
+int figaro_plan_execute_eager(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
+                              void *stream);
 void figaro_plan_destroy(figaro_plan *plan);
 
 #ifdef __cplusplus

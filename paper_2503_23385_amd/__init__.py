@@ -59,7 +59,7 @@ EXPORTS = [
     "figaro_r_workspace_size", "figaro_r", "figaro_compact", "figaro_inspect",
     "figaro_sigma_workspace_size", "figaro_sigma", "figaro_sigma_jacobi", "figaro_sigma_bidiag", "figaro_status", "figaro_last_error",
     "figaro_plan_create", "figaro_plan_workspace_size", "figaro_plan_offsets",
-    "figaro_plan_execute", "figaro_plan_destroy", "figaro_timing_enable", "figaro_timing_read",
+    "figaro_plan_execute", "figaro_plan_execute_eager", "figaro_plan_destroy", "figaro_timing_enable", "figaro_timing_read",
     "figaro_sigma_noalloc",
 ]
 
@@ -93,6 +93,7 @@ def lib():
     L.figaro_plan_workspace_size.argtypes = [P, ctypes.POINTER(SZ)]
     L.figaro_plan_offsets.argtypes = [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.figaro_plan_execute.argtypes = [P, P, SZ, P, P, P]
+    L.figaro_plan_execute_eager.argtypes = [P, P, SZ, P, P, P]
     L.figaro_plan_destroy.argtypes = [P]
     L.figaro_plan_destroy.restype = None
     L.figaro_timing_enable.argtypes = [I32]
@@ -346,6 +347,12 @@ class Plan:
         _check(lib().figaro_plan_execute(self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                          ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(S.data_ptr()),
                                          _stream_ptr(stream)))
+
+    def execute_eager(self, ws, R, S, stream=None):
+        """The same launches without the graph (one by one on the stream; stage timing sees them)."""
+        _check(lib().figaro_plan_execute_eager(self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                               ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                               _stream_ptr(stream)))
 
     def __del__(self):
         try:

@@ -102,6 +102,15 @@ hipError_t launch_group_init(int32_t *status, int64_t *counts, int32_t *ticket, 
 // Cartesian product: the initialisation of launch_group_init and the one-group table in one launch.
 hipError_t launch_group_cartesian(int32_t *status, int32_t *flags, int64_t nflags, Groups g, int64_t m1,
                                   int64_t m2, hipStream_t s);
+// The same for a batch of Cartesian products (device table, one entry per instance).
+struct CartInit {
+    int32_t *status;
+    int32_t *flags;
+    int64_t nflags;
+    Groups g;
+    int64_t m1, m2;
+};
+hipError_t launch_group_cartesian_batch(const CartInit *tab, int count, hipStream_t s);
 hipError_t launch_group_keys(const int32_t *kA, int64_t m1, const int32_t *kB, int64_t m2,
                              Groups g, int32_t *blkA, int32_t *blkB, int32_t *runA, int32_t *runB,
                              int32_t *matchA, int32_t *blkM, int64_t *blkS, int32_t *status,
@@ -130,6 +139,8 @@ struct ScanJob {
     double *tileS;
     double *carry;
     int64_t ntiles;
+    Groups g;           // the group table the job's side arrays belong to
+    int32_t cartesian;  // one group spanning the whole table
 };
 ScanJob scan_job(const void *X, int64_t ldx, int64_t m, int64_t n, ScanSide side, void *out, double *heads,
                  int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp);
@@ -137,6 +148,12 @@ ScanJob scan_job(const void *X, int64_t ldx, int64_t m, int64_t n, ScanSide side
 // reduce, carry scan, tile write); two jobs need the same cpt and storage types.
 hipError_t launch_seg_scan(const ScanJob &j0, const ScanJob &j1, int cpt, int in_f64, int out_f64, Groups g,
                            int cartesian, hipStream_t s);
+// One pass (0 tile reduce, 1 carry scan, 2 tile write) over a batch of jobs (device table
+// `jobs`, each with its own group table): tile_map[b] = (job, tile) for each of the ntiles
+// tile blocks, col_map[b] = (job, column) for each of the ncols carry blocks; every job of
+// the batch has the same cpt and the same input and storage types.
+hipError_t launch_seg_scan_batch(int pass, const ScanJob *jobs, const int2 *tile_map, int64_t ntiles,
+                                 const int2 *col_map, int64_t ncols, int cpt, int in_f64, int out_f64, hipStream_t s);
 // Claim 1 region 1: [sqrt(m2_g) A_r | H(B_g)].
 hipError_t launch_assemble_a(const void *A, int in_f64, int64_t lda, int64_t m1, int64_t n1,
                              int64_t n2, Groups g, int cartesian, const double *heads, void *M1,
@@ -179,12 +196,31 @@ struct TreeRegion {
 // One launch for one or two regions of the same padded width np (np <= 64).
 hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
                             hipStream_t s);
+// A batch of regions of padded width np <= 64 in one launch: device table regs, and
+// map[b] = (region, leaf) for each of the nblocks workgroups (leaves beyond what a region's
+// device-side row count needs exit at once).
+hipError_t launch_tsqr_tree_batch(int np, int acc_f64, int in_f64, const TreeRegion *regs, const int2 *map,
+                                  int64_t nblocks, hipStream_t s);
 // Root of the two-sided form of a Cartesian product (N = na + nb <= 128): diag(R_TA, R_TB)
 // absorbs the head row built from the head sums hA, hB; R (ld ldr) receives the result
 // with row signs normalised.
 hipError_t launch_merge_cartesian(int np, const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
                                   Groups g, const double *hA, const double *hB, double *R, int64_t ldr,
                                   hipStream_t s);
+// The same for a batch of instances: one entry per instance, all of padded width np.
+struct CartRoot {
+    const double *Ta;
+    int64_t lda;
+    int32_t na;
+    const double *Tb;
+    int64_t ldb;
+    int32_t nb;
+    Groups g;
+    const double *hA, *hB;
+    double *R;
+    int64_t ldr;
+};
+hipError_t launch_merge_cartesian_batch(int np, const CartRoot *tab, int count, hipStream_t s);
 // out (na + nb rows, ld ldo) <- the upper triangular block diagonal [Ta 0; 0 Tb].
 hipError_t launch_block_diag(const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
                              double *out, int64_t ldo, hipStream_t s);

@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -374,73 +375,95 @@ int check_ws(const Layout &L, void *ws, size_t ws_bytes)
         if (e_ != hipSuccess) return hip_fail(e_, where); \
     } while (0)
 
+// Grouping stage: the group table, counts and status, and zeroed tree counters.
+int run_grouping(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, void *ws,
+                 hipStream_t s)
+{
+    Groups g = groups_of(ws, L);
+    int32_t *status = at<int32_t>(ws, L.status);
+    Stage st("group", s);
+    if (sh.keyed) {
+        HIPCHK(launch_group_init(status, g.counts, nullptr, at<int32_t>(ws, L.counters_base), L.counters_total, s),
+               "init");
+        HIPCHK(launch_group_keys(A->keys, sh.m1, B->keys, sh.m2, g, at<int32_t>(ws, L.blkA), at<int32_t>(ws, L.blkB),
+                                 at<int32_t>(ws, L.runA), at<int32_t>(ws, L.runB), at<int32_t>(ws, L.matchA),
+                                 at<int32_t>(ws, L.blkM), at<int64_t>(ws, L.blkS), status, s),
+               "grouping");
+    } else {
+        HIPCHK(launch_group_cartesian(status, at<int32_t>(ws, L.counters_base), L.counters_total, g, sh.m1, sh.m2,
+                                      s),
+               "grouping");
+    }
+    return FIGARO_OK;
+}
+
+// The head/tail scan jobs of one problem: B's (both forms), then A's (two-sided form).
+int scan_jobs(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, void *ws,
+              ScanJob *jobs)
+{
+    Groups g = groups_of(ws, L);
+    const Region &rb = L.regions.back();  // region of B's tails in both forms
+    ScanSide sideB{g.offB, g.m2, g.m1, g.r2, 0};
+    jobs[0] = scan_job(B->data, sh.ldb, sh.m2, sh.n2, sideB, at<void>(ws, rb.buf), at<double>(ws, L.headsB),
+                       at<int32_t>(ws, L.tileF[1]), at<double>(ws, L.tileS[1]), at<double>(ws, L.carry[1]), L.spB);
+    int n = 1;
+    if (sh.two_sided) {
+        ScanSide sideA{g.offA, g.m1, g.m2, g.r1, 1};
+        jobs[1] = scan_job(A->data, sh.lda, sh.m1, sh.n1, sideA, at<void>(ws, L.regions[1].buf),
+                           at<double>(ws, L.headsA), at<int32_t>(ws, L.tileF[0]), at<double>(ws, L.tileS[0]),
+                           at<double>(ws, L.carry[0]), L.spA);
+        n = 2;
+    }
+    for (int i = 0; i < n; i++) {
+        jobs[i].g = g;
+        jobs[i].cartesian = !sh.keyed;
+    }
+    return n;
+}
+
+// Region-1 assembly (Claim 1 form) or the head rows (two-sided form), after the scans.
+int run_assembly(const figaro_table *A, const Shape &sh, const Layout &L, void *ws, hipStream_t s)
+{
+    Groups g = groups_of(ws, L);
+    Stage st("assemble", s);
+    if (!sh.two_sided) {
+        HIPCHK(launch_assemble_a(A->data, sh.in_f64, sh.lda, sh.m1, sh.n1, sh.n2, g, !sh.keyed,
+                                 at<double>(ws, L.headsB), at<void>(ws, L.regions[0].buf), L.m_f64, s),
+               "region-1 assembly");
+    } else {
+        HIPCHK(launch_head_rows(g, L.gcap, at<double>(ws, L.headsA), at<double>(ws, L.headsB), sh.n1, sh.n2,
+                                at<void>(ws, L.regions[0].buf), L.m_f64, s),
+               "head rows");
+    }
+    return FIGARO_OK;
+}
+
 // Grouping, head/tail scans and assembly: fills the regions' row buffers (the head rows
 // of the two-sided form only when head_rows is set).
 int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L,
                 void *ws, hipStream_t s, bool head_rows = true)
 {
-    Groups g = groups_of(ws, L);
-    int32_t *status = at<int32_t>(ws, L.status);
-    {
-        Stage st("group", s);
-        if (sh.keyed) {
-            HIPCHK(launch_group_init(status, g.counts, nullptr, at<int32_t>(ws, L.counters_base),
-                                     L.counters_total, s),
-                   "init");
-            HIPCHK(launch_group_keys(A->keys, sh.m1, B->keys, sh.m2, g, at<int32_t>(ws, L.blkA),
-                                     at<int32_t>(ws, L.blkB), at<int32_t>(ws, L.runA),
-                                     at<int32_t>(ws, L.runB), at<int32_t>(ws, L.matchA),
-                                     at<int32_t>(ws, L.blkM), at<int64_t>(ws, L.blkS), status, s),
-                   "grouping");
-        } else {
-            HIPCHK(launch_group_cartesian(status, at<int32_t>(ws, L.counters_base), L.counters_total, g, sh.m1,
-                                          sh.m2, s),
-                   "grouping");
-        }
-    }
-    double *hB = at<double>(ws, L.headsB);
-    const Region &rb = L.regions.back();  // region of B's tails in both forms
+    int rc = run_grouping(A, B, sh, L, ws, s);
+    if (rc) return rc;
+    ScanJob jobs[2];
+    const int nj = scan_jobs(A, B, sh, L, ws, jobs);
     const ScanJob none{};
-    ScanSide sideB{g.offB, g.m2, g.m1, g.r2, 0};
-    const ScanJob jb = scan_job(B->data, sh.ldb, sh.m2, sh.n2, sideB, at<void>(ws, rb.buf), hB,
-                                at<int32_t>(ws, L.tileF[1]), at<double>(ws, L.tileS[1]),
-                                at<double>(ws, L.carry[1]), L.spB);
-    if (!sh.two_sided) {
-        {
-            Stage st("scan", s);
-            HIPCHK(launch_seg_scan(jb, none, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+    Groups g = groups_of(ws, L);
+    {
+        // both tables in one launch per pass when their tiles have the same column layout
+        Stage st("scan", s);
+        if (nj == 2 && L.spA.cpt == L.spB.cpt) {
+            HIPCHK(launch_seg_scan(jobs[0], jobs[1], L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+                   "head/tail scans");
+        } else {
+            HIPCHK(launch_seg_scan(jobs[0], none, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
                    "head/tail scan of B");
-        }
-        Stage st("assemble", s);
-        HIPCHK(launch_assemble_a(A->data, sh.in_f64, sh.lda, sh.m1, sh.n1, sh.n2, g, !sh.keyed, hB,
-                                 at<void>(ws, L.regions[0].buf), L.m_f64, s),
-               "region-1 assembly");
-    } else {
-        double *hA = at<double>(ws, L.headsA);
-        ScanSide sideA{g.offA, g.m1, g.m2, g.r1, 1};
-        const ScanJob ja = scan_job(A->data, sh.lda, sh.m1, sh.n1, sideA, at<void>(ws, L.regions[1].buf), hA,
-                                    at<int32_t>(ws, L.tileF[0]), at<double>(ws, L.tileS[0]),
-                                    at<double>(ws, L.carry[0]), L.spA);
-        {
-            // both tables in one launch per pass when their tiles have the same column layout
-            Stage st("scan", s);
-            if (L.spA.cpt == L.spB.cpt) {
-                HIPCHK(launch_seg_scan(jb, ja, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
-                       "head/tail scans");
-            } else {
-                HIPCHK(launch_seg_scan(jb, none, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
-                       "head/tail scan of B");
-                HIPCHK(launch_seg_scan(ja, none, L.spA.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+            if (nj == 2)
+                HIPCHK(launch_seg_scan(jobs[1], none, L.spA.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
                        "head/tail scan of A");
-            }
-        }
-        if (head_rows) {
-            Stage st("assemble", s);
-            HIPCHK(launch_head_rows(g, L.gcap, hA, hB, sh.n1, sh.n2, at<void>(ws, L.regions[0].buf),
-                                    L.m_f64, s),
-                   "head rows");
         }
     }
+    if (!sh.two_sided || head_rows) return run_assembly(A, sh, L, ws, s);
     return FIGARO_OK;
 }
 
@@ -499,19 +522,20 @@ int run_refine(const figaro_table *A, const figaro_table *B, const Shape &sh, co
     return FIGARO_OK;
 }
 
-int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
-          int64_t ldr, void *ws, hipStream_t s)
+// A Cartesian product in the two-sided form has one head row: one kernel builds it,
+// merges it into diag(R_TA, R_TB) and normalises the row signs.
+bool cartesian_root(const Shape &sh, const Layout &L)
+{
+    return sh.two_sided && L.regions[0].skip && L.np_root <= 128;
+}
+
+// Everything after the regions' trees: the merge of their triangles, the row signs and
+// the refinement sweep.
+int run_root(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
+             int64_t ldr, void *ws, hipStream_t s)
 {
     const int N = (int)sh.N();
-    // A Cartesian product in the two-sided form has one head row: one kernel builds it,
-    // merges it into diag(R_TA, R_TB) and normalises the row signs.
-    const bool cart_root = sh.two_sided && L.regions[0].skip && L.np_root <= 128;
-    int rc = run_compact(A, B, sh, L, ws, s, !cart_root);
-    if (rc) return rc;
-    const int acc = sh.precision == FIGARO_PLAIN_FP64;
-    rc = run_regions(L, acc, ws, s);
-    if (rc) return rc;
-    if (cart_root) {
+    if (cartesian_root(sh, L)) {
         const Region &ra = L.regions[1], &rb = L.regions[2];
         {
             Stage st("tsqr_root", s);
@@ -570,6 +594,16 @@ int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const L
         HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, at<double>(ws, L.rt), N, s), "sign normalisation");
     }
     return run_refine(A, B, sh, L, R, ldr, ws, s);
+}
+
+int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
+          int64_t ldr, void *ws, hipStream_t s)
+{
+    int rc = run_compact(A, B, sh, L, ws, s, !cartesian_root(sh, L));
+    if (rc) return rc;
+    rc = run_regions(L, sh.precision == FIGARO_PLAIN_FP64, ws, s);
+    if (rc) return rc;
+    return run_root(A, B, sh, L, R, ldr, ws, s);
 }
 
 }  // namespace
@@ -846,60 +880,276 @@ int figaro_status(const void *ws, void *stream, int32_t *code)
 }  // extern "C"
 
 // ------------------------------------------------------------------ plans
+//
+// A plan runs its instances stage by stage: each stage is one launch (or one short
+// sequence) over every instance at once, driven by device tables of per-instance
+// descriptors, so that the batch fills the GPU rather than any one instance:
+//   1. grouping: one launch for all Cartesian instances (their one-group tables and
+//      zeroed tree counters); a keyed instance runs its own grouping launches;
+//   2. head/tail scans: one three-launch sequence (tile reduce, carry scan, tile write)
+//      over the tiles of every instance's tables, per (columns per thread, input type);
+//   3. region assembly where the form needs it (per instance);
+//   4. TSQR: one tree launch per padded width <= 64 over the leaves of every region of
+//      every instance (each region with its own node counters and root); wider regions
+//      run their own panel-tree launches;
+//   5. roots: one launch per padded width over the Cartesian two-sided instances; the
+//      others (and the refinement sweep) per instance;
+//   6. sigma: two launches per width class over all instances (bidiagonal route).
+// Each instance owns one slice of the workspace.
 
 struct figaro_plan {
     std::vector<figaro_instance> inst;
     std::vector<Shape> shapes;
     std::vector<Layout> layouts;
+    std::vector<size_t> ws_off;        // each instance's workspace slice
     std::vector<int64_t> r_off, s_off;
     int64_t r_total = 0, s_total = 0;
     size_t ws_bytes = 0;
-    size_t lane_bytes = 0;          // workspace slice of one lane
-    std::vector<int> lane;          // lane of each instance
-    int nlanes = 1;
+    size_t msin_off = 0;               // multisection inputs of every instance (2 N_i + 2 doubles each)
     hipStream_t cap_stream = nullptr;
-    // Batched sigma: per width class, a contiguous run of (r_off, s_off, n, msin offset)
-    // entries in the device table `stab` (owned by the plan); the multisection inputs of
-    // every instance sit after the lanes' workspace slices.
-    int64_t *stab = nullptr;           // uploaded at the first execution (creation is host-only)
-    std::vector<int64_t> stab_host;
-    std::vector<std::pair<int, std::pair<int, int>>> sclass;  // (class, (first entry, count))
-    size_t msin_off = 0;               // byte offset of the multisection inputs in the workspace
-    std::vector<hipStream_t> lane_streams;
-    std::vector<hipEvent_t> lane_events;  // [0]: fork, [1 + l]: join of lane l
-    // One captured graph per (ws, R, sigma) triple.
-    std::map<std::tuple<void *, double *, double *>, hipGraphExec_t> graphs;
+    // Per (ws, R, sigma): the device launch tables (built and uploaded when that triple
+    // is first executed, owned by the plan) and the captured graph.
+    struct Exec {
+        unsigned char *tables = nullptr;
+        hipGraphExec_t graph = nullptr;
+    };
+    std::map<std::tuple<void *, double *, double *>, Exec> execs;
 };
 
 namespace {
 
-// Instances run as nlanes parallel branches: lane l owns workspace slice l and runs its
-// instances in order; the branches fork from and join back into s.
-int plan_enqueue(figaro_plan *plan, void *ws, double *R, double *sigma, hipStream_t s)
+// Host image of a plan's device tables, each array 256-byte aligned; offsets are
+// relative to the start of the device allocation.
+struct TableImage {
+    std::vector<unsigned char> bytes;
+    template <typename T>
+    size_t add(const std::vector<T> &v)
+    {
+        const size_t off = align_up(bytes.size());
+        bytes.resize(off + std::max<size_t>(1, v.size() * sizeof(T)));
+        if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+};
+
+// Stage names of the batched launches, by padded width (4 .. 512).
+const char *class_name(const char *const (&names)[8], int np)
 {
-    HIPCHK(hipEventRecord(plan->lane_events[0], s), "fork");
-    for (int l = 0; l < plan->nlanes; l++)
-        HIPCHK(hipStreamWaitEvent(plan->lane_streams[l], plan->lane_events[0], 0), "fork wait");
-    for (size_t i = 0; i < plan->inst.size(); i++) {
+    int i = 0;
+    while (i < 7 && (4 << i) < np) i++;
+    return names[i];
+}
+const char *const kTreeNames[8] = {"tsqr_np4", "tsqr_np8", "tsqr_np16", "tsqr_np32",
+                                   "tsqr_np64", "tsqr_np128", "tsqr_np256", "tsqr_np512"};
+const char *const kRootNames[8] = {"root_np4", "root_np8", "root_np16", "root_np32",
+                                   "root_np64", "root_np128", "root_np256", "root_np512"};
+const char *const kSigmaNames[8] = {"sigma_np4", "sigma_np8", "sigma_np16", "sigma_np32",
+                                    "sigma_np64", "sigma_np128", "sigma_np256", "sigma_np512"};
+
+// One step of a batch: enqueues its launches given the device address of the tables.
+using Step = std::function<int(const unsigned char *tables, hipStream_t s)>;
+
+struct Program {
+    TableImage img;
+    std::vector<Step> steps;
+};
+
+// The steps and tables of one execution of the plan with these buffers.
+Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigma)
+{
+    Program P;
+    const size_t count = plan->inst.size();
+    const int prec = plan->shapes[0].precision;
+    const int acc = prec == FIGARO_PLAIN_FP64;
+    const int m_f64 = acc;
+    auto slice = [&](size_t i) { return (void *)((char *)ws + plan->ws_off[i]); };
+
+    // 1. grouping
+    std::vector<CartInit> inits;
+    for (size_t i = 0; i < count; i++) {
         const Shape &sh = plan->shapes[i];
+        const Layout &L = plan->layouts[i];
+        void *lws = slice(i);
+        if (sh.keyed) {
+            const figaro_instance *in = &plan->inst[i];
+            P.steps.push_back([in, sh, &L, lws](const unsigned char *, hipStream_t s) {
+                return run_grouping(&in->A, &in->B, sh, L, lws, s);
+            });
+        } else {
+            inits.push_back(CartInit{at<int32_t>(lws, L.status), at<int32_t>(lws, L.counters_base),
+                                     L.counters_total, groups_of(lws, L), sh.m1, sh.m2});
+        }
+    }
+    if (!inits.empty()) {
+        const size_t off = P.img.add(inits);
+        const int n = (int)inits.size();
+        P.steps.push_back([off, n](const unsigned char *t, hipStream_t s) {
+            Stage st("group", s);
+            HIPCHK(launch_group_cartesian_batch((const CartInit *)(t + off), n, s), "batched grouping");
+            return FIGARO_OK;
+        });
+    }
+
+    // 2. head/tail scans, per (cpt, input type)
+    std::map<std::pair<int, int>, std::vector<ScanJob>> scan_cls;
+    for (size_t i = 0; i < count; i++) {
+        const Shape &sh = plan->shapes[i];
+        const Layout &L = plan->layouts[i];
+        ScanJob jobs[2];
+        const int nj = scan_jobs(&plan->inst[i].A, &plan->inst[i].B, sh, L, slice(i), jobs);
+        const ScanPlan *sp[2] = {&L.spB, &L.spA};
+        for (int j = 0; j < nj; j++)
+            if (jobs[j].ntiles > 0) scan_cls[{sp[j]->cpt, sh.in_f64}].push_back(jobs[j]);
+    }
+    for (auto &kv : scan_cls) {
+        const std::vector<ScanJob> &jobs = kv.second;
+        std::vector<int2> tiles, cols;
+        for (int j = 0; j < (int)jobs.size(); j++) {
+            for (int64_t t = 0; t < jobs[j].ntiles; t++) tiles.push_back(make_int2(j, (int)t));
+            for (int c = 0; c < jobs[j].n; c++) cols.push_back(make_int2(j, c));
+        }
+        const size_t jo = P.img.add(jobs), to = P.img.add(tiles), co = P.img.add(cols);
+        const int64_t nt = (int64_t)tiles.size(), nc = (int64_t)cols.size();
+        const int cpt = kv.first.first, in_f64 = kv.first.second;
+        static const char *const pass_name[3] = {"scan_reduce", "scan_carry", "scan_write"};
+        for (int pass = 0; pass < 3; pass++) {
+            P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+                Stage st(pass_name[pass], s);
+                HIPCHK(launch_seg_scan_batch(pass, (const ScanJob *)(t + jo), (const int2 *)(t + to), nt,
+                                             (const int2 *)(t + co), nc, cpt, in_f64, m_f64, s),
+                       "batched head/tail scans");
+                return FIGARO_OK;
+            });
+        }
+    }
+
+    // 3. assembly (Claim 1 region 1; head rows of keyed two-sided instances)
+    for (size_t i = 0; i < count; i++) {
+        const Shape &sh = plan->shapes[i];
+        const Layout &L = plan->layouts[i];
+        if (cartesian_root(sh, L)) continue;
+        const figaro_instance *in = &plan->inst[i];
+        void *lws = slice(i);
+        P.steps.push_back([in, sh, &L, lws](const unsigned char *, hipStream_t s) {
+            return run_assembly(&in->A, sh, L, lws, s);
+        });
+    }
+
+    // 4. trees: narrow regions batched by padded width, wide ones per region
+    std::map<int, std::vector<TreeRegion>> tree_cls;
+    for (size_t i = 0; i < count; i++) {
+        const Layout &L = plan->layouts[i];
+        void *lws = slice(i);
+        for (const Region &r : L.regions) {
+            if (r.skip || r.rows_cap == 0) continue;
+            if (r.wave) {
+                tree_cls[r.np].push_back(tree_region(r, L, lws));
+            } else {
+                const TreeRegion tr = tree_region(r, L, lws);
+                const int np = r.np;
+                const char *name = r.name;
+                P.steps.push_back([tr, np, name, acc, m_f64](const unsigned char *, hipStream_t s) {
+                    Stage st(name, s);
+                    HIPCHK(launch_tsqr_panel_tree(np, acc, m_f64, &tr, 1, s), "tsqr panel tree");
+                    return FIGARO_OK;
+                });
+            }
+        }
+    }
+    for (auto &kv : tree_cls) {
+        const std::vector<TreeRegion> &regs = kv.second;
+        std::vector<int2> map;
+        for (int j = 0; j < (int)regs.size(); j++)
+            for (int l = 0; l < regs[j].nleaves; l++) map.push_back(make_int2(j, l));
+        const size_t ro = P.img.add(regs), mo = P.img.add(map);
+        const int64_t nb = (int64_t)map.size();
+        const int np = kv.first;
+        const char *name = class_name(kTreeNames, np);
+        P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+            Stage st(name, s);
+            HIPCHK(launch_tsqr_tree_batch(np, acc, m_f64, (const TreeRegion *)(t + ro), (const int2 *)(t + mo), nb,
+                                          s),
+                   "batched tsqr tree");
+            return FIGARO_OK;
+        });
+    }
+
+    // 5. roots: Cartesian two-sided instances batched by padded width, the rest per instance
+    std::map<int, std::vector<CartRoot>> root_cls;
+    for (size_t i = 0; i < count; i++) {
+        const Shape &sh = plan->shapes[i];
+        const Layout &L = plan->layouts[i];
+        void *lws = slice(i);
+        const int N = (int)sh.N();
+        double *Ri = R + plan->r_off[i];
+        if (cartesian_root(sh, L)) {
+            const Region &ra = L.regions[1], &rb = L.regions[2];
+            root_cls[L.np_root].push_back(CartRoot{at<double>(lws, ra.root), ra.np, ra.width, at<double>(lws, rb.root),
+                                                   rb.np, rb.width, groups_of(lws, L), at<double>(lws, L.headsA),
+                                                   at<double>(lws, L.headsB), L.refine ? at<double>(lws, L.rt) : Ri,
+                                                   L.refine ? N : (int64_t)N});
+        } else {
+            const figaro_instance *in = &plan->inst[i];
+            P.steps.push_back([in, sh, &L, Ri, N, lws](const unsigned char *, hipStream_t s) {
+                return run_root(&in->A, &in->B, sh, L, Ri, N, lws, s);
+            });
+        }
+    }
+    for (auto &kv : root_cls) {
+        const size_t off = P.img.add(kv.second);
+        const int n = (int)kv.second.size(), np = kv.first;
+        const char *name = class_name(kRootNames, np);
+        P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+            Stage st(name, s);
+            HIPCHK(launch_merge_cartesian_batch(np, (const CartRoot *)(t + off), n, s), "batched cartesian roots");
+            return FIGARO_OK;
+        });
+    }
+    // refinement of the batched roots (the others refine inside run_root)
+    for (size_t i = 0; i < count; i++) {
+        const Shape &sh = plan->shapes[i];
+        const Layout &L = plan->layouts[i];
+        if (!L.refine || !cartesian_root(sh, L)) continue;
+        const figaro_instance *in = &plan->inst[i];
+        void *lws = slice(i);
+        double *Ri = R + plan->r_off[i];
         const int64_t N = sh.N();
-        const int l = plan->lane[i];
-        hipStream_t ls = plan->lane_streams[l];
-        void *lws = (char *)ws + (size_t)l * plan->lane_bytes;
-        int rc = run_r(&plan->inst[i].A, &plan->inst[i].B, sh, plan->layouts[i], R + plan->r_off[i], N, lws, ls);
+        P.steps.push_back([in, sh, &L, Ri, N, lws](const unsigned char *, hipStream_t s) {
+            return run_refine(&in->A, &in->B, sh, L, Ri, N, lws, s);
+        });
+    }
+
+    // 6. sigma: per width class, one bidiagonalisation workgroup per instance, then one
+    // multisection workgroup per singular value
+    for (int c = 8; c <= 128; c *= 2) {
+        std::vector<int64_t> tab;
+        for (size_t i = 0; i < count; i++) {
+            if (sigma_width_class((int)plan->shapes[i].N()) != c) continue;
+            tab.push_back(plan->r_off[i]);
+            tab.push_back(plan->s_off[i]);
+            tab.push_back(plan->shapes[i].N());
+            tab.push_back(2 * plan->s_off[i] + 2 * (int64_t)i);
+        }
+        if (tab.empty()) continue;
+        const size_t off = P.img.add(tab);
+        const int n = (int)(tab.size() / 4);
+        double *msin = at<double>(ws, plan->msin_off);
+        const char *name = class_name(kSigmaNames, c);
+        P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+            Stage st(name, s);
+            HIPCHK(launch_sigma_batch(c, R, sigma, (const int64_t *)(t + off), n, msin, s), "batched sigma");
+            return FIGARO_OK;
+        });
+    }
+    return P;
+}
+
+int run_program(const Program &P, const unsigned char *tables, hipStream_t s)
+{
+    for (const Step &st : P.steps) {
+        int rc = st(tables, s);
         if (rc) return rc;
     }
-    for (int l = 0; l < plan->nlanes; l++) {
-        HIPCHK(hipEventRecord(plan->lane_events[1 + l], plan->lane_streams[l]), "join");
-        HIPCHK(hipStreamWaitEvent(s, plan->lane_events[1 + l], 0), "join wait");
-    }
-    // sigma of every instance: per width class, one bidiagonalisation workgroup per instance,
-    // then one multisection workgroup per singular value
-    double *msin = at<double>(ws, plan->msin_off);
-    for (const auto &c : plan->sclass)
-        HIPCHK(launch_sigma_batch(c.first, R, sigma, plan->stab + 4 * (int64_t)c.second.first, c.second.second, msin,
-                                  s),
-               "batched sigma");
     return FIGARO_OK;
 }
 
@@ -912,7 +1162,7 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
 {
     if (!inst || count < 1 || !out) return fail(FIGARO_EINVAL, "bad plan arguments");
     figaro_plan *p = new figaro_plan();
-    size_t wsmax = 0;
+    size_t off = 0;
     for (int i = 0; i < count; i++) {
         Shape sh;
         int rc = make_shape(&inst[i].A, &inst[i].B, precision, &sh);
@@ -927,49 +1177,17 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
         Layout L = make_layout(sh);
         p->inst.push_back(inst[i]);
         p->shapes.push_back(sh);
-        p->layouts.push_back(L);
+        p->ws_off.push_back(off);
+        off += align_up(L.total);
+        p->layouts.push_back(std::move(L));
         p->r_off.push_back(p->r_total);
         p->s_off.push_back(p->s_total);
         p->r_total += sh.N() * sh.N();
         p->s_total += sh.N();
-        wsmax = std::max(wsmax, align_up(L.total));
     }
-    // Lanes: largest instances first, each to the lane with the least work so far
-    // (work ~ rows x N^2; ties to the lower lane, so the assignment is deterministic).
-    p->nlanes = std::min(count, kPlanLanes);
-    p->lane.assign(count, 0);
-    std::vector<int> order(count);
-    for (int i = 0; i < count; i++) order[i] = i;
-    auto work = [&](int i) {
-        const Shape &sh = p->shapes[i];
-        return (double)(sh.m1 + sh.m2) * (double)(sh.N() * sh.N());
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-    std::vector<double> load(p->nlanes, 0.0);
-    for (int i : order) {
-        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        p->lane[i] = l;
-        load[l] += work(i);
-    }
-    p->lane_bytes = wsmax;
-    p->msin_off = wsmax * p->nlanes;
+    p->msin_off = off;
     // multisection inputs: 2 N + 2 doubles per instance
     p->ws_bytes = p->msin_off + align_up(sizeof(double) * (size_t)(2 * p->s_total + 2 * (int64_t)count));
-    // instance table of the batched sigma, grouped by width class
-    std::vector<int64_t> tab;
-    for (int c = 8; c <= 128; c *= 2) {
-        const int first = (int)(tab.size() / 4);
-        for (int i = 0; i < count; i++) {
-            if (sigma_width_class((int)p->shapes[i].N()) != c) continue;
-            tab.push_back(p->r_off[i]);
-            tab.push_back(p->s_off[i]);
-            tab.push_back(p->shapes[i].N());
-            tab.push_back(2 * p->s_off[i] + 2 * (int64_t)i);
-        }
-        const int n = (int)(tab.size() / 4) - first;
-        if (n > 0) p->sclass.push_back({c, {first, n}});
-    }
-    p->stab_host = std::move(tab);
     *out = p;
     return FIGARO_OK;
 }
@@ -993,38 +1211,61 @@ int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
     return FIGARO_OK;
 }
 
-int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
-                        void *stream)
+namespace {
+
+int plan_check(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma)
 {
     if (!plan || !R || !sigma) return fail(FIGARO_EINVAL, "plan, R or sigma is NULL");
     if (!ws) return fail(FIGARO_EINVAL, "workspace is NULL");
     if (((uintptr_t)ws) % kAlign) return fail(FIGARO_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < plan->ws_bytes) return fail(FIGARO_EWORKSPACE, "workspace too small");
-    hipStream_t s = (hipStream_t)stream;
+    return FIGARO_OK;
+}
+
+// The record of (ws, R, sigma); its launch tables (the image of `prog`) are uploaded on
+// first use.
+int plan_exec(figaro_plan *plan, void *ws, double *R, double *sigma, const Program &prog,
+              figaro_plan::Exec **out)
+{
     auto key = std::make_tuple(ws, R, sigma);
-    auto it = plan->graphs.find(key);
-    if (!plan->stab) {
-        const size_t nb = sizeof(int64_t) * std::max<size_t>(1, plan->stab_host.size());
-        HIPCHK(hipMalloc((void **)&plan->stab, nb), "plan instance table");
-        HIPCHK(hipMemcpy(plan->stab, plan->stab_host.data(), sizeof(int64_t) * plan->stab_host.size(),
-                         hipMemcpyHostToDevice),
-               "plan instance table");
-    }
-    if (it == plan->graphs.end()) {
-        if (!plan->cap_stream) {
-            HIPCHK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking), "plan stream");
-            plan->lane_streams.assign(plan->nlanes, nullptr);
-            for (auto &ls : plan->lane_streams)
-                HIPCHK(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking), "plan lane stream");
-            plan->lane_events.assign(plan->nlanes + 1, nullptr);
-            for (auto &ev : plan->lane_events)
-                HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "plan event");
+    auto it = plan->execs.find(key);
+    if (it == plan->execs.end()) {
+        figaro_plan::Exec ex;
+        const size_t nb = prog.img.bytes.size();
+        HIPCHK(hipMalloc((void **)&ex.tables, std::max<size_t>(nb, 1)), "plan launch tables");
+        if (nb) {
+            hipError_t e = hipMemcpy(ex.tables, prog.img.bytes.data(), nb, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(ex.tables);
+                return hip_fail(e, "plan launch tables");
+            }
         }
+        it = plan->execs.emplace(key, ex).first;
+    }
+    *out = &it->second;
+    return FIGARO_OK;
+}
+
+}  // namespace
+
+int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
+                        void *stream)
+{
+    int rc = plan_check(plan, ws, ws_bytes, R, sigma);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    auto it = plan->execs.find(std::make_tuple(ws, R, sigma));
+    if (it == plan->execs.end() || !it->second.graph) {
+        const Program prog = build_program(plan, ws, R, sigma);
+        figaro_plan::Exec *ex = nullptr;
+        rc = plan_exec(plan, ws, R, sigma, prog, &ex);
+        if (rc) return rc;
+        if (!plan->cap_stream)
+            HIPCHK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking), "plan stream");
         hipGraph_t graph = nullptr;
-        HIPCHK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal),
-               "begin capture");
+        HIPCHK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
         t_capturing = true;
-        int rc = plan_enqueue(plan, ws, R, sigma, plan->cap_stream);
+        rc = run_program(prog, ex->tables, plan->cap_stream);
         t_capturing = false;
         hipError_t e = hipStreamEndCapture(plan->cap_stream, &graph);
         if (rc) {
@@ -1036,23 +1277,34 @@ int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R,
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-        it = plan->graphs.emplace(key, exec).first;
+        ex->graph = exec;
+        it = plan->execs.find(std::make_tuple(ws, R, sigma));
     }
     Stage st("plan_graph", s);
-    HIPCHK(hipGraphLaunch(it->second, s), "graph launch");
+    HIPCHK(hipGraphLaunch(it->second.graph, s), "graph launch");
     return FIGARO_OK;
+}
+
+int figaro_plan_execute_eager(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
+                              void *stream)
+{
+    int rc = plan_check(plan, ws, ws_bytes, R, sigma);
+    if (rc) return rc;
+    const Program prog = build_program(plan, ws, R, sigma);
+    figaro_plan::Exec *ex = nullptr;
+    rc = plan_exec(plan, ws, R, sigma, prog, &ex);
+    if (rc) return rc;
+    return run_program(prog, ex->tables, (hipStream_t)stream);
 }
 
 void figaro_plan_destroy(figaro_plan *plan)
 {
     if (!plan) return;
-    for (auto &kv : plan->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (auto ev : plan->lane_events)
-        if (ev) (void)hipEventDestroy(ev);
-    for (auto ls : plan->lane_streams)
-        if (ls) (void)hipStreamDestroy(ls);
+    for (auto &kv : plan->execs) {
+        if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
+        if (kv.second.tables) (void)hipFree(kv.second.tables);
+    }
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
-    if (plan->stab) (void)hipFree(plan->stab);
     delete plan;
 }
 

@@ -30,14 +30,9 @@ __global__ void k_init(int32_t *status, int64_t *counts, int32_t *ticket, int32_
     for (int64_t j = i; j < nflags; j += (int64_t)gridDim.x * blockDim.x) flags[j] = 0;
 }
 
-// The whole grouping of a Cartesian product (one group) with the initialisation of
-// k_init in the same launch: node counters zeroed by every thread, the status, counts
-// and the one-group table written by thread 0.
-__global__ void k_cartesian(int32_t *status, int32_t *flags, int64_t nflags, Groups g, int64_t m1, int64_t m2)
+// The one-group table of a Cartesian product, its counts and status (one thread).
+__device__ inline void cartesian_table(int32_t *status, Groups g, int64_t m1, int64_t m2)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t j = i; j < nflags; j += (int64_t)gridDim.x * blockDim.x) flags[j] = 0;
-    if (i != 0) return;
     *status = kStatusOk;
     for (int c = 0; c < CNT_SLOTS; c++) g.counts[c] = 0;
     const bool nonempty = m1 > 0 && m2 > 0;
@@ -53,6 +48,24 @@ __global__ void k_cartesian(int32_t *status, int32_t *flags, int64_t nflags, Gro
     g.m2[0] = (int32_t)m2;
     g.r1[0] = 0;
     g.r2[0] = 0;
+}
+
+// The whole grouping of a Cartesian product (one group) with the initialisation of
+// k_init in the same launch: node counters zeroed by every thread, the status, counts
+// and the one-group table written by thread 0.
+__global__ void k_cartesian(int32_t *status, int32_t *flags, int64_t nflags, Groups g, int64_t m1, int64_t m2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t j = i; j < nflags; j += (int64_t)gridDim.x * blockDim.x) flags[j] = 0;
+    if (i == 0) cartesian_table(status, g, m1, m2);
+}
+
+// A batch of Cartesian instances, one workgroup each: its counters zeroed, its table set.
+__global__ void k_cartesian_batch(const CartInit *__restrict__ tab)
+{
+    const CartInit c = tab[blockIdx.x];
+    for (int64_t j = threadIdx.x; j < c.nflags; j += blockDim.x) c.flags[j] = 0;
+    if (threadIdx.x == 0) cartesian_table(c.status, c.g, c.m1, c.m2);
 }
 
 // Workgroup exclusive scan of one int per thread; returns the prefix and sets *total.
@@ -324,6 +337,13 @@ hipError_t launch_group_cartesian(int32_t *status, int32_t *flags, int64_t nflag
     if (blocks < 1) blocks = 1;
     if (blocks > 4096) blocks = 4096;
     k_cartesian<<<(unsigned)blocks, 256, 0, s>>>(status, flags, nflags, g, m1, m2);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_cartesian_batch(const CartInit *tab, int count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    k_cartesian_batch<<<(unsigned)count, 256, 0, s>>>(tab);
     return hipGetLastError();
 }
 

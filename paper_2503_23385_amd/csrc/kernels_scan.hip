@@ -28,6 +28,7 @@ constexpr int kScanThreads = 256;
 constexpr int kMaxTileRows = 512;
 constexpr int kMaxCols = 512;
 constexpr int kCarryThreads = 1024;
+constexpr int kBatchCarryThreads = 64;
 
 template <typename T>
 __device__ inline double to_f64(T v) { return (double)v; }
@@ -58,11 +59,12 @@ __device__ inline int first_end_gt(const int32_t *start, const int32_t *size, in
 // One tile of a table's rows: reduce (WRITE = false) or write tails/heads (WRITE = true).
 // The tiles of two jobs (the two tables of the two-sided form) share one launch: blocks
 // [0, j0.ntiles) take job 0, the rest job 1.
+// Tile t of job J (its table's rows, group table J.g).
 template <typename Tin, typename Tout, int CPT, int RPT, bool WRITE>
-__global__ __launch_bounds__(kScanThreads) void k_seg_tile(ScanJob j0, ScanJob j1, Groups g, int cartesian)
+__device__ __forceinline__ void seg_tile(const ScanJob &J, const int t)
 {
-    const bool second = (int64_t)blockIdx.x >= j0.ntiles;
-    const ScanJob &J = second ? j1 : j0;
+    const Groups g = J.g;
+    const int cartesian = J.cartesian;
     const Tin *__restrict__ B = (const Tin *)J.in;
     const int64_t ldb = J.ld;
     const int m2 = J.m, n2 = J.n, Q = J.q;
@@ -78,7 +80,6 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_tile(ScanJob j0, ScanJob j
     const int q = tid / ncolthr;
     const bool active = q < Q;
     const int TR = Q * RPT;
-    const int t = (int)(blockIdx.x - (second ? j0.ntiles : 0));
     const int64_t t0 = (int64_t)t * TR;
     const int G = (int)g.counts[CNT_G];
 
@@ -245,26 +246,43 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_tile(ScanJob j0, ScanJob j
     }
 }
 
+// The tiles of up to two inline jobs (the two tables of the two-sided form) in one
+// launch: blocks [0, j0.ntiles) take job 0, the rest job 1.
+template <typename Tin, typename Tout, int CPT, int RPT, bool WRITE>
+__global__ __launch_bounds__(kScanThreads) void k_seg_tile(ScanJob j0, ScanJob j1)
+{
+    const bool second = (int64_t)blockIdx.x >= j0.ntiles;
+    seg_tile<Tin, Tout, CPT, RPT, WRITE>(second ? j1 : j0, (int)(blockIdx.x - (second ? j0.ntiles : 0)));
+}
+
+// The tiles of a batch of jobs (device table): block b takes tile map[b].y of job map[b].x.
+template <typename Tin, typename Tout, int CPT, int RPT, bool WRITE>
+__global__ __launch_bounds__(kScanThreads) void k_seg_tile_batch(const ScanJob *__restrict__ jobs,
+                                                                 const int2 *__restrict__ map)
+{
+    const int2 e = map[blockIdx.x];
+    const ScanJob J = jobs[e.x];
+    seg_tile<Tin, Tout, CPT, RPT, WRITE>(J, e.y);
+}
+
 // Exclusive segmented scan of the tile aggregates, per column: carry[t] = the sums
 // carried into tile t.  One workgroup per column: each thread reduces a run of
 // consecutive tiles, the thread aggregates are scanned in LDS (Hillis-Steele with the
 // segmented operator (f1, s1) + (f2, s2) = (f1 | f2, f2 ? s2 : s1 + s2)), and each thread
 // rescans its run with the carry it receives.  The combination order is fixed, so the
 // result does not depend on timing.
-__global__ __launch_bounds__(kCarryThreads) void k_carry_scan(ScanJob j0, ScanJob j1)
+template <int NT>
+__device__ __forceinline__ void carry_scan(const ScanJob &J, const int c)
 {
-    // blocks [0, j0.n) take the columns of job 0, the rest those of job 1
-    const bool second = (int)blockIdx.x >= j0.n;
-    const ScanJob &J = second ? j1 : j0;
     const int32_t *__restrict__ tileF = J.tileF;
     const double *__restrict__ tileS = J.tileS;
     double *__restrict__ carry = J.carry;
     const int T = (int)J.ntiles, n2 = J.n;
-    const int c = (int)blockIdx.x - (second ? j0.n : 0), tid = threadIdx.x;
-    const int L = (T + kCarryThreads - 1) / kCarryThreads;
+    const int tid = threadIdx.x;
+    const int L = (T + NT - 1) / NT;
     const int tb = min(T, tid * L), te = min(T, tb + L);
-    __shared__ int sf[2][kCarryThreads];
-    __shared__ double ss[2][kCarryThreads];
+    __shared__ int sf[2][NT];
+    __shared__ double ss[2][NT];
     int F = 0;
     double S = 0.0;
     for (int t = tb; t < te; t++) {
@@ -277,7 +295,7 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry_scan(ScanJob j0, ScanJo
     sf[0][tid] = F;
     ss[0][tid] = S;
     __syncthreads();
-    for (int off = 1; off < kCarryThreads; off <<= 1) {
+    for (int off = 1; off < NT; off <<= 1) {
         int f = sf[cur][tid];
         double v = ss[cur][tid];
         if (tid >= off) {
@@ -298,6 +316,23 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry_scan(ScanJob j0, ScanJo
         const double st = tileS[(int64_t)t * n2 + c];
         run = ft ? st : run + st;
     }
+}
+
+// blocks [0, j0.n) take the columns of job 0, the rest those of job 1
+__global__ __launch_bounds__(kCarryThreads) void k_carry_scan(ScanJob j0, ScanJob j1)
+{
+    const bool second = (int)blockIdx.x >= j0.n;
+    carry_scan<kCarryThreads>(second ? j1 : j0, (int)blockIdx.x - (second ? j0.n : 0));
+}
+
+// A batch (device table): block b scans column map[b].y of job map[b].x.  The jobs of a
+// batch have few tiles each, so a block is one wave.
+__global__ __launch_bounds__(kBatchCarryThreads) void k_carry_scan_batch(const ScanJob *__restrict__ jobs,
+                                                                        const int2 *__restrict__ map)
+{
+    const int2 e = map[blockIdx.x];
+    const ScanJob J = jobs[e.x];
+    carry_scan<kBatchCarryThreads>(J, e.y);
 }
 
 template <typename Tin, typename Tout>
@@ -407,15 +442,18 @@ ScanJob scan_job(const void *X, int64_t ldx, int64_t m, int64_t n, ScanSide side
     return j;
 }
 
-hipError_t launch_seg_scan(const ScanJob &j0, const ScanJob &j1, int cpt, int in_f64, int out_f64, Groups g,
+hipError_t launch_seg_scan(const ScanJob &j0_in, const ScanJob &j1_in, int cpt, int in_f64, int out_f64, Groups g,
                            int cartesian, hipStream_t s)
 {
+    ScanJob j0 = j0_in, j1 = j1_in;
+    j0.g = j1.g = g;
+    j0.cartesian = j1.cartesian = cartesian;
     const int64_t tiles = j0.ntiles + j1.ntiles;
     if (tiles == 0) return hipSuccess;
     if (j0.n > kMaxCols || j1.n > kMaxCols) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)tiles;
 #define FIGARO_TILE(TI, TO, CPT, WR) \
-    k_seg_tile<TI, TO, CPT, 16, WR><<<grid, kScanThreads, 0, s>>>(j0, j1, g, cartesian)
+    k_seg_tile<TI, TO, CPT, 16, WR><<<grid, kScanThreads, 0, s>>>(j0, j1)
 #define FIGARO_TILE_ALL(WR)                                                                       \
     do {                                                                                          \
         if (cpt == 1) {                                                                           \
@@ -441,6 +479,39 @@ hipError_t launch_seg_scan(const ScanJob &j0, const ScanJob &j1, int cpt, int in
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     FIGARO_TILE_ALL(true);
+#undef FIGARO_TILE_ALL
+#undef FIGARO_TILE
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_scan_batch(int pass, const ScanJob *jobs, const int2 *tile_map, int64_t ntiles,
+                                 const int2 *col_map, int64_t ncols, int cpt, int in_f64, int out_f64, hipStream_t s)
+{
+    if (ntiles == 0) return hipSuccess;
+    if (ntiles > INT32_MAX || ncols > INT32_MAX) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)ntiles;
+#define FIGARO_TILE(TI, TO, CPT, WR) \
+    k_seg_tile_batch<TI, TO, CPT, 16, WR><<<grid, kScanThreads, 0, s>>>(jobs, tile_map)
+#define FIGARO_TILE_ALL(WR)                                                                       \
+    do {                                                                                          \
+        if (cpt == 1) {                                                                           \
+            if (in_f64 && out_f64) FIGARO_TILE(double, double, 1, WR);                            \
+            else if (in_f64) FIGARO_TILE(double, float, 1, WR);                                   \
+            else if (out_f64) FIGARO_TILE(float, double, 1, WR);                                  \
+            else FIGARO_TILE(float, float, 1, WR);                                                \
+        } else {                                                                                  \
+            if (in_f64 && out_f64) FIGARO_TILE(double, double, 2, WR);                            \
+            else if (in_f64) FIGARO_TILE(double, float, 2, WR);                                   \
+            else if (out_f64) FIGARO_TILE(float, double, 2, WR);                                  \
+            else FIGARO_TILE(float, float, 2, WR);                                                \
+        }                                                                                         \
+    } while (0)
+    if (pass == 0) FIGARO_TILE_ALL(false);
+    else if (pass == 1) {
+        if (ncols > 0) k_carry_scan_batch<<<(unsigned)ncols, kBatchCarryThreads, 0, s>>>(jobs, col_map);
+    } else {
+        FIGARO_TILE_ALL(true);
+    }
 #undef FIGARO_TILE_ALL
 #undef FIGARO_TILE
     return hipGetLastError();

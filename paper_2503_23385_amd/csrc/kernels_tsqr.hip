@@ -505,8 +505,9 @@ __device__ inline void wg_load_tri(WgState<NP, Tacc> &st, const double *T, int w
 // tree of the region's arity; at each node the last child to arrive (per-node atomic
 // counter) combines all children in child order.  slots: the node triangles of every
 // level (width x NP doubles each); counters: one int per parent node, zero on entry.
+// Leaf g of region rg, then the climb of its tree.
 template <int NP, typename Tin, typename Tacc, bool STAGED>
-__global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion reg0, TreeRegion reg1)
+__device__ __forceinline__ void tree_leaf(const TreeRegion &rg, const int g)
 {
     using Gm = WaveGeom<NP>;
     constexpr int WV = tree_waves(NP);
@@ -515,10 +516,6 @@ __global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion re
     __shared__ __align__(16) Tacc Xs[WV][Gm::BR];
     __shared__ __align__(16) double red[2][NP][tree_red_stride(NP)];
     __shared__ int s_old;
-    int g = blockIdx.x;
-    const bool second = g >= reg0.nleaves;
-    const TreeRegion rg = second ? reg1 : reg0;
-    if (second) g -= reg0.nleaves;
     const int width = rg.width;
     const int64_t rows = src_rows(rg.src);
     // leaves follow the device-side row count; surplus workgroups leave at once
@@ -572,6 +569,23 @@ __global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion re
         n = (n + A - 1) / A;
     }
     wg_store<NP, Tacc>(st, rg.root, width);
+}
+
+template <int NP, typename Tin, typename Tacc, bool STAGED>
+__global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree(TreeRegion reg0, TreeRegion reg1)
+{
+    const bool second = (int)blockIdx.x >= reg0.nleaves;
+    tree_leaf<NP, Tin, Tacc, STAGED>(second ? reg1 : reg0, (int)blockIdx.x - (second ? reg0.nleaves : 0));
+}
+
+// The regions of a batch (device table): block b is leaf map[b].y of region map[b].x.
+template <int NP, typename Tin, typename Tacc, bool STAGED>
+__global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree_batch(const TreeRegion *__restrict__ regs,
+                                                                         const int2 *__restrict__ map)
+{
+    const int2 e = map[blockIdx.x];
+    const TreeRegion rg = regs[e.x];
+    tree_leaf<NP, Tin, Tacc, STAGED>(rg, e.y);
 }
 
 __global__ void k_sign_normalise(const double *Rin, int64_t ldin, int n, double *R, int64_t ldr)
@@ -646,7 +660,39 @@ hipError_t launch_tree_np(int acc_f64, int in_f64, const TreeRegion *regs, int n
     return hipGetLastError();
 }
 
+template <int NP>
+hipError_t launch_tree_batch_np(int acc_f64, int in_f64, const TreeRegion *regs, const int2 *map, int64_t nblocks,
+                                hipStream_t s)
+{
+    const unsigned grid = (unsigned)nblocks;
+#define FIGARO_TREE(TI, TA) \
+    k_tsqr_tree_batch<NP, TI, TA, false><<<grid, 64 * tree_waves(NP), 0, s>>>(regs, map)
+    if (acc_f64) {
+        if (in_f64) FIGARO_TREE(double, double);
+        else FIGARO_TREE(float, double);
+    } else {
+        if (in_f64) FIGARO_TREE(double, float);
+        else FIGARO_TREE(float, float);
+    }
+#undef FIGARO_TREE
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_tsqr_tree_batch(int np, int acc_f64, int in_f64, const TreeRegion *regs, const int2 *map,
+                                  int64_t nblocks, hipStream_t s)
+{
+    if (nblocks == 0) return hipSuccess;
+    if (nblocks > INT32_MAX) return hipErrorInvalidValue;
+    switch (np) {
+#define FIGARO_CASE(NPV) \
+    case NPV: return launch_tree_batch_np<NPV>(acc_f64, in_f64, regs, map, nblocks, s);
+    FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64)
+#undef FIGARO_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
 
 int tsqr_padded_width(int n)
 {
@@ -723,9 +769,9 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
 // first nonzero entry; -0.0 becomes +0.0).  With no group (an empty table) nothing is
 // absorbed.
 template <int NP>
-__global__ __launch_bounds__(64) void k_merge_cartesian(const double *Ta, int64_t lda, int na, const double *Tb,
-                                                        int64_t ldb, int nb, Groups g, const double *hA,
-                                                        const double *hB, double *R, int64_t ldr)
+__device__ __forceinline__ void merge_cartesian_lds(const double *Ta, int64_t lda, int na, const double *Tb,
+                                                    int64_t ldb, int nb, Groups g, const double *hA,
+                                                    const double *hB, double *R, int64_t ldr)
 {
     constexpr int CPL = NP > 64 ? NP / 64 : 1;
     __shared__ double Rp[packed_size(NP)];
@@ -820,9 +866,9 @@ __global__ __launch_bounds__(64) void k_merge_cartesian(const double *Ta, int64_
 // scalars of step j come from lane j by lane reads, and row i is written out by the
 // lanes straight from r[i].
 template <int NP>
-__global__ __launch_bounds__(64) void k_merge_cartesian_reg(const double *Ta, int64_t lda, int na, const double *Tb,
-                                                            int64_t ldb, int nb, Groups g, const double *hA,
-                                                            const double *hB, double *R, int64_t ldr)
+__device__ __forceinline__ void merge_cartesian_reg(const double *Ta, int64_t lda, int na, const double *Tb,
+                                                    int64_t ldb, int nb, Groups g, const double *hA,
+                                                    const double *hB, double *R, int64_t ldr)
 {
     static_assert(NP <= 64, "one column per lane");
     const int k = threadIdx.x, width = na + nb;
@@ -886,19 +932,53 @@ __global__ __launch_bounds__(64) void k_merge_cartesian_reg(const double *Ta, in
     }
 }
 
+// One Cartesian root per workgroup: R in registers up to NP = 64, in LDS at NP = 128.
+template <int NP>
+__device__ __forceinline__ void merge_cartesian(const CartRoot &c)
+{
+    if constexpr (NP <= 64)
+        merge_cartesian_reg<NP>(c.Ta, c.lda, c.na, c.Tb, c.ldb, c.nb, c.g, c.hA, c.hB, c.R, c.ldr);
+    else
+        merge_cartesian_lds<NP>(c.Ta, c.lda, c.na, c.Tb, c.ldb, c.nb, c.g, c.hA, c.hB, c.R, c.ldr);
+}
+
+template <int NP>
+__global__ __launch_bounds__(64) void k_merge_cartesian(CartRoot c)
+{
+    merge_cartesian<NP>(c);
+}
+
+// A batch of Cartesian roots of one padded width (device table), one workgroup each.
+template <int NP>
+__global__ __launch_bounds__(64) void k_merge_cartesian_batch(const CartRoot *__restrict__ tab)
+{
+    const CartRoot c = tab[blockIdx.x];
+    merge_cartesian<NP>(c);
+}
+
+hipError_t launch_merge_cartesian_batch(int np, const CartRoot *tab, int count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    switch (np) {
+#define FIGARO_MC(NPV) \
+    case NPV: k_merge_cartesian_batch<NPV><<<(unsigned)count, 64, 0, s>>>(tab); return hipGetLastError();
+    FIGARO_MC(4) FIGARO_MC(8) FIGARO_MC(16) FIGARO_MC(32) FIGARO_MC(64) FIGARO_MC(128)
+#undef FIGARO_MC
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_merge_cartesian(int np, const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
                                   Groups g, const double *hA, const double *hB, double *R, int64_t ldr,
                                   hipStream_t s)
 {
     if (na < 1 || nb < 1) return hipErrorInvalidValue;
+    const CartRoot c{Ta, lda, na, Tb, ldb, nb, g, hA, hB, R, ldr};
     switch (np) {
 #define FIGARO_MC(NPV) \
-    case NPV: k_merge_cartesian_reg<NPV><<<1, 64, 0, s>>>(Ta, lda, na, Tb, ldb, nb, g, hA, hB, R, ldr); return hipGetLastError();
-    FIGARO_MC(4) FIGARO_MC(8) FIGARO_MC(16) FIGARO_MC(32) FIGARO_MC(64)
+    case NPV: k_merge_cartesian<NPV><<<1, 64, 0, s>>>(c); return hipGetLastError();
+    FIGARO_MC(4) FIGARO_MC(8) FIGARO_MC(16) FIGARO_MC(32) FIGARO_MC(64) FIGARO_MC(128)
 #undef FIGARO_MC
-    case 128:
-        k_merge_cartesian<128><<<1, 64, 0, s>>>(Ta, lda, na, Tb, ldb, nb, g, hA, hB, R, ldr);
-        return hipGetLastError();
     default: return hipErrorInvalidValue;
     }
 }

@@ -381,3 +381,60 @@ def test_plan_graph_replays_match_oracle(prec, tol, two_sided):
             es = np.linalg.norm(Sg - So) / np.linalg.norm(So)
             assert er <= tol and es <= tol, (rep, i, er, es)
         del junk
+
+
+def mixed_plan_instances():
+    """Instances of every kind a plan batches by stage or runs on its own: Cartesian and
+    keyed, FP64 and FP32 inputs, padded widths 8 to 128, a ragged keyed join whose root
+    is merged per instance, and an empty join."""
+    rng = lambda k: W.rng_for(720, k)  # noqa: E731
+    out = [
+        W.random_instance(rng(1), 700, 4, 900, 4),
+        W.random_instance(rng(2), 3000, 5, 2500, 7, n_values=40, key_skew=1.1),
+        W.random_instance(rng(3), 1500, 64, 1300, 64, n_values=25),
+        W.random_instance(rng(4), 5000, 32, 4000, 32, dtype=np.float32),
+        W.random_instance(rng(5), 2200, 16, 1800, 48),
+        W.Instance(np.ones((10, 3)), np.ones((8, 2)), np.arange(10, dtype=np.int32),
+                   np.arange(100, 108, dtype=np.int32)),
+        W.random_instance(rng(6), 1200, 60, 1100, 61),
+    ]
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("fp32_refine", 1e-12)])
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_plan_mixed_instances(prec, tol, two_sided):
+    """A plan whose instances take every route of the stage-by-stage batch, each instance
+    against the oracle, on two replays and on an eager run."""
+    insts = mixed_plan_instances()
+    say(f"[plan mixed] {prec} two_sided={two_sided} shapes={[i.shape for i in insts]}")
+    tens = [to_dev(i) for i in insts]
+    plan = fg().Plan(tens, prec, two_sided=two_sided)
+    d = tens[0][0].device
+    ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=d)
+    R = torch.zeros(plan.r_total, dtype=torch.float64, device=d)
+    S = torch.zeros(plan.s_total, dtype=torch.float64, device=d)
+    refs = []
+    for inst in insts:
+        Ro = oracle.r(inst)
+        refs.append((Ro, oracle.sigma(Ro)))
+    for rep in range(3):
+        R.fill_(7.0)
+        S.fill_(7.0)
+        if rep < 2:
+            plan.execute(ws, R, S)
+        else:
+            plan.execute_eager(ws, R, S)
+        torch.cuda.synchronize()
+        Rh, Sh = R.cpu().numpy(), S.cpu().numpy()
+        for i, inst in enumerate(insts):
+            N = inst.A.shape[1] + inst.B.shape[1]
+            Rg = Rh[plan.r_off[i]:plan.r_off[i] + N * N].reshape(N, N)
+            Sg = Sh[plan.s_off[i]:plan.s_off[i] + N]
+            Ro, So = refs[i]
+            if not np.any(Ro):
+                assert not np.any(Rg) and not np.any(Sg), (rep, i)
+                continue
+            er = relF(Rg, Ro)
+            es = np.linalg.norm(Sg - So) / np.linalg.norm(So)
+            assert er <= tol and es <= tol, (rep, i, inst.shape, er, es)
