@@ -62,6 +62,8 @@ def parse():
                     help="comma list: layout:precision (single workloads) or batched|loop:layout:precision (cfg4)")
     ap.add_argument("--flush-reps", type=int, default=8, help="single steps timed after a cache flush")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the tree autotuner (run before timing; its choices are listed under tuning)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
@@ -286,6 +288,8 @@ def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref, time
             fg.r(A, B, kA, kB, prec, ws=ws, out=R, two_sided=two)
             fg.sigma(R, out=S, ws=sws)
 
+        if not args.no_autotune:
+            fg.r_autotune(A, B, kA, kB, prec, two_sided=two, ws=ws, out=R)
         ms = timer.steps(step, args.steps, args.warmup)
         assert fg.status(ws) == 0
         flushed = timer.flushed(step, args.flush_reps)
@@ -328,6 +332,8 @@ def bench_batch(args, insts, desc, forms_spec, torch, fg, dev, stream, refs, tim
             ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=dev)
             R = torch.zeros(plan.r_total, dtype=torch.float64, device=dev)
             S = torch.zeros(plan.s_total, dtype=torch.float64, device=dev)
+            if not args.no_autotune:
+                plan.autotune(ws, R, S)
             r_off, s_off = plan.r_off, plan.s_off
             step = lambda: plan.execute(ws, R, S)  # noqa: E731
             eager = lambda: plan.execute_eager(ws, R, S)  # noqa: E731
@@ -518,6 +524,7 @@ def main():
         "roofline_hbm": out.get("roofline_hbm"),
         "cpu_baseline": cpu,
         "forms": out["forms"],
+        "tuning": fg.tune_table(),
     }
     print(json.dumps(line))
 

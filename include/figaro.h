@@ -292,6 +292,40 @@ int figaro_plan_execute_eager(figaro_plan *plan, void *ws, size_t ws_bytes, doub
                               void *stream);
 void figaro_plan_destroy(figaro_plan *plan);
 
+/* ------------------------------------------------------------ autotuning */
+
+/*
+ * The TSQR reduction of each narrow region (padded width <= 64) runs one of two
+ * tree kernels (one workgroup per leaf, or one wave per leaf) with leaves of a
+ * chosen number of row blocks.  A process-wide tuning table, keyed by
+ * (accumulation type, padded width, single call or plan, log2 of the rows),
+ * holds the choice; its built-in defaults were measured on MI355X.
+ *
+ * figaro_plan_autotune / figaro_r_autotune time every candidate of the table
+ * on the caller's own problem (the same buffers figaro_plan_execute / figaro_r
+ * take: one warm-up and three timed runs per candidate, stage events on
+ * `stream`), keep the fastest per class of regions, and set the table entries
+ * of the row counts the problem holds.  Synchronous; they allocate launch
+ * tables, overwrite R / sigma / ws, drop the plan's captured graphs (the next
+ * execution captures again), and record stage events into the timing of
+ * figaro_timing_enable (consumed).  Workspace sizes do not depend on the
+ * table.  Not thread-safe against concurrent calls that lay out regions.
+ */
+int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma, void *stream);
+int figaro_r_autotune(const figaro_table *A, const figaro_table *B, int32_t precision, double *R, int64_t ldr,
+                      void *ws, size_t ws_bytes, void *stream);
+/*
+ * Tuning cache: JSON lines, one entry per line with the fields arch ("gfx950"),
+ * acc_f64, np, batched, rows_log2, kind (0 workgroup tree, 1 wave tree),
+ * leaf_blocks, arity, ms.  figaro_tune_load merges a file into the table (the
+ * file named by the environment variable FIGARO_TUNE_CACHE is merged at first
+ * use); figaro_tune_save writes the whole table; figaro_tune_dump copies it into
+ * buf (NUL-terminated, at most cap bytes) and its full length into *len.
+ */
+int figaro_tune_load(const char *path);
+int figaro_tune_save(const char *path);
+int figaro_tune_dump(char *buf, size_t cap, size_t *len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,7 +59,8 @@ EXPORTS = [
     "figaro_r_workspace_size", "figaro_r", "figaro_compact", "figaro_inspect",
     "figaro_sigma_workspace_size", "figaro_sigma", "figaro_sigma_jacobi", "figaro_sigma_bidiag", "figaro_status", "figaro_last_error",
     "figaro_plan_create", "figaro_plan_workspace_size", "figaro_plan_offsets",
-    "figaro_plan_execute", "figaro_plan_execute_eager", "figaro_plan_destroy", "figaro_timing_enable", "figaro_timing_read",
+    "figaro_plan_execute", "figaro_plan_execute_eager", "figaro_plan_destroy", "figaro_plan_autotune",
+    "figaro_r_autotune", "figaro_tune_load", "figaro_tune_save", "figaro_tune_dump", "figaro_timing_enable", "figaro_timing_read",
     "figaro_sigma_noalloc",
 ]
 
@@ -94,6 +95,11 @@ def lib():
     L.figaro_plan_offsets.argtypes = [P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.figaro_plan_execute.argtypes = [P, P, SZ, P, P, P]
     L.figaro_plan_execute_eager.argtypes = [P, P, SZ, P, P, P]
+    L.figaro_plan_autotune.argtypes = [P, P, SZ, P, P, P]
+    L.figaro_r_autotune.argtypes = [TP, TP, I32, P, I64, P, SZ, P]
+    L.figaro_tune_load.argtypes = [ctypes.c_char_p]
+    L.figaro_tune_save.argtypes = [ctypes.c_char_p]
+    L.figaro_tune_dump.argtypes = [P, SZ, ctypes.POINTER(SZ)]
     L.figaro_plan_destroy.argtypes = [P]
     L.figaro_plan_destroy.restype = None
     L.figaro_timing_enable.argtypes = [I32]
@@ -300,6 +306,40 @@ def inspect(A, B, keys_A, keys_B, precision, ws, stream=None, two_sided=False):
     return out
 
 
+def r_autotune(A, B, keys_A=None, keys_B=None, precision="fp64", two_sided=False, ws=None, out=None, stream=None):
+    """Time the tree candidates of figaro_r on this problem and keep the fastest (tuning table)."""
+    torch = _torch()
+    ta, tb = make_table(A, keys_A), make_table(B, keys_B)
+    N = A.shape[1] + B.shape[1]
+    if ws is None:
+        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision, two_sided), A.device)
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.float64, device=A.device)
+    require_device("ws", ws, A.device)
+    require_device("out", out, A.device)
+    _check(lib().figaro_r_autotune(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided),
+                                   ctypes.c_void_p(out.data_ptr()), out.stride(0), ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel(), _stream_ptr(stream)))
+
+
+def tune_load(path):
+    _check(lib().figaro_tune_load(os.fsencode(path)))
+
+
+def tune_save(path):
+    _check(lib().figaro_tune_save(os.fsencode(path)))
+
+
+def tune_table():
+    """The tuning table as a list of dicts."""
+    import json
+    n = ctypes.c_size_t(0)
+    _check(lib().figaro_tune_dump(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().figaro_tune_dump(buf, n.value + 1, ctypes.byref(n)))
+    return [json.loads(line) for line in buf.value.decode().splitlines() if line.strip()]
+
+
 def timing_enable(on=True):
     _check(lib().figaro_timing_enable(1 if on else 0))
 
@@ -353,6 +393,12 @@ class Plan:
         _check(lib().figaro_plan_execute_eager(self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                                ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(S.data_ptr()),
                                                _stream_ptr(stream)))
+
+    def autotune(self, ws, R, S, stream=None):
+        """Time the tree candidates on this plan and keep the fastest per width class."""
+        _check(lib().figaro_plan_autotune(self.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                          ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                          _stream_ptr(stream)))
 
     def __del__(self):
         try:

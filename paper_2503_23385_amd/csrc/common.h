@@ -193,14 +193,18 @@ struct TreeRegion {
     int32_t *counters;
     double *root;
 };
-// One launch for one or two regions of the same padded width np (np <= 64).
+// One launch for one or two regions of the same padded width np (np <= 64), one workgroup
+// per leaf, or one wave per leaf when wave_tree is set.
 hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
-                            hipStream_t s);
+                            hipStream_t s, int wave_tree = 0);
 // A batch of regions of padded width np <= 64 in one launch: device table regs, and
-// map[b] = (region, leaf) for each of the nblocks workgroups (leaves beyond what a region's
-// device-side row count needs exit at once).
-hipError_t launch_tsqr_tree_batch(int np, int acc_f64, int in_f64, const TreeRegion *regs, const int2 *map,
-                                  int64_t nblocks, hipStream_t s);
+// map[i] = (region, leaf) for each of the nitems leaves (leaves beyond what a region's
+// device-side row count needs exit at once).  wave_tree: one wave per leaf (triangles
+// and tree nodes of the wave tree: rows per leaf a multiple of tsqr_wave_block_rows);
+// else one workgroup per leaf (the workgroup tree of launch_tsqr_tree).
+hipError_t launch_tsqr_tree_batch(int wave_tree, int np, int acc_f64, int in_f64, const TreeRegion *regs,
+                                  const int2 *map, int64_t nitems, hipStream_t s);
+int tsqr_wave_block_rows(int np);  // rows per block of the wave tree (np <= 64)
 // Root of the two-sided form of a Cartesian product (N = na + nb <= 128): diag(R_TA, R_TB)
 // absorbs the head row built from the head sums hA, hB; R (ld ldr) receives the result
 // with row signs normalised.

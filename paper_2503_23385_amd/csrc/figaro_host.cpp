@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "common.h"
+#include "tune.h"
 #include "../../include/figaro.h"
 
 using namespace figaro;
@@ -137,8 +138,10 @@ struct Region {
     int cnt;
     int width, col_off, np;
     bool wave;                // narrow tree kernel (np <= 64); else the panel tree kernel
+    bool wave_tree;           // narrow regions: one wave per leaf (else one workgroup per leaf)
     bool skip;                // rows absorbed directly by the root merge (no tree of its own)
     int leaves, arity;        // most leaves; tree arity
+    int64_t nslots, ncnt;     // node triangles and counters reserved (for every tuning candidate)
     int64_t rows_per_leaf;    // leaves follow the device row count: ceil(rows / rows_per_leaf)
     size_t slots, counters, root;
     int64_t ncounters;
@@ -214,7 +217,43 @@ int env_int(const char *name, int dflt)
     return x > 0 ? x : dflt;
 }
 
-Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int col_off, int acc_f64)
+constexpr int kMaxWaveLeaves = 1 << 16;
+
+// Tree kernel and leaves of a narrow region under tuning entry t.
+void apply_tree(Region &r, const TreeTune &t, int acc_f64)
+{
+    int64_t leaves;
+    if (t.kind == TREE_WAVE) {
+        r.wave_tree = true;
+        r.rows_per_leaf = (int64_t)std::max(1, t.leaf_blocks) * tsqr_wave_block_rows(r.np);
+        leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+        r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxWaveLeaves));
+        r.arity = std::max(2, std::min(32, t.arity));
+        return;
+    }
+    r.wave_tree = false;
+    const int br = tsqr_block_rows(r.np, acc_f64);
+    if (t.leaf_blocks > 0) {
+        r.rows_per_leaf = (int64_t)t.leaf_blocks * br;
+    } else {
+        // default rule (measured): leaves of two blocks, lengthened to keep a region at
+        // kLeafTarget leaves (two per compute unit when the two tails share a launch):
+        // shorter leaves add workgroups that wait for a compute unit, longer ones add
+        // sequential column steps
+        const int64_t per_leaf = (r.rows_cap + kLeafTarget - 1) / kLeafTarget;
+        r.rows_per_leaf = std::max<int64_t>(2 * br, (per_leaf + br - 1) / br * br);
+    }
+    leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+    r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxTreeLeaves));
+    r.arity = tsqr_tree_arity(r.np, r.width);
+}
+
+// A region of rows_cap rows reduced by a tree: narrow regions (np <= 64) take the tree
+// kernel and leaf length of the tuning table; their node storage is sized for every
+// candidate the autotuner may switch to, so that the workspace size does not depend on
+// the tuning.  Wide regions take the panel tree with leaves of 4 panel blocks.
+Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int col_off, int acc_f64,
+                   bool batched = false)
 {
     Region r;
     r.name = name;
@@ -224,31 +263,38 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     r.col_off = col_off;
     r.np = tsqr_padded_width(width);
     r.wave = r.np <= 64;
-    const int br = tsqr_block_rows(r.np, acc_f64);
-    // Leaf sizes (fixed through FIGARO_LEAF_BLOCKS / FIGARO_WG_LEAF_BLOCKS).  Narrow trees
-    // (measured): leaves of two blocks, lengthened to keep a region at kLeafTarget leaves
-    // (two per compute unit when the two tails share a launch): shorter leaves add
-    // workgroups that wait for a compute unit, longer ones add sequential column steps.
-    // The wide tree keeps at most one leaf per compute unit and a half.
-    static const int wave_blocks = env_int("FIGARO_LEAF_BLOCKS", 0);
-    static const int wg_blocks = env_int("FIGARO_WG_LEAF_BLOCKS", 4);
-    if (!r.wave) {
-        r.rows_per_leaf = (int64_t)wg_blocks * br;
-    } else if (wave_blocks > 0) {
-        r.rows_per_leaf = (int64_t)wave_blocks * br;
-    } else {
-        const int64_t per_leaf = (r.rows_cap + kLeafTarget - 1) / kLeafTarget;
-        r.rows_per_leaf = std::max<int64_t>(2 * br, (per_leaf + br - 1) / br * br);
-    }
-    const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
-    r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, r.wave ? kMaxTreeLeaves : kMaxPanelLeaves));
     r.ncounters = 0;
     r.skip = false;
-    r.arity = r.wave ? tsqr_tree_arity(r.np, width) : 2;
+    if (!r.wave) {
+        r.wave_tree = false;
+        r.rows_per_leaf = (int64_t)4 * tsqr_block_rows(r.np, acc_f64);
+        const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+        r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxPanelLeaves));
+        r.arity = 2;
+        tsqr_panel_tree_sizes(r.leaves, &r.nslots, &r.ncnt);
+        return r;
+    }
+    const TuneKey key{acc_f64, r.np, batched ? 1 : 0, rows_log2(r.rows_cap)};
+    std::vector<TreeTune> cands = tune_candidates(key);
+    cands.push_back(tune_default(key));
+    r.nslots = r.ncnt = 0;
+    for (const TreeTune &t : cands) {
+        Region c = r;
+        apply_tree(c, t, acc_f64);
+        int64_t ns = 0, nc = 0;
+        tsqr_tree_sizes(c.leaves, c.arity, &ns, &nc);
+        r.nslots = std::max(r.nslots, ns);
+        r.ncnt = std::max(r.ncnt, nc);
+    }
+    apply_tree(r, tune_get(key), acc_f64);
+    int64_t ns = 0, nc = 0;
+    tsqr_tree_sizes(r.leaves, r.arity, &ns, &nc);
+    r.nslots = std::max(r.nslots, ns);
+    r.ncnt = std::max(r.ncnt, nc);
     return r;
 }
 
-Layout make_layout(const Shape &s)
+Layout make_layout(const Shape &s, bool batched = false)
 {
     Layout L;
     size_t off = 0;
@@ -294,17 +340,17 @@ Layout make_layout(const Shape &s)
     }
     const int N = (int)s.N();
     if (!s.two_sided) {
-        Region a = make_region("tsqr_m1", s.m1, CNT_R1, N, 0, L.m_f64);
-        Region b = make_region("tsqr_m2", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64);
+        Region a = make_region("tsqr_m1", s.m1, CNT_R1, N, 0, L.m_f64, batched);
+        Region b = make_region("tsqr_m2", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64, batched);
         a.buf = take(esz * std::max<int64_t>(1, a.rows_cap) * N);
         b.buf = take(esz * std::max<int64_t>(1, b.rows_cap) * s.n2);
         L.regions = {a, b};
     } else {
-        Region h = make_region("tsqr_heads", L.gcap, CNT_G, N, 0, L.m_f64);
+        Region h = make_region("tsqr_heads", L.gcap, CNT_G, N, 0, L.m_f64, batched);
         // Cartesian product: a single head row, absorbed by the root merge itself.
         h.skip = !s.keyed;
-        Region ta = make_region("tsqr_ta", s.m1 - 1, CNT_TA, (int)s.n1, 0, L.m_f64);
-        Region tb = make_region("tsqr_tb", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64);
+        Region ta = make_region("tsqr_ta", s.m1 - 1, CNT_TA, (int)s.n1, 0, L.m_f64, batched);
+        Region tb = make_region("tsqr_tb", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64, batched);
         h.buf = take(esz * h.rows_cap * N);
         ta.buf = take(esz * std::max<int64_t>(1, ta.rows_cap) * s.n1);
         tb.buf = take(esz * std::max<int64_t>(1, tb.rows_cap) * s.n2);
@@ -313,9 +359,7 @@ Layout make_layout(const Shape &s)
     int64_t ctot = 0;
     for (Region &r : L.regions) {
         const size_t tsz = sizeof(double) * (size_t)r.width * r.np;
-        int64_t ns = 0, nc = 0;
-        if (r.wave) tsqr_tree_sizes(r.leaves, r.arity, &ns, &nc);
-        else tsqr_panel_tree_sizes(r.leaves, &ns, &nc);
+        const int64_t ns = r.nslots, nc = r.ncnt;
         r.slots = take(tsz * ns);
         r.ncounters = nc;
         r.counters = (size_t)ctot;  // index into the shared counter block
@@ -496,14 +540,15 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
         int n = 1;
         const char *name = r.name;
         for (size_t j = i + 1; j < nr && n < 2; j++) {
-            if (!done[j] && !L.regions[j].skip && L.regions[j].np == r.np) {
+            if (!done[j] && !L.regions[j].skip && L.regions[j].np == r.np &&
+                L.regions[j].wave_tree == r.wave_tree) {
                 tr[n++] = tree_region(L.regions[j], L, ws);
                 done[j] = true;
                 name = "tsqr_tails";
             }
         }
         Stage st(name, s);
-        if (r.wave) HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr tree");
+        if (r.wave) HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s, r.wave_tree), "tsqr tree");
         else HIPCHK(launch_tsqr_panel_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr panel tree");
     }
     return FIGARO_OK;
@@ -1036,14 +1081,14 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
     }
 
     // 4. trees: narrow regions batched by padded width, wide ones per region
-    std::map<int, std::vector<TreeRegion>> tree_cls;
+    std::map<std::pair<int, int>, std::vector<TreeRegion>> tree_cls;
     for (size_t i = 0; i < count; i++) {
         const Layout &L = plan->layouts[i];
         void *lws = slice(i);
         for (const Region &r : L.regions) {
             if (r.skip || r.rows_cap == 0) continue;
             if (r.wave) {
-                tree_cls[r.np].push_back(tree_region(r, L, lws));
+                tree_cls[{r.np, r.wave_tree ? 1 : 0}].push_back(tree_region(r, L, lws));
             } else {
                 const TreeRegion tr = tree_region(r, L, lws);
                 const int np = r.np;
@@ -1063,12 +1108,12 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
             for (int l = 0; l < regs[j].nleaves; l++) map.push_back(make_int2(j, l));
         const size_t ro = P.img.add(regs), mo = P.img.add(map);
         const int64_t nb = (int64_t)map.size();
-        const int np = kv.first;
+        const int np = kv.first.first, wave_tree = kv.first.second;
         const char *name = class_name(kTreeNames, np);
         P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
             Stage st(name, s);
-            HIPCHK(launch_tsqr_tree_batch(np, acc, m_f64, (const TreeRegion *)(t + ro), (const int2 *)(t + mo), nb,
-                                          s),
+            HIPCHK(launch_tsqr_tree_batch(wave_tree, np, acc, m_f64, (const TreeRegion *)(t + ro),
+                                          (const int2 *)(t + mo), nb, s),
                    "batched tsqr tree");
             return FIGARO_OK;
         });
@@ -1174,7 +1219,7 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
             delete p;
             return fail(FIGARO_EINVAL, "plan instances need n1 + n2 <= 128 in this build");
         }
-        Layout L = make_layout(sh);
+        Layout L = make_layout(sh, true);
         p->inst.push_back(inst[i]);
         p->shapes.push_back(sh);
         p->ws_off.push_back(off);
@@ -1295,6 +1340,186 @@ int figaro_plan_execute_eager(figaro_plan *plan, void *ws, size_t ws_bytes, doub
     rc = plan_exec(plan, ws, R, sigma, prog, &ex);
     if (rc) return rc;
     return run_program(prog, ex->tables, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------ autotuning
+//
+// For each class of narrow regions (same accumulation type and padded width) the
+// candidates of the tuning table are timed on the caller's own problem: the launches
+// run eagerly with stage events (one warm-up, then three timed runs), the class's tree
+// stage is read, and the fastest candidate becomes the table entry of every row count the
+// class holds.  Tuning allocates (launch tables) and synchronises; it changes neither
+// workspace sizes nor results beyond rounding order.
+}  // extern "C"
+
+namespace {
+
+struct TimingGuard {
+    bool was;
+    TimingGuard() : was(g_timing.on.load()) { g_timing.on.store(true); }
+    ~TimingGuard() { g_timing.on.store(was); }
+};
+
+// Milliseconds of the recorded stages accepted by `want`, summed; every record is consumed.
+template <typename F>
+int take_stage_ms(F want, double *ms)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    double tot = 0.0;
+    for (auto &r : g_timing.recs) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "tuning sync");
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "tuning elapsed");
+        if (want(r.name)) tot += t;
+        g_timing.pool.push_back(r.a);
+        g_timing.pool.push_back(r.b);
+    }
+    g_timing.recs.clear();
+    *ms = tot;
+    return FIGARO_OK;
+}
+
+constexpr int kTuneReps = 3;
+
+void plan_drop_execs(figaro_plan *plan)
+{
+    for (auto &kv : plan->execs) {
+        if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
+        if (kv.second.tables) (void)hipFree(kv.second.tables);
+    }
+    plan->execs.clear();
+}
+
+void plan_relayout(figaro_plan *plan)
+{
+    for (size_t i = 0; i < plan->inst.size(); i++) plan->layouts[i] = make_layout(plan->shapes[i], true);
+}
+
+}  // namespace
+
+extern "C" {
+
+int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma, void *stream)
+{
+    int rc = plan_check(plan, ws, ws_bytes, R, sigma);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int acc = plan->shapes[0].precision == FIGARO_PLAIN_FP64;
+    // classes: padded width -> the row counts (log2) of its regions
+    std::map<int, std::vector<int>> cls;
+    for (const Layout &L : plan->layouts)
+        for (const Region &r : L.regions)
+            if (r.wave && !r.skip && r.rows_cap > 0) cls[r.np].push_back(rows_log2(r.rows_cap));
+    plan_drop_execs(plan);
+    TimingGuard tg;
+    for (auto &kv : cls) {
+        const int np = kv.first;
+        const TuneKey key{acc, np, 1, 0};
+        const char *stage = class_name(kTreeNames, np);
+        double best_ms = 1e300;
+        TreeTune best = tune_default(key);
+        for (const TreeTune &cand : tune_candidates(key)) {
+            tune_override(&key, &cand);
+            plan_relayout(plan);
+            const Program prog = build_program(plan, ws, R, sigma);
+            figaro_plan::Exec *ex = nullptr;
+            rc = plan_exec(plan, ws, R, sigma, prog, &ex);
+            if (!rc) rc = run_program(prog, ex->tables, s);  // warm-up
+            double ms = 0.0;
+            if (!rc) rc = take_stage_ms([](const char *) { return false; }, &ms);
+            for (int i = 0; i < kTuneReps && !rc; i++) rc = run_program(prog, ex->tables, s);
+            if (!rc) rc = take_stage_ms([stage](const char *n) { return std::strcmp(n, stage) == 0; }, &ms);
+            plan_drop_execs(plan);
+            if (rc) {
+                tune_override(nullptr, nullptr);
+                plan_relayout(plan);
+                return rc;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+        }
+        tune_override(nullptr, nullptr);
+        for (int l : kv.second) tune_set(TuneKey{acc, np, 1, l}, best, best_ms / kTuneReps);
+    }
+    plan_relayout(plan);
+    return FIGARO_OK;
+}
+
+int figaro_r_autotune(const figaro_table *A, const figaro_table *B, int32_t precision, double *R, int64_t ldr,
+                      void *ws, size_t ws_bytes, void *stream)
+{
+    Shape sh;
+    int rc = make_shape(A, B, precision, &sh);
+    if (rc) return rc;
+    if (!R) return fail(FIGARO_EINVAL, "R is NULL");
+    if (ldr < sh.N()) return fail(FIGARO_EINVAL, "ldr < n1 + n2");
+    Layout L0 = make_layout(sh);
+    rc = check_ws(L0, ws, ws_bytes);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int acc = sh.precision == FIGARO_PLAIN_FP64;
+    std::map<int, std::vector<int>> cls;
+    for (const Region &r : L0.regions)
+        if (r.wave && !r.skip && r.rows_cap > 0) cls[r.np].push_back(rows_log2(r.rows_cap));
+    TimingGuard tg;
+    auto is_tree = [](const char *n) { return std::strncmp(n, "tsqr_", 5) == 0 && std::strcmp(n, "tsqr_root") != 0; };
+    for (auto &kv : cls) {
+        const int np = kv.first;
+        const TuneKey key{acc, np, 0, 0};
+        double best_ms = 1e300;
+        TreeTune best = tune_default(key);
+        for (const TreeTune &cand : tune_candidates(key)) {
+            tune_override(&key, &cand);
+            const Layout L = make_layout(sh);
+            double ms = 0.0;
+            rc = run_r(A, B, sh, L, R, ldr, ws, s);
+            if (!rc) rc = take_stage_ms([](const char *) { return false; }, &ms);
+            for (int i = 0; i < kTuneReps && !rc; i++) rc = run_r(A, B, sh, L, R, ldr, ws, s);
+            if (!rc) rc = take_stage_ms(is_tree, &ms);
+            if (rc) {
+                tune_override(nullptr, nullptr);
+                return rc;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+        }
+        tune_override(nullptr, nullptr);
+        for (int l : kv.second) tune_set(TuneKey{acc, np, 0, l}, best, best_ms / kTuneReps);
+    }
+    return FIGARO_OK;
+}
+
+int figaro_tune_load(const char *path)
+{
+    if (!path) return fail(FIGARO_EINVAL, "path is NULL");
+    const int n = tune_load(path);
+    if (n < 0) return fail(FIGARO_EINVAL, std::string("cannot read tuning cache ") + path);
+    return FIGARO_OK;
+}
+
+int figaro_tune_save(const char *path)
+{
+    if (!path) return fail(FIGARO_EINVAL, "path is NULL");
+    if (tune_save(path) != 0) return fail(FIGARO_EINVAL, std::string("cannot write tuning cache ") + path);
+    return FIGARO_OK;
+}
+
+int figaro_tune_dump(char *buf, size_t cap, size_t *len)
+{
+    const std::string d = tune_dump();
+    if (len) *len = d.size();
+    if (buf && cap > 0) {
+        const size_t n = std::min(cap - 1, d.size());
+        std::memcpy(buf, d.data(), n);
+        buf[n] = 0;
+    }
+    return FIGARO_OK;
 }
 
 void figaro_plan_destroy(figaro_plan *plan)

@@ -588,6 +588,233 @@ __global__ __launch_bounds__(64 * tree_waves(NP)) void k_tsqr_tree_batch(const T
     tree_leaf<NP, Tin, Tacc, STAGED>(rg, e.y);
 }
 
+// ------------------------------------------------------------------ one wave per triangle (tree)
+//
+// For launches with many more leaves than SIMDs (batches, long regions): each wave owns
+// one triangle, so a column step needs no workgroup barrier and no LDS partial sums.
+// With one row set per wave (NP = 64) the dot products are lane-local and the pivot
+// column comes by lane reads; with several row sets the partial dots meet by lane swaps
+// and the pivot column by a per-wave LDS slot.  The waves of a region then climb a tree
+// of the region's arity as in the workgroup tree (per-node counters, last child combines
+// the children in child order).
+
+constexpr int kWtWaves = 4;  // independent waves per workgroup
+
+// Absorb one block (RPT rows per lane in x) into the wave's triangle, columns [jstart, width).
+template <int NP, typename Tacc>
+__device__ inline void wt_block(Tacc (&x)[WaveGeom<NP>::RPT], Tacc *Rp, Tacc *xb, int k, int h, int jstart,
+                                int width)
+{
+    constexpr int RPT = WaveGeom<NP>::RPT, H = WaveGeom<NP>::H;
+    const bool col_ok = k < width;
+    for (int j = jstart; j < width; j++) {
+        const double alpha = (double)Rp[pidx(NP, j, j)];
+        const Tacc rjk = Rp[pidx(NP, j, (k > j && col_ok) ? k : j)];
+        Tacc xj[RPT];
+        if constexpr (H == 1) {
+#pragma unroll
+            for (int i = 0; i < RPT; i++) xj[i] = readlane_t(x[i], j);
+        } else {
+            __builtin_amdgcn_wave_barrier();
+            if (k == j) {
+#pragma unroll
+                for (int i = 0; i < RPT; i++) xb[i] = x[i];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int i = 0; i < RPT; i++) xj[i] = xb[i];
+        }
+        Tacc dp[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) dp[i] = xj[i] * x[i];
+#pragma unroll
+        for (int i = 8; i < RPT; i++) dp[i & 7] = fma(xj[i], x[i], dp[i & 7]);
+        double d = (double)(((dp[0] + dp[1]) + (dp[2] + dp[3])) + ((dp[4] + dp[5]) + (dp[6] + dp[7])));
+#pragma unroll
+        for (int off = NP; off < 32; off <<= 1) d += __shfl_xor(d, off, 64);
+        if constexpr (H >= 2) d = half_swap_sum(d);
+        const double s = readlane_f64(d, j);
+        const double q = fma(alpha, alpha, s);
+        // A column whose norm is below the normal range is left untouched (tau = 0).
+        const bool ok = s > 0.0 && q >= DBL_MIN;
+        const double r = rsq_refined(ok ? q : 1.0);
+        const double sg = alpha >= 0.0 ? 1.0 : -1.0;
+        const double nrm = q * r;
+        const double beta = -sg * nrm;
+        const double inv_beta = -sg * r;
+        const double scl = rcp_refined(ok ? alpha + sg * nrm : 1.0);
+        const double tau = 1.0 - alpha * inv_beta;
+        const double w = (double)rjk + scl * d;
+        const bool upd = ok && k > j && col_ok;
+        const Tacc c = upd ? (Tacc)(w * inv_beta) : Tacc(0);
+        if (upd) {
+#pragma unroll
+            for (int i = 0; i < RPT; i++) x[i] += c * xj[i];
+        }
+        if (ok && h == 0 && k >= j && col_ok) Rp[pidx(NP, j, k)] = upd ? (Tacc)((double)rjk - tau * w) : (Tacc)beta;
+    }
+}
+
+// Buffer-resource loads: one 32-bit offset register per load, and a load whose offset is
+// at or past the resource's size returns 0.  (Descriptor word 3 of a raw 32-bit buffer on
+// gfx9-family GPUs.)
+constexpr int kBufWord3 = 0x00020000;
+
+template <typename T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+// Absorb rows [r0, r1) of src in blocks of BR rows.  tri_rows > 0: src is a stack of
+// triangles of that many rows (a block inside one skips its known-zero columns).  Each
+// block is read through a buffer resource that starts at its first row and ends at
+// min(r1, block end): rows past r1 and columns outside the source (their offsets are set
+// past the end) load as 0 with no branch or mask, so a block's loads are in flight
+// together.  With FP32 accumulation the next block's loads are issued before the current
+// block's column steps, which hide them.
+template <int NP, typename Tin, typename Tacc, bool PREFETCH>
+__device__ inline void wt_absorb_rows(Tacc *Rp, Tacc *xb, const RowSrc &src, int64_t r0, int64_t r1, int tri_rows,
+                                      int width, int k, int h)
+{
+    constexpr int RPT = WaveGeom<NP>::RPT, BR = WaveGeom<NP>::BR;
+    if (r0 >= r1) return;
+    const int c = k - src.col_off;
+    const bool col_in = k < width && c >= 0 && c < src.width;
+    const uint32_t row_bytes = (uint32_t)(src.ld * (int64_t)sizeof(Tin));
+    const uint32_t lane_off = (uint32_t)(((int64_t)h * RPT * src.ld + (c < 0 ? 0 : c)) * (int64_t)sizeof(Tin));
+    auto load_rows = [&](Tacc (&y)[RPT], int64_t rb) {
+        const uint32_t nrec = (uint32_t)(min(r1 - rb, (int64_t)BR) * (int64_t)row_bytes);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const char *)src.p + rb * (int64_t)row_bytes), (short)0, (int)nrec, kBufWord3);
+        const uint32_t off = col_in ? lane_off : nrec;
+#pragma unroll
+        for (int i = 0; i < RPT; i++) y[i] = (Tacc)buf_load<Tin>(rs, off + (uint32_t)i * row_bytes);
+    };
+    Tacc xn[PREFETCH ? RPT : 1];
+    if constexpr (PREFETCH) load_rows(xn, r0);
+    for (int64_t rb = r0; rb < r1; rb += BR) {
+        Tacc x[RPT];
+        if constexpr (PREFETCH) {
+#pragma unroll
+            for (int i = 0; i < RPT; i++) x[i] = xn[i];
+            if (rb + BR < r1) load_rows(xn, rb + BR);
+        } else {
+            load_rows(x, rb);
+        }
+        int jstart = src.col_off;
+        if (tri_rows > 0) {
+            const int64_t off = rb % tri_rows;
+            if (off + BR <= tri_rows) jstart += (int)off;
+        }
+        wt_block<NP, Tacc>(x, Rp, xb, k, h, jstart, width);
+    }
+}
+
+template <int NP, typename Tacc>
+__device__ inline void wt_load_tri(Tacc *Rp, const double *T, int width, int lane)
+{
+    for (int e = lane; e < WaveGeom<NP>::PS; e += 64) Rp[e] = Tacc(0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (T) {
+        staged_copy<8, double>(
+            width * NP, lane, 64, [&](int e) { return T[e]; },
+            [&](int e, double v) {
+                const int j = e / NP, kk = e - j * NP;
+                if (kk >= j && kk < width) Rp[pidx(NP, j, kk)] = (Tacc)v;
+            });
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// A value the whole wave holds (read from lane 0), so that the compiler keeps it and
+// everything derived from it in scalar registers.
+__device__ inline int64_t wave_uniform(int64_t v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Leaf g of region rg by one wave, then the climb of its tree.
+template <int NP, typename Tin, typename Tacc>
+__device__ __forceinline__ void wt_leaf(const TreeRegion &rg, const int g, Tacc *Rp, Tacc *xbase, int lane)
+{
+    using Gm = WaveGeom<NP>;
+    const int k = lane % NP, h = lane / NP;
+    Tacc *xb = xbase + h * Gm::RPT;
+    const int width = rg.width;
+    const int64_t rows = wave_uniform(src_rows(rg.src));
+    const int64_t want = (rows + rg.rows_per_leaf - 1) / rg.rows_per_leaf;
+    const int nleaves = (int)max((int64_t)1, min((int64_t)rg.nleaves, want));
+    if (g >= nleaves) return;
+    wt_load_tri<NP, Tacc>(Rp, nullptr, width, lane);
+    int64_t chunk = (rows + nleaves - 1) / nleaves;
+    chunk = ((chunk + Gm::BR - 1) / Gm::BR) * Gm::BR;
+    const int64_t r0 = (int64_t)g * chunk, r1 = min(rows, r0 + chunk);
+    wt_absorb_rows<NP, Tin, Tacc, sizeof(Tacc) == 4>(Rp, xb, rg.src, r0, r1, 0, width, k, h);
+
+    const int64_t tsz = (int64_t)width * NP;
+    const int A = rg.arity;
+    int node = g, n = nleaves;
+    int64_t soff = 0, coff = 0;
+    while (n > 1) {
+        const int parent = node / A, first = parent * A;
+        const int nchild = min(A, n - first);
+        if (nchild > 1) {
+            wave_store<NP, Tacc>(Rp, rg.slots + (soff + node) * tsz, width, lane);
+            __threadfence();
+            int old = 0;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(&rg.counters[coff + parent], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            old = __builtin_amdgcn_readfirstlane(old);  // lane 0's value, uniform in the wave
+            if (old != nchild - 1) return;  // the last child to arrive combines this node
+            __threadfence();
+            // R <- first child; absorb the others, stacked in child order.
+            wt_load_tri<NP, Tacc>(Rp, rg.slots + (soff + first) * tsz, width, lane);
+            const RowSrc sib{rg.slots + (soff + first + 1) * tsz, nullptr, (int64_t)(nchild - 1) * width, NP, 0,
+                             width};
+            wt_absorb_rows<NP, double, Tacc, false>(Rp, xb, sib, 0, sib.rows_host, width, width, k, h);
+        }
+        node = parent;
+        soff += n;
+        coff += (n + A - 1) / A;
+        n = (n + A - 1) / A;
+    }
+    wave_store<NP, Tacc>(Rp, rg.root, width, lane);
+}
+
+// The regions of a batch by waves (device table): wave item of the grid is leaf map[item].y
+// of region map[item].x; surplus waves of the last workgroup leave at once (no workgroup
+// barrier follows).
+template <int NP, typename Tin, typename Tacc>
+__global__ __launch_bounds__(64 * kWtWaves) void k_tsqr_wtree_batch(const TreeRegion *__restrict__ regs,
+                                                                    const int2 *__restrict__ map, int64_t nitems)
+{
+    using Gm = WaveGeom<NP>;
+    __shared__ Tacc Rs[kWtWaves][Gm::PS];
+    __shared__ __align__(16) Tacc Xs[kWtWaves][Gm::BR];
+    // the wave index is uniform in each wave; say so, so that everything derived from it
+    // (the item, its region descriptor, the buffer resources) lives in scalar registers
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t item = (int64_t)blockIdx.x * kWtWaves + wv;
+    if (item >= nitems) return;
+    const int2 e = map[item];
+    const TreeRegion rg = regs[e.x];
+    wt_leaf<NP, Tin, Tacc>(rg, e.y, Rs[wv], Xs[wv], lane);
+}
+
 __global__ void k_sign_normalise(const double *Rin, int64_t ldin, int n, double *R, int64_t ldr)
 {
     // one wave per row
@@ -660,13 +887,49 @@ hipError_t launch_tree_np(int acc_f64, int in_f64, const TreeRegion *regs, int n
     return hipGetLastError();
 }
 
-template <int NP>
-hipError_t launch_tree_batch_np(int acc_f64, int in_f64, const TreeRegion *regs, const int2 *map, int64_t nblocks,
-                                hipStream_t s)
+// One or two regions by waves (a single call): wave item i < reg0.nleaves is leaf i of
+// region 0, the rest leaves of region 1.
+template <int NP, typename Tin, typename Tacc>
+__global__ __launch_bounds__(64 * kWtWaves) void k_tsqr_wtree(TreeRegion reg0, TreeRegion reg1)
 {
-    const unsigned grid = (unsigned)nblocks;
-#define FIGARO_TREE(TI, TA) \
-    k_tsqr_tree_batch<NP, TI, TA, false><<<grid, 64 * tree_waves(NP), 0, s>>>(regs, map)
+    using Gm = WaveGeom<NP>;
+    __shared__ Tacc Rs[kWtWaves][Gm::PS];
+    __shared__ __align__(16) Tacc Xs[kWtWaves][Gm::BR];
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int item = (int)blockIdx.x * kWtWaves + wv;
+    if (item >= reg0.nleaves + reg1.nleaves) return;
+    const bool second = item >= reg0.nleaves;
+    wt_leaf<NP, Tin, Tacc>(second ? reg1 : reg0, item - (second ? reg0.nleaves : 0), Rs[wv], Xs[wv], lane);
+}
+
+template <int NP>
+hipError_t launch_wtree_np(int acc_f64, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s)
+{
+    TreeRegion r0 = regs[0];
+    TreeRegion r1 = nreg > 1 ? regs[1] : TreeRegion{};
+    const unsigned grid = (unsigned)((r0.nleaves + r1.nleaves + kWtWaves - 1) / kWtWaves);
+#define FIGARO_TREE(TI, TA) k_tsqr_wtree<NP, TI, TA><<<grid, 64 * kWtWaves, 0, s>>>(r0, r1)
+    if (acc_f64) {
+        if (in_f64) FIGARO_TREE(double, double);
+        else FIGARO_TREE(float, double);
+    } else {
+        if (in_f64) FIGARO_TREE(double, float);
+        else FIGARO_TREE(float, float);
+    }
+#undef FIGARO_TREE
+    return hipGetLastError();
+}
+
+template <int NP>
+hipError_t launch_tree_batch_np(int wave_tree, int acc_f64, int in_f64, const TreeRegion *regs, const int2 *map,
+                                int64_t nitems, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(wave_tree ? (nitems + kWtWaves - 1) / kWtWaves : nitems);
+#define FIGARO_TREE(TI, TA)                                                                              \
+    do {                                                                                                 \
+        if (wave_tree) k_tsqr_wtree_batch<NP, TI, TA><<<grid, 64 * kWtWaves, 0, s>>>(regs, map, nitems);  \
+        else k_tsqr_tree_batch<NP, TI, TA, false><<<grid, 64 * tree_waves(NP), 0, s>>>(regs, map);        \
+    } while (0)
     if (acc_f64) {
         if (in_f64) FIGARO_TREE(double, double);
         else FIGARO_TREE(float, double);
@@ -680,14 +943,14 @@ hipError_t launch_tree_batch_np(int acc_f64, int in_f64, const TreeRegion *regs,
 
 }  // namespace
 
-hipError_t launch_tsqr_tree_batch(int np, int acc_f64, int in_f64, const TreeRegion *regs, const int2 *map,
-                                  int64_t nblocks, hipStream_t s)
+hipError_t launch_tsqr_tree_batch(int wave_tree, int np, int acc_f64, int in_f64, const TreeRegion *regs,
+                                  const int2 *map, int64_t nitems, hipStream_t s)
 {
-    if (nblocks == 0) return hipSuccess;
-    if (nblocks > INT32_MAX) return hipErrorInvalidValue;
+    if (nitems == 0) return hipSuccess;
+    if (nitems > INT32_MAX) return hipErrorInvalidValue;
     switch (np) {
 #define FIGARO_CASE(NPV) \
-    case NPV: return launch_tree_batch_np<NPV>(acc_f64, in_f64, regs, map, nblocks, s);
+    case NPV: return launch_tree_batch_np<NPV>(wave_tree, acc_f64, in_f64, regs, map, nitems, s);
     FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64)
 #undef FIGARO_CASE
     default: return hipErrorInvalidValue;
@@ -707,6 +970,8 @@ int tsqr_block_rows(int np, int acc_f64)
     if (np <= 64) return tree_waves(np) * wave_block_rows(np);  // tree kernel: waves x row sets x rows per lane
     return tsqr_panel_rows(np, acc_f64);                   // workgroup panel kernel
 }
+
+int tsqr_wave_block_rows(int np) { return wave_block_rows(np); }
 
 int tsqr_tree_arity(int np, int width)
 {
@@ -742,12 +1007,13 @@ hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *ini
 }
 
 hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
-                            hipStream_t s)
+                            hipStream_t s, int wave_tree)
 {
     if (nreg < 1 || nreg > 2) return hipErrorInvalidValue;
     switch (np) {
 #define FIGARO_CASE(NPV) \
-    case NPV: return launch_tree_np<NPV>(acc_f64, in_f64, regs, nreg, s);
+    case NPV: return wave_tree ? launch_wtree_np<NPV>(acc_f64, in_f64, regs, nreg, s) \
+                               : launch_tree_np<NPV>(acc_f64, in_f64, regs, nreg, s);
     FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64)
 #undef FIGARO_CASE
     default: return hipErrorInvalidValue;

@@ -154,3 +154,31 @@ def test_plan_host_checks():
     bad = (fg.Instance * 1)()
     bad[0].A, bad[0].B = table(10, 3, ld=1), table(12, 2)
     assert L.figaro_plan_create(bad, 1, 0, ctypes.byref(h)) == fg.FIGARO_EINVAL
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    """The tuning cache (host only): entries load, malformed or foreign lines are skipped,
+    the table saves and reloads, and workspace sizes do not depend on the table."""
+    A, B = table(200000, 32), table(150000, 32)
+    before = {p: ws_size(A, B, p)[1] for p in (0, 1, 0x100, 0x101)}
+    path = tmp_path / "tune.jsonl"
+    good = ('{"arch":"gfx950","acc_f64":0,"np":32,"batched":0,"rows_log2":18,"kind":1,'
+            '"leaf_blocks":16,"arity":2,"ms":0.5}')
+    lines = [good,
+             '{"arch":"gfx942","acc_f64":0,"np":32,"batched":0,"rows_log2":18,"kind":1,"leaf_blocks":8,"arity":2}',
+             '{"arch":"gfx950","acc_f64":0,"np":32,"batched":0,"rows_log2":17,"kind":5,"leaf_blocks":8,"arity":2}',
+             'not json']
+    path.write_text("\n".join(lines) + "\n")
+    assert fg.lib().figaro_tune_load(os.fsencode(str(path))) == 0
+    tab = fg.tune_table()
+    mine = [e for e in tab if e["np"] == 32 and e["batched"] == 0 and e["acc_f64"] == 0]
+    assert any(e["rows_log2"] == 18 and e["kind"] == 1 and e["leaf_blocks"] == 16 for e in mine)
+    assert not any(e["rows_log2"] == 17 for e in mine)
+    out = tmp_path / "saved.jsonl"
+    assert fg.lib().figaro_tune_save(os.fsencode(str(out))) == 0
+    saved = out.read_text().splitlines()
+    assert any('"rows_log2":18' in line and '"leaf_blocks":16' in line for line in saved)
+    assert fg.lib().figaro_tune_load(os.fsencode(str(out))) == 0
+    assert fg.lib().figaro_tune_load(os.fsencode(str(tmp_path / "missing.jsonl"))) == fg.FIGARO_EINVAL
+    after = {p: ws_size(A, B, p)[1] for p in (0, 1, 0x100, 0x101)}
+    assert before == after

@@ -1,0 +1,95 @@
+"""The tuned tree variants against the oracle: single calls reduced by the wave tree, and
+plans and single calls after the autotuner has timed its candidates on them."""
+import numpy as np
+import pytest
+
+import oracle
+from bruteforce import relF
+from test_gpu_parity import CASES, dev, fg, mixed_plan_instances, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def cache_lines(kind, leaf_blocks, arity, batched):
+    out = []
+    for acc in (0, 1):
+        for np_ in (4, 8, 16, 32, 64):
+            for rl in range(0, 41):
+                out.append(f'{{"arch":"gfx950","acc_f64":{acc},"np":{np_},"batched":{batched},"rows_log2":{rl},'
+                           f'"kind":{kind},"leaf_blocks":{leaf_blocks},"arity":{arity},"ms":0}}')
+    return "\n".join(out) + "\n"
+
+
+@pytest.fixture
+def wave_tree_single_calls(tmp_path):
+    path = tmp_path / "wave.jsonl"
+    path.write_text(cache_lines(1, 4, 2, 0))
+    fg().tune_load(str(path))
+    yield
+    back = tmp_path / "wg.jsonl"
+    back.write_text(cache_lines(0, 0, 0, 0))
+    fg().tune_load(str(back))
+
+
+@pytest.mark.parametrize("name", ["cart_ragged", "keyed_zipf_n64", "keyed_uniform_sparse", "cart_tail_leaf",
+                                  "keyed_singleton_B", "cart_n125_ragged"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_single_call_wave_tree(wave_tree_single_calls, name, prec, two_sided):
+    inst = CASES[name]
+    say(f"[wave tree] {name} {prec} two_sided={two_sided}")
+    A, B, kA, kB = to_dev(inst)
+    R, ws = fg().r(A, B, kA, kB, prec, two_sided=two_sided)
+    S = fg().sigma(R)
+    torch.cuda.synchronize()
+    assert fg().status(ws) == 0
+    Ro = oracle.r(inst)
+    So = oracle.sigma(Ro)
+    er = relF(R.cpu().numpy(), Ro)
+    es = np.linalg.norm(S.cpu().numpy() - So) / np.linalg.norm(So)
+    say(f"    relF(R)={er:.3e} rel2(sigma)={es:.3e}")
+    assert er <= TOL[prec] and es <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_r_autotune_then_parity(prec):
+    inst = CASES["keyed_zipf_n64"]
+    A, B, kA, kB = to_dev(inst)
+    fg().r_autotune(A, B, kA, kB, prec, two_sided=True)
+    R, ws = fg().r(A, B, kA, kB, prec, two_sided=True)
+    torch.cuda.synchronize()
+    er = relF(R.cpu().numpy(), oracle.r(inst))
+    assert er <= TOL[prec]
+    assert any(e["batched"] == 0 for e in fg().tune_table())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plan_autotune_then_parity(prec):
+    insts = mixed_plan_instances()
+    tens = [to_dev(i) for i in insts]
+    plan = fg().Plan(tens, prec, two_sided=True)
+    d = dev()
+    ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=d)
+    R = torch.zeros(plan.r_total, dtype=torch.float64, device=d)
+    S = torch.zeros(plan.s_total, dtype=torch.float64, device=d)
+    plan.execute(ws, R, S)
+    plan.autotune(ws, R, S)
+    for rep in range(2):
+        R.fill_(3.0)
+        S.fill_(3.0)
+        plan.execute(ws, R, S)
+        torch.cuda.synchronize()
+        Rh, Sh = R.cpu().numpy(), S.cpu().numpy()
+        for i, inst in enumerate(insts):
+            N = inst.A.shape[1] + inst.B.shape[1]
+            Rg = Rh[plan.r_off[i]:plan.r_off[i] + N * N].reshape(N, N)
+            Ro = oracle.r(inst)
+            if not np.any(Ro):
+                assert not np.any(Rg)
+                continue
+            assert relF(Rg, Ro) <= TOL[prec], (rep, i)
+    assert any(e["batched"] == 1 for e in fg().tune_table())
