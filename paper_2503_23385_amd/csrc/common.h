@@ -241,6 +241,40 @@ hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int 
 // and Y (N x N each), partial (partial_cap doubles, at least refine_partial_elems), failed
 // (one int: 1 when X was not positive definite, then R = R~).
 int64_t refine_partial_elems(int64_t n1, int64_t n2);
+// One block of the closed-form Gram matrix (A^T A weighted, B^T B weighted, or the cross
+// block), reduced over row chunks into per-chunk partials and then summed in a fixed order.
+struct GramJob {
+    const void *X;
+    int64_t ld;
+    int32_t m, nx, ny, mode, in_f64;
+    const int32_t *off, *size, *other;
+    const int64_t *Gp;
+    int32_t cartesian;
+    const double *hB;
+    int32_t gx, gy, nch;
+    int64_t rows_per_chunk;
+    double *partial;
+    double *gram;
+    int32_t ldg, row0, col0, mirror;
+};
+// The three Gram jobs of one problem (partial: refine_partial_elems doubles); returns 3.
+int gram_jobs(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B, int64_t ldb, int64_t m2,
+              int n2, Groups g, int cartesian, const double *hB, double *partial, double *gram, GramJob *jobs);
+// A batch of Gram jobs of one input type: tile_map[b] = (job, ti, tj, chunk), red_map[b] =
+// (job, block of 256 entries).
+hipError_t launch_gram_batch(int in_f64, const GramJob *jobs, const int4 *tile_map, int64_t ntiles,
+                             const int2 *red_map, int64_t nred, hipStream_t s);
+// The N x N part of the sweep (N <= 128) for a batch of instances, one workgroup each
+// (after their Gram matrices are formed).
+struct RefineSmall {
+    const double *gram, *Rt;
+    int32_t ldt, n;
+    double *Y;
+    int32_t *failed;
+    double *R;
+    int64_t ldr;
+};
+hipError_t launch_refine_small_batch(const RefineSmall *tab, int count, hipStream_t s);
 hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B,
                          int64_t ldb, int64_t m2, int n2, Groups g, int cartesian, const double *hB,
                          const double *Rt, int ldt, double *gram, double *Y, double *partial,

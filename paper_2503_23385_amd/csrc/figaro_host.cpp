@@ -576,8 +576,10 @@ bool cartesian_root(const Shape &sh, const Layout &L)
 
 // Everything after the regions' trees: the merge of their triangles, the row signs and
 // the refinement sweep.
+// refine = false: the refined forms leave R~ (signs normalised) in the workspace for a
+// batched refinement sweep.
 int run_root(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
-             int64_t ldr, void *ws, hipStream_t s)
+             int64_t ldr, void *ws, hipStream_t s, bool refine = true)
 {
     const int N = (int)sh.N();
     if (cartesian_root(sh, L)) {
@@ -590,7 +592,7 @@ int run_root(const figaro_table *A, const figaro_table *B, const Shape &sh, cons
                                           L.refine ? at<double>(ws, L.rt) : R, L.refine ? N : ldr, s),
                    "cartesian root merge");
         }
-        return L.refine ? run_refine(A, B, sh, L, R, ldr, ws, s) : FIGARO_OK;
+        return L.refine && refine ? run_refine(A, B, sh, L, R, ldr, ws, s) : FIGARO_OK;
     }
     // Merge in FP64.
     const Region &r0 = L.regions[0];
@@ -638,7 +640,7 @@ int run_root(const figaro_table *A, const figaro_table *B, const Shape &sh, cons
         Stage st("sign", s);
         HIPCHK(launch_sign_normalise(cur, 1, cur_ld, N, at<double>(ws, L.rt), N, s), "sign normalisation");
     }
-    return run_refine(A, B, sh, L, R, ldr, ws, s);
+    return refine ? run_refine(A, B, sh, L, R, ldr, ws, s) : FIGARO_OK;
 }
 
 int run_r(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
@@ -1136,7 +1138,7 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
         } else {
             const figaro_instance *in = &plan->inst[i];
             P.steps.push_back([in, sh, &L, Ri, N, lws](const unsigned char *, hipStream_t s) {
-                return run_root(&in->A, &in->B, sh, L, Ri, N, lws, s);
+                return run_root(&in->A, &in->B, sh, L, Ri, N, lws, s, false);
             });
         }
     }
@@ -1150,17 +1152,56 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
             return FIGARO_OK;
         });
     }
-    // refinement of the batched roots (the others refine inside run_root)
+    // refinement sweep of every instance (refined forms): the Gram blocks of all instances
+    // in one tile launch and one reduce launch per input type, then one workgroup per
+    // instance for the N x N part
+    std::vector<GramJob> gjobs[2];
+    std::vector<RefineSmall> smalls;
     for (size_t i = 0; i < count; i++) {
         const Shape &sh = plan->shapes[i];
         const Layout &L = plan->layouts[i];
-        if (!L.refine || !cartesian_root(sh, L)) continue;
-        const figaro_instance *in = &plan->inst[i];
+        if (!L.refine) continue;
         void *lws = slice(i);
-        double *Ri = R + plan->r_off[i];
-        const int64_t N = sh.N();
-        P.steps.push_back([in, sh, &L, Ri, N, lws](const unsigned char *, hipStream_t s) {
-            return run_refine(&in->A, &in->B, sh, L, Ri, N, lws, s);
+        const figaro_instance *in = &plan->inst[i];
+        GramJob j3[3];
+        gram_jobs(in->A.data, sh.in_f64, sh.lda, sh.m1, (int)sh.n1, in->B.data, sh.ldb, sh.m2, (int)sh.n2,
+                  groups_of(lws, L), !sh.keyed, at<double>(lws, L.headsB), at<double>(lws, L.partial),
+                  at<double>(lws, L.gram), j3);
+        for (const GramJob &J : j3) gjobs[sh.in_f64].push_back(J);
+        const int N = (int)sh.N();
+        smalls.push_back(RefineSmall{at<double>(lws, L.gram), at<double>(lws, L.rt), N, N, at<double>(lws, L.gy),
+                                     at<int32_t>(lws, L.failed), R + plan->r_off[i], N});
+    }
+    for (int f = 0; f < 2; f++) {
+        const std::vector<GramJob> &jobs = gjobs[f];
+        if (jobs.empty()) continue;
+        std::vector<int4> tiles;
+        std::vector<int2> reds;
+        for (int j = 0; j < (int)jobs.size(); j++) {
+            const GramJob &J = jobs[j];
+            for (int ti = 0; ti < J.gx; ti++)
+                for (int tj = 0; tj < J.gy; tj++)
+                    for (int c = 0; c < J.nch; c++) tiles.push_back(make_int4(j, ti, tj, c));
+            const int64_t out = (int64_t)J.nx * (J.mode == 0 ? J.nx : J.ny);
+            for (int64_t b = 0; b < (out + 255) / 256; b++) reds.push_back(make_int2(j, (int)b));
+        }
+        const size_t jo = P.img.add(jobs), to = P.img.add(tiles), ro = P.img.add(reds);
+        const int64_t nt = (int64_t)tiles.size(), nr = (int64_t)reds.size();
+        P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+            Stage st("refine_gram", s);
+            HIPCHK(launch_gram_batch(f, (const GramJob *)(t + jo), (const int4 *)(t + to), nt, (const int2 *)(t + ro),
+                                     nr, s),
+                   "batched gram");
+            return FIGARO_OK;
+        });
+    }
+    if (!smalls.empty()) {
+        const size_t off = P.img.add(smalls);
+        const int n = (int)smalls.size();
+        P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+            Stage st("refine_solve", s);
+            HIPCHK(launch_refine_small_batch((const RefineSmall *)(t + off), n, s), "batched refinement");
+            return FIGARO_OK;
         });
     }
 

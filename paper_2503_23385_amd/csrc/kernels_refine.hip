@@ -37,21 +37,20 @@ __device__ inline int group_of_row(const int32_t *off, const int32_t *size, int 
     return -1;
 }
 
+// One output tile (ti, tj) of a Gram block over one chunk of rows:
 // mode 0: C += w_r X_r^T X_r over rows of X (w_r = other[g(r)], the other table's group size)
 // mode 1: C += X_r^T (sqrt(other[g]) hB[g]) over rows of X (the cross block, X = A)
-template <typename Tin, int MODE>
-__global__ __launch_bounds__(256) void k_gram_tile(const Tin *__restrict__ X, int64_t ldx, int m, int nx,
-                                                   const int32_t *off, const int32_t *size,
-                                                   const int32_t *other, const int64_t *Gp,
-                                                   int cartesian, const double *__restrict__ hB, int ny,
-                                                   int64_t rows_per_chunk, double *__restrict__ partial)
+template <typename Tin>
+__device__ __forceinline__ void gram_tile(const GramJob &J, int ti, int tj, int chunk)
 {
-    const int ti = blockIdx.x, tj = blockIdx.y, chunk = blockIdx.z;
+    const Tin *__restrict__ X = (const Tin *)J.X;
+    const int64_t ldx = J.ld;
+    const int m = J.m, nx = J.nx, ny = J.ny, mode = J.mode;
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;  // 16 x 16 threads, 4 x 4 outputs each
-    const int G = (int)*Gp;
-    const int64_t r0 = (int64_t)chunk * rows_per_chunk;
-    const int64_t r1 = min((int64_t)m, r0 + rows_per_chunk);
+    const int G = (int)*J.Gp;
+    const int64_t r0 = (int64_t)chunk * J.rows_per_chunk;
+    const int64_t r1 = min((int64_t)m, r0 + J.rows_per_chunk);
     __shared__ double xi[kRowsPerStage][kTile];
     __shared__ double yj[kRowsPerStage][kTile];
     __shared__ int grp[kRowsPerStage];
@@ -59,7 +58,7 @@ __global__ __launch_bounds__(256) void k_gram_tile(const Tin *__restrict__ X, in
     for (int64_t rb = r0; rb < r1; rb += kRowsPerStage) {
         if (tid < kRowsPerStage) {
             const int64_t s = rb + tid;
-            grp[tid] = s >= r1 ? -1 : cartesian ? (G > 0 ? 0 : -1) : group_of_row(off, size, G, s);
+            grp[tid] = s >= r1 ? -1 : J.cartesian ? (G > 0 ? 0 : -1) : group_of_row(J.off, J.size, G, s);
         }
         __syncthreads();
         // stage rows: i-columns of X, j-columns of X (weighted) or of the group's B sum
@@ -73,10 +72,10 @@ __global__ __launch_bounds__(256) void k_gram_tile(const Tin *__restrict__ X, in
                 if (g >= 0) {
                     const int ci = ti * kTile + c, cj = tj * kTile + c;
                     if (ci < nx) vi = (double)X[s * ldx + ci];
-                    if (MODE == 0) {
-                        if (cj < nx) vj = (double)other[g] * (double)X[s * ldx + cj];
+                    if (mode == 0) {
+                        if (cj < nx) vj = (double)J.other[g] * (double)X[s * ldx + cj];
                     } else {
-                        if (cj < ny) vj = sqrt((double)other[g]) * hB[(int64_t)g * ny + cj];
+                        if (cj < ny) vj = sqrt((double)J.other[g]) * J.hB[(int64_t)g * ny + cj];
                     }
                 }
             }
@@ -99,8 +98,8 @@ __global__ __launch_bounds__(256) void k_gram_tile(const Tin *__restrict__ X, in
         }
         __syncthreads();
     }
-    const int NY = MODE == 0 ? nx : ny;
-    double *out = partial + (int64_t)chunk * nx * NY;
+    const int NY = mode == 0 ? nx : ny;
+    double *out = J.partial + (int64_t)chunk * nx * NY;
 #pragma unroll
     for (int u = 0; u < 4; u++)
 #pragma unroll
@@ -110,17 +109,46 @@ __global__ __launch_bounds__(256) void k_gram_tile(const Tin *__restrict__ X, in
         }
 }
 
-// Gram(N x N) block at (row0, col0) (+ its transpose when `mirror`) = sum of chunks, fixed order.
-__global__ void k_gram_reduce(const double *__restrict__ partial, int nchunks, int rows, int cols,
-                              double *__restrict__ gram, int ldg, int row0, int col0, int mirror)
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_gram_tile(GramJob J)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)rows * cols) return;
+    gram_tile<Tin>(J, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// The tiles of a batch of Gram jobs: block b is tile (map[b].y, map[b].z) of chunk map[b].w
+// of job map[b].x.
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_gram_tile_batch(const GramJob *__restrict__ jobs, const int4 *__restrict__ map)
+{
+    const int4 e = map[blockIdx.x];
+    const GramJob J = jobs[e.x];
+    gram_tile<Tin>(J, e.y, e.z, e.w);
+}
+
+// Entry e of the job's Gram block at (row0, col0) of the N x N Gram (+ its transpose when
+// mirror) = the sum of the job's chunk partials, in a fixed order.
+__device__ __forceinline__ void gram_reduce(const GramJob &J, int64_t e)
+{
+    const int NY = J.mode == 0 ? J.nx : J.ny;
+    const int64_t cnt = (int64_t)J.nx * NY;
+    if (e >= cnt) return;
     double s = 0.0;
-    for (int c = 0; c < nchunks; c++) s += partial[(int64_t)c * rows * cols + e];
-    const int i = (int)(e / cols), j = (int)(e - (int64_t)i * cols);
-    gram[(int64_t)(row0 + i) * ldg + col0 + j] = s;
-    if (mirror) gram[(int64_t)(col0 + j) * ldg + row0 + i] = s;
+    for (int c = 0; c < J.nch; c++) s += J.partial[(int64_t)c * cnt + e];
+    const int i = (int)(e / NY), j = (int)(e - (int64_t)i * NY);
+    J.gram[(int64_t)(J.row0 + i) * J.ldg + J.col0 + j] = s;
+    if (J.mirror) J.gram[(int64_t)(J.col0 + j) * J.ldg + J.row0 + i] = s;
+}
+
+__global__ void k_gram_reduce(GramJob J)
+{
+    gram_reduce(J, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void k_gram_reduce_batch(const GramJob *__restrict__ jobs, const int2 *__restrict__ map)
+{
+    const int2 e = map[blockIdx.x];
+    const GramJob J = jobs[e.x];
+    gram_reduce(J, (int64_t)e.y * blockDim.x + threadIdx.x);
 }
 
 // Row i of Y = row i of G times Rt^-1 (Y Rt = G), Rt upper triangular; one workgroup per row.
@@ -201,52 +229,78 @@ __global__ void k_lt_times_r(const double *__restrict__ L, int ldl, const double
     R[(int64_t)i * ldr + j] = s;
 }
 
-// The whole N x N part in one workgroup for N <= 128: R~ and the lower triangle of X
-// live in LDS (packed), Y = Gram R~^-1 goes through global scratch.
-//   1. row i (one thread each): y = g_i R~^-1 by forward substitution;
-//   2. column j (one thread each, in place over Y): x = R~^-T y_:,j; keep k >= j;
-//   3. right-looking Cholesky of X in LDS;
-//   4. R = L^T R~.
+// The whole N x N part in one workgroup for N <= 128, with the triangles in LDS:
+//   1. T = R~^-1 (upper): R~ staged in LDS, then thread j forms column j by back
+//      substitution (t_j = 1 / R~_jj, t_k = -(sum_{l=k+1..j} R~_kl t_l) / R~_kk);
+//   2. Y = Gram T (through global scratch, every thread a set of entries);
+//   3. X = T^T Y, lower triangle only (X is symmetric in exact arithmetic);
+//   4. right-looking Cholesky X = L L^T in LDS;
+//   5. R = L^T R~.
+// A zero or non-finite pivot (R~ singular to working precision) skips the sweep: R = R~.
 constexpr int kSmallMax = 128;
+constexpr int kSmallThreads = 1024;
 __device__ inline int lpk(int i, int j) { return i * (i + 1) / 2 + j; }       // lower packed, j <= i
 __device__ inline int upk(int n, int i, int j) { return i * n - i * (i - 1) / 2 + (j - i); }  // upper, j >= i
 
-__global__ __launch_bounds__(1024) void k_refine_small(const double *__restrict__ gram, const double *__restrict__ Rt,
-                                                       int ldt, int n, double *__restrict__ Y,
-                                                       int32_t *failed, double *__restrict__ R, int64_t ldr)
+__device__ __forceinline__ void refine_small(const double *__restrict__ gram, const double *__restrict__ Rt, int ldt,
+                                             int n, double *__restrict__ Y, int32_t *failed, double *__restrict__ R,
+                                             int64_t ldr)
 {
-    __shared__ double Ru[kSmallMax * (kSmallMax + 1) / 2];
-    __shared__ double Xl[kSmallMax * (kSmallMax + 1) / 2];
+    __shared__ double Tu[kSmallMax * (kSmallMax + 1) / 2];  // R~, then R~^-1 (upper, packed)
+    __shared__ double Xl[kSmallMax * (kSmallMax + 1) / 2];  // R~ staged, then X and L (lower, packed)
     __shared__ double piv;
     __shared__ int bad;
     const int tid = threadIdx.x, nt = blockDim.x;
+    // R~ (upper) staged into Xl's space, read as R~_kl = Xl[upk(n, k, l)]
     for (int e = tid; e < n * n; e += nt) {
         const int i = e / n, j = e - i * n;
-        if (j >= i) Ru[upk(n, i, j)] = Rt[(int64_t)i * ldt + j];
+        if (j >= i) Xl[upk(n, i, j)] = Rt[(int64_t)i * ldt + j];
     }
     if (tid == 0) bad = 0;
     __syncthreads();
-    if (tid < n) {  // row tid of Y: y_k = (g_k - sum_{l<k} y_l R_lk) / R_kk
-        const int i = tid;
-        for (int k = 0; k < n; k++) {
-            double acc = gram[(int64_t)i * n + k];
-            for (int l = 0; l < k; l++) acc = fma(-Y[(int64_t)i * n + l], Ru[upk(n, l, k)], acc);
-            Y[(int64_t)i * n + k] = acc / Ru[upk(n, k, k)];
-        }
-    }
-    __syncthreads();
-    if (tid < n) {  // column tid of X, in place over Y: x_k = (y_kj - sum_{l<k} R_lk x_l) / R_kk
+    if (tid < n) {
         const int j = tid;
-        for (int k = 0; k < n; k++) {
-            double acc = Y[(int64_t)k * n + j];
-            for (int l = 0; l < k; l++) acc = fma(-Ru[upk(n, l, k)], Y[(int64_t)l * n + j], acc);
-            const double xk = acc / Ru[upk(n, k, k)];
-            Y[(int64_t)k * n + j] = xk;
-            if (k >= j) Xl[lpk(k, j)] = xk;
+        Tu[upk(n, j, j)] = 1.0 / Xl[upk(n, j, j)];
+        for (int k = j - 1; k >= 0; k--) {
+            double a0 = 0.0, a1 = 0.0;
+            int l = k + 1;
+            for (; l + 1 <= j; l += 2) {
+                a0 = fma(Xl[upk(n, k, l)], Tu[upk(n, l, j)], a0);
+                a1 = fma(Xl[upk(n, k, l + 1)], Tu[upk(n, l + 1, j)], a1);
+            }
+            if (l <= j) a0 = fma(Xl[upk(n, k, l)], Tu[upk(n, l, j)], a0);
+            Tu[upk(n, k, j)] = -(a0 + a1) / Xl[upk(n, k, k)];
         }
     }
     __syncthreads();
-    // X is symmetric in exact arithmetic; its lower triangle (from the column solves) is used.
+    // Y = Gram T: Y_ij = sum_{k <= j} G_ik T_kj
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e / n, j = e - i * n;
+        const double *g = gram + (int64_t)i * n;
+        double a0 = 0.0, a1 = 0.0;
+        int k = 0;
+        for (; k + 1 <= j; k += 2) {
+            a0 = fma(g[k], Tu[upk(n, k, j)], a0);
+            a1 = fma(g[k + 1], Tu[upk(n, k + 1, j)], a1);
+        }
+        if (k <= j) a0 = fma(g[k], Tu[upk(n, k, j)], a0);
+        Y[(int64_t)i * n + j] = a0 + a1;
+    }
+    __syncthreads();
+    // X = T^T Y, lower: X_ij = sum_{k <= i} T_ki Y_kj (j <= i)
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e / n, j = e - i * n;
+        if (j > i) continue;
+        double a0 = 0.0, a1 = 0.0;
+        int k = 0;
+        for (; k + 1 <= i; k += 2) {
+            a0 = fma(Tu[upk(n, k, i)], Y[(int64_t)k * n + j], a0);
+            a1 = fma(Tu[upk(n, k + 1, i)], Y[(int64_t)(k + 1) * n + j], a1);
+        }
+        if (k <= i) a0 = fma(Tu[upk(n, k, i)], Y[(int64_t)k * n + j], a0);
+        Xl[lpk(i, j)] = a0 + a1;
+    }
+    __syncthreads();
     for (int k = 0; k < n; k++) {
         if (tid == 0) {
             const double d = Xl[lpk(k, k)];
@@ -260,14 +314,9 @@ __global__ __launch_bounds__(1024) void k_refine_small(const double *__restrict_
         for (int i = k + 1 + tid; i < n; i += nt) Xl[lpk(i, k)] /= p;
         __syncthreads();
         const int rem = n - k - 1;
-        for (int e = tid; e < rem * (rem + 1) / 2; e += nt) {
-            // e -> (i, j) with k < j <= i < n
-            int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-            while ((i + 1) * (i + 2) / 2 <= e) i++;
-            while (i * (i + 1) / 2 > e) i--;
-            const int j = e - i * (i + 1) / 2;
-            const int ii = k + 1 + i, jj = k + 1 + j;
-            Xl[lpk(ii, jj)] -= Xl[lpk(ii, k)] * Xl[lpk(jj, k)];
+        for (int e = tid; e < rem * rem; e += nt) {
+            const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+            if (j <= i) Xl[lpk(i, j)] -= Xl[lpk(i, k)] * Xl[lpk(j, k)];
         }
         __syncthreads();
     }
@@ -275,66 +324,121 @@ __global__ __launch_bounds__(1024) void k_refine_small(const double *__restrict_
     if (tid == 0) *failed = bad;
     for (int e = tid; e < n * n; e += nt) {
         const int i = e / n, j = e - i * n;
-        double s = 0.0;
+        double v = 0.0;
         if (fail) {
-            s = j >= i ? Ru[upk(n, i, j)] : 0.0;
+            v = j >= i ? Rt[(int64_t)i * ldt + j] : 0.0;
         } else if (j >= i) {
-            for (int k = i; k <= j; k++) s = fma(Xl[lpk(k, i)], Ru[upk(n, k, j)], s);
+            for (int k = i; k <= j; k++) v = fma(Xl[lpk(k, i)], Rt[(int64_t)k * ldt + j], v);
         }
-        R[(int64_t)i * ldr + j] = s;
+        R[(int64_t)i * ldr + j] = v;
     }
 }
 
-template <typename Tin>
-hipError_t gram_blocks(const void *A, int64_t lda, int64_t m1, int n1, const void *B, int64_t ldb,
-                       int64_t m2, int n2, Groups g, int cartesian, const double *hB, double *partial,
-                       int64_t partial_cap, double *gram, hipStream_t s)
+__global__ __launch_bounds__(kSmallThreads) void k_refine_small(const double *__restrict__ gram,
+                                                               const double *__restrict__ Rt, int ldt, int n,
+                                                               double *__restrict__ Y, int32_t *failed,
+                                                               double *__restrict__ R, int64_t ldr)
+{
+    refine_small(gram, Rt, ldt, n, Y, failed, R, ldr);
+}
+
+// One workgroup per instance of a batch.
+__global__ __launch_bounds__(kSmallThreads) void k_refine_small_batch(const RefineSmall *__restrict__ tab)
+{
+    const RefineSmall j = tab[blockIdx.x];
+    refine_small(j.gram, j.Rt, j.ldt, j.n, j.Y, j.failed, j.R, j.ldr);
+}
+
+// Row chunks of a Gram block: about 2048 workgroups per block, at least 256 rows each.
+int64_t gram_chunks(int64_t m, int64_t tiles)
+{
+    const int64_t c = std::min<int64_t>((m + 255) / 256, (2048 + tiles - 1) / tiles);
+    return std::max<int64_t>(c, 1);
+}
+
+int64_t gram_need(int64_t nx, int64_t ny)
+{
+    const int64_t tiles = ((nx + kTile - 1) / kTile) * ((ny + kTile - 1) / kTile);
+    return (2048 + tiles - 1) / tiles * nx * ny;
+}
+
+}  // namespace
+
+int gram_jobs(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B, int64_t ldb, int64_t m2,
+              int n2, Groups g, int cartesian, const double *hB, double *partial, double *gram, GramJob *jobs)
 {
     const int N = n1 + n2;
-    // Row chunks: about 2048 workgroups in all, at least 256 rows each, partials within the cap.
-    auto chunks_for = [&](int64_t m, int64_t tiles, int64_t out_elems) {
-        int64_t c = std::min<int64_t>((m + 255) / 256, (2048 + tiles - 1) / tiles);
-        c = std::min<int64_t>(c, partial_cap / out_elems);
-        return std::max<int64_t>(c, 1);
+    const int64_t p0 = gram_need(n1, n1), p1 = gram_need(n2, n2);
+    struct Spec {
+        const void *X;
+        int64_t ld, m;
+        int nx, ny, mode;
+        const int32_t *off, *size, *other;
+        int row0, col0, mirror;
+        double *part;
     };
-    struct Job { const Tin *X; int64_t ld, m; int nx, ny, mode; const int32_t *off, *size, *other; int row0, col0, mirror; };
-    Job jobs[3] = {
-        {(const Tin *)A, lda, m1, n1, n1, 0, g.offA, g.m1, g.m2, 0, 0, 0},
-        {(const Tin *)B, ldb, m2, n2, n2, 0, g.offB, g.m2, g.m1, n1, n1, 0},
-        {(const Tin *)A, lda, m1, n1, n2, 1, g.offA, g.m1, g.m2, 0, n1, 1},
+    const Spec spec[3] = {
+        {A, lda, m1, n1, n1, 0, g.offA, g.m1, g.m2, 0, 0, 0, partial},
+        {B, ldb, m2, n2, n2, 0, g.offB, g.m2, g.m1, n1, n1, 0, partial + p0},
+        {A, lda, m1, n1, n2, 1, g.offA, g.m1, g.m2, 0, n1, 1, partial + p0 + p1},
     };
-    for (const Job &jb : jobs) {
-        const int gx = (jb.nx + kTile - 1) / kTile, gy = (jb.ny + kTile - 1) / kTile;
-        const int64_t out_elems = (int64_t)jb.nx * jb.ny;
-        const int64_t nch = chunks_for(jb.m, (int64_t)gx * gy, out_elems);
-        const int64_t per = (jb.m + nch - 1) / nch;
-        dim3 grid(gx, gy, (unsigned)nch);
-        if (jb.mode == 0)
-            k_gram_tile<Tin, 0><<<grid, 256, 0, s>>>(jb.X, jb.ld, (int)jb.m, jb.nx, jb.off, jb.size,
-                                                     jb.other, g.counts + CNT_G, cartesian, hB, jb.ny, per, partial);
-        else
-            k_gram_tile<Tin, 1><<<grid, 256, 0, s>>>(jb.X, jb.ld, (int)jb.m, jb.nx, jb.off, jb.size,
-                                                     jb.other, g.counts + CNT_G, cartesian, hB, jb.ny, per, partial);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        k_gram_reduce<<<(unsigned)((out_elems + 255) / 256), 256, 0, s>>>(partial, (int)nch, jb.nx, jb.ny, gram,
-                                                                         N, jb.row0, jb.col0, jb.mirror);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    for (int k = 0; k < 3; k++) {
+        const Spec &sp = spec[k];
+        GramJob &J = jobs[k];
+        J.X = sp.X;
+        J.ld = sp.ld;
+        J.m = (int32_t)sp.m;
+        J.nx = sp.nx;
+        J.ny = sp.ny;
+        J.mode = sp.mode;
+        J.in_f64 = in_f64;
+        J.off = sp.off;
+        J.size = sp.size;
+        J.other = sp.other;
+        J.Gp = g.counts + CNT_G;
+        J.cartesian = cartesian;
+        J.hB = hB;
+        J.gx = (sp.nx + kTile - 1) / kTile;
+        J.gy = (sp.ny + kTile - 1) / kTile;
+        J.nch = (int32_t)gram_chunks(sp.m, (int64_t)J.gx * J.gy);
+        J.rows_per_chunk = (sp.m + J.nch - 1) / J.nch;
+        J.partial = sp.part;
+        J.gram = gram;
+        J.ldg = N;
+        J.row0 = sp.row0;
+        J.col0 = sp.col0;
+        J.mirror = sp.mirror;
     }
-    return hipSuccess;
+    return 3;
 }
+
+hipError_t launch_gram_batch(int in_f64, const GramJob *jobs, const int4 *tile_map, int64_t ntiles,
+                             const int2 *red_map, int64_t nred, hipStream_t s)
+{
+    if (ntiles == 0) return hipSuccess;
+    if (in_f64) k_gram_tile_batch<double><<<(unsigned)ntiles, 256, 0, s>>>(jobs, tile_map);
+    else k_gram_tile_batch<float><<<(unsigned)ntiles, 256, 0, s>>>(jobs, tile_map);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_gram_reduce_batch<<<(unsigned)nred, 256, 0, s>>>(jobs, red_map);
+    return hipGetLastError();
+}
+
+namespace {
 
 }  // namespace
 
 int64_t refine_partial_elems(int64_t n1, int64_t n2)
 {
-    // the most any Gram block asks for: ceil(2048 / tiles) chunks of nx * ny partial sums
-    auto need = [](int64_t nx, int64_t ny) {
-        const int64_t tiles = ((nx + kTile - 1) / kTile) * ((ny + kTile - 1) / kTile);
-        return (2048 + tiles - 1) / tiles * nx * ny;
-    };
-    return std::max(need(n1, n1), std::max(need(n2, n2), need(n1, n2)));
+    // the partial sums of the three Gram blocks, side by side
+    return gram_need(n1, n1) + gram_need(n2, n2) + gram_need(n1, n2);
+}
+
+hipError_t launch_refine_small_batch(const RefineSmall *tab, int count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    k_refine_small_batch<<<(unsigned)count, kSmallThreads, 0, s>>>(tab);
+    return hipGetLastError();
 }
 
 hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B,
@@ -343,19 +447,28 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
                          int64_t partial_cap, int32_t *failed, double *R, int64_t ldr, hipStream_t s)
 {
     const int N = n1 + n2;
-    hipError_t e = in_f64 ? gram_blocks<double>(A, lda, m1, n1, B, ldb, m2, n2, g, cartesian, hB, partial,
-                                                partial_cap, gram, s)
-                          : gram_blocks<float>(A, lda, m1, n1, B, ldb, m2, n2, g, cartesian, hB, partial,
-                                               partial_cap, gram, s);
-    if (e != hipSuccess) return e;
+    if (partial_cap < refine_partial_elems(n1, n2)) return hipErrorInvalidValue;
+    GramJob jobs[3];
+    gram_jobs(A, in_f64, lda, m1, n1, B, ldb, m2, n2, g, cartesian, hB, partial, gram, jobs);
+    for (const GramJob &J : jobs) {
+        dim3 grid(J.gx, J.gy, (unsigned)J.nch);
+        if (in_f64) k_gram_tile<double><<<grid, 256, 0, s>>>(J);
+        else k_gram_tile<float><<<grid, 256, 0, s>>>(J);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t out_elems = (int64_t)J.nx * (J.mode == 0 ? J.nx : J.ny);
+        k_gram_reduce<<<(unsigned)((out_elems + 255) / 256), 256, 0, s>>>(J);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (N <= kSmallMax) {
-        k_refine_small<<<1, 1024, 0, s>>>(gram, Rt, ldt, N, Y, failed, R, ldr);
+        k_refine_small<<<1, kSmallThreads, 0, s>>>(gram, Rt, ldt, N, Y, failed, R, ldr);
         return hipGetLastError();
     }
     const size_t shm = sizeof(double) * N;
     // Y = Gram Rt^-1 ; then X^T = Y^T Rt^-1 (X symmetric), written over gram
     k_right_solve<<<N, 256, shm, s>>>(gram, N, Rt, ldt, N, Y, N, 0);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_right_solve<<<N, 256, shm, s>>>(Y, N, Rt, ldt, N, gram, N, 1);
     e = hipGetLastError();
