@@ -235,7 +235,8 @@ void tsqr_panel_tree_sizes(int nleaves, int64_t *slots, int64_t *counters);
 hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,
                                  int64_t ldr, hipStream_t s);
 
-// One FP64 refinement sweep (kernels_refine.hip): from the approximate R~ (Rt, upper,
+// One FP64 refinement sweep (kernels_refine.hip; part 0: the Gram matrix only, 1: the rest,
+// 2: both): from the approximate R~ (Rt, upper,
 // positive diagonal) and the exact per-group Gram matrix of the join, R = chol(X)^T R~ with
 // X = R~^-T (J^T J) R~^-1.  hB: the groups' heads of B (H(B_g), gcap x n2).  Scratch: gram
 // and Y (N x N each), partial (partial_cap doubles, at least refine_partial_elems), failed
@@ -250,7 +251,7 @@ struct GramJob {
     const int32_t *off, *size, *other;
     const int64_t *Gp;
     int32_t cartesian;
-    const double *hB;
+    const double *hA, *hB;  // group heads H(A_g) (mode 2 only) and H(B_g)
     int32_t gx, gy, nch;
     int64_t rows_per_chunk;
     double *partial;
@@ -258,8 +259,11 @@ struct GramJob {
     int32_t ldg, row0, col0, mirror;
 };
 // The three Gram jobs of one problem (partial: refine_partial_elems doubles); returns 3.
+// With the heads of A (hA, gcap x n1; the two-sided form) the cross block is summed over
+// the groups' heads (mode 2) instead of A's rows (mode 1).
 int gram_jobs(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B, int64_t ldb, int64_t m2,
-              int n2, Groups g, int cartesian, const double *hB, double *partial, double *gram, GramJob *jobs);
+              int n2, Groups g, int cartesian, const double *hA, const double *hB, int64_t gcap, double *partial,
+              double *gram, GramJob *jobs, int64_t blocks);  // blocks: workgroups per job to aim at (<= 1024)
 // A batch of Gram jobs of one input type: tile_map[b] = (job, ti, tj, chunk), red_map[b] =
 // (job, block of 256 entries).
 hipError_t launch_gram_batch(int in_f64, const GramJob *jobs, const int4 *tile_map, int64_t ntiles,
@@ -276,9 +280,11 @@ struct RefineSmall {
 };
 hipError_t launch_refine_small_batch(const RefineSmall *tab, int count, hipStream_t s);
 hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B,
-                         int64_t ldb, int64_t m2, int n2, Groups g, int cartesian, const double *hB,
+                         int64_t ldb, int64_t m2, int n2, Groups g, int cartesian, const double *hA,
+                         const double *hB, int64_t gcap,
                          const double *Rt, int ldt, double *gram, double *Y, double *partial,
-                         int64_t partial_cap, int32_t *failed, double *R, int64_t ldr, hipStream_t s);
+                         int64_t partial_cap, int32_t *failed, double *R, int64_t ldr, hipStream_t s,
+                         int part = 2);
 
 // Jacobi (kernels_jacobi.hip)
 // ctrl: 8 ints (ctrl[0] receives the sweep count, -1 after a timed-out run); scratch:

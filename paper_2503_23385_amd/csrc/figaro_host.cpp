@@ -118,7 +118,7 @@ constexpr int kPrecMask = 0xff;
 constexpr int kMaxTreeLeaves = 2048;
 constexpr int64_t kLeafTarget = 256;
 constexpr int kMaxPanelLeaves = 128;
-constexpr int kPlanLanes = 8;  // parallel branches of a batched plan's graph
+constexpr int kBatchGramBlocks = 64;  // Gram workgroups per job in a batch
 
 struct Shape {
     int64_t m1, n1, lda, m2, n2, ldb;
@@ -558,12 +558,15 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
 int run_refine(const figaro_table *A, const figaro_table *B, const Shape &sh, const Layout &L, double *R,
                int64_t ldr, void *ws, hipStream_t s)
 {
-    Stage st("refine", s);
-    HIPCHK(launch_refine(A->data, sh.in_f64, sh.lda, sh.m1, (int)sh.n1, B->data, sh.ldb, sh.m2, (int)sh.n2,
-                         groups_of(ws, L), !sh.keyed, at<double>(ws, L.headsB), at<double>(ws, L.rt), (int)sh.N(),
-                         at<double>(ws, L.gram), at<double>(ws, L.gy), at<double>(ws, L.partial),
-                         L.partial_cap, at<int32_t>(ws, L.failed), R, ldr, s),
-           "refinement sweep");
+    for (int part = 0; part < 2; part++) {
+        Stage st(part == 0 ? "refine_gram" : "refine_solve", s);
+        HIPCHK(launch_refine(A->data, sh.in_f64, sh.lda, sh.m1, (int)sh.n1, B->data, sh.ldb, sh.m2, (int)sh.n2,
+                             groups_of(ws, L), !sh.keyed, sh.two_sided ? at<double>(ws, L.headsA) : nullptr,
+                             at<double>(ws, L.headsB), L.gcap, at<double>(ws, L.rt), (int)sh.N(),
+                             at<double>(ws, L.gram), at<double>(ws, L.gy), at<double>(ws, L.partial),
+                             L.partial_cap, at<int32_t>(ws, L.failed), R, ldr, s, part),
+               "refinement sweep");
+    }
     return FIGARO_OK;
 }
 
@@ -1165,8 +1168,9 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
         const figaro_instance *in = &plan->inst[i];
         GramJob j3[3];
         gram_jobs(in->A.data, sh.in_f64, sh.lda, sh.m1, (int)sh.n1, in->B.data, sh.ldb, sh.m2, (int)sh.n2,
-                  groups_of(lws, L), !sh.keyed, at<double>(lws, L.headsB), at<double>(lws, L.partial),
-                  at<double>(lws, L.gram), j3);
+                  groups_of(lws, L), !sh.keyed, sh.two_sided ? at<double>(lws, L.headsA) : nullptr,
+                  at<double>(lws, L.headsB), L.gcap, at<double>(lws, L.partial), at<double>(lws, L.gram), j3,
+                  kBatchGramBlocks);
         for (const GramJob &J : j3) gjobs[sh.in_f64].push_back(J);
         const int N = (int)sh.N();
         smalls.push_back(RefineSmall{at<double>(lws, L.gram), at<double>(lws, L.rt), N, N, at<double>(lws, L.gy),

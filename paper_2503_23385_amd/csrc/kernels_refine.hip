@@ -47,65 +47,82 @@ __device__ __forceinline__ void gram_tile(const GramJob &J, int ti, int tj, int 
     const int64_t ldx = J.ld;
     const int m = J.m, nx = J.nx, ny = J.ny, mode = J.mode;
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;  // 16 x 16 threads, 4 x 4 outputs each
     const int G = (int)*J.Gp;
     const int64_t r0 = (int64_t)chunk * J.rows_per_chunk;
-    const int64_t r1 = min((int64_t)m, r0 + J.rows_per_chunk);
+    int64_t r1 = min((int64_t)m, r0 + J.rows_per_chunk);
+    if (mode == 2) r1 = min(r1, (int64_t)G);  // rows past the group count are empty
     __shared__ double xi[kRowsPerStage][kTile];
     __shared__ double yj[kRowsPerStage][kTile];
     __shared__ int grp[kRowsPerStage];
-    double acc[4][4] = {};
+    // wave w accumulates the 16 x 16 subtiles (w, v), v = 0..3, of the 64 x 64 tile on the
+    // FP64 matrix cores: D += A B with A = the i-columns of 4 staged rows transposed
+    // (lane l supplies A[l % 16][l / 16]) and B = the j-columns (lane l supplies
+    // B[l / 16][l % 16]); lane l holds D[l / 16 + 4 r][l % 16] in element r
+    const int wv = tid >> 6, lane = tid & 63;
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    d4 acc[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++) acc[v] = d4{0.0, 0.0, 0.0, 0.0};
     for (int64_t rb = r0; rb < r1; rb += kRowsPerStage) {
         if (tid < kRowsPerStage) {
             const int64_t s = rb + tid;
-            grp[tid] = s >= r1 ? -1 : J.cartesian ? (G > 0 ? 0 : -1) : group_of_row(J.off, J.size, G, s);
+            // mode 2: rows are the groups themselves
+            grp[tid] = s >= r1 ? -1
+                       : mode == 2 ? (s < G ? (int)s : -1)
+                       : J.cartesian ? (G > 0 ? 0 : -1)
+                                     : group_of_row(J.off, J.size, G, s);
         }
         __syncthreads();
-        // stage rows: i-columns of X, j-columns of X (weighted) or of the group's B sum
-#pragma unroll 4
-        for (int e = tid; e < kRowsPerStage * kTile; e += 256) {
-            const int rr = e / kTile, c = e - rr * kTile;
-            const int64_t s = rb + rr;
-            double vi = 0.0, vj = 0.0;
-            {
-                const int g = grp[rr];
-                if (g >= 0) {
-                    const int ci = ti * kTile + c, cj = tj * kTile + c;
-                    if (ci < nx) vi = (double)X[s * ldx + ci];
-                    if (mode == 0) {
-                        if (cj < nx) vj = (double)J.other[g] * (double)X[s * ldx + cj];
-                    } else {
-                        if (cj < ny) vj = sqrt((double)J.other[g]) * J.hB[(int64_t)g * ny + cj];
-                    }
-                }
+        // stage rows: i-columns of X, j-columns of X (weighted) or of the group's B sum.
+        // Every load is issued unconditionally (row and column clamped into range) and
+        // masked afterwards, so that a thread's loads are in flight together.
+        constexpr int PER = kRowsPerStage * kTile / 256;
+        double vi[PER], vj[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int e = tid + 256 * u, rr = e / kTile, c = e - rr * kTile;
+            const int64_t s = min(rb + rr, r1 - 1);
+            const int g = max(grp[rr], 0);
+            const int ci = min(ti * kTile + c, nx - 1), cj = min(tj * kTile + c, (mode == 0 ? nx : ny) - 1);
+            if (mode == 2) {
+                // sum_g a_g b_g^T with a_g = sqrt(m1_g) H(A_g), b_g = sqrt(m2_g) H(B_g)
+                vi[u] = sqrt((double)J.size[g]) * J.hA[(int64_t)g * nx + ci];
+                vj[u] = sqrt((double)J.other[g]) * J.hB[(int64_t)g * ny + cj];
+            } else if (mode == 0) {
+                vi[u] = (double)X[s * ldx + ci];
+                vj[u] = (double)J.other[g] * (double)X[s * ldx + cj];
+            } else {
+                vi[u] = (double)X[s * ldx + ci];
+                vj[u] = sqrt((double)J.other[g]) * J.hB[(int64_t)g * ny + cj];
             }
-            xi[rr][c] = vi;
-            yj[rr][c] = vj;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int e = tid + 256 * u, rr = e / kTile, c = e - rr * kTile;
+            const bool live = grp[rr] >= 0;
+            xi[rr][c] = (live && ti * kTile + c < nx) ? vi[u] : 0.0;
+            yj[rr][c] = (live && tj * kTile + c < (mode == 0 ? nx : ny)) ? vj[u] : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < kRowsPerStage; rr++) {
-            double a[4], b[4];
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                a[u] = xi[rr][ty * 4 + u];
-                b[u] = yj[rr][tx * 4 + u];
+        for (int k0 = 0; k0 < kRowsPerStage; k0 += 4) {
+            const double a = xi[k0 + lane / 16][wv * 16 + lane % 16];
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const double b = yj[k0 + lane / 16][v * 16 + lane % 16];
+                acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[v], 0, 0, 0);
             }
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) acc[u][v] = fma(a[u], b[v], acc[u][v]);
         }
         __syncthreads();
     }
     const int NY = mode == 0 ? nx : ny;
     double *out = J.partial + (int64_t)chunk * nx * NY;
 #pragma unroll
-    for (int u = 0; u < 4; u++)
+    for (int v = 0; v < 4; v++)
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int i = ti * kTile + ty * 4 + u, j = tj * kTile + tx * 4 + v;
-            if (i < nx && j < NY) out[(int64_t)i * NY + j] = acc[u][v];
+        for (int r = 0; r < 4; r++) {
+            const int i = ti * kTile + wv * 16 + lane / 16 + 4 * r, j = tj * kTile + v * 16 + lane % 16;
+            if (i < nx && j < NY) out[(int64_t)i * NY + j] = acc[v][r];
         }
 }
 
@@ -132,8 +149,14 @@ __device__ __forceinline__ void gram_reduce(const GramJob &J, int64_t e)
     const int NY = J.mode == 0 ? J.nx : J.ny;
     const int64_t cnt = (int64_t)J.nx * NY;
     if (e >= cnt) return;
-    double s = 0.0;
-    for (int c = 0; c < J.nch; c++) s += J.partial[(int64_t)c * cnt + e];
+    // eight interleaved partial sums (their loads in flight together), combined in a fixed order
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int c = 0;
+    for (; c + 8 <= J.nch; c += 8)
+#pragma unroll
+        for (int u = 0; u < 8; u++) a[u] += J.partial[(int64_t)(c + u) * cnt + e];
+    for (int u = 0; c < J.nch; c++, u++) a[u] += J.partial[(int64_t)c * cnt + e];
+    const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     const int i = (int)(e / NY), j = (int)(e - (int64_t)i * NY);
     J.gram[(int64_t)(J.row0 + i) * J.ldg + J.col0 + j] = s;
     if (J.mirror) J.gram[(int64_t)(J.col0 + j) * J.ldg + J.row0 + i] = s;
@@ -349,23 +372,26 @@ __global__ __launch_bounds__(kSmallThreads) void k_refine_small_batch(const Refi
     refine_small(j.gram, j.Rt, j.ldt, j.n, j.Y, j.failed, j.R, j.ldr);
 }
 
-// Row chunks of a Gram block: about 2048 workgroups per block, at least 256 rows each.
-int64_t gram_chunks(int64_t m, int64_t tiles)
+// Row chunks of a Gram block: about `blocks` workgroups per block (1024 for a single
+// problem; a batch, whose jobs fill the GPU together, asks for fewer), at least 256 rows each.
+constexpr int64_t kGramBlocks = 1024, kGramMinRows = 256;
+int64_t gram_chunks(int64_t m, int64_t tiles, int64_t blocks)
 {
-    const int64_t c = std::min<int64_t>((m + 255) / 256, (2048 + tiles - 1) / tiles);
+    const int64_t c = std::min<int64_t>((m + kGramMinRows - 1) / kGramMinRows, (blocks + tiles - 1) / tiles);
     return std::max<int64_t>(c, 1);
 }
 
 int64_t gram_need(int64_t nx, int64_t ny)
 {
     const int64_t tiles = ((nx + kTile - 1) / kTile) * ((ny + kTile - 1) / kTile);
-    return (2048 + tiles - 1) / tiles * nx * ny;
+    return (kGramBlocks + tiles - 1) / tiles * nx * ny;
 }
 
 }  // namespace
 
 int gram_jobs(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B, int64_t ldb, int64_t m2,
-              int n2, Groups g, int cartesian, const double *hB, double *partial, double *gram, GramJob *jobs)
+              int n2, Groups g, int cartesian, const double *hA, const double *hB, int64_t gcap, double *partial,
+              double *gram, GramJob *jobs, int64_t blocks)
 {
     const int N = n1 + n2;
     const int64_t p0 = gram_need(n1, n1), p1 = gram_need(n2, n2);
@@ -380,7 +406,8 @@ int gram_jobs(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const 
     const Spec spec[3] = {
         {A, lda, m1, n1, n1, 0, g.offA, g.m1, g.m2, 0, 0, 0, partial},
         {B, ldb, m2, n2, n2, 0, g.offB, g.m2, g.m1, n1, n1, 0, partial + p0},
-        {A, lda, m1, n1, n2, 1, g.offA, g.m1, g.m2, 0, n1, 1, partial + p0 + p1},
+        hA ? Spec{nullptr, 0, gcap, n1, n2, 2, g.offA, g.m1, g.m2, 0, n1, 1, partial + p0 + p1}
+           : Spec{A, lda, m1, n1, n2, 1, g.offA, g.m1, g.m2, 0, n1, 1, partial + p0 + p1},
     };
     for (int k = 0; k < 3; k++) {
         const Spec &sp = spec[k];
@@ -397,10 +424,11 @@ int gram_jobs(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const 
         J.other = sp.other;
         J.Gp = g.counts + CNT_G;
         J.cartesian = cartesian;
+        J.hA = hA;
         J.hB = hB;
         J.gx = (sp.nx + kTile - 1) / kTile;
         J.gy = (sp.ny + kTile - 1) / kTile;
-        J.nch = (int32_t)gram_chunks(sp.m, (int64_t)J.gx * J.gy);
+        J.nch = (int32_t)gram_chunks(sp.m, (int64_t)J.gx * J.gy, std::min(blocks, kGramBlocks));
         J.rows_per_chunk = (sp.m + J.nch - 1) / J.nch;
         J.partial = sp.part;
         J.gram = gram;
@@ -442,15 +470,17 @@ hipError_t launch_refine_small_batch(const RefineSmall *tab, int count, hipStrea
 }
 
 hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int n1, const void *B,
-                         int64_t ldb, int64_t m2, int n2, Groups g, int cartesian, const double *hB,
+                         int64_t ldb, int64_t m2, int n2, Groups g, int cartesian, const double *hA,
+                         const double *hB, int64_t gcap,
                          const double *Rt, int ldt, double *gram, double *Y, double *partial,
-                         int64_t partial_cap, int32_t *failed, double *R, int64_t ldr, hipStream_t s)
+                         int64_t partial_cap, int32_t *failed, double *R, int64_t ldr, hipStream_t s, int part)
 {
     const int N = n1 + n2;
     if (partial_cap < refine_partial_elems(n1, n2)) return hipErrorInvalidValue;
     GramJob jobs[3];
-    gram_jobs(A, in_f64, lda, m1, n1, B, ldb, m2, n2, g, cartesian, hB, partial, gram, jobs);
+    gram_jobs(A, in_f64, lda, m1, n1, B, ldb, m2, n2, g, cartesian, hA, hB, gcap, partial, gram, jobs, kGramBlocks);
     for (const GramJob &J : jobs) {
+        if (part == 1) break;
         dim3 grid(J.gx, J.gy, (unsigned)J.nch);
         if (in_f64) k_gram_tile<double><<<grid, 256, 0, s>>>(J);
         else k_gram_tile<float><<<grid, 256, 0, s>>>(J);
@@ -461,6 +491,7 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (part == 0) return hipSuccess;
     if (N <= kSmallMax) {
         k_refine_small<<<1, kSmallThreads, 0, s>>>(gram, Rt, ldt, N, Y, failed, R, ldr);
         return hipGetLastError();
