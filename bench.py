@@ -292,6 +292,7 @@ def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref, time
             fg.r_autotune(A, B, kA, kB, prec, two_sided=two, ws=ws, out=R)
         ms = timer.steps(step, args.steps, args.warmup)
         assert fg.status(ws) == 0
+        memory = fg.memory_report(A, B, kA, kB, ws, prec, two_sided=two)
         flushed = timer.flushed(step, args.flush_reps)
         stage_ms, launches = timer.stages(step, args.steps, fg)
         sweeps = int(sws[:4].view(torch.int32)[0].item())
@@ -301,7 +302,8 @@ def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref, time
             errs = {"R_relF": er, "sigma_rel2": es, "reference": "FP64 oracle"}
         forms[spec] = {"ms_per_step": ms, "value": join_rows / (ms / 1e3), "flushed": flushed,
                        "stage_ms": stage_ms, "launches_per_step": launches,
-                       "errors_vs_oracle": errs, "jacobi_sweeps": sweeps, "layout": layout, "precision": prec}
+                       "errors_vs_oracle": errs, "jacobi_sweeps": sweeps, "layout": layout, "precision": prec,
+                       "memory": memory}
         del ws, R, S
     ok = [k for k, f in forms.items()
           if f["errors_vs_oracle"] is None
@@ -309,9 +311,12 @@ def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref, time
     chosen = min(ok, key=lambda k: forms[k]["ms_per_step"])
     f = forms[chosen]
     work = stage_work(inst, f["layout"] == "two_sided", f["precision"], f["jacobi_sweeps"])
+    mem = f["memory"]
+    memory = dict(mem, join_over_compact=mem["join_bytes"] / max(mem["compact_bytes"], 1.0),
+                  join_over_workspace=mem["join_bytes"] / max(mem["workspace_bytes"], 1.0))
     return {"value": f["value"], "ms_per_step": f["ms_per_step"], "chosen": chosen, "precision": f["precision"],
             "roofline": roofline_of(f, work, f["precision"]), "forms": forms, "join_rows": join_rows,
-            "config": {"workload": desc, "join_rows": join_rows, "form": chosen}}
+            "memory": memory, "config": {"workload": desc, "join_rows": join_rows, "form": chosen}}
 
 
 def instance_tables(fg, A, B):
@@ -525,6 +530,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": out["forms"],
         "tuning": fg.tune_table(),
+        "memory": out.get("memory"),
     }
     print(json.dumps(line))
 

@@ -239,6 +239,39 @@ int figaro_timing_enable(int32_t on);
 int figaro_timing_read(const char **names, double *ms, int32_t *launches, int32_t cap,
                        int32_t *count);
 
+/* ------------------------------------------------------------ unsorted inputs, memory */
+
+/*
+ * The method takes relations sorted by the join attribute (Experiments
+ * section).  figaro_sort_table lifts that precondition: it writes `in`'s rows
+ * to `out` (device, same dtype and cols, row-major with ld_out >= cols) and
+ * their keys to keys_out (device, rows entries) in ascending signed key order,
+ * rows with equal keys in their input order (a stable sort; LSD radix sort of
+ * the keys with their row indices, 8 passes of 4-bit digits, then a row
+ * gather).  in->keys is required.  `out` must not alias in->data; keys_out may
+ * alias in->keys only if the caller no longer needs the unsorted keys (they
+ * are read in the first pass).  Workspace: figaro_sort_workspace_size(rows)
+ * bytes, 256-byte aligned, caller-owned.  Asynchronous.
+ */
+int figaro_sort_workspace_size(int64_t rows, size_t *bytes);
+int figaro_sort_table(const figaro_table *in, void *out, int64_t ld_out, int32_t *keys_out, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/*
+ * Memory footprint of the compact path against the materialised join (the
+ * paper's memory claim, Abstract): the join's rows (sum m1_g m2_g), its bytes
+ * in the inputs' element type (join_rows x (n1 + n2)), the inputs (rows and
+ * keys), the compact matrix as stored by the form (rows and bytes), and the
+ * workspace of figaro_r.  Synchronous: waits for `stream`, then reads the
+ * counts that figaro_r or figaro_compact left in `ws` for these tables.
+ */
+typedef struct figaro_memory {
+    int64_t groups, join_rows, compact_rows;
+    double input_bytes, compact_bytes, workspace_bytes, join_bytes;
+} figaro_memory;
+int figaro_memory_report(const figaro_table *A, const figaro_table *B, int32_t precision, const void *ws,
+                         size_t ws_bytes, void *stream, figaro_memory *out);
+
 /* ------------------------------------------------------------ batching */
 
 /*

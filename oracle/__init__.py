@@ -158,5 +158,14 @@ def sigma(R, max_sweeps=60, return_sweeps=False):
     return (out, sw) if return_sweeps else out
 
 
+def sort_table(X, keys):
+    """The rows of X and their keys in ascending (signed int32) key order, rows with equal keys
+    in their input order: the plain definition of a stable sort (the method's precondition on
+    its relations, Experiments section), with numpy's stable argsort as the sorting step."""
+    keys = np.asarray(keys, dtype=np.int32)
+    order = np.argsort(keys, kind="stable")
+    return np.ascontiguousarray(np.asarray(X)[order]), np.ascontiguousarray(keys[order])
+
+
 def num_threads() -> int:
     return int(lib().oracle_num_threads())

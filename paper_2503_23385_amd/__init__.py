@@ -51,6 +51,12 @@ class View(ctypes.Structure):
                 ("m_dtype", ctypes.c_int32), ("status", ctypes.c_void_p)]
 
 
+class Memory(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_int64), ("join_rows", ctypes.c_int64), ("compact_rows", ctypes.c_int64),
+                ("input_bytes", ctypes.c_double), ("compact_bytes", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_double), ("join_bytes", ctypes.c_double)]
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("A", Table), ("B", Table)]
 
@@ -60,6 +66,7 @@ EXPORTS = [
     "figaro_sigma_workspace_size", "figaro_sigma", "figaro_sigma_jacobi", "figaro_sigma_bidiag", "figaro_status", "figaro_last_error",
     "figaro_plan_create", "figaro_plan_workspace_size", "figaro_plan_offsets",
     "figaro_plan_execute", "figaro_plan_execute_eager", "figaro_plan_destroy", "figaro_plan_autotune",
+    "figaro_sort_workspace_size", "figaro_sort_table", "figaro_memory_report",
     "figaro_r_autotune", "figaro_tune_load", "figaro_tune_save", "figaro_tune_dump", "figaro_timing_enable", "figaro_timing_read",
     "figaro_sigma_noalloc",
 ]
@@ -97,6 +104,9 @@ def lib():
     L.figaro_plan_execute_eager.argtypes = [P, P, SZ, P, P, P]
     L.figaro_plan_autotune.argtypes = [P, P, SZ, P, P, P]
     L.figaro_r_autotune.argtypes = [TP, TP, I32, P, I64, P, SZ, P]
+    L.figaro_sort_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
+    L.figaro_sort_table.argtypes = [TP, P, I64, P, P, SZ, P]
+    L.figaro_memory_report.argtypes = [TP, TP, I32, P, SZ, P, ctypes.POINTER(Memory)]
     L.figaro_tune_load.argtypes = [ctypes.c_char_p]
     L.figaro_tune_save.argtypes = [ctypes.c_char_p]
     L.figaro_tune_dump.argtypes = [P, SZ, ctypes.POINTER(SZ)]
@@ -320,6 +330,35 @@ def r_autotune(A, B, keys_A=None, keys_B=None, precision="fp64", two_sided=False
     _check(lib().figaro_r_autotune(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided),
                                    ctypes.c_void_p(out.data_ptr()), out.stride(0), ctypes.c_void_p(ws.data_ptr()),
                                    ws.numel(), _stream_ptr(stream)))
+
+
+def sort_table(X, keys, stream=None):
+    """Rows of X and their int32 keys in ascending key order, equal keys in input order (on the
+    device).  Returns (X_sorted, keys_sorted)."""
+    torch = _torch()
+    require_device("X", X)
+    require_device("keys", keys, X.device)
+    t = make_table(X, keys)
+    n = ctypes.c_size_t(0)
+    _check(lib().figaro_sort_workspace_size(X.shape[0], ctypes.byref(n)))
+    ws = alloc_workspace(n.value, X.device)
+    out = torch.empty((X.shape[0], X.shape[1]), dtype=X.dtype, device=X.device)
+    kout = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    _check(lib().figaro_sort_table(ctypes.byref(t), ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                   ctypes.c_void_p(kout.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream_ptr(stream)))
+    return out, kout
+
+
+def memory_report(A, B, keys_A, keys_B, ws, precision="fp64", two_sided=False, stream=None):
+    """Memory footprint (dict) of the compact path against the materialised join, from the counts
+    that r() or compact() left in ws (synchronous)."""
+    ta, tb = make_table(A, keys_A), make_table(B, keys_B)
+    m = Memory()
+    _check(lib().figaro_memory_report(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
+                                      ctypes.byref(m)))
+    return {k: getattr(m, k) for k, _ in Memory._fields_}
 
 
 def tune_load(path):

@@ -23,6 +23,7 @@ SOURCES = [
     "kernels_panel.hip",
     "kernels_jacobi.hip",
     "kernels_refine.hip",
+    "kernels_sort.hip",
     "tune.cpp",
     "figaro_host.cpp",
 ]

@@ -286,6 +286,12 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
                          int64_t partial_cap, int32_t *failed, double *R, int64_t ldr, hipStream_t s,
                          int part = 2);
 
+// Stable sort of a table's rows by key (kernels_sort.hip): out rows (ld_out) and keys_out
+// in ascending signed key order, equal keys in input order.  ws: sort_workspace_bytes(n).
+int64_t sort_workspace_bytes(int64_t n);
+hipError_t launch_sort_table(const void *X, int elem_bytes, int64_t ld, int64_t n, int64_t cols, const int32_t *keys,
+                             void *out, int64_t ld_out, int32_t *keys_out, void *ws, hipStream_t s);
+
 // Jacobi (kernels_jacobi.hip)
 // ctrl: 8 ints (ctrl[0] receives the sweep count, -1 after a timed-out run); scratch:
 // jacobi_scratch_doubles(n) doubles (none for n <= 128).

@@ -872,6 +872,69 @@ int figaro_sigma_noalloc(const double *R, int64_t n, int64_t ldr, double *sigma,
     return sigma_jacobi(R, n, ldr, sigma, ws, (hipStream_t)stream, false);
 }
 
+int figaro_sort_workspace_size(int64_t rows, size_t *bytes)
+{
+    if (rows < 0 || rows > INT32_MAX - 1) return fail(FIGARO_EINVAL, "rows out of range");
+    if (!bytes) return fail(FIGARO_EINVAL, "bytes is NULL");
+    *bytes = (size_t)sort_workspace_bytes(rows);
+    return FIGARO_OK;
+}
+
+int figaro_sort_table(const figaro_table *in, void *out, int64_t ld_out, int32_t *keys_out, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    int rc = check_table(in, "in");
+    if (rc) return rc;
+    if (!in->keys && in->rows > 0) return fail(FIGARO_EINVAL, "the table has no keys to sort by");
+    if (in->rows > 0 && (!out || !keys_out)) return fail(FIGARO_EINVAL, "out or keys_out is NULL");
+    if (ld_out < in->cols) return fail(FIGARO_EINVAL, "ld_out < cols");
+    if (out == in->data) return fail(FIGARO_EINVAL, "out must not alias the input rows");
+    if (!ws) return fail(FIGARO_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(FIGARO_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < (size_t)sort_workspace_bytes(in->rows))
+        return fail(FIGARO_EWORKSPACE, "workspace too small: need " + std::to_string(sort_workspace_bytes(in->rows)));
+    Stage st("sort", (hipStream_t)stream);
+    HIPCHK(launch_sort_table(in->data, in->dtype == FIGARO_F64 ? 8 : 4, in->ld, in->rows, in->cols, in->keys, out,
+                             ld_out, keys_out, ws, (hipStream_t)stream),
+           "sort");
+    return FIGARO_OK;
+}
+
+int figaro_memory_report(const figaro_table *A, const figaro_table *B, int32_t precision, const void *ws,
+                         size_t ws_bytes, void *stream, figaro_memory *out)
+{
+    Shape sh;
+    int rc = make_shape(A, B, precision, &sh);
+    if (rc) return rc;
+    if (!out) return fail(FIGARO_EINVAL, "out is NULL");
+    Layout L = make_layout(sh);
+    rc = check_ws(L, const_cast<void *>(ws), ws_bytes);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream), "memory report sync");
+    int64_t counts[CNT_SLOTS];
+    HIPCHK(hipMemcpy(counts, (const char *)ws + L.counts, sizeof counts, hipMemcpyDeviceToHost), "memory report read");
+    const int64_t N = sh.N();
+    const double esz_in = sh.in_f64 ? 8.0 : 4.0, esz_m = L.m_f64 ? 8.0 : 4.0;
+    out->groups = counts[CNT_G];
+    out->join_rows = counts[CNT_JOIN];
+    double compact = 0.0;
+    int64_t crows = 0;
+    if (!sh.two_sided) {
+        crows = counts[CNT_R1] + counts[CNT_R2];
+        compact = esz_m * ((double)counts[CNT_R1] * N + (double)counts[CNT_R2] * sh.n2);
+    } else {
+        crows = counts[CNT_G] + counts[CNT_TA] + counts[CNT_R2];
+        compact = esz_m * ((double)counts[CNT_G] * N + (double)counts[CNT_TA] * sh.n1 + (double)counts[CNT_R2] * sh.n2);
+    }
+    out->compact_rows = crows;
+    out->input_bytes = esz_in * ((double)sh.m1 * sh.n1 + (double)sh.m2 * sh.n2) +
+                       (sh.keyed ? 4.0 * (double)(sh.m1 + sh.m2) : 0.0);
+    out->compact_bytes = compact;
+    out->workspace_bytes = (double)L.total;
+    out->join_bytes = esz_in * (double)counts[CNT_JOIN] * (double)N;
+    return FIGARO_OK;
+}
+
 int figaro_timing_enable(int32_t on)
 {
     g_timing.on.store(on != 0);

@@ -342,3 +342,21 @@ def test_sigma_diagonal_and_zero():
     d = np.array([3.0, -1.0, 0.0, 2.0])
     assert np.array_equal(oracle.sigma(np.diag(d)), np.array([3.0, 2.0, 1.0, 0.0]))
     assert np.array_equal(oracle.sigma(np.zeros((3, 3))), np.zeros(3))
+
+
+# ------------------------------------------------------------------ sort (unsorted inputs)
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sort_table_matches_brute_force(seed):
+    """oracle.sort_table against a brute-force stable sort: Python's sorted() on (key, row index)."""
+    rng = W.rng_for(120, seed)
+    m = int(rng.integers(0, 300))
+    keys = rng.integers(-5, 6 if seed % 2 else 2 ** 31 - 1, size=m).astype(np.int32)
+    if seed == 3:
+        keys[:] = np.int32(-2 ** 31)
+    X = rng.standard_normal((m, 3))
+    Xs, ks = oracle.sort_table(X, keys)
+    order = [i for _, i in sorted((int(k), i) for i, k in enumerate(keys))]
+    assert np.array_equal(ks, keys[order])
+    assert np.array_equal(Xs, X[order])
+    assert np.all(np.diff(ks.astype(np.int64)) >= 0)
