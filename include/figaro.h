@@ -239,6 +239,23 @@ int figaro_timing_enable(int32_t on);
 int figaro_timing_read(const char **names, double *ms, int32_t *launches, int32_t cap,
                        int32_t *count);
 
+/*
+ * Singular values and right singular vectors of R (Abstract: the right
+ * singular vectors of the join; Related Works: the SVD of the join through R):
+ * one-sided Jacobi as in figaro_sigma_jacobi with every rotation also applied
+ * to the columns of V, which starts as the identity, so that R V = U diag(sigma)
+ * with V orthogonal.  R (device, n x n, ld ldr >= n) is read only.  sigma
+ * (device, n) receives the values descending (equal values in column order);
+ * V (device, n x n row-major, ld ldv >= n) column j receives the vector of
+ * sigma[j] (unique up to sign where sigma[j] is simple).  FP64 throughout; the
+ * right singular vectors of J equal those of R.  n <= 128.  Workspace:
+ * figaro_svd_workspace_size(n) bytes, 256-byte aligned (a control block and V's
+ * columns during the sweeps).  Asynchronous.
+ */
+int figaro_svd_workspace_size(int64_t n, size_t *bytes);
+int figaro_svd(const double *R, int64_t n, int64_t ldr, double *sigma, double *V, int64_t ldv, void *ws,
+               size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ unsorted inputs, memory */
 
 /*

@@ -54,6 +54,8 @@ def lib():
         L.oracle_r.restype = ctypes.c_int
         L.oracle_sigma.argtypes = [dp, i64, i64, dp, ctypes.c_int]
         L.oracle_sigma.restype = ctypes.c_int
+        L.oracle_svd_v.argtypes = [dp, i64, i64, dp, dp, i64, ctypes.c_int]
+        L.oracle_svd_v.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -156,6 +158,19 @@ def sigma(R, max_sweeps=60, return_sweeps=False):
     if sw < 0:
         raise OracleError(f"oracle_sigma failed: {sw}")
     return (out, sw) if return_sweeps else out
+
+
+def svd_v(R, max_sweeps=60):
+    """Singular values (descending) and right singular vectors of a square R by one-sided
+    Jacobi with the rotations accumulated: V[:, j] belongs to sigma[j]."""
+    R = np.ascontiguousarray(np.asarray(R, dtype=np.float64))
+    N = R.shape[0]
+    s = np.zeros(N, dtype=np.float64)
+    V = np.zeros((N, N), dtype=np.float64)
+    sw = lib().oracle_svd_v(_p(R), N, N, _p(s), _p(V), N, max_sweeps)
+    if sw < 0:
+        raise OracleError(f"oracle_svd_v failed: {sw}")
+    return s, V
 
 
 def sort_table(X, keys):

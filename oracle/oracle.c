@@ -387,4 +387,85 @@ int oracle_sigma(const double *R, int64_t N, int64_t ldr, double *sigma, int max
     return sweeps;
 }
 
+/*
+ * Right singular vectors (Abstract: the right singular vectors of the join;
+ * Related Works: the SVD of the join through its R).  The one-sided Jacobi of
+ * oracle_sigma, with every rotation also applied to the columns of V, which
+ * starts as the identity, so that on exit R V has orthogonal columns of norms
+ * sigma and V is orthogonal.  Outputs sigma descending (equal values in column
+ * order) and V row-major (ldv): V[i * ldv + j] is component i of the right
+ * singular vector of sigma[j].  Returns the sweeps taken or a negative code.
+ */
+int oracle_svd_v(const double *R, int64_t N, int64_t ldr, double *sigma, double *V, int64_t ldv, int max_sweeps)
+{
+    if (N <= 0 || ldr < N || ldv < N) return ORACLE_EINVAL;
+    double *C = (double *)malloc(sizeof(double) * (size_t)N * (size_t)N);
+    double *Q = (double *)malloc(sizeof(double) * (size_t)N * (size_t)N);
+    double *nrm = (double *)malloc(sizeof(double) * (size_t)N);
+    int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    for (int64_t i = 0; i < N; i++)
+        for (int64_t k = 0; k < N; k++) {
+            C[k * N + i] = R[i * ldr + k];
+            Q[k * N + i] = (i == k) ? 1.0 : 0.0;
+        }
+    const double tol = (double)N * ldexp(1.0, -53);
+    int sweeps = 0;
+    for (; sweeps < max_sweeps;) {
+        int64_t rotations = 0;
+        for (int64_t p = 0; p < N - 1; p++) {
+            for (int64_t q = p + 1; q < N; q++) {
+                double *cp = C + p * N, *cq = C + q * N;
+                double alpha = 0.0, beta = 0.0, gamma = 0.0;
+                for (int64_t i = 0; i < N; i++) {
+                    alpha += cp[i] * cp[i];
+                    beta += cq[i] * cq[i];
+                    gamma += cp[i] * cq[i];
+                }
+                if (fabs(gamma) <= tol * sqrt(alpha * beta)) continue;
+                const double zeta = (beta - alpha) / (2.0 * gamma);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = c * t;
+                double *vp = Q + p * N, *vq = Q + q * N;
+                for (int64_t i = 0; i < N; i++) {
+                    const double xp = cp[i], xq = cq[i];
+                    cp[i] = c * xp - s * xq;
+                    cq[i] = s * xp + c * xq;
+                    const double yp = vp[i], yq = vq[i];
+                    vp[i] = c * yp - s * yq;
+                    vq[i] = s * yp + c * yq;
+                }
+                rotations++;
+            }
+        }
+        sweeps++;
+        if (rotations == 0) break;
+    }
+    for (int64_t k = 0; k < N; k++) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < N; i++) acc += C[k * N + i] * C[k * N + i];
+        nrm[k] = sqrt(acc);
+        ord[k] = k;
+    }
+    /* descending by norm, equal norms in column order (insertion sort: stable) */
+    for (int64_t a = 1; a < N; a++) {
+        const int64_t x = ord[a];
+        int64_t b = a - 1;
+        while (b >= 0 && nrm[ord[b]] < nrm[x]) {
+            ord[b + 1] = ord[b];
+            b--;
+        }
+        ord[b + 1] = x;
+    }
+    for (int64_t j = 0; j < N; j++) {
+        sigma[j] = nrm[ord[j]];
+        for (int64_t i = 0; i < N; i++) V[i * ldv + j] = Q[ord[j] * N + i];
+    }
+    free(C);
+    free(Q);
+    free(nrm);
+    free(ord);
+    return sweeps;
+}
+
 int oracle_num_threads(void) { return nthreads(); }

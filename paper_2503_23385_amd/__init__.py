@@ -66,7 +66,8 @@ EXPORTS = [
     "figaro_sigma_workspace_size", "figaro_sigma", "figaro_sigma_jacobi", "figaro_sigma_bidiag", "figaro_status", "figaro_last_error",
     "figaro_plan_create", "figaro_plan_workspace_size", "figaro_plan_offsets",
     "figaro_plan_execute", "figaro_plan_execute_eager", "figaro_plan_destroy", "figaro_plan_autotune",
-    "figaro_sort_workspace_size", "figaro_sort_table", "figaro_memory_report",
+    "figaro_sort_workspace_size", "figaro_sort_table", "figaro_memory_report", "figaro_svd_workspace_size",
+    "figaro_svd",
     "figaro_r_autotune", "figaro_tune_load", "figaro_tune_save", "figaro_tune_dump", "figaro_timing_enable", "figaro_timing_read",
     "figaro_sigma_noalloc",
 ]
@@ -104,6 +105,8 @@ def lib():
     L.figaro_plan_execute_eager.argtypes = [P, P, SZ, P, P, P]
     L.figaro_plan_autotune.argtypes = [P, P, SZ, P, P, P]
     L.figaro_r_autotune.argtypes = [TP, TP, I32, P, I64, P, SZ, P]
+    L.figaro_svd_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
+    L.figaro_svd.argtypes = [P, I64, I64, P, P, I64, P, SZ, P]
     L.figaro_sort_workspace_size.argtypes = [I64, ctypes.POINTER(SZ)]
     L.figaro_sort_table.argtypes = [TP, P, I64, P, P, SZ, P]
     L.figaro_memory_report.argtypes = [TP, TP, I32, P, SZ, P, ctypes.POINTER(Memory)]
@@ -330,6 +333,25 @@ def r_autotune(A, B, keys_A=None, keys_B=None, precision="fp64", two_sided=False
     _check(lib().figaro_r_autotune(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided),
                                    ctypes.c_void_p(out.data_ptr()), out.stride(0), ctypes.c_void_p(ws.data_ptr()),
                                    ws.numel(), _stream_ptr(stream)))
+
+
+def svd(R, stream=None):
+    """Singular values (descending) and right singular vectors V (column j for sigma[j]) of a
+    square FP64 device matrix R, n <= 128.  Returns (sigma, V)."""
+    torch = _torch()
+    require_device("R", R)
+    if R.dtype != torch.float64 or R.dim() != 2 or R.shape[0] != R.shape[1] or R.stride(1) != 1:
+        raise ValueError("R must be a square FP64 matrix with unit column stride")
+    n = R.shape[0]
+    nb = ctypes.c_size_t(0)
+    _check(lib().figaro_svd_workspace_size(n, ctypes.byref(nb)))
+    ws = alloc_workspace(nb.value, R.device)
+    S = torch.empty(n, dtype=torch.float64, device=R.device)
+    V = torch.empty((n, n), dtype=torch.float64, device=R.device)
+    _check(lib().figaro_svd(ctypes.c_void_p(R.data_ptr()), n, R.stride(0), ctypes.c_void_p(S.data_ptr()),
+                            ctypes.c_void_p(V.data_ptr()), n, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                            _stream_ptr(stream)))
+    return S, V
 
 
 def sort_table(X, keys, stream=None):

@@ -298,6 +298,12 @@ hipError_t launch_sort_table(const void *X, int elem_bytes, int64_t ld, int64_t 
 int64_t jacobi_scratch_doubles(int n);
 hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
                          int32_t *ctrl, double *scratch, hipStream_t s);
+// Singular values and right singular vectors of R (n <= 128): one-sided Jacobi that also
+// rotates V (scratch: svd_v_scratch_doubles(n), V's columns during the sweeps); V (n x n,
+// ld ldv) row i, column k = component i of the k-th right singular vector (sigma descending).
+int64_t svd_v_scratch_doubles(int n);
+hipError_t launch_svd_v(const double *R, int n, int64_t ldr, double *sigma, double *V, int64_t ldv, int max_sweeps,
+                        int32_t *ctrl, double *scratch, hipStream_t s);
 // The bidiagonal route for n <= 128: bidiagonalisation + multisection (ctrl[0] = 0 sweeps).
 int64_t sigma_bidiag_scratch_doubles(int n);  // multisection inputs of the bidiagonal route (n <= 128)
 // bidiagonalisation of R (one workgroup), leaving the multisection inputs in msin

@@ -812,6 +812,32 @@ int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, 
     return sigma_bidiag(R, n, ldr, sigma, ws, (hipStream_t)stream);
 }
 
+int figaro_svd_workspace_size(int64_t n, size_t *bytes)
+{
+    if (n < 1 || n > 128) return fail(FIGARO_EINVAL, "n out of range [1, 128] for the singular vectors");
+    if (!bytes) return fail(FIGARO_EINVAL, "bytes is NULL");
+    *bytes = kAlign + sizeof(double) * (size_t)svd_v_scratch_doubles((int)n);
+    return FIGARO_OK;
+}
+
+int figaro_svd(const double *R, int64_t n, int64_t ldr, double *sigma, double *V, int64_t ldv, void *ws,
+               size_t ws_bytes, void *stream)
+{
+    if (n < 1 || n > 128) return fail(FIGARO_EINVAL, "n out of range [1, 128] for the singular vectors");
+    if (!R || !sigma || !V) return fail(FIGARO_EINVAL, "R, sigma or V is NULL");
+    if (ldr < n || ldv < n) return fail(FIGARO_EINVAL, "ldr or ldv < n");
+    if (!ws) return fail(FIGARO_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(FIGARO_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    figaro_svd_workspace_size(n, &need);
+    if (ws_bytes < need) return fail(FIGARO_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    Stage st("svd_v", (hipStream_t)stream);
+    hipError_t e = launch_svd_v(R, (int)n, ldr, sigma, V, ldv, 60, (int32_t *)ws, at<double>(ws, kAlign),
+                                (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "singular vectors");
+    return FIGARO_OK;
+}
+
 // ------------------------------------------------------------ sigma without allocation
 //
 // The workspace of figaro_sigma for every n <= FIGARO_MAX_N (a 256-byte control block and

@@ -101,9 +101,12 @@ struct JacobiGeom {
     static constexpr int LDC = NPC + LP;
 };
 
+// With Vc (global, NPC columns of NPC doubles, column-major) the rotations are also
+// applied to the columns of V, which starts as the identity: R V = U Sigma, and V (n x n,
+// ld ldv) receives the right singular vectors in the order of sigma.
 template <int NPC, int LP>
 __device__ __forceinline__ void jacobi_lds_body(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps,
-                                int32_t *sweeps_out)
+                                int32_t *sweeps_out, double *Vc = nullptr, double *V = nullptr, int64_t ldv = 0)
 {
     using Gm = JacobiGeom<NPC, LP>;
     constexpr int RPL = Gm::RPL, PAIRS = Gm::PAIRS, LDC = Gm::LDC;
@@ -142,6 +145,7 @@ __device__ __forceinline__ void jacobi_lds_body(const double *R, int n, int64_t 
     for (int e = tid; e < NPC * NPC; e += nthr) {
         double &x = C[(e / NPC) * LDC + e % NPC];
         x = ldexp(x, -ex);
+        if (Vc) Vc[e] = (e / NPC == e % NPC) ? 1.0 : 0.0;
     }
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; sweep++) {
@@ -193,6 +197,20 @@ __device__ __forceinline__ void jacobi_lds_body(const double *R, int n, int64_t 
                     cp[r * LP] = c * xp[r] - s * xq[r];
                     cq[r * LP] = s * xp[r] + c * xq[r];
                 }
+                if (Vc) {
+                    double *vp = Vc + p * NPC + sub, *vq = Vc + q * NPC + sub;
+                    double yp[RPL], yq[RPL];
+#pragma unroll
+                    for (int r = 0; r < RPL; r++) {
+                        yp[r] = vp[r * LP];
+                        yq[r] = vq[r * LP];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RPL; r++) {
+                        vp[r * LP] = c * yp[r] - s * yq[r];
+                        vq[r * LP] = s * yp[r] + c * yq[r];
+                    }
+                }
                 if (sub == 0) s_rot = 1;
             }
             __syncthreads();
@@ -216,6 +234,8 @@ __device__ __forceinline__ void jacobi_lds_body(const double *R, int n, int64_t 
             rank += (u > v) || (u == v && j < k);
         }
         sigma[rank] = v;
+        if (V)
+            for (int i = 0; i < n; i++) V[(int64_t)i * ldv + rank] = Vc[k * NPC + i];
     }
     if (tid == 0 && sweeps_out) *sweeps_out = sweeps;
 }
@@ -225,6 +245,14 @@ __global__ __launch_bounds__((JacobiGeom<NPC, LP>::THREADS))
 void k_jacobi_lds(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps, int32_t *sweeps_out)
 {
     jacobi_lds_body<NPC, LP>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+}
+
+template <int NPC, int LP>
+__global__ __launch_bounds__((JacobiGeom<NPC, LP>::THREADS))
+void k_jacobi_v(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps, int32_t *sweeps_out, double *Vc,
+                double *V, int64_t ldv)
+{
+    jacobi_lds_body<NPC, LP>(R, n, ldr, sigma, max_sweeps, sweeps_out, Vc, V, ldv);
 }
 
 // Lanes per pair for a width class: FIGARO_JACOBI_LP (4, 8 or 16) when it is set and
@@ -255,6 +283,16 @@ hipError_t launch_npc(const double *R, int n, int64_t ldr, double *sigma, int ma
         return hipGetLastError();
     }
     k_jacobi_lds<NPC, 4><<<1, JacobiGeom<NPC, 4>::THREADS, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out);
+    return hipGetLastError();
+}
+
+template <int NPC>
+hipError_t launch_v_npc(const double *R, int n, int64_t ldr, double *sigma, int max_sweeps, int32_t *sweeps_out,
+                        double *Vc, double *V, int64_t ldv, hipStream_t s)
+{
+    constexpr int LP = NPC <= 8 ? NPC : 16;
+    k_jacobi_v<NPC, LP><<<1, JacobiGeom<NPC, LP>::THREADS, 0, s>>>(R, n, ldr, sigma, max_sweeps, sweeps_out, Vc, V,
+                                                                    ldv);
     return hipGetLastError();
 }
 
@@ -934,6 +972,23 @@ hipError_t launch_gk(const double *R, int n, int64_t ldr, int32_t *ctrl, double 
 }
 
 }  // namespace
+
+int64_t svd_v_scratch_doubles(int n)
+{
+    const int npc = n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128;
+    return (int64_t)npc * npc;
+}
+
+hipError_t launch_svd_v(const double *R, int n, int64_t ldr, double *sigma, double *V, int64_t ldv, int max_sweeps,
+                        int32_t *ctrl, double *scratch, hipStream_t s)
+{
+    if (n < 1 || n > 128) return hipErrorInvalidValue;
+    if (n <= 8) return launch_v_npc<8>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, V, ldv, s);
+    if (n <= 16) return launch_v_npc<16>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, V, ldv, s);
+    if (n <= 32) return launch_v_npc<32>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, V, ldv, s);
+    if (n <= 64) return launch_v_npc<64>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, V, ldv, s);
+    return launch_v_npc<128>(R, n, ldr, sigma, max_sweeps, ctrl, scratch, V, ldv, s);
+}
 
 int64_t sigma_bidiag_scratch_doubles(int n) { return n <= 128 ? 2 * (int64_t)n + 2 : 0; }
 

@@ -360,3 +360,48 @@ def test_sort_table_matches_brute_force(seed):
     assert np.array_equal(ks, keys[order])
     assert np.array_equal(Xs, X[order])
     assert np.all(np.diff(ks.astype(np.int64)) >= 0)
+
+
+# ------------------------------------------------------------------ right singular vectors
+
+def _sign_fix(V):
+    """Each column's entry of largest magnitude made positive (the sign is free)."""
+    idx = np.argmax(np.abs(V), axis=0)
+    sg = np.sign(V[idx, np.arange(V.shape[1])])
+    sg[sg == 0] = 1.0
+    return V * sg[None, :]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_svd_v_invariants_and_lapack(seed):
+    """V orthogonal, R V with orthogonal columns of norms sigma, sigma equal to oracle_sigma's,
+    and V equal (up to column signs) to LAPACK's right singular vectors of R."""
+    rng = W.rng_for(121, seed)
+    n = [5, 16, 33, 64][seed]
+    R = np.triu(rng.standard_normal((n, n)))
+    s, V = oracle.svd_v(R)
+    assert np.allclose(s, oracle.sigma(R), rtol=1e-13, atol=0)
+    assert np.abs(V.T @ V - np.eye(n)).max() < 1e-13
+    RV = R @ V
+    assert np.abs(RV.T @ RV - np.diag(s ** 2)).max() < 1e-12 * s[0] ** 2
+    _, sl, Vt = np.linalg.svd(R)
+    assert np.allclose(s, sl, rtol=1e-12)
+    assert np.abs(_sign_fix(V) - _sign_fix(Vt.T)).max() < 1e-9
+
+
+def test_svd_v_of_join_matches_lapack():
+    """The right singular vectors of the join (through the oracle's R) against LAPACK on the
+    explicit join."""
+    rng = W.rng_for(122)
+    inst = W.random_instance(rng, 40, 3, 30, 4, n_values=5)
+    J = join_matrix(inst)
+    s, V = oracle.svd_v(oracle.r(inst))
+    _, sl, Vt = np.linalg.svd(J)
+    assert np.allclose(s, sl, rtol=1e-12)
+    assert np.abs(_sign_fix(V) - _sign_fix(Vt.T)).max() < 1e-9
+
+
+def test_svd_v_diagonal():
+    s, V = oracle.svd_v(np.diag([1.0, -3.0, 2.0]))
+    assert np.array_equal(s, [3.0, 2.0, 1.0])
+    assert np.array_equal(np.abs(V), np.array([[0, 0, 1], [1, 0, 0], [0, 1, 0]], dtype=float))
