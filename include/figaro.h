@@ -37,7 +37,7 @@ extern "C" {
 
 /* ------------------------------------------------------------- codes */
 #define FIGARO_OK 0
-#define FIGARO_EINVAL (-1)      /* invalid argument (null pointer, ld < cols, dtype mismatch, N = 0, keys on one side only, unsupported width) */
+#define FIGARO_EINVAL (-1)      /* invalid argument (null pointer, ld < cols, dtype mismatch, N = 0, keys on one side only, unsupported width or route) */
 #define FIGARO_EUNSORTED (-2)   /* keys not non-decreasing (detected on the device, reported by figaro_status) */
 #define FIGARO_EWORKSPACE (-3)  /* workspace smaller than the size query returned */
 #define FIGARO_EHIP (-4)        /* HIP runtime error; see figaro_last_error() */
@@ -61,6 +61,18 @@ extern "C" {
  * and the m2_g - 1 rows [0 | sqrt(m1_g) T(B_g)].  Same R, fewer flops.
  */
 #define FIGARO_TWO_SIDED 0x100
+
+/*
+ * Flag OR'ed into `precision` (FP64 only): the Givens route.  After Claim 1,
+ * the compact matrix is reduced by Givens rotations entry by entry (Section 1:
+ * the continuation of Claim 1), in place of Householder reflectors: every
+ * region's rows are absorbed one at a time into the triangle of their leaf by
+ * plane rotations (one wave per leaf), and the leaves' triangles are merged the
+ * same way in a binary tree.  The root merges are those of the other routes.
+ * Every region must be at most 64 columns wide (the tails, and region 1 / the
+ * head rows of a natural join), else FIGARO_EINVAL.
+ */
+#define FIGARO_GIVENS 0x200
 
 /* largest supported join width N = n1 + n2 */
 #define FIGARO_MAX_N 512
@@ -199,6 +211,16 @@ int figaro_sigma_jacobi(const double *R, int64_t n, int64_t ldr, double *sigma,
  */
 int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma,
                         void *ws, size_t ws_bytes, void *stream);
+/*
+ * The squareroot-free route (Related Works: dqds, when only the singular values
+ * are required): the bidiagonalisation of figaro_sigma_bidiag, then the
+ * differential qd algorithm with shifts on the squared bidiagonal entries (one
+ * thread: shifted transforms, bottom deflation, a zero-shift repeat of any
+ * transform that would lose positivity).  Same arguments, workspace and n <= 128
+ * as figaro_sigma_bidiag.
+ */
+int figaro_sigma_dqds(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,
+                      void *stream);
 
 /*
  * figaro_sigma without a workspace argument, for callers that cannot allocate

@@ -25,10 +25,11 @@ FIGARO_F64 = 1
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_refine": 2}
 FIGARO_TWO_SIDED = 0x100
+FIGARO_GIVENS = 0x200
 
 
-def precision_code(precision, two_sided=False):
-    return PRECISIONS[precision] | (FIGARO_TWO_SIDED if two_sided else 0)
+def precision_code(precision, two_sided=False, givens=False):
+    return PRECISIONS[precision] | (FIGARO_TWO_SIDED if two_sided else 0) | (FIGARO_GIVENS if givens else 0)
 
 
 class FigaroError(RuntimeError):
@@ -67,7 +68,7 @@ EXPORTS = [
     "figaro_plan_create", "figaro_plan_workspace_size", "figaro_plan_offsets",
     "figaro_plan_execute", "figaro_plan_execute_eager", "figaro_plan_destroy", "figaro_plan_autotune",
     "figaro_sort_workspace_size", "figaro_sort_table", "figaro_memory_report", "figaro_svd_workspace_size",
-    "figaro_svd",
+    "figaro_svd", "figaro_sigma_dqds",
     "figaro_r_autotune", "figaro_tune_load", "figaro_tune_save", "figaro_tune_dump", "figaro_timing_enable", "figaro_timing_read",
     "figaro_sigma_noalloc",
 ]
@@ -94,6 +95,7 @@ def lib():
     L.figaro_sigma.argtypes = [P, I64, I64, P, P, SZ, P]
     L.figaro_sigma_jacobi.argtypes = [P, I64, I64, P, P, SZ, P]
     L.figaro_sigma_bidiag.argtypes = [P, I64, I64, P, P, SZ, P]
+    L.figaro_sigma_dqds.argtypes = [P, I64, I64, P, P, SZ, P]
     L.figaro_sigma_noalloc.argtypes = [P, I64, I64, P, P]
     L.figaro_status.argtypes = [P, P, ctypes.POINTER(I32)]
     L.figaro_last_error.argtypes = []
@@ -177,11 +179,11 @@ def make_table(X, keys=None) -> Table:
                  _dtype_code(X), keys.data_ptr() if keys is not None else None)
 
 
-def r_workspace_size(A, B, keys_A=None, keys_B=None, precision="fp64", two_sided=False) -> int:
+def r_workspace_size(A, B, keys_A=None, keys_B=None, precision="fp64", two_sided=False, givens=False) -> int:
     ta, tb = make_table(A, keys_A), make_table(B, keys_B)
     n = ctypes.c_size_t(0)
     _check(lib().figaro_r_workspace_size(ctypes.byref(ta), ctypes.byref(tb),
-                                         precision_code(precision, two_sided), ctypes.byref(n)))
+                                         precision_code(precision, two_sided, givens), ctypes.byref(n)))
     return n.value
 
 
@@ -191,21 +193,22 @@ def alloc_workspace(nbytes, device):
 
 
 def r(A, B, keys_A=None, keys_B=None, precision="fp64", ws=None, out=None, stream=None,
-      two_sided=False):
-    """R (N x N, FP64, diag >= 0) of the join of A and B on the device.  Returns (R, ws)."""
+      two_sided=False, givens=False):
+    """R (N x N, FP64, diag >= 0) of the join of A and B on the device.  Returns (R, ws).
+    givens: reduce the compact matrix by Givens rotations (FP64) instead of Householder."""
     torch = _torch()
     ta, tb = make_table(A, keys_A), make_table(B, keys_B)
     require_device("B", B, A.device)
     N = A.shape[1] + B.shape[1]
     if ws is None:
-        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision, two_sided), A.device)
+        ws = alloc_workspace(r_workspace_size(A, B, keys_A, keys_B, precision, two_sided, givens), A.device)
     if out is None:
         out = torch.empty((N, N), dtype=torch.float64, device=A.device)
     require_device("ws", ws, A.device)
     require_device("out", out, A.device)
     if out.dtype != torch.float64 or out.dim() != 2 or out.shape[0] < N or out.shape[1] < N or out.stride(1) != 1:
         raise ValueError("out must be an FP64 N x N (or larger) matrix with unit column stride")
-    _check(lib().figaro_r(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided),
+    _check(lib().figaro_r(ctypes.byref(ta), ctypes.byref(tb), precision_code(precision, two_sided, givens),
                           ctypes.c_void_p(out.data_ptr()), out.stride(0),
                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
     return out, ws
@@ -221,7 +224,8 @@ def sigma(R, out=None, ws=None, stream=None, method="default"):
     """Singular values (descending, FP64) of a square device matrix R.
 
     method: "default" (bidiagonal route for n <= 128, Jacobi above), "jacobi" (one-sided
-    Jacobi, any n <= 512) or "bidiag" (bidiagonalisation + multisection, n <= 128)."""
+    Jacobi, any n <= 512), "bidiag" (bidiagonalisation + multisection, n <= 128) or "dqds"
+    (bidiagonalisation + dqds, n <= 128)."""
     torch = _torch()
     require_device("R", R)
     if R.dtype != torch.float64 or R.dim() != 2 or R.shape[0] != R.shape[1] or R.stride(1) != 1:
@@ -235,7 +239,8 @@ def sigma(R, out=None, ws=None, stream=None, method="default"):
     require_device("ws", ws, R.device)
     if out.dtype != torch.float64 or out.numel() < n:
         raise ValueError("out must hold n FP64 values")
-    fns = {"default": lib().figaro_sigma, "jacobi": lib().figaro_sigma_jacobi, "bidiag": lib().figaro_sigma_bidiag}
+    fns = {"default": lib().figaro_sigma, "jacobi": lib().figaro_sigma_jacobi, "bidiag": lib().figaro_sigma_bidiag,
+           "dqds": lib().figaro_sigma_dqds}
     if method not in fns:
         raise ValueError(f"unknown sigma method {method!r}")
     fn = fns[method]

@@ -197,6 +197,9 @@ struct TreeRegion {
 // per leaf, or one wave per leaf when wave_tree is set.
 hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
                             hipStream_t s, int wave_tree = 0);
+// One or two regions of padded width np <= 64 by Givens rotations (one wave per leaf, rows
+// absorbed one at a time; FP64), tree nodes as in the wave tree.
+hipError_t launch_givens_tree(int np, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s);
 // A batch of regions of padded width np <= 64 in one launch: device table regs, and
 // map[i] = (region, leaf) for each of the nitems leaves (leaves beyond what a region's
 // device-side row count needs exit at once).  wave_tree: one wave per leaf (triangles
@@ -310,6 +313,8 @@ int64_t sigma_bidiag_scratch_doubles(int n);  // multisection inputs of the bidi
 hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s);
 // multisection: one workgroup per singular value
 hipError_t launch_sigma_msect(const double *msin, int n, double *sigma, hipStream_t s);
+// dqds on the same inputs (the squared bidiagonal entries), one thread
+hipError_t launch_sigma_dqds(const double *msin, int n, double *sigma, hipStream_t s);
 // Width class (padded n: 8..128) of the bidiagonal route; 0 above 128.
 int sigma_width_class(int n);
 // Independent problems of one width class by the bidiagonal route, two launches; tab

@@ -126,6 +126,7 @@ struct Shape {
     bool keyed;
     int precision;  // FIGARO_PLAIN_FP64 / FIGARO_MIXED_FP32 / FIGARO_MIXED_FP32_REFINE
     bool two_sided;
+    bool givens;    // regions reduced by Givens rotations (FIGARO_GIVENS)
     int64_t N() const { return n1 + n2; }
 };
 
@@ -139,6 +140,7 @@ struct Region {
     int width, col_off, np;
     bool wave;                // narrow tree kernel (np <= 64); else the panel tree kernel
     bool wave_tree;           // narrow regions: one wave per leaf (else one workgroup per leaf)
+    bool givens;              // narrow regions: leaves absorb rows by Givens rotations
     bool skip;                // rows absorbed directly by the root merge (no tree of its own)
     int leaves, arity;        // most leaves; tree arity
     int64_t nslots, ncnt;     // node triangles and counters reserved (for every tuning candidate)
@@ -190,7 +192,7 @@ int make_shape(const figaro_table *A, const figaro_table *B, int32_t precision, 
     if ((A->keys == nullptr) != (B->keys == nullptr))
         return fail(FIGARO_EINVAL, "keys must be given for both tables or for neither");
     const int prec = precision & kPrecMask;
-    if ((precision & ~(kPrecMask | FIGARO_TWO_SIDED)) != 0 ||
+    if ((precision & ~(kPrecMask | FIGARO_TWO_SIDED | FIGARO_GIVENS)) != 0 ||
         (prec != FIGARO_PLAIN_FP64 && prec != FIGARO_MIXED_FP32 && prec != FIGARO_MIXED_FP32_REFINE))
         return fail(FIGARO_EINVAL, "unknown precision or flag");
     const int64_t N = A->cols + B->cols;
@@ -206,6 +208,15 @@ int make_shape(const figaro_table *A, const figaro_table *B, int32_t precision, 
     sh->keyed = A->keys != nullptr;
     sh->precision = prec;
     sh->two_sided = (precision & FIGARO_TWO_SIDED) != 0;
+    sh->givens = (precision & FIGARO_GIVENS) != 0;
+    if (sh->givens) {
+        if (prec != FIGARO_PLAIN_FP64) return fail(FIGARO_EINVAL, "the Givens route runs in FP64 only");
+        // every region must be narrow: the tails (both forms), region 1 / the head rows
+        // (N wide) unless a Cartesian product's single head row goes to the root
+        const bool wide_rows = !sh->two_sided || sh->keyed;
+        if (A->cols > 64 || B->cols > 64 || (wide_rows && N > 64))
+            return fail(FIGARO_EINVAL, "the Givens route takes regions up to 64 columns");
+    }
     return FIGARO_OK;
 }
 
@@ -252,10 +263,13 @@ void apply_tree(Region &r, const TreeTune &t, int acc_f64)
 // kernel and leaf length of the tuning table; their node storage is sized for every
 // candidate the autotuner may switch to, so that the workspace size does not depend on
 // the tuning.  Wide regions take the panel tree with leaves of 4 panel blocks.
+constexpr int64_t kGivensLeafRows = 256;
+
 Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int col_off, int acc_f64,
-                   bool batched = false)
+                   bool batched = false, bool givens = false)
 {
     Region r;
+    r.givens = false;
     r.name = name;
     r.rows_cap = std::max<int64_t>(0, rows_cap);
     r.cnt = cnt;
@@ -272,6 +286,17 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
         r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxPanelLeaves));
         r.arity = 2;
         tsqr_panel_tree_sizes(r.leaves, &r.nslots, &r.ncnt);
+        return r;
+    }
+    if (givens) {
+        // rows absorbed one at a time by one wave per leaf: leaves of a fixed length, binary tree
+        r.givens = true;
+        r.wave_tree = true;
+        r.rows_per_leaf = kGivensLeafRows;
+        const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+        r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxWaveLeaves));
+        r.arity = 2;
+        tsqr_tree_sizes(r.leaves, r.arity, &r.nslots, &r.ncnt);
         return r;
     }
     const TuneKey key{acc_f64, r.np, batched ? 1 : 0, rows_log2(r.rows_cap)};
@@ -340,17 +365,17 @@ Layout make_layout(const Shape &s, bool batched = false)
     }
     const int N = (int)s.N();
     if (!s.two_sided) {
-        Region a = make_region("tsqr_m1", s.m1, CNT_R1, N, 0, L.m_f64, batched);
-        Region b = make_region("tsqr_m2", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64, batched);
+        Region a = make_region("tsqr_m1", s.m1, CNT_R1, N, 0, L.m_f64, batched, s.givens);
+        Region b = make_region("tsqr_m2", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64, batched, s.givens);
         a.buf = take(esz * std::max<int64_t>(1, a.rows_cap) * N);
         b.buf = take(esz * std::max<int64_t>(1, b.rows_cap) * s.n2);
         L.regions = {a, b};
     } else {
-        Region h = make_region("tsqr_heads", L.gcap, CNT_G, N, 0, L.m_f64, batched);
+        Region h = make_region("tsqr_heads", L.gcap, CNT_G, N, 0, L.m_f64, batched, s.givens);
         // Cartesian product: a single head row, absorbed by the root merge itself.
         h.skip = !s.keyed;
-        Region ta = make_region("tsqr_ta", s.m1 - 1, CNT_TA, (int)s.n1, 0, L.m_f64, batched);
-        Region tb = make_region("tsqr_tb", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64, batched);
+        Region ta = make_region("tsqr_ta", s.m1 - 1, CNT_TA, (int)s.n1, 0, L.m_f64, batched, s.givens);
+        Region tb = make_region("tsqr_tb", s.m2 - 1, CNT_R2, (int)s.n2, (int)s.n1, L.m_f64, batched, s.givens);
         h.buf = take(esz * h.rows_cap * N);
         ta.buf = take(esz * std::max<int64_t>(1, ta.rows_cap) * s.n1);
         tb.buf = take(esz * std::max<int64_t>(1, tb.rows_cap) * s.n2);
@@ -541,14 +566,15 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
         const char *name = r.name;
         for (size_t j = i + 1; j < nr && n < 2; j++) {
             if (!done[j] && !L.regions[j].skip && L.regions[j].np == r.np &&
-                L.regions[j].wave_tree == r.wave_tree) {
+                L.regions[j].wave_tree == r.wave_tree && L.regions[j].givens == r.givens) {
                 tr[n++] = tree_region(L.regions[j], L, ws);
                 done[j] = true;
                 name = "tsqr_tails";
             }
         }
         Stage st(name, s);
-        if (r.wave) HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s, r.wave_tree), "tsqr tree");
+        if (r.givens) HIPCHK(launch_givens_tree(r.np, L.m_f64, tr, n, s), "givens tree");
+        else if (r.wave) HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s, r.wave_tree), "tsqr tree");
         else HIPCHK(launch_tsqr_panel_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr panel tree");
     }
     return FIGARO_OK;
@@ -801,6 +827,25 @@ int figaro_sigma_jacobi(const double *R, int64_t n, int64_t ldr, double *sigma, 
     int rc = sigma_common(R, n, ldr, sigma, ws, ws_bytes);
     if (rc) return rc;
     return sigma_jacobi(R, n, ldr, sigma, ws, (hipStream_t)stream);
+}
+
+int figaro_sigma_dqds(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    int rc = sigma_common(R, n, ldr, sigma, ws, ws_bytes);
+    if (rc) return rc;
+    if (n > 128) return fail(FIGARO_EINVAL, "the dqds route takes n <= 128");
+    hipStream_t st = (hipStream_t)stream;
+    double *msin = at<double>(ws, kAlign);
+    {
+        Stage sg("sigma_bidiag", st);
+        hipError_t e = launch_sigma_bidiag(R, (int)n, ldr, (int32_t *)ws, msin, st);
+        if (e != hipSuccess) return hip_fail(e, "sigma bidiagonalisation");
+    }
+    Stage sg("sigma_dqds", st);
+    hipError_t e = launch_sigma_dqds(msin, (int)n, sigma, st);
+    if (e != hipSuccess) return hip_fail(e, "dqds");
+    return FIGARO_OK;
 }
 
 int figaro_sigma_bidiag(const double *R, int64_t n, int64_t ldr, double *sigma, void *ws, size_t ws_bytes,

@@ -964,6 +964,117 @@ __global__ __launch_bounds__(kMsThreads) void k_sigma_msect_batch(const int64_t 
     sigma_msect_body(msin + e[3], n, k, sigma + e[1]);
 }
 
+// ------------------------------------------------------------------ dqds
+//
+// The squareroot-free route for singular values alone (Related Works: dqds).  The
+// bidiagonal B (diagonal d, superdiagonal e) left by the bidiagonalisation is held as
+// q_i = d_i^2 and e_i = e_i^2 (the multisection inputs: the Golub-Kahan off-diagonals
+// squared, d_1^2, e_1^2, d_2^2, ...).  One differential qd transform with shift tau:
+//     d = q_1 - tau;  for i < N:  qh_i = d + e_i,  t = q_{i+1} / qh_i,  eh_i = e_i t,
+//                                 d = d t - tau;  qh_N = d,
+// maps the pair to that of B^T B - tau I with every quantity positive while tau is below
+// its smallest eigenvalue.  Transforms repeat until the last e is negligible; then
+// q_N + (the shifts so far) is an eigenvalue of B^T B and the bottom row is deflated.
+// Shifts: half the smallest d of the previous transform; a transform that would turn a
+// quantity negative is undone and repeated with tau = 0, which cannot fail.  A zero e
+// (split) passes d on unchanged.  One thread per problem (the transforms are a serial
+// recurrence); sigma = 2^ex sqrt(lambda), sorted descending.
+constexpr int kDqdsMaxN = 128;
+
+// qs, es: room for a copy of q and e (LDS), to undo a failed transform.
+__device__ void dqds_serial(double *q, double *e, int n, double scale2, double *lam, double *qs, double *es)
+{
+    const double eps = 0x1p-53;
+    const double tiny = eps * eps * scale2;  // squares below this are zero at the working precision
+    int N = n;
+    double S = 0.0;     // shifts applied to the active rows so far
+    double tau = 0.0;
+    int iters = 0;
+    const int max_iters = 64 * n + 64;
+    while (N > 0) {
+        if (N == 1) {
+            lam[0] = q[0] + S;
+            break;
+        }
+        const double en = e[N - 2];
+        if (en <= eps * (q[N - 1] + S) || en <= tiny || iters >= max_iters) {
+            lam[N - 1] = q[N - 1] + S;
+            N--;
+            tau = 0.0;
+            continue;
+        }
+        iters++;
+        for (int i = 0; i < N; i++) qs[i] = q[i];
+        for (int i = 0; i < N - 1; i++) es[i] = e[i];
+        bool ok;
+        double dmin;
+        for (;;) {
+            ok = true;
+            double d = q[0] - tau;
+            dmin = d;
+            if (d < 0.0) ok = false;
+            for (int i = 0; ok && i < N - 1; i++) {
+                if (e[i] == 0.0) {
+                    q[i] = d;
+                    d = q[i + 1] - tau;
+                } else {
+                    const double qh = d + e[i];
+                    if (!(qh > 0.0)) {
+                        ok = false;
+                        break;
+                    }
+                    const double t = q[i + 1] / qh;
+                    e[i] = e[i] * t;
+                    q[i] = qh;
+                    d = d * t - tau;
+                }
+                if (d < 0.0) ok = false;
+                dmin = fmin(dmin, d);
+            }
+            if (ok) {
+                q[N - 1] = d;
+                break;
+            }
+            // undo and repeat without a shift
+            for (int i = 0; i < N; i++) q[i] = qs[i];
+            for (int i = 0; i < N - 1; i++) e[i] = es[i];
+            if (tau == 0.0) {  // cannot happen in exact arithmetic; take the values as they are
+                dmin = 0.0;
+                break;
+            }
+            tau = 0.0;
+        }
+        S += tau;
+        tau = 0.5 * fmax(dmin, 0.0);
+    }
+}
+
+__device__ __forceinline__ void sigma_dqds_body(const double *msin, int n, double *sigma)
+{
+    __shared__ double q[kDqdsMaxN], e[kDqdsMaxN], lam[kDqdsMaxN], qs[kDqdsMaxN], es[kDqdsMaxN];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += blockDim.x) {
+        q[i] = msin[2 + 2 * i];
+        e[i] = i + 1 < n ? msin[3 + 2 * i] : 0.0;
+    }
+    __syncthreads();
+    const double bound = msin[0];
+    const int ex = (int)msin[1];
+    if (tid == 0) dqds_serial(q, e, n, bound * bound, lam, qs, es);
+    __syncthreads();
+    for (int k = tid; k < n; k += blockDim.x) {
+        const double v = lam[k];
+        int rank = 0;
+        for (int j = 0; j < n; j++) rank += (lam[j] > v) || (lam[j] == v && j < k);
+        sigma[rank] = ldexp(sqrt(fmax(v, 0.0)), ex);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_sigma_dqds(const double *msin, int n, double *sigma)
+{
+    sigma_dqds_body(msin, n, sigma);
+}
+
 template <int NPC>
 hipError_t launch_gk(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s)
 {
@@ -1001,6 +1112,13 @@ hipError_t launch_sigma_bidiag(const double *R, int n, int64_t ldr, int32_t *ctr
     if (n <= 64) return launch_gk<64>(R, n, ldr, ctrl, msin, s);
     if (n <= 128) return launch_gk<128>(R, n, ldr, ctrl, msin, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_sigma_dqds(const double *msin, int n, double *sigma, hipStream_t s)
+{
+    if (n <= 0 || n > kDqdsMaxN) return hipErrorInvalidValue;
+    k_sigma_dqds<<<1, 64, 0, s>>>(msin, n, sigma);
+    return hipGetLastError();
 }
 
 hipError_t launch_sigma_msect(const double *msin, int n, double *sigma, hipStream_t s)

@@ -889,6 +889,117 @@ hipError_t launch_tree_np(int acc_f64, int in_f64, const TreeRegion *regs, int n
 
 // One or two regions by waves (a single call): wave item i < reg0.nleaves is leaf i of
 // region 0, the rest leaves of region 1.
+// ------------------------------------------------------------------ Givens rotations (one wave per triangle)
+//
+// The continuation of Claim 1 entry by entry (Section 1): each new row x is absorbed
+// into R by plane rotations, column by column: the rotation of (R_jj, x_j) that zeroes
+// x_j touches row j of R and x only, and leaves zeros where they are.  Lane k holds
+// column k of R (row j in r[j], the loop over j unrolled so every index is static) and
+// entry k of the current row; the two scalars of step j come from lane j by lane reads.
+// R keeps a non-negative diagonal throughout (R_jj <- |(R_jj, x_j)|).  FP64.
+
+// Absorb rows [r0, r1) of src (one row at a time, the next row's load issued before the
+// current row's rotations).
+template <int NP, typename Tin>
+__device__ inline void gv_absorb_rows(double (&r)[NP], const RowSrc &src, int64_t r0, int64_t r1, int width, int k)
+{
+    const int c = k - src.col_off;
+    const bool col_in = k < width && c >= 0 && c < src.width;
+    const Tin *col = (const Tin *)src.p + (c < 0 ? 0 : (c < src.width ? c : src.width - 1));
+    if (r0 >= r1) return;
+    double xn = (double)col[r0 * src.ld];
+    for (int64_t row = r0; row < r1; row++) {
+        double x = col_in ? xn : 0.0;
+        if (row + 1 < r1) xn = (double)col[(row + 1) * src.ld];
+#pragma unroll
+        for (int j = 0; j < NP; j++) {
+            const double a = readlane_f64(r[j], j), b = readlane_f64(x, j);
+            const double q = fma(a, a, b * b);
+            // (columns past the width hold zeros: b = 0 leaves them alone)
+            if (b != 0.0 && q >= DBL_MIN) {
+                const double inv = rsq_refined(q);
+                const double cs = a * inv, sn = b * inv;
+                if (k > j) {
+                    const double rj = r[j];
+                    r[j] = fma(cs, rj, sn * x);
+                    x = fma(cs, x, -sn * rj);
+                } else if (k == j) {
+                    r[j] = q * inv;
+                    x = 0.0;
+                }
+            }
+        }
+    }
+}
+
+template <int NP>
+__device__ inline void gv_store(const double (&r)[NP], double *out, int width, int k)
+{
+#pragma unroll
+    for (int j = 0; j < NP; j++)
+        if (j < width && k < NP) out[(int64_t)j * NP + k] = (k >= j && k < width) ? r[j] : 0.0;
+}
+
+// Leaf g of region rg by one wave (rows by rotations), then the climb of its tree (the
+// last child absorbs its siblings' triangles, row by row, in child order).
+template <int NP, typename Tin>
+__device__ __forceinline__ void gv_leaf(const TreeRegion &rg, const int g, int lane)
+{
+    const int k = lane;
+    const int width = rg.width;
+    const int64_t rows = wave_uniform(src_rows(rg.src));
+    const int64_t want = (rows + rg.rows_per_leaf - 1) / rg.rows_per_leaf;
+    const int nleaves = (int)max((int64_t)1, min((int64_t)rg.nleaves, want));
+    if (g >= nleaves) return;
+    double r[NP];
+#pragma unroll
+    for (int j = 0; j < NP; j++) r[j] = 0.0;
+    const int64_t chunk = (rows + nleaves - 1) / nleaves;
+    const int64_t r0 = (int64_t)g * chunk, r1 = min(rows, r0 + chunk);
+    gv_absorb_rows<NP, Tin>(r, rg.src, r0, r1, width, k);
+    const int64_t tsz = (int64_t)width * NP;
+    const int A = rg.arity;
+    int node = g, n = nleaves;
+    int64_t soff = 0, coff = 0;
+    while (n > 1) {
+        const int parent = node / A, first = parent * A;
+        const int nchild = min(A, n - first);
+        if (nchild > 1) {
+            gv_store<NP>(r, rg.slots + (soff + node) * tsz, width, k);
+            __threadfence();
+            int old = 0;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(&rg.counters[coff + parent], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            old = __builtin_amdgcn_readfirstlane(old);
+            if (old != nchild - 1) return;  // the last child to arrive combines this node
+            __threadfence();
+            const double *T = rg.slots + (soff + first) * tsz;
+#pragma unroll
+            for (int j = 0; j < NP; j++) r[j] = (j < width && k < width) ? T[(int64_t)j * NP + k] : 0.0;
+            const RowSrc sib{rg.slots + (soff + first + 1) * tsz, nullptr, (int64_t)(nchild - 1) * width, NP, 0,
+                             width};
+            gv_absorb_rows<NP, double>(r, sib, 0, sib.rows_host, width, k);
+        }
+        node = parent;
+        soff += n;
+        coff += (n + A - 1) / A;
+        n = (n + A - 1) / A;
+    }
+    gv_store<NP>(r, rg.root, width, k);
+}
+
+// One or two regions by rotations: wave item i < reg0.nleaves is leaf i of region 0,
+// the rest leaves of region 1.
+template <int NP, typename Tin>
+__global__ __launch_bounds__(64 * kWtWaves) void k_givens_tree(TreeRegion reg0, TreeRegion reg1)
+{
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int item = (int)blockIdx.x * kWtWaves + wv;
+    if (item >= reg0.nleaves + reg1.nleaves) return;
+    const bool second = item >= reg0.nleaves;
+    gv_leaf<NP, Tin>(second ? reg1 : reg0, item - (second ? reg0.nleaves : 0), lane);
+}
+
 template <int NP, typename Tin, typename Tacc>
 __global__ __launch_bounds__(64 * kWtWaves) void k_tsqr_wtree(TreeRegion reg0, TreeRegion reg1)
 {
@@ -1001,6 +1112,24 @@ hipError_t launch_tsqr_stream(int np, int acc_f64, int in_f64, const double *ini
     case NPV: return launch_np<NPV>(acc_f64, in_f64, init, init_ld, s0, s1, nsrc, width, tri_rows, nwg, tri, tri_stride, s);
     FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64) FIGARO_CASE(128) FIGARO_CASE(256)
     FIGARO_CASE(512)
+#undef FIGARO_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_givens_tree(int np, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s)
+{
+    if (nreg < 1 || nreg > 2) return hipErrorInvalidValue;
+    TreeRegion r0 = regs[0];
+    TreeRegion r1 = nreg > 1 ? regs[1] : TreeRegion{};
+    const unsigned grid = (unsigned)((r0.nleaves + r1.nleaves + kWtWaves - 1) / kWtWaves);
+    switch (np) {
+#define FIGARO_CASE(NPV)                                                                      \
+    case NPV:                                                                                 \
+        if (in_f64) k_givens_tree<NPV, double><<<grid, 64 * kWtWaves, 0, s>>>(r0, r1);       \
+        else k_givens_tree<NPV, float><<<grid, 64 * kWtWaves, 0, s>>>(r0, r1);               \
+        return hipGetLastError();
+    FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64)
 #undef FIGARO_CASE
     default: return hipErrorInvalidValue;
     }

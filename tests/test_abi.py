@@ -56,7 +56,10 @@ def test_workspace_size_ok_and_monotone():
     (table(dtype=7), table(dtype=7), 0),                  # bad dtype
     (table(), table(), 9),                                # bad precision
     (table(cols=300), table(cols=300), 1),                # N > 512
-    (table(), table(), 0x200),                            # unknown flag
+    (table(), table(), 0x400),                            # unknown flag
+    (table(), table(), 0x201),                            # Givens route with FP32
+    (table(cols=40), table(cols=30), 0x200),              # Givens route, region 1 wider than 64
+    (table(cols=65), table(cols=3), 0x300),               # Givens route, a tail wider than 64
     (table(), table(), 0x101 | 0x400),                    # unknown flag beside a valid one
 ])
 def test_invalid_arguments_rejected_on_host(A, B, prec):

@@ -167,7 +167,7 @@ def test_cfg4_full_batch(prec):
 
 
 @pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3"])
-@pytest.mark.parametrize("method", ["jacobi", "bidiag"])
+@pytest.mark.parametrize("method", ["jacobi", "bidiag", "dqds"])
 def test_sigma_routes_on_oracle_r(name, method):
     """Both sigma routes (n <= 128) on the oracle's own R, against the oracle's sigma."""
     _, _, refs = workload(name)
@@ -178,7 +178,7 @@ def test_sigma_routes_on_oracle_r(name, method):
     assert es <= 1e-12
 
 
-@pytest.mark.parametrize("method", ["jacobi", "bidiag"])
+@pytest.mark.parametrize("method", ["jacobi", "bidiag", "dqds"])
 def test_sigma_routes_on_batch_r(method):
     """Every width class of the batch (n = 16, 32, 64, 128), each sigma route against the oracle."""
     _, _, refs = workload("cfg4")

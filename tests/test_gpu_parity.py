@@ -266,7 +266,7 @@ SPECIAL = special_matrices()
 
 
 @pytest.mark.parametrize("name", list(SPECIAL))
-@pytest.mark.parametrize("method", ["jacobi", "bidiag"])
+@pytest.mark.parametrize("method", ["jacobi", "bidiag", "dqds"])
 def test_sigma_routes_match_lapack(name, method):
     """Both sigma routes (one-sided Jacobi; bidiagonalisation + multisection) on special
     matrices against LAPACK's singular values (numpy.linalg.svd), normwise rel2 <= 1e-12."""
@@ -438,3 +438,44 @@ def test_plan_mixed_instances(prec, tol, two_sided):
             er = relF(Rg, Ro)
             es = np.linalg.norm(Sg - So) / np.linalg.norm(So)
             assert er <= tol and es <= tol, (rep, i, inst.shape, er, es)
+
+
+# ------------------------------------------------------------------ the Givens route
+
+@pytest.mark.parametrize("name", ["cart_tiny", "cart_ragged", "cart_uniform_paper", "keyed_zipf_n64",
+                                  "keyed_uniform_sparse", "keyed_one_big_group", "keyed_narrow", "keyed_singleton_B",
+                                  "cart_tail_leaf", "cart_n125_ragged"])
+@pytest.mark.parametrize("form", ["claim1", "two_sided"])
+def test_givens_route(name, form):
+    """R by Givens rotations entry by entry after Claim 1 (Section 1) against the oracle's R."""
+    inst = CASES[name]
+    N = inst.A.shape[1] + inst.B.shape[1]
+    two = form == "two_sided"
+    if N > 64 and not (two and inst.keys_A is None):
+        pytest.skip("the Givens route takes regions up to 64 columns")
+    say(f"[givens] {name} {form}")
+    A, B, kA, kB = to_dev(inst)
+    R, ws = fg().r(A, B, kA, kB, "fp64", two_sided=two, givens=True)
+    S = fg().sigma(R)
+    torch.cuda.synchronize()
+    assert fg().status(ws) == 0
+    Ro, So = oracle_results(inst)
+    Rg = R.cpu().numpy()
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) >= 0)
+    d = np.abs(np.diag(Ro))
+    if d.size and d.min() <= 1e-10 * max(d.max(), 1e-300):
+        Gm = gram_closed_form(inst)
+        assert np.allclose(Rg.T @ Rg, Gm, rtol=1e-10, atol=1e-10 * max(1, np.abs(Gm).max()))
+        return
+    er = relF(Rg, Ro)
+    es = np.linalg.norm(S.cpu().numpy() - So) / np.linalg.norm(So)
+    say(f"    relF(R)={er:.3e} rel2(sigma)={es:.3e}")
+    assert er <= 1e-12 and es <= 1e-12
+
+
+def test_givens_route_full_cfg2():
+    inst = W.config2()
+    A, B, kA, kB = to_dev(inst)
+    R, ws = fg().r(A, B, kA, kB, "fp64", two_sided=True, givens=True)
+    torch.cuda.synchronize()
+    assert relF(R.cpu().numpy(), oracle.r(inst)) <= 1e-12
