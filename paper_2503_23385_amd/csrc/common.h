@@ -321,6 +321,6 @@ int sigma_width_class(int n);
 // (device): 4 int64 per problem (element offset of its R in R, of its sigma in sigma, n,
 // of its 2n + 2 multisection doubles in msin), R packed n x n (ld n).
 hipError_t launch_sigma_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count, double *msin,
-                              hipStream_t s);
+                              hipStream_t s, int dqds = 0);  // dqds: the values by dqds, else by multisection
 
 }  // namespace figaro

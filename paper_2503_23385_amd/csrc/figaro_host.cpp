@@ -1359,9 +1359,10 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
         const int n = (int)(tab.size() / 4);
         double *msin = at<double>(ws, plan->msin_off);
         const char *name = class_name(kSigmaNames, c);
+        const int dqds = tune_get(TuneKey{TUNE_SIGMA, c, 1, 0}).kind == SIGMA_DQDS;
         P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
             Stage st(name, s);
-            HIPCHK(launch_sigma_batch(c, R, sigma, (const int64_t *)(t + off), n, msin, s), "batched sigma");
+            HIPCHK(launch_sigma_batch(c, R, sigma, (const int64_t *)(t + off), n, msin, s, dqds), "batched sigma");
             return FIGARO_OK;
         });
     }
@@ -1625,6 +1626,40 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         for (int l : kv.second) tune_set(TuneKey{acc, np, 1, l}, best, best_ms / kTuneReps);
     }
     plan_relayout(plan);
+    // sigma route per width class (multisection or dqds after the bidiagonalisation)
+    std::vector<int> scls;
+    for (const Shape &sh : plan->shapes) {
+        const int c = sigma_width_class((int)sh.N());
+        if (c && std::find(scls.begin(), scls.end(), c) == scls.end()) scls.push_back(c);
+    }
+    for (int c : scls) {
+        const TuneKey key{TUNE_SIGMA, c, 1, 0};
+        const char *stage = class_name(kSigmaNames, c);
+        double best_ms = 1e300;
+        TreeTune best = tune_default(key);
+        for (const TreeTune &cand : tune_candidates(key)) {
+            tune_override(&key, &cand);
+            const Program prog = build_program(plan, ws, R, sigma);
+            figaro_plan::Exec *ex = nullptr;
+            rc = plan_exec(plan, ws, R, sigma, prog, &ex);
+            if (!rc) rc = run_program(prog, ex->tables, s);
+            double ms = 0.0;
+            if (!rc) rc = take_stage_ms([](const char *) { return false; }, &ms);
+            for (int i = 0; i < kTuneReps && !rc; i++) rc = run_program(prog, ex->tables, s);
+            if (!rc) rc = take_stage_ms([stage](const char *n) { return std::strcmp(n, stage) == 0; }, &ms);
+            plan_drop_execs(plan);
+            if (rc) {
+                tune_override(nullptr, nullptr);
+                return rc;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+        }
+        tune_override(nullptr, nullptr);
+        tune_set(key, best, best_ms / kTuneReps);
+    }
     return FIGARO_OK;
 }
 

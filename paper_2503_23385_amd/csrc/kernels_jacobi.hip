@@ -1075,6 +1075,13 @@ __global__ __launch_bounds__(64) void k_sigma_dqds(const double *msin, int n, do
     sigma_dqds_body(msin, n, sigma);
 }
 
+// Batched: workgroup b takes entry b of tab (entries as k_sigma_gk_batch).
+__global__ __launch_bounds__(64) void k_sigma_dqds_batch(const int64_t *tab, const double *msin, double *sigma)
+{
+    const int64_t *e = tab + 4 * (int64_t)blockIdx.x;
+    sigma_dqds_body(msin + e[3], (int)e[2], sigma + e[1]);
+}
+
 template <int NPC>
 hipError_t launch_gk(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s)
 {
@@ -1136,7 +1143,7 @@ int sigma_width_class(int n)
 }
 
 hipError_t launch_sigma_batch(int npc, const double *R, double *sigma, const int64_t *tab, int count, double *msin,
-                              hipStream_t s)
+                              hipStream_t s, int dqds)
 {
     if (count <= 0) return hipSuccess;
     switch (npc) {
@@ -1149,7 +1156,8 @@ hipError_t launch_sigma_batch(int npc, const double *R, double *sigma, const int
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_sigma_msect_batch<<<dim3(npc, count), kMsThreads, 0, s>>>(tab, msin, sigma);
+    if (dqds) k_sigma_dqds_batch<<<count, 64, 0, s>>>(tab, msin, sigma);
+    else k_sigma_msect_batch<<<dim3(npc, count), kMsThreads, 0, s>>>(tab, msin, sigma);
     return hipGetLastError();
 }
 

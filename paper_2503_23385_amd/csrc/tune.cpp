@@ -68,7 +68,7 @@ int load_locked(const std::string &path)
             continue;
         parse_double(line, "ms", &ms);
         if ((t.kind != TREE_WG && t.kind != TREE_WAVE) || t.leaf_blocks < 0 || t.leaf_blocks > 1024 || t.arity < 2 ||
-            t.arity > 32)
+            t.arity > 32 || k.acc_f64 < 0 || k.acc_f64 > TUNE_SIGMA)
             continue;
         g_table[key4(k)] = Entry{t, ms};
         n++;
@@ -96,6 +96,7 @@ int rows_log2(int64_t rows)
 
 TreeTune tune_default(const TuneKey &k)
 {
+    if (k.acc_f64 == TUNE_SIGMA) return TreeTune{SIGMA_MSECT, 0, 2};
     if (k.batched) {
         // measured on the 256-instance batch: 32 blocks per leaf at padded widths 32 and 64,
         // 16 at narrower widths; binary trees (the shortest climb for the last leaf)
@@ -107,6 +108,11 @@ TreeTune tune_default(const TuneKey &k)
 std::vector<TreeTune> tune_candidates(const TuneKey &k)
 {
     std::vector<TreeTune> c;
+    if (k.acc_f64 == TUNE_SIGMA) {
+        c.push_back(TreeTune{SIGMA_MSECT, 0, 2});
+        c.push_back(TreeTune{SIGMA_DQDS, 0, 2});
+        return c;
+    }
     if (k.batched) {
         for (int b : {8, 16, 32, 64}) c.push_back(TreeTune{TREE_WAVE, b, 2});
     } else {

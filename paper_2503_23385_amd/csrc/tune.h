@@ -12,6 +12,9 @@
 namespace figaro {
 
 enum : int { TREE_WG = 0, TREE_WAVE = 1 };
+// Entries with acc_f64 == TUNE_SIGMA hold the route of a plan's sigma width class np
+// (kind SIGMA_MSECT or SIGMA_DQDS after the bidiagonalisation).
+enum : int { TUNE_SIGMA = 2, SIGMA_MSECT = 0, SIGMA_DQDS = 1 };
 
 struct TreeTune {
     int kind;         // TREE_WG: one workgroup per leaf; TREE_WAVE: one wave per leaf

@@ -93,3 +93,31 @@ def test_plan_autotune_then_parity(prec):
                 continue
             assert relF(Rg, Ro) <= TOL[prec], (rep, i)
     assert any(e["batched"] == 1 for e in fg().tune_table())
+
+
+@pytest.mark.parametrize("route", [1, 0])
+def test_plan_sigma_routes(tmp_path, route):
+    """The batched sigma by dqds (route 1) and by multisection (route 0) after the
+    bidiagonalisation, each against the oracle."""
+    path = tmp_path / "sigma.jsonl"
+    path.write_text("".join(f'{{"arch":"gfx950","acc_f64":2,"np":{c},"batched":1,"rows_log2":0,"kind":{route},'
+                            f'"leaf_blocks":0,"arity":2,"ms":0}}\n' for c in (8, 16, 32, 64, 128)))
+    fg().tune_load(str(path))
+    insts = mixed_plan_instances()
+    tens = [to_dev(i) for i in insts]
+    plan = fg().Plan(tens, "fp64", two_sided=True)
+    d = dev()
+    ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=d)
+    R = torch.zeros(plan.r_total, dtype=torch.float64, device=d)
+    S = torch.zeros(plan.s_total, dtype=torch.float64, device=d)
+    plan.execute(ws, R, S)
+    torch.cuda.synchronize()
+    Sh = S.cpu().numpy()
+    for i, inst in enumerate(insts):
+        N = inst.A.shape[1] + inst.B.shape[1]
+        So = oracle.sigma(oracle.r(inst))
+        Sg = Sh[plan.s_off[i]:plan.s_off[i] + N]
+        if not np.any(So):
+            assert not np.any(Sg)
+            continue
+        assert np.linalg.norm(Sg - So) / np.linalg.norm(So) <= 1e-12, (route, i)
