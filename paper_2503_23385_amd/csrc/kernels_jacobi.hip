@@ -523,7 +523,7 @@ hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int
 namespace figaro {
 namespace {
 
-constexpr int kGkThreads = 256;   // load and scale; four waves bidiagonalise (wave 0 alone above width 64)
+constexpr int kGkThreads = 256;   // load and scale; four waves bidiagonalise
 constexpr int kMsThreads = 256;   // multisection points per round (one workgroup per value)
 constexpr int kMsRounds = 7;      // 257^7 > 2^55: the final interval is below 2^-53 of the bound
 
@@ -533,8 +533,6 @@ struct GkGeom {
     // its own row can use 128-bit reads; lane i then starts 4 i banks further, so 16
     // lanes cover the 64 banks (the fewest passes a 128-bit read of 64 lanes can take)
     static constexpr int LDA = NPC + 2;
-    static constexpr int CPL = NPC > 64 ? NPC / 64 : 1; // rows / columns per lane in the bidiagonalisation
-    static constexpr int CH = NPC < 16 ? NPC : 16;      // rows per chunk of the reflector loops
 };
 
 // Reflector scalars for (alpha, s = |x|^2): tau, beta, scl = 1 / (alpha - beta); tau = 0 if s is 0.
@@ -578,128 +576,6 @@ __device__ inline double wave_sum(double v)
 {
     v = dpp_group_sum<16>(v);
     return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
-}
-
-// Order the LDS accesses of the lanes of one wave (the only wave at work).  The LDS
-// executes the instructions of one wave in issue order, so a read issued after a write
-// of another lane sees it; the wave barrier keeps the compiler from moving LDS accesses
-// across this point.
-__device__ inline void wave_sync() { __builtin_amdgcn_wave_barrier(); }
-
-// Reflector applied to one vector x of this lane (a column of A for a left reflector,
-// a row for a right one): x <- x - tau (v . x) v over the active entries [lo, n), in
-// whole chunks of CH entries (v is zero outside [lo, n) and A is zero beyond n, so the
-// extra entries add nothing and are written back unchanged).  X(e) addresses entry e
-// of x in LDS.  Returns the new entry lo of x (v_lo = 1), which the caller needs next,
-// without reading it back.  (Keeping the chunks in registers between the two passes
-// measured slower: it exceeds the architectural registers and the compiler moves them
-// through accumulation registers.)
-template <int CH, typename Addr>
-__device__ inline double reflect_vector(double *A, const double *v, double tau, int lo, int n, Addr X)
-{
-    const int c0 = lo / CH, c1 = (n + CH - 1) / CH;
-    const double xlo = A[X(lo)];
-    double w[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = c0; c < c1; c++) {
-        double x[CH], u[CH];
-#pragma unroll
-        for (int r = 0; r < CH; r++) {
-            x[r] = A[X(c * CH + r)];
-            u[r] = v[c * CH + r];
-        }
-#pragma unroll
-        for (int r = 0; r < CH; r++) w[r & 3] = fma(u[r], x[r], w[r & 3]);
-    }
-    const double t = ((w[0] + w[1]) + (w[2] + w[3])) * tau;
-    for (int c = c0; c < c1; c++) {
-        double x[CH], u[CH];
-#pragma unroll
-        for (int r = 0; r < CH; r++) {
-            x[r] = A[X(c * CH + r)];
-            u[r] = v[c * CH + r];
-        }
-#pragma unroll
-        for (int r = 0; r < CH; r++) A[X(c * CH + r)] = fma(-t, u[r], x[r]);
-    }
-    return fma(-t, 1.0, xlo);
-}
-
-// Householder bidiagonalisation of the n x n matrix A (LDS, row stride LDA) by one wave:
-// d receives the diagonal, e the superdiagonal of B = U^T A V.  Lane l owns rows and
-// columns l + 64 c.  Step k: the left reflector of column k (its entries are in
-// registers, left there by the previous step) is reduced with a wave sum and applied to
-// the columns j > k by their owners (a dot product and an update over rows k..n-1);
-// the updated row k comes back in registers, gives the right reflector, which the row
-// owners apply to the rows i > k, leaving column k + 1 in registers for step k + 1.
-// No workgroup barrier: the wave orders its own LDS accesses.
-template <int NPC>
-__device__ void gk_bidiag_wave(double *A, double *vl, double *vr, double *dd, double *ee, int n, int lane)
-{
-    constexpr int LDA = GkGeom<NPC>::LDA, CPL = GkGeom<NPC>::CPL, CH = GkGeom<NPC>::CH;
-    double a[CPL];  // A[i][k] for this lane's rows i
-#pragma unroll
-    for (int c = 0; c < CPL; c++) {
-        const int i = lane + 64 * c;
-        a[c] = i < n ? A[i * LDA] : 0.0;
-    }
-    for (int k = 0; k < n; k++) {
-        // ---- left reflector from column k, rows k..n-1
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < CPL; c++) {
-            const int i = lane + 64 * c;
-            if (i > k && i < n) s = fma(a[c], a[c], s);
-        }
-        s = wave_sum(s);
-        double alpha = 0.0;
-#pragma unroll
-        for (int c = 0; c < CPL; c++)
-            if (k / 64 == c) alpha = readlane_f64(a[c], k % 64);
-        double tau, beta, scl;
-        gk_reflector(alpha, s, tau, beta, scl);
-#pragma unroll
-        for (int c = 0; c < CPL; c++) {
-            const int i = lane + 64 * c;
-            if (i < NPC) vl[i] = i > k && i < n ? a[c] * scl : (i == k ? 1.0 : 0.0);
-        }
-        if (lane == 0) dd[k] = beta;
-        wave_sync();
-        double rk[CPL];  // A[k][j] for this lane's columns j, after the left reflector
-#pragma unroll
-        for (int c = 0; c < CPL; c++) {
-            const int j = lane + 64 * c;
-            rk[c] = j > k && j < n ? reflect_vector<CH>(A, vl, tau, k, n, [j](int e) { return e * LDA + j; })
-                                   : 0.0;
-        }
-        if (k + 1 >= n) break;
-        // ---- right reflector from row k, columns k+1..n-1
-        s = 0.0;
-#pragma unroll
-        for (int c = 0; c < CPL; c++) {
-            const int j = lane + 64 * c;
-            if (j > k + 1 && j < n) s = fma(rk[c], rk[c], s);
-        }
-        s = wave_sum(s);
-        alpha = 0.0;
-#pragma unroll
-        for (int c = 0; c < CPL; c++)
-            if ((k + 1) / 64 == c) alpha = readlane_f64(rk[c], (k + 1) % 64);
-        gk_reflector(alpha, s, tau, beta, scl);
-#pragma unroll
-        for (int c = 0; c < CPL; c++) {
-            const int j = lane + 64 * c;
-            if (j < NPC) vr[j] = j > k + 1 && j < n ? rk[c] * scl : (j == k + 1 ? 1.0 : 0.0);
-        }
-        if (lane == 0) ee[k] = beta;
-        wave_sync();
-#pragma unroll
-        for (int c = 0; c < CPL; c++) {
-            const int i = lane + 64 * c;
-            a[c] = i > k && i < n ? reflect_vector<CH>(A, vr, tau, k + 1, n, [i](int e) { return i * LDA + e; })
-                                  : 0.0;
-        }
-        wave_sync();
-    }
 }
 
 // The same bidiagonalisation by the four waves of the workgroup (NPC <= 64).  Every wave
@@ -775,14 +651,125 @@ __device__ void gk_bidiag_wg(double *A, double (*red)[64], double *dd, double *e
     }
 }
 
+// The same by four waves at NPC = 128: every lane owns two columns (left half-step) or two
+// rows (right half-step), c = lane + 64 u, and each wave a quarter of the other index
+// (32 entries in registers); the partial dot products of the two columns (rows) meet in
+// LDS as above.
+template <int NPC>
+__device__ void gk_bidiag_wg2(double *A, double (*red)[NPC], double *dd, double *ee, int n, int lane, int wv)
+{
+    static_assert(NPC == 128, "two columns per lane");
+    constexpr int LDA = GkGeom<NPC>::LDA, RW = NPC / 4;
+    const int w = __builtin_amdgcn_readfirstlane(wv);
+    const int e0 = w * RW;      // first entry of this wave's quarter
+    const int vsel = w >> 1;    // the reflector entries e0 .. e0 + RW - 1 sit in v[vsel]
+    const int voff = (w & 1) * RW;
+    for (int k = 0; k < n; k++) {
+        // ---- left reflector from column k (rows k..n-1), applied to the columns j > k
+        {
+            double x[2][RW];  // A[e0 + r][lane + 64 u]
+#pragma unroll
+            for (int u = 0; u < 2; u++)
+#pragma unroll
+                for (int r = 0; r < RW; r++) x[u][r] = A[(e0 + r) * LDA + lane + 64 * u];
+            double a[2], v[2];
+            double ss = 0.0;
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int i = lane + 64 * u;
+                a[u] = A[i * LDA + k];
+                ss = fma(i > k && i < n ? a[u] : 0.0, a[u], ss);
+            }
+            const double s = wave_sum(ss);
+            const double alpha = readlane_f64(k < 64 ? a[0] : a[1], k & 63);
+            double tau, beta, scl;
+            gk_reflector(alpha, s, tau, beta, scl);
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int i = lane + 64 * u;
+                v[u] = i == k ? 1.0 : (i > k && i < n ? a[u] * scl : 0.0);
+            }
+            const double vq = vsel ? v[1] : v[0];
+            double ve[RW], p[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+            for (int r = 0; r < RW; r++) {
+                ve[r] = readlane_f64(vq, voff + r);
+#pragma unroll
+                for (int u = 0; u < 2; u++) p[u][r & 1] = fma(ve[r], x[u][r], p[u][r & 1]);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; u++) red[w][lane + 64 * u] = p[u][0] + p[u][1];
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int j = lane + 64 * u;
+                const double t = ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) * tau;
+                if (j > k && j < n && e0 + RW > k) {
+#pragma unroll
+                    for (int r = 0; r < RW; r++) A[(e0 + r) * LDA + j] = fma(-t, ve[r], x[u][r]);
+                }
+            }
+            if (lane == 0 && w == 0) dd[k] = beta;
+            __syncthreads();
+        }
+        if (k + 1 >= n) break;
+        // ---- right reflector from row k (columns k+1..n-1), applied to the rows i > k
+        {
+            double x[2][RW];  // A[lane + 64 u][e0 + r]
+#pragma unroll
+            for (int u = 0; u < 2; u++)
+#pragma unroll
+                for (int r = 0; r < RW; r++) x[u][r] = A[(lane + 64 * u) * LDA + e0 + r];
+            double rk[2], v[2];
+            double ss = 0.0;
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int j = lane + 64 * u;
+                rk[u] = A[k * LDA + j];
+                ss = fma(j > k + 1 && j < n ? rk[u] : 0.0, rk[u], ss);
+            }
+            const double s = wave_sum(ss);
+            const double alpha = readlane_f64(k + 1 < 64 ? rk[0] : rk[1], (k + 1) & 63);
+            double tau, beta, scl;
+            gk_reflector(alpha, s, tau, beta, scl);
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int j = lane + 64 * u;
+                v[u] = j == k + 1 ? 1.0 : (j > k + 1 && j < n ? rk[u] * scl : 0.0);
+            }
+            const double vq = vsel ? v[1] : v[0];
+            double ve[RW], p[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+            for (int r = 0; r < RW; r++) {
+                ve[r] = readlane_f64(vq, voff + r);
+#pragma unroll
+                for (int u = 0; u < 2; u++) p[u][r & 1] = fma(ve[r], x[u][r], p[u][r & 1]);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; u++) red[w][lane + 64 * u] = p[u][0] + p[u][1];
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int i = lane + 64 * u;
+                const double t = ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i])) * tau;
+                if (i > k && i < n && e0 + RW > k + 1) {
+#pragma unroll
+                    for (int r = 0; r < RW; r++) A[i * LDA + e0 + r] = fma(-t, ve[r], x[u][r]);
+                }
+            }
+            if (lane == 0 && w == 0) ee[k] = beta;
+            __syncthreads();
+        }
+    }
+}
+
 template <int NPC>
 __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ldr, double *msin, int32_t *ctrl)
 {
     using Gm = GkGeom<NPC>;
     constexpr int LDA = Gm::LDA;
     __shared__ double A[NPC * LDA];
-    __shared__ double vl[NPC], vr[NPC];
-    __shared__ double red[4][64];
+    __shared__ double red[4][NPC > 64 ? NPC : 64];
     __shared__ double dd[NPC], ee[NPC];
     __shared__ double sc[2];
     __shared__ int s_exp;
@@ -817,7 +804,7 @@ __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ld
     if constexpr (NPC <= 64) {
         gk_bidiag_wg<NPC>(A, red, dd, ee, n, lane, wv);
     } else {
-        if (wv == 0) gk_bidiag_wave<NPC>(A, vl, vr, dd, ee, n, lane);
+        gk_bidiag_wg2<NPC>(A, red, dd, ee, n, lane, wv);
     }
     __syncthreads();
     // ---- inputs of the multisection: the Golub-Kahan tridiagonal T (zero diagonal,
