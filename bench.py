@@ -109,7 +109,14 @@ def stage_work(inst, two_sided, precision, sweeps):
     n1, n2 = inst.A.shape[1], inst.B.shape[1]
     N = n1 + n2
     R1, R2, TA, G = int(m1g.sum()), int((m2g - 1).sum()), int((m1g - 1).sum()), len(m1g)
+    esz_in = inst.A.dtype.itemsize
+    esz_m = 8 if precision == "fp64" else 4
+    in_bytes = (inst.A.shape[0] * n1 + inst.B.shape[0] * n2) * esz_in if two_sided else inst.B.shape[0] * n2 * esz_in
+    out_bytes = ((TA * n1 + R2 * n2) if two_sided else R2 * n2) * esz_m
     work = {
+        # the write pass reads the scanned tables and writes every tail row once; the reduce pass reads them
+        "scan_write": ("hbm", (in_bytes + out_bytes) / 1e9),
+        "scan_reduce": ("hbm", in_bytes / 1e9),
         "tsqr_m1": ("alu", flops(R1, N)),
         "tsqr_m2": ("alu", flops(R2, n2)),
         "tsqr_ta": ("alu", flops(TA, n1)),
@@ -315,7 +322,8 @@ def bench_single(args, inst, desc, forms_spec, torch, fg, dev, stream, ref, time
     memory = dict(mem, join_over_compact=mem["join_bytes"] / max(mem["compact_bytes"], 1.0),
                   join_over_workspace=mem["join_bytes"] / max(mem["workspace_bytes"], 1.0))
     return {"value": f["value"], "ms_per_step": f["ms_per_step"], "chosen": chosen, "precision": f["precision"],
-            "roofline": roofline_of(f, work, f["precision"]), "forms": forms, "join_rows": join_rows,
+            "roofline": roofline_of(f, work, f["precision"], bound="alu"),
+            "roofline_hbm": roofline_of(f, work, f["precision"], bound="hbm"), "forms": forms, "join_rows": join_rows,
             "memory": memory, "config": {"workload": desc, "join_rows": join_rows, "form": chosen}}
 
 

@@ -145,9 +145,10 @@ struct ScanJob {
 ScanJob scan_job(const void *X, int64_t ldx, int64_t m, int64_t n, ScanSide side, void *out, double *heads,
                  int32_t *tileF, double *tileS, double *carry, const ScanPlan &sp);
 // Scans one or two jobs (an empty second job has ntiles = 0) in three launches (tile
-// reduce, carry scan, tile write); two jobs need the same cpt and storage types.
+// reduce, carry scan, tile write; pass 0, 1 or 2 alone, or all three for pass < 0); two
+// jobs need the same cpt and storage types.
 hipError_t launch_seg_scan(const ScanJob &j0, const ScanJob &j1, int cpt, int in_f64, int out_f64, Groups g,
-                           int cartesian, hipStream_t s);
+                           int cartesian, hipStream_t s, int pass = -1);
 // One pass (0 tile reduce, 1 carry scan, 2 tile write) over a batch of jobs (device table
 // `jobs`, each with its own group table): tile_map[b] = (job, tile) for each of the ntiles
 // tile blocks, col_map[b] = (job, column) for each of the ncols carry blocks; every job of

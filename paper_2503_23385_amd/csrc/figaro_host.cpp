@@ -518,17 +518,18 @@ int run_compact(const figaro_table *A, const figaro_table *B, const Shape &sh, c
     const int nj = scan_jobs(A, B, sh, L, ws, jobs);
     const ScanJob none{};
     Groups g = groups_of(ws, L);
-    {
+    static const char *const pass_name[3] = {"scan_reduce", "scan_carry", "scan_write"};
+    for (int pass = 0; pass < 3; pass++) {
         // both tables in one launch per pass when their tiles have the same column layout
-        Stage st("scan", s);
+        Stage st(pass_name[pass], s);
         if (nj == 2 && L.spA.cpt == L.spB.cpt) {
-            HIPCHK(launch_seg_scan(jobs[0], jobs[1], L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+            HIPCHK(launch_seg_scan(jobs[0], jobs[1], L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s, pass),
                    "head/tail scans");
         } else {
-            HIPCHK(launch_seg_scan(jobs[0], none, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+            HIPCHK(launch_seg_scan(jobs[0], none, L.spB.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s, pass),
                    "head/tail scan of B");
             if (nj == 2)
-                HIPCHK(launch_seg_scan(jobs[1], none, L.spA.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s),
+                HIPCHK(launch_seg_scan(jobs[1], none, L.spA.cpt, sh.in_f64, L.m_f64, g, !sh.keyed, s, pass),
                        "head/tail scan of A");
         }
     }

@@ -443,7 +443,7 @@ ScanJob scan_job(const void *X, int64_t ldx, int64_t m, int64_t n, ScanSide side
 }
 
 hipError_t launch_seg_scan(const ScanJob &j0_in, const ScanJob &j1_in, int cpt, int in_f64, int out_f64, Groups g,
-                           int cartesian, hipStream_t s)
+                           int cartesian, hipStream_t s, int pass)
 {
     ScanJob j0 = j0_in, j1 = j1_in;
     j0.g = j1.g = g;
@@ -468,17 +468,22 @@ hipError_t launch_seg_scan(const ScanJob &j0_in, const ScanJob &j1_in, int cpt, 
             else FIGARO_TILE(float, float, 2, WR);                                                \
         }                                                                                         \
     } while (0)
-    FIGARO_TILE_ALL(false);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // jobs without tiles have no columns to carry
-    ScanJob c0 = j0, c1 = j1;
-    if (c0.ntiles == 0) c0.n = 0;
-    if (c1.ntiles == 0) c1.n = 0;
-    k_carry_scan<<<(unsigned)(c0.n + c1.n), kCarryThreads, 0, s>>>(c0, c1);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    FIGARO_TILE_ALL(true);
+    hipError_t e;
+    if (pass < 0 || pass == 0) {
+        FIGARO_TILE_ALL(false);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (pass < 0 || pass == 1) {
+        // jobs without tiles have no columns to carry
+        ScanJob c0 = j0, c1 = j1;
+        if (c0.ntiles == 0) c0.n = 0;
+        if (c1.ntiles == 0) c1.n = 0;
+        k_carry_scan<<<(unsigned)(c0.n + c1.n), kCarryThreads, 0, s>>>(c0, c1);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (pass < 0 || pass == 2) FIGARO_TILE_ALL(true);
 #undef FIGARO_TILE_ALL
 #undef FIGARO_TILE
     return hipGetLastError();
