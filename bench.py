@@ -145,6 +145,8 @@ def batch_stage_work(insts, precision):
             work[k] = ("alu", work.get(k, ("alu", 0.0))[1] + flops(rows, w))
         in_bytes += inst.A.nbytes + inst.B.nbytes
         out_bytes += ((m1 - 1) * n1 + (m2 - 1) * n2) * esz
+    # every narrow width's trees in one launch
+    work["tsqr_narrow"] = ("alu", sum(v[1] for k, v in work.items() if k.startswith("tsqr_np")))
     # the write pass reads every table and writes every tail row once; the reduce pass reads
     work["scan_write"] = ("hbm", (in_bytes + out_bytes) / 1e9)
     work["scan_reduce"] = ("hbm", in_bytes / 1e9)
@@ -163,7 +165,8 @@ STAGE_KERNELS = {
     "scan_reduce": ("paper_2503_23385_amd/csrc/kernels_scan.hip", "k_seg_tile_batch"),
 }
 for _np in (4, 8, 16, 32, 64):
-    STAGE_KERNELS[f"tsqr_np{_np}"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree_batch")
+    STAGE_KERNELS[f"tsqr_np{_np}"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_wtree_batch")
+STAGE_KERNELS["tsqr_narrow"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_wtree_multi")
 
 
 def measured_traffic(workload, stage, form=None):

@@ -249,9 +249,12 @@ const char *figaro_last_error(void);
 /*
  * Per-stage device timing, for measurement.  Off by default.  When on, every
  * kernel launch of the library is bracketed by two hipEventRecord calls on
- * its stream, under a stage name ("group", "scan", "assemble", "tsqr_leaf_m1",
- * "tsqr_leaf_m2", "tsqr_tree", "tsqr_root", "sign", "jacobi", "sigma_bidiag",
- * "sigma_msect").
+ * its stream, under a stage name: "group", "scan_reduce", "scan_carry",
+ * "scan_write", "assemble", a region tree ("tsqr_m1", "tsqr_m2", "tsqr_heads",
+ * "tsqr_tails"), "tsqr_root", "sign", "refine_gram", "refine_solve",
+ * "jacobi", "sigma_bidiag", "sigma_msect", "sigma_dqds"; a plan's stages
+ * ("tsqr_narrow" for its narrow trees, "tsqr_np<w>", "root_np<w>",
+ * "sigma_np<w>" per padded width w) and "plan_graph" for a graph launch.
  * figaro_timing_read is synchronous: it waits for the recorded events, writes
  * up to `cap` entries (stage name, total milliseconds, number of launches)
  * accumulated since the previous read, sets *count and clears the record.
@@ -340,12 +343,14 @@ int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
  *   grouping (one launch for all Cartesian instances; a keyed instance runs its
  *   own grouping), head/tail scans (one tile-reduce / carry-scan / tile-write
  *   sequence over the tiles of every table), the regions' TSQR (one tree launch
- *   per padded width up to 64 over the leaves of every region of every instance,
- *   each region with its own node counters and root; wider regions per region),
+ *   over the leaves of every region of padded width up to 64 of every instance,
+ *   the widest leaves first, each region with its own node counters and root;
+ *   wider regions per region),
  *   the roots (one launch per padded width for the Cartesian instances of the
  *   two-sided form; the others, and the refinement sweep, per instance), and
  *   sigma by the bidiagonal route of figaro_sigma_bidiag (two launches per width
- *   class over all instances).  Each instance owns one slice of `ws`; the
+ *   class over all instances; the multisection there locates each value with
+ *   16 lanes and 16 points per round, 14 rounds).  Each instance owns one slice of `ws`; the
  *   multisection inputs sit after the slices.  Instances need n1 + n2 <= 128.
  * The first call with a given (ws, R, sigma) allocates and uploads that
  * triple's launch tables (synchronous; freed by figaro_plan_destroy) and

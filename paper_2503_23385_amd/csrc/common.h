@@ -208,6 +208,10 @@ hipError_t launch_givens_tree(int np, int in_f64, const TreeRegion *regs, int nr
 // else one workgroup per leaf (the workgroup tree of launch_tsqr_tree).
 hipError_t launch_tsqr_tree_batch(int wave_tree, int np, int acc_f64, int in_f64, const TreeRegion *regs,
                                   const int2 *map, int64_t nitems, hipStream_t s);
+// The wave-tree regions of every narrow width of a batch in one launch: item i is leaf
+// map[i].y of region map[i].x of padded width map[i].z (4 .. 64).
+hipError_t launch_tsqr_wtree_multi(int acc_f64, int in_f64, const TreeRegion *regs, const int4 *map, int64_t nitems,
+                                   hipStream_t s);
 int tsqr_wave_block_rows(int np);  // rows per block of the wave tree (np <= 64)
 // Root of the two-sided form of a Cartesian product (N = na + nb <= 128): diag(R_TA, R_TB)
 // absorbs the head row built from the head sums hA, hB; R (ld ldr) receives the result

@@ -1140,7 +1140,9 @@ struct Program {
 };
 
 // The steps and tables of one execution of the plan with these buffers.
-Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigma)
+// fuse_trees: the wave-tree classes of every width share one launch (the autotuner times
+// each class in a launch of its own).
+Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigma, bool fuse_trees = true)
 {
     Program P;
     const size_t count = plan->inst.size();
@@ -1241,6 +1243,35 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
             }
         }
     }
+    if (fuse_trees) {
+        // every wave-tree class in one launch, the widest leaves first
+        std::vector<TreeRegion> regs;
+        std::vector<int4> map;
+        for (auto it = tree_cls.rbegin(); it != tree_cls.rend(); ++it) {
+            if (!it->first.second) continue;
+            const int np = it->first.first;
+            for (const TreeRegion &tr : it->second) {
+                const int j = (int)regs.size();
+                regs.push_back(tr);
+                for (int l = 0; l < tr.nleaves; l++) map.push_back(make_int4(j, l, np, 0));
+            }
+        }
+        for (auto it = tree_cls.begin(); it != tree_cls.end();) {
+            if (it->first.second) it = tree_cls.erase(it);
+            else ++it;
+        }
+        if (!map.empty()) {
+            const size_t ro = P.img.add(regs), mo = P.img.add(map);
+            const int64_t nb = (int64_t)map.size();
+            P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+                Stage st("tsqr_narrow", s);
+                HIPCHK(launch_tsqr_wtree_multi(acc, m_f64, (const TreeRegion *)(t + ro), (const int4 *)(t + mo), nb,
+                                               s),
+                       "batched tsqr trees");
+                return FIGARO_OK;
+            });
+        }
+    }
     for (auto &kv : tree_cls) {
         const std::vector<TreeRegion> &regs = kv.second;
         std::vector<int2> map;
@@ -1320,7 +1351,8 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
             const GramJob &J = jobs[j];
             for (int ti = 0; ti < J.gx; ti++)
                 for (int tj = 0; tj < J.gy; tj++)
-                    for (int c = 0; c < J.nch; c++) tiles.push_back(make_int4(j, ti, tj, c));
+                    for (int c = 0; c < J.nch; c++)
+                        if (J.mode != 0 || tj <= ti) tiles.push_back(make_int4(j, ti, tj, c));  // symmetric: lower tiles
             const int64_t out = (int64_t)J.nx * (J.mode == 0 ? J.nx : J.ny);
             for (int64_t b = 0; b < (out + 255) / 256; b++) reds.push_back(make_int2(j, (int)b));
         }
@@ -1604,7 +1636,7 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         for (const TreeTune &cand : tune_candidates(key)) {
             tune_override(&key, &cand);
             plan_relayout(plan);
-            const Program prog = build_program(plan, ws, R, sigma);
+            const Program prog = build_program(plan, ws, R, sigma, false);
             figaro_plan::Exec *ex = nullptr;
             rc = plan_exec(plan, ws, R, sigma, prog, &ex);
             if (!rc) rc = run_program(prog, ex->tables, s);  // warm-up

@@ -940,15 +940,61 @@ __global__ __launch_bounds__(kMsThreads) void k_sigma_msect(const double *msin, 
     sigma_msect_body(msin, n, blockIdx.x, sigma);
 }
 
-// Batched: workgroup (k, b) locates value k of entry b of tab (entries as k_sigma_gk_batch);
-// workgroups with k >= n leave at once.
-__global__ __launch_bounds__(kMsThreads) void k_sigma_msect_batch(const int64_t *tab, const double *msin,
-                                                                  double *sigma)
+// Multisection by lane groups, for batches: G lanes locate one value with G points per
+// round (a wave holds 64 / G values; a workgroup 4 waves of one entry).  Fewer points per
+// round need more rounds, (G + 1)^rounds > 2^55 as above, but far fewer Sturm counts per
+// value (G = 16: 14 x 16 instead of 7 x 256), and no workgroup barrier inside the rounds.
+template <int G>
+struct MsWave {
+    static constexpr int VPW = 64 / G;                  // values per wave
+    static constexpr int VPB = 4 * VPW;                 // values per workgroup
+    static constexpr int ROUNDS = G == 16 ? 14 : G == 8 ? 19 : G == 4 ? 24 : 10;
+};
+
+template <int G>
+__device__ __forceinline__ void sigma_msect_wave_body(const double *msin, int n, int k0, double *sigma)
+{
+    static_assert(G == 4 || G == 8 || G == 16 || G == 64, "lane group");
+    __shared__ double bb[256];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = 2 * n - 1;
+    for (int i = tid; i < m; i += 256) bb[i] = msin[2 + i];
+    const double bound = msin[0];
+    const int ex = (int)msin[1];
+    __syncthreads();
+    const int grp = lane / G, idx = lane % G;
+    const int k = k0 + wv * MsWave<G>::VPW + grp;
+    const int target = 2 * n - k;
+    const double step = 1.0 / (double)(G + 1);
+    const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    double lo = 0.0, up = bound;
+    for (int it = 0; it < MsWave<G>::ROUNDS; it++) {
+        const double w = up - lo;
+        const double x = lo + w * ((double)(idx + 1) * step);
+        const bool below = gk_sturm_count(bb, m, x) < target;
+        const unsigned long long mk = (__ballot(below) >> (grp * G)) & gmask;
+        // last point of the group below the target, first one not below
+        const int ilo = mk ? 63 - __builtin_clzll(mk) : -1;
+        const unsigned long long nm = ~mk & gmask;
+        const int iup = nm ? __builtin_ctzll(nm) : G;
+        const double xlo = ilo >= 0 ? lo + w * ((double)(ilo + 1) * step) : lo;
+        const double xup = iup < G ? lo + w * ((double)(iup + 1) * step) : up;
+        lo = xlo;
+        up = xup;
+    }
+    if (idx == 0 && k < n) sigma[k] = ldexp(0.5 * (lo + up), ex);
+}
+
+// Workgroup (b, e) locates values [b VPB, (b + 1) VPB) of entry e of tab (entries as
+// k_sigma_gk_batch); workgroups past the entry's width leave at once.
+template <int G>
+__global__ __launch_bounds__(256) void k_sigma_msect_wave_batch(const int64_t *tab, const double *msin,
+                                                                double *sigma)
 {
     const int64_t *e = tab + 4 * (int64_t)blockIdx.y;
-    const int n = (int)e[2], k = blockIdx.x;
-    if (k >= n) return;
-    sigma_msect_body(msin + e[3], n, k, sigma + e[1]);
+    const int n = (int)e[2], k0 = blockIdx.x * MsWave<G>::VPB;
+    if (k0 >= n) return;
+    sigma_msect_wave_body<G>(msin + e[3], n, k0, sigma + e[1]);
 }
 
 // ------------------------------------------------------------------ dqds
@@ -1144,7 +1190,11 @@ hipError_t launch_sigma_batch(int npc, const double *R, double *sigma, const int
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dqds) k_sigma_dqds_batch<<<count, 64, 0, s>>>(tab, msin, sigma);
-    else k_sigma_msect_batch<<<dim3(npc, count), kMsThreads, 0, s>>>(tab, msin, sigma);
+    else {
+        constexpr int G = 16;
+        const unsigned nb = (unsigned)((npc + MsWave<G>::VPB - 1) / MsWave<G>::VPB);
+        k_sigma_msect_wave_batch<G><<<dim3(nb, count), 256, 0, s>>>(tab, msin, sigma);
+    }
     return hipGetLastError();
 }
 

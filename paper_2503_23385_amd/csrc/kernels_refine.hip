@@ -11,7 +11,7 @@
 //
 // Kernels: a tiled split-K Gram (each workgroup one 64 x 64 output tile over a
 // chunk of rows; chunks summed afterwards in a fixed order), row-parallel
-// triangular solves, a one-workgroup right-looking Cholesky, and a parallel
+// triangular solves, a blocked right-looking Cholesky (one launch per block column), and a parallel
 // triangular product.
 #include "common.h"
 
@@ -43,6 +43,8 @@ __device__ inline int group_of_row(const int32_t *off, const int32_t *size, int 
 template <typename Tin>
 __device__ __forceinline__ void gram_tile(const GramJob &J, int ti, int tj, int chunk)
 {
+    // mode 0 is symmetric: only the tiles on or below the diagonal are formed
+    if (J.mode == 0 && tj > ti) return;
     const Tin *__restrict__ X = (const Tin *)J.X;
     const int64_t ldx = J.ld;
     const int m = J.m, nx = J.nx, ny = J.ny, mode = J.mode;
@@ -149,15 +151,17 @@ __device__ __forceinline__ void gram_reduce(const GramJob &J, int64_t e)
     const int NY = J.mode == 0 ? J.nx : J.ny;
     const int64_t cnt = (int64_t)J.nx * NY;
     if (e >= cnt) return;
+    const int i = (int)(e / NY), j = (int)(e - (int64_t)i * NY);
+    // mode 0: an entry of a tile above the diagonal is read from its mirror image
+    const int64_t src = (J.mode == 0 && j / kTile > i / kTile) ? (int64_t)j * NY + i : e;
     // eight interleaved partial sums (their loads in flight together), combined in a fixed order
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int c = 0;
     for (; c + 8 <= J.nch; c += 8)
 #pragma unroll
-        for (int u = 0; u < 8; u++) a[u] += J.partial[(int64_t)(c + u) * cnt + e];
-    for (int u = 0; c < J.nch; c++, u++) a[u] += J.partial[(int64_t)c * cnt + e];
+        for (int u = 0; u < 8; u++) a[u] += J.partial[(int64_t)(c + u) * cnt + src];
+    for (int u = 0; c < J.nch; c++, u++) a[u] += J.partial[(int64_t)c * cnt + src];
     const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    const int i = (int)(e / NY), j = (int)(e - (int64_t)i * NY);
     J.gram[(int64_t)(J.row0 + i) * J.ldg + J.col0 + j] = s;
     if (J.mirror) J.gram[(int64_t)(J.col0 + j) * J.ldg + J.row0 + i] = s;
 }
@@ -196,43 +200,128 @@ __global__ __launch_bounds__(256) void k_right_solve(const double *__restrict__ 
     for (int k = threadIdx.x; k < n; k += blockDim.x) Y[(int64_t)i * ldy + k] = y[k];
 }
 
-// In place: X <- lower Cholesky factor of (X + X^T) / 2 (one workgroup, right-looking).
-// *failed <- 1 when a pivot is not a positive finite number (R~ singular to working
-// precision, e.g. a rank-deficient join), else 0.
-__global__ __launch_bounds__(1024) void k_cholesky(double *X, int ldx, int n, int32_t *failed)
+// Blocked right-looking Cholesky of (X + X^T) / 2 = L L^T, one launch per block column kb
+// of kCb columns.  The launch reads block column kb of X (not written in the step) and
+// updates the trailing lower blocks (i, j), kb < j <= i, each by one workgroup, which
+// recomputes what it needs of block column kb: the diagonal factor L_kk (in LDS) and the
+// panel blocks L_ik = X_ik L_kk^-T and L_jk.  Workgroup 0 stores L_kk, and workgroup
+// (i, kb + 1) stores L_ik, into L (a separate buffer, so no block is read after it is
+// overwritten).  Step 0 reads X symmetrised.  Padding past n acts as the identity.
+// *failed <- 1 when a pivot is not a positive finite number (step 0 first sets it from
+// its own pivots, so no clearing is needed), else it stays 0.
+constexpr int kCb = 32;
+__device__ inline double chol_load(const double *X, int ldx, int n, int r, int c, bool sym)
 {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < n * n; e += nt) {
-        const int i = e / n, j = e - i * n;
-        if (i > j) {
-            const double s = 0.5 * (X[(int64_t)i * ldx + j] + X[(int64_t)j * ldx + i]);
-            X[(int64_t)i * ldx + j] = s;
+    if (r >= n || c >= n) return r == c ? 1.0 : 0.0;
+    const double v = X[(int64_t)r * ldx + c];
+    return sym ? 0.5 * (v + X[(int64_t)c * ldx + r]) : v;
+}
+
+__global__ __launch_bounds__(256) void k_chol_step(double *X, int ldx, int n, int kb, double *L, int ldl,
+                                                   int32_t *failed)
+{
+    __shared__ double D[kCb][kCb + 1];
+    __shared__ double P[2][kCb][kCb + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const bool sym = kb == 0;
+    const int nblk = (n + kCb - 1) / kCb;
+    // block pair of this workgroup: 0 -> the diagonal factor only; else (i, j), kb < j <= i
+    int bi = kb, bj = kb;
+    if (blockIdx.x > 0) {
+        int t = blockIdx.x - 1;
+        bj = kb + 1;
+        while (t >= nblk - bj) {
+            t -= nblk - bj;
+            bj++;
+        }
+        bi = bj + t;
+    }
+    const int k0 = kb * kCb, i0 = bi * kCb, j0 = bj * kCb;
+    for (int e = tid; e < kCb * kCb; e += 256) {
+        const int r = e / kCb, c = e - r * kCb;
+        D[r][c] = c <= r ? chol_load(X, ldx, n, k0 + r, k0 + c, sym) : 0.0;
+        if (blockIdx.x > 0) {
+            P[0][r][c] = chol_load(X, ldx, n, i0 + r, k0 + c, sym);
+            P[1][r][c] = chol_load(X, ldx, n, j0 + r, k0 + c, sym);
         }
     }
     __syncthreads();
-    __shared__ double piv;
-    __shared__ int bad;
-    if (tid == 0) bad = 0;
-    for (int k = 0; k < n; k++) {
-        if (tid == 0) {
-            const double d = X[(int64_t)k * ldx + k];
+    // diagonal factor by wave 0, lane r owning row r
+    if (wv == 0) {
+        int bad = 0;
+        for (int c = 0; c < kCb; c++) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double d = D[c][c];
             const bool ok = d > 0.0 && d <= DBL_MAX;
-            piv = ok ? sqrt(d) : 1.0;
-            if (!ok) bad = 1;
-            X[(int64_t)k * ldx + k] = piv;
+            const double p = ok ? sqrt(d) : 1.0;
+            bad |= !ok;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane == c) D[c][c] = p;
+            if (lane > c && lane < kCb) D[lane][c] /= p;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane > c && lane < kCb) {
+                const double lr = D[lane][c];
+                for (int cc = c + 1; cc <= lane; cc++) D[lane][cc] -= lr * D[cc][c];
+            }
         }
-        __syncthreads();
-        const double p = piv;
-        for (int i = k + 1 + tid; i < n; i += nt) X[(int64_t)i * ldx + k] /= p;
-        __syncthreads();
-        const int rem = n - k - 1;
-        for (int e = tid; e < rem * rem; e += nt) {
-            const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-            if (j <= i) X[(int64_t)i * ldx + j] -= X[(int64_t)i * ldx + k] * X[(int64_t)j * ldx + k];
-        }
-        __syncthreads();
+        if (blockIdx.x == 0 && lane == 0 && (bad || kb == 0)) *failed = bad;
     }
-    if (tid == 0) *failed = bad;
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        for (int e = tid; e < kCb * kCb; e += 256) {
+            const int r = e / kCb, c = e - r * kCb;
+            if (k0 + r < n && k0 + c < n) L[(int64_t)(k0 + r) * ldl + k0 + c] = c <= r ? D[r][c] : 0.0;
+        }
+        return;
+    }
+    // panel blocks: row r of P[s] <- row r of X_(i or j),k times L_kk^-T (forward substitution)
+    const bool same = bi == bj;
+    if (tid < 2 * kCb && (tid < kCb || !same)) {
+        const int s = tid / kCb, r = tid % kCb;
+        double a[kCb];
+#pragma unroll
+        for (int c = 0; c < kCb; c++) a[c] = P[s][r][c];
+#pragma unroll
+        for (int c = 0; c < kCb; c++) {
+            double v = a[c];
+#pragma unroll
+            for (int t = 0; t < c; t++) v = fma(-a[t], D[c][t], v);
+            a[c] = v / D[c][c];
+        }
+#pragma unroll
+        for (int c = 0; c < kCb; c++) P[s][r][c] = a[c];
+    }
+    __syncthreads();
+    const int sj = same ? 0 : 1;
+    if (bj == kb + 1) {
+        for (int e = tid; e < kCb * kCb; e += 256) {
+            const int r = e / kCb, c = e - r * kCb;
+            if (i0 + r < n && k0 + c < n) L[(int64_t)(i0 + r) * ldl + k0 + c] = P[0][r][c];
+        }
+    }
+    // X_ij -= L_ik L_jk^T (each thread four entries of one row); a diagonal block keeps its
+    // upper part untouched (step 0 reads it as the transpose partner of the lower part)
+    const int r = tid / 8, c0 = (tid % 8) * 4;
+    double acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) acc[q] = chol_load(X, ldx, n, i0 + r, j0 + c0 + q, sym);
+#pragma unroll 8
+    for (int t = 0; t < kCb; t++) {
+        const double lr = P[0][r][t];
+#pragma unroll
+        for (int q = 0; q < 4; q++) acc[q] = fma(-lr, P[sj][c0 + q][t], acc[q]);
+    }
+    if (i0 + r < n) {
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (j0 + c0 + q < n && (!same || c0 + q <= r)) X[(int64_t)(i0 + r) * ldx + j0 + c0 + q] = acc[q];
+    }
 }
 
 // R = L^T Rt (both triangular): R_ij = sum_{k=i..j} L_ki Rt_kj, zeros below the diagonal.
@@ -504,11 +593,16 @@ hipError_t launch_refine(const void *A, int in_f64, int64_t lda, int64_t m1, int
     k_right_solve<<<N, 256, shm, s>>>(Y, N, Rt, ldt, N, gram, N, 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_cholesky<<<1, 1024, 0, s>>>(gram, N, N, failed);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // L (lower) into Y's space: Y is not read again
+    const int nblk = (N + kCb - 1) / kCb;
+    for (int kb = 0; kb < nblk; kb++) {
+        const int rem = nblk - kb - 1;
+        k_chol_step<<<(unsigned)(1 + rem * (rem + 1) / 2), 256, 0, s>>>(gram, N, N, kb, Y, N, failed);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int64_t nn = (int64_t)N * N;
-    k_lt_times_r<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(gram, N, Rt, ldt, N, failed, R, ldr);
+    k_lt_times_r<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(Y, N, Rt, ldt, N, failed, R, ldr);
     return hipGetLastError();
 }
 

@@ -815,6 +815,40 @@ __global__ __launch_bounds__(64 * kWtWaves) void k_tsqr_wtree_batch(const TreeRe
     wt_leaf<NP, Tin, Tacc>(rg, e.y, Rs[wv], Xs[wv], lane);
 }
 
+// Every narrow width of a batch in one launch: wave item i is leaf map[i].y of region
+// map[i].x, of padded width map[i].z (the map lists the widest leaves first, so that the
+// longest leaves start first and the narrower ones fill the compute units as the wide
+// ones drain).  Each wave's LDS slice holds its triangle and then its row buffer, carved
+// for its own width: the slice of the widest width, as in the single-width kernel.
+__host__ __device__ constexpr int wt_slice_tri(int np) { return (packed_size(np) + 3) / 4 * 4; }
+constexpr int kWtSlice = wt_slice_tri(64) + 32;  // the largest of wt_slice_tri(np) + rows of a block
+static_assert(kWtSlice >= wt_slice_tri(32) + 64 && kWtSlice >= wt_slice_tri(16) + 128 &&
+                  kWtSlice >= wt_slice_tri(8) + 256 && kWtSlice >= wt_slice_tri(4) + 512,
+              "wave slice");
+
+// At least four waves per SIMD (measured on the 256-instance batch: 3.3 ms against 3.6 ms
+// with the registers the compiler would otherwise take, at the cost of a few spilled values).
+template <typename Tin, typename Tacc>
+__global__ __launch_bounds__(64 * kWtWaves, 4) void k_tsqr_wtree_multi(const TreeRegion *__restrict__ regs,
+                                                                    const int4 *__restrict__ map, int64_t nitems)
+{
+    __shared__ __align__(16) Tacc Ls[kWtWaves][kWtSlice];
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t item = (int64_t)blockIdx.x * kWtWaves + wv;
+    if (item >= nitems) return;
+    const int4 e = map[item];
+    const TreeRegion rg = regs[e.x];
+    Tacc *sl = Ls[wv];
+    switch (__builtin_amdgcn_readfirstlane(e.z)) {
+    case 64: wt_leaf<64, Tin, Tacc>(rg, e.y, sl, sl + wt_slice_tri(64), lane); break;
+    case 32: wt_leaf<32, Tin, Tacc>(rg, e.y, sl, sl + wt_slice_tri(32), lane); break;
+    case 16: wt_leaf<16, Tin, Tacc>(rg, e.y, sl, sl + wt_slice_tri(16), lane); break;
+    case 8: wt_leaf<8, Tin, Tacc>(rg, e.y, sl, sl + wt_slice_tri(8), lane); break;
+    case 4: wt_leaf<4, Tin, Tacc>(rg, e.y, sl, sl + wt_slice_tri(4), lane); break;
+    default: break;
+    }
+}
+
 __global__ void k_sign_normalise(const double *Rin, int64_t ldin, int n, double *R, int64_t ldr)
 {
     // one wave per row
@@ -1066,6 +1100,24 @@ hipError_t launch_tsqr_tree_batch(int wave_tree, int np, int acc_f64, int in_f64
 #undef FIGARO_CASE
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_tsqr_wtree_multi(int acc_f64, int in_f64, const TreeRegion *regs, const int4 *map, int64_t nitems,
+                                   hipStream_t s)
+{
+    if (nitems == 0) return hipSuccess;
+    if (nitems > INT32_MAX) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)((nitems + kWtWaves - 1) / kWtWaves);
+#define FIGARO_MULTI(TI, TA) k_tsqr_wtree_multi<TI, TA><<<grid, 64 * kWtWaves, 0, s>>>(regs, map, nitems)
+    if (acc_f64) {
+        if (in_f64) FIGARO_MULTI(double, double);
+        else FIGARO_MULTI(float, double);
+    } else {
+        if (in_f64) FIGARO_MULTI(double, float);
+        else FIGARO_MULTI(float, float);
+    }
+#undef FIGARO_MULTI
+    return hipGetLastError();
 }
 
 int tsqr_padded_width(int n)
