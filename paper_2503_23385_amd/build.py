@@ -21,6 +21,7 @@ SOURCES = [
     "kernels_scan.hip",
     "kernels_tsqr.hip",
     "kernels_panel.hip",
+    "kernels_wqr.hip",
     "kernels_jacobi.hip",
     "kernels_refine.hip",
     "kernels_sort.hip",

@@ -193,7 +193,22 @@ struct TreeRegion {
     double *slots;
     int32_t *counters;
     double *root;
+    void *vbuf;  // wide regions: one reflector side buffer (wqr_vbuf_bytes) per leaf
 };
+// Wide regions (padded width 128, 256 or 512), one or two of the same width per launch:
+// one workgroup per leaf of at most wqr_leaf_rows rows, each factorised in place by the
+// blocked Householder QR; leaves' triangles merged pairwise up an in-kernel binary tree
+// (slots and counters as tsqr_panel_tree_sizes).  in_f64: the regions' storage type.
+hipError_t launch_wqr_tree(int np, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s);
+int64_t wqr_leaf_rows(int in_f64);
+int64_t wqr_vbuf_bytes();
+// top <- R of [top; bottom] for two FP64 upper triangles of width <= 512 (bottom is
+// overwritten; vbuf: wqr_vbuf_bytes).  One workgroup.
+hipError_t launch_wqr_merge(double *top, int64_t ld1, double *bottom, int64_t ld2, int width, double *vbuf,
+                            hipStream_t s);
+// dst (n x n) <- the w x w triangle src at rows [0, w), columns [off, off + w); zeros elsewhere.
+hipError_t launch_wqr_pad(const double *src, int64_t lds, int w, int off, double *dst, int64_t ldd, int n,
+                          hipStream_t s);
 // One launch for one or two regions of the same padded width np (np <= 64), one workgroup
 // per leaf, or one wave per leaf when wave_tree is set.
 hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg,
@@ -236,9 +251,11 @@ hipError_t launch_merge_cartesian_batch(int np, const CartRoot *tab, int count, 
 // out (na + nb rows, ld ldo) <- the upper triangular block diagonal [Ta 0; 0 Tb].
 hipError_t launch_block_diag(const double *Ta, int64_t lda, int na, const double *Tb, int64_t ldb, int nb,
                              double *out, int64_t ldo, hipStream_t s);
-// Wide regions (padded widths 128..512): in-kernel binary tree over panel-kernel leaves,
-// one or two regions of the same padded width per launch.
+// Wide regions of padded width 128 (one or two per launch): in-kernel binary tree over
+// leaves that stream blocks of rows through LDS (kernels_panel.hip); wider regions take
+// launch_wqr_tree.
 hipError_t launch_tsqr_panel_tree(int np, int acc_f64, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s);
+// Node triangles and counters of a binary in-kernel tree over nleaves leaves (wide regions).
 void tsqr_panel_tree_sizes(int nleaves, int64_t *slots, int64_t *counters);
 hipError_t launch_sign_normalise(const void *Rin, int in_f64, int64_t ldin, int n, double *R,
                                  int64_t ldr, hipStream_t s);

@@ -117,6 +117,10 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int kPrecMask = 0xff;
 constexpr int kMaxTreeLeaves = 2048;
 constexpr int64_t kLeafTarget = 256;
+// Wide regions up to this padded width take the streaming panel tree, wider ones the
+// blocked QR tree (measured: the panel tree is the faster at 128 on the 2^20-row join,
+// the blocked one at 256 and 512 on the 2^18 x 256 join).
+constexpr int kPanelTreeMaxNp = 128;
 constexpr int kMaxPanelLeaves = 128;
 constexpr int kBatchGramBlocks = 64;  // Gram workgroups per job in a batch
 
@@ -146,6 +150,7 @@ struct Region {
     int64_t nslots, ncnt;     // node triangles and counters reserved (for every tuning candidate)
     int64_t rows_per_leaf;    // leaves follow the device row count: ceil(rows / rows_per_leaf)
     size_t slots, counters, root;
+    size_t vbuf;              // wide regions: reflector side buffers, one per leaf
     int64_t ncounters;
 };
 
@@ -281,10 +286,19 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     r.skip = false;
     if (!r.wave) {
         r.wave_tree = false;
-        r.rows_per_leaf = (int64_t)4 * tsqr_block_rows(r.np, acc_f64);
-        const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
-        r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxPanelLeaves));
         r.arity = 2;
+        if (r.np <= kPanelTreeMaxNp) {
+            // rows streamed through LDS into each leaf's triangle, leaves of 4 blocks
+            r.rows_per_leaf = (int64_t)4 * tsqr_block_rows(r.np, acc_f64);
+            const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+            r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxPanelLeaves));
+        } else {
+            // blocked QR of each leaf's rows at once: leaves as long as the kernel takes
+            // (the regions of a form are stored in FP64 exactly when it accumulates in FP64)
+            r.rows_per_leaf = wqr_leaf_rows(acc_f64);
+            const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+            r.leaves = (int)std::max<int64_t>(1, leaves);
+        }
         tsqr_panel_tree_sizes(r.leaves, &r.nslots, &r.ncnt);
         return r;
     }
@@ -390,6 +404,7 @@ Layout make_layout(const Shape &s, bool batched = false)
         r.counters = (size_t)ctot;  // index into the shared counter block
         ctot += nc;
         r.root = take(tsz);
+        r.vbuf = (r.wave || r.np <= kPanelTreeMaxNp) ? 0 : take((size_t)wqr_vbuf_bytes() * (size_t)r.leaves);
     }
     L.counters_total = ctot;
     L.counters_base = take(sizeof(int32_t) * std::max<int64_t>(1, ctot));
@@ -549,6 +564,7 @@ TreeRegion tree_region(const Region &r, const Layout &L, void *ws)
     t.slots = at<double>(ws, r.slots);
     t.counters = at<int32_t>(ws, L.counters_base) + r.counters;
     t.root = at<double>(ws, r.root);
+    t.vbuf = (r.wave || r.np <= kPanelTreeMaxNp) ? nullptr : at<void>(ws, r.vbuf);
     return t;
 }
 
@@ -576,7 +592,8 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
         Stage st(name, s);
         if (r.givens) HIPCHK(launch_givens_tree(r.np, L.m_f64, tr, n, s), "givens tree");
         else if (r.wave) HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s, r.wave_tree), "tsqr tree");
-        else HIPCHK(launch_tsqr_panel_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr panel tree");
+        else if (r.np <= kPanelTreeMaxNp) HIPCHK(launch_tsqr_panel_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr panel tree");
+        else HIPCHK(launch_wqr_tree(r.np, L.m_f64, tr, n, s), "wide tsqr tree");
     }
     return FIGARO_OK;
 }
@@ -640,18 +657,34 @@ int run_root(const figaro_table *A, const figaro_table *B, const Shape &sh, cons
         HIPCHK(launch_block_diag(at<double>(ws, ra.root), ra.np, ra.width, at<double>(ws, rb.root), rb.np,
                                  rb.width, init, L.np_root, s),
                "block diagonal");
-        Groups g = groups_of(ws, L);
-        const RowSrc heads = r0.skip ? RowSrc{at<void>(ws, r0.buf), g.counts + CNT_G, 0, N, 0, N}
-                                     : RowSrc{cur, nullptr, N, r0.np, 0, N};
-        HIPCHK(launch_tsqr_stream(L.np_root, 1, r0.skip ? L.m_f64 : 1, init, L.np_root, heads, none, 1, N,
+        if (!r0.skip && L.np_root > kPanelTreeMaxNp) {
+            // wide: the heads' triangle merged into diag(R_TA, R_TB) in place
+            HIPCHK(launch_wqr_merge(init, L.np_root, at<double>(ws, r0.root), r0.np, N, at<double>(ws, r0.vbuf), s),
+                   "wide root merge");
+            cur = init;
+        } else {
+            Groups g = groups_of(ws, L);
+            const RowSrc heads = r0.skip ? RowSrc{at<void>(ws, r0.buf), g.counts + CNT_G, 0, N, 0, N}
+                                         : RowSrc{cur, nullptr, N, r0.np, 0, N};
+            HIPCHK(launch_tsqr_stream(L.np_root, 1, r0.skip ? L.m_f64 : 1, init, L.np_root, heads, none, 1, N,
                                       r0.skip ? 0 : N, 1, out, (int64_t)N * L.np_root, s),
                    "tsqr merge");
-        cur = out;
+            cur = out;
+        }
         cur_ld = L.np_root;
     } else {
         Stage st("tsqr_root", s);
         for (size_t i = 1; i < L.regions.size(); i++) {
             const Region &r = L.regions[i];
+            if (L.np_root > kPanelTreeMaxNp) {
+                // wide: region i's triangle, placed at its columns, merged into region 0's root
+                double *pad = at<double>(ws, L.rtmp[0]);
+                HIPCHK(launch_wqr_pad(at<double>(ws, r.root), r.np, r.width, r.col_off, pad, L.np_root, N, s),
+                       "pad triangle");
+                HIPCHK(launch_wqr_merge(at<double>(ws, r0.root), r0.np, pad, L.np_root, N, at<double>(ws, r0.vbuf), s),
+                       "wide root merge");
+                continue;
+            }
             double *out = at<double>(ws, L.rtmp[(i - 1) & 1]);
             RowSrc tri{at<double>(ws, r.root), nullptr, r.width, r.np, r.col_off, r.width};
             HIPCHK(launch_tsqr_stream(L.np_root, 1, 1, cur, cur_ld, tri, none, 1, N, r.width, 1, out,
@@ -1237,7 +1270,8 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
                 const char *name = r.name;
                 P.steps.push_back([tr, np, name, acc, m_f64](const unsigned char *, hipStream_t s) {
                     Stage st(name, s);
-                    HIPCHK(launch_tsqr_panel_tree(np, acc, m_f64, &tr, 1, s), "tsqr panel tree");
+                    if (np <= kPanelTreeMaxNp) HIPCHK(launch_tsqr_panel_tree(np, acc, m_f64, &tr, 1, s), "tsqr panel tree");
+                    else HIPCHK(launch_wqr_tree(np, m_f64, &tr, 1, s), "wide tsqr tree");
                     return FIGARO_OK;
                 });
             }

@@ -1,6 +1,9 @@
-// Householder TSQR for wide rows (padded widths 128, 256, 512): blocked
-// (compact-WY) form of the structured update R <- triu(QR([R; X])) of the
-// QR step (Experiments section; the stages of Section 1's reduction).
+// Householder TSQR for wide rows streamed into a triangle: blocked (compact-WY)
+// form of the structured update R <- triu(QR([R; X])) of the QR step
+// (Experiments section; the stages of Section 1's reduction).  It reduces the
+// regions of padded width 128 (a binary in-kernel tree over leaves) and merges
+// triangles into roots of padded width up to 128 and the single head row of a
+// wide Cartesian product; wider regions take the blocked QR of kernels_wqr.hip.
 //
 // One workgroup (4 waves) owns one triangle R, kept in FP64 in its output
 // slot, and streams blocks of B rows X through LDS (B set by the LDS budget).
