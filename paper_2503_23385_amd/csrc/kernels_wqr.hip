@@ -40,11 +40,21 @@ constexpr int kQGroups = kQThreads / kQb;   // 32 row groups of the column steps
 constexpr int kQCh = 256;                   // rows of V staged per chunk of the update
 constexpr int kQSub = 32 / kQWaves;         // 16-column subtiles per wave (at most 31 + G)
 
+constexpr int kQMergeRpt = (kQb + 512 + kQGroups - 1) / kQGroups;  // rows per thread of a merge
+
 template <typename S>
 struct QGeom {
-    static constexpr int RPT = sizeof(S) == 4 ? 64 : 32;  // active rows per thread
+    static constexpr int RPT = 32;                        // active rows per thread
     static constexpr int MAXR = kQGroups * RPT;           // active rows of a problem
 };
+
+// Bytes of one workgroup's reflector side buffer: V of a leaf panel (MAXR x 16 of the
+// storage type) or of a merge panel (up to 16 + 512 rows x 16 FP64).
+constexpr int64_t kQVbufBytes = (int64_t)kQb * (kQGroups * QGeom<double>::RPT * (int64_t)sizeof(double) >
+                                                        (kQb + 512) * (int64_t)sizeof(double)
+                                                    ? kQGroups * QGeom<double>::RPT * (int64_t)sizeof(double)
+                                                    : (kQb + 512) * (int64_t)sizeof(double));
+static_assert(kQVbufBytes >= (int64_t)kQb * QGeom<float>::MAXR * (int64_t)sizeof(float), "side buffer");
 
 template <typename T>
 struct QVec4;
@@ -128,6 +138,8 @@ __device__ inline void qst(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
 // The active rows of one panel as two byte ranges: rows [0, n0) in range 0 (stride ld0
 // bytes), rows [n0, n0 + n1) in range 1 (stride ld1); columns [0, w).  An access outside
 // them (row past the active rows, column >= w) reads 0 and writes nothing.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 template <typename S>
 struct QBuf {
     __amdgpu_buffer_rsrc_t r0, r1;
@@ -152,6 +164,21 @@ struct QBuf {
     {
         qst(r0, off0(a, c), v);
         if (n1 > 0) qst(r1, off1(a, c), v);
+    }
+    // 16 bytes at (row a, columns [c, c + 16 / sizeof(S))): callers keep c + that <= w
+    __device__ u32x4 load16(int a, int c) const
+    {
+        u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r0, (int)off0(a, c), 0, 0);
+        if (n1 > 0) {
+            const u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(r1, (int)off1(a, c), 0, 0);
+            v |= v1;  // one of the two reads is all zero bits
+        }
+        return v;
+    }
+    __device__ void store16(int a, int c, u32x4 v) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b128(v, r0, (int)off0(a, c), 0, 0);
+        if (n1 > 0) __builtin_amdgcn_raw_buffer_store_b128(v, r1, (int)off1(a, c), 0, 0);
     }
 };
 
@@ -199,14 +226,275 @@ struct QLds {
     int flag;
 };
 
+// T of the panel (wave 0, lanes 0..15 own a row each, left to right in LDS) from
+// G = V^T V in LDS and the panel's tau.
+template <typename S>
+__device__ inline void q_make_t(QLds<S> &L, int wv, int lane)
+{
+    if (wv == 0 && lane < kQb) {
+        const int i = lane;
+        for (int jj = 0; jj < kQb; jj++) L.u.T[i][jj] = jj == i ? L.tau[i] : 0.0;
+        for (int jj = i + 1; jj < kQb; jj++) {
+            double a = 0.0;
+            for (int kk = i; kk < jj; kk++) a = fma(L.u.T[i][kk], L.u.G[kk][jj], a);
+            L.u.T[i][jj] = -L.tau[jj] * a;
+        }
+    }
+}
+
+// V chunk [rb, rb + kQCh) of the side buffer into LDS (rows past na as zeros).
+template <typename S>
+__device__ inline void q_stage_v(QLds<S> &L, const S *vbuf, int rb, int na)
+{
+    for (int e = threadIdx.x; e < kQCh * kQb; e += kQThreads) {
+        const int rr = e / kQb, kk = e % kQb;
+        L.u.vch[rr][kk] = rb + rr < na ? vbuf[(int64_t)(rb + rr) * kQb + kk] : S(0);
+    }
+}
+
+// Trailing update, one 16-column subtile per access (any width).
+template <typename S>
+__device__ void q_trail_scalar(QLds<S> &L, const QBuf<S> &q, const S *vbuf, int na, int c0, int width, int wv,
+                               int lane)
+{
+    using V4 = typename QVec4<S>::type;
+    const int l16 = lane & 15, l4 = lane >> 4;
+        const int nsub = (width - c0 + kQb - 1) / kQb;  // subtile nsub is G = V^T V
+        V4 acc[kQSub];
+#pragma unroll
+        for (int u = 0; u < kQSub; u++) acc[u] = V4{0, 0, 0, 0};
+        for (int rb = 0; rb < na; rb += kQCh) {
+            q_stage_v<S>(L, vbuf, rb, na);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kQSub; u++) {
+                const int s = wv + kQWaves * u;
+                if (s > nsub) continue;
+                if (s == nsub) {
+                    const int nk = min(kQCh, na - rb + 3) / 4;
+                    for (int kk = 0; kk < nk; kk++) {
+                        const S a = L.u.vch[4 * kk + l4][l16];
+                        acc[u] = qmfma(a, a, acc[u]);
+                    }
+                } else {
+                    const int col = c0 + kQb * s + l16;
+                    // batches of 16 loads, the next batch in flight during a batch's products
+                    // (rows past the active ones read 0, and whole batches past them are skipped)
+                    const int nk = min(kQCh, na - rb + 3) / 4;
+                    constexpr int NB = 8;
+                    S b[NB], bn[NB];
+#pragma unroll
+                    for (int kk = 0; kk < NB; kk++) b[kk] = q.load(rb + 4 * kk + l4, col);
+                    for (int k0 = 0; k0 < nk; k0 += NB) {
+                        if (k0 + NB < nk) {
+#pragma unroll
+                            for (int kk = 0; kk < NB; kk++) bn[kk] = q.load(rb + 4 * (k0 + NB + kk) + l4, col);
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < NB; kk++)
+                            acc[u] = qmfma(L.u.vch[4 * (k0 + kk) + l4][l16], b[kk], acc[u]);
+#pragma unroll
+                        for (int kk = 0; kk < NB; kk++) b[kk] = bn[kk];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < kQSub; u++) {
+            if (wv + kQWaves * u == nsub) {
+#pragma unroll
+                for (int r = 0; r < 4; r++) L.u.G[qrow_of<S>(l4, r)][l16] = (double)acc[u][r];
+            }
+        }
+        __syncthreads();
+        q_make_t<S>(L, wv, lane);
+        __syncthreads();
+        // W = T^T Z for each of the wave's subtiles
+#pragma unroll
+        for (int u = 0; u < kQSub; u++) {
+            if (wv + kQWaves * u >= nsub) continue;
+#pragma unroll
+            for (int r = 0; r < 4; r++) L.u.zb[wv][qrow_of<S>(l4, r)][l16] = (double)acc[u][r];
+            q_wave_sync();
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int mm = qrow_of<S>(l4, r);
+                double w = 0.0;
+                for (int kk = 0; kk <= mm; kk++) w = fma(L.u.T[kk][mm], L.u.zb[wv][kk][l16], w);
+                L.u.wb[wv][u][mm][l16] = (S)w;
+            }
+            q_wave_sync();
+        }
+        // A -= V W
+        for (int rb = 0; rb < na; rb += kQCh) {
+            __syncthreads();
+            q_stage_v<S>(L, vbuf, rb, na);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kQSub; u++) {
+                const int s = wv + kQWaves * u;
+                if (s >= nsub) continue;
+                const int col = c0 + kQb * s + l16;
+                // two 16-row blocks at a time: their 8 loads first, then products and stores
+                for (int sub0 = 0; sub0 < kQCh / 16; sub0 += 2) {
+                    if (rb + 16 * sub0 >= na) break;
+                    S cur[2][4];
+#pragma unroll
+                    for (int b4 = 0; b4 < 2; b4++)
+#pragma unroll
+                        for (int r = 0; r < 4; r++)
+                            cur[b4][r] = q.load(rb + 16 * (sub0 + b4) + qrow_of<S>(l4, r), col);
+#pragma unroll
+                    for (int b4 = 0; b4 < 2; b4++) {
+                        V4 d = {0, 0, 0, 0};
+#pragma unroll
+                        for (int kk = 0; kk < 4; kk++)
+                            d = qmfma(L.u.vch[16 * (sub0 + b4) + l16][4 * kk + l4], L.u.wb[wv][u][4 * kk + l4][l16],
+                                      d);
+#pragma unroll
+                        for (int r = 0; r < 4; r++)
+                            q.store(rb + 16 * (sub0 + b4) + qrow_of<S>(l4, r), col, cur[b4][r] - d[r]);
+                    }
+                }
+            }
+        }
+}
+
+// Trailing update with 16-byte accesses (width a multiple of VW = 16 / sizeof(S)): wave
+// wv owns groups gi = wv, wv + 8, ... of 16 VW columns; within a group, subtile v holds
+// columns c0 + 16 VW gi + VW n + v (n = 0..15), so that a lane's 16 bytes at columns
+// VW l16 .. VW l16 + VW - 1 of the group are column l16 of subtiles 0..VW-1.
+// The last wave also forms G = V^T V.
+template <typename S>
+__device__ void q_trail_vec(QLds<S> &L, const QBuf<S> &q, const S *vbuf, int na, int c0, int width, int wv,
+                            int lane)
+{
+    using V4 = typename QVec4<S>::type;
+    constexpr int VW = 16 / (int)sizeof(S);
+    constexpr int GPW = kQSub / VW;  // groups per wave
+    typedef S SV __attribute__((ext_vector_type(VW)));
+    const int l16 = lane & 15, l4 = lane >> 4;
+    const int ng = (width - c0 + 16 * VW - 1) / (16 * VW);
+    const bool gwave = wv == kQWaves - 1;
+    V4 acc[GPW][VW], accg = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < GPW; u++)
+#pragma unroll
+        for (int v = 0; v < VW; v++) acc[u][v] = V4{0, 0, 0, 0};
+    for (int rb = 0; rb < na; rb += kQCh) {
+        q_stage_v<S>(L, vbuf, rb, na);
+        __syncthreads();
+        const int nk = min(kQCh, na - rb + 3) / 4;
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int gi = wv + kQWaves * u;
+            if (gi >= ng) continue;
+            const int col = c0 + 16 * VW * gi + VW * l16;  // past the width: reads 0
+            constexpr int NB = 8;
+            u32x4 b[NB], bn[NB];
+#pragma unroll
+            for (int kk = 0; kk < NB; kk++) b[kk] = q.load16(rb + 4 * kk + l4, col);
+            for (int k0 = 0; k0 < nk; k0 += NB) {
+                if (k0 + NB < nk) {
+#pragma unroll
+                    for (int kk = 0; kk < NB; kk++) bn[kk] = q.load16(rb + 4 * (k0 + NB + kk) + l4, col);
+                }
+#pragma unroll
+                for (int kk = 0; kk < NB; kk++) {
+                    const S a = L.u.vch[4 * (k0 + kk) + l4][l16];
+                    const SV bv = __builtin_bit_cast(SV, b[kk]);
+#pragma unroll
+                    for (int v = 0; v < VW; v++) acc[u][v] = qmfma(a, bv[v], acc[u][v]);
+                }
+#pragma unroll
+                for (int kk = 0; kk < NB; kk++) b[kk] = bn[kk];
+            }
+        }
+        if (gwave) {
+            for (int kk = 0; kk < nk; kk++) {
+                const S a = L.u.vch[4 * kk + l4][l16];
+                accg = qmfma(a, a, accg);
+            }
+        }
+        __syncthreads();
+    }
+    if (gwave) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) L.u.G[qrow_of<S>(l4, r)][l16] = (double)accg[r];
+    }
+    __syncthreads();
+    q_make_t<S>(L, wv, lane);
+    __syncthreads();
+    // W = T^T Z for each subtile of the wave's groups (wb slot VW u + v)
+#pragma unroll
+    for (int u = 0; u < GPW; u++) {
+        if (wv + kQWaves * u >= ng) continue;
+#pragma unroll
+        for (int v = 0; v < VW; v++) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) L.u.zb[wv][qrow_of<S>(l4, r)][l16] = (double)acc[u][v][r];
+            q_wave_sync();
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int mm = qrow_of<S>(l4, r);
+                double w = 0.0;
+                for (int kk = 0; kk <= mm; kk++) w = fma(L.u.T[kk][mm], L.u.zb[wv][kk][l16], w);
+                L.u.wb[wv][VW * u + v][mm][l16] = (S)w;
+            }
+            q_wave_sync();
+        }
+    }
+    // A -= V W, two 16-row blocks at a time: their loads first, then products and stores
+    for (int rb = 0; rb < na; rb += kQCh) {
+        __syncthreads();
+        q_stage_v<S>(L, vbuf, rb, na);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int gi = wv + kQWaves * u;
+            if (gi >= ng) continue;
+            const int col = c0 + 16 * VW * gi + VW * l16;
+            for (int sub0 = 0; sub0 < kQCh / 16; sub0 += 2) {
+                if (rb + 16 * sub0 >= na) break;
+                u32x4 cur[2][4];
+#pragma unroll
+                for (int b4 = 0; b4 < 2; b4++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) cur[b4][r] = q.load16(rb + 16 * (sub0 + b4) + qrow_of<S>(l4, r), col);
+#pragma unroll
+                for (int b4 = 0; b4 < 2; b4++) {
+                    V4 d[VW];
+#pragma unroll
+                    for (int v = 0; v < VW; v++) {
+                        d[v] = V4{0, 0, 0, 0};
+#pragma unroll
+                        for (int kk = 0; kk < 4; kk++)
+                            d[v] = qmfma(L.u.vch[16 * (sub0 + b4) + l16][4 * kk + l4],
+                                         L.u.wb[wv][VW * u + v][4 * kk + l4][l16], d[v]);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        SV x = __builtin_bit_cast(SV, cur[b4][r]);
+#pragma unroll
+                        for (int v = 0; v < VW; v++) x[v] -= d[v][r];
+                        q.store16(rb + 16 * (sub0 + b4) + qrow_of<S>(l4, r), col, __builtin_bit_cast(u32x4, x));
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Blocked QR of one problem in place.  kind 0 (leaf): rows [0, m) at X (stride ld);
 // kind 1 (merge): top triangle X (stride ld), bottom triangle Y (stride ldy), width rows
 // each.  vbuf holds V of the current panel (MAXR x 16).
-template <typename S>
+// RPT: active rows per thread (a leaf up to MAXR rows in all; a merge at most 16 + 512,
+// 17 per row group).
+template <typename S, int RPT>
 __device__ __forceinline__ void q_factor(QLds<S> &L, int kind, S *X, int64_t ld, int64_t m, S *Y, int64_t ldy, int width, S *vbuf)
 {
-    using V4 = typename QVec4<S>::type;
-    constexpr int RPT = QGeom<S>::RPT;
+    static_assert(kQGroups * RPT <= QGeom<S>::MAXR, "pivot column buffer");
     const int t = threadIdx.x, wv = t >> 6;
     for (int p0 = 0; p0 < width; p0 += kQb) {
         // column of the panel and row group, lane indices; the empty asm makes them (and
@@ -219,7 +507,7 @@ __device__ __forceinline__ void q_factor(QLds<S> &L, int kind, S *X, int64_t ld,
         if (kind == 0) {
             const int64_t left = m - p0;
             if (left <= 0) break;
-            q = qbuf<S>(X + (int64_t)p0 * ld, ld, (int)min(left, (int64_t)QGeom<S>::MAXR), nullptr, 0, 0, width);
+            q = qbuf<S>(X + (int64_t)p0 * ld, ld, (int)min(left, (int64_t)(kQGroups * RPT)), nullptr, 0, 0, width);
         } else {
             q = qbuf<S>(X + (int64_t)p0 * ld, ld, min(kQb, width - p0), Y, ldy, min(width, p0 + kQb), width);
         }
@@ -241,9 +529,9 @@ __device__ __forceinline__ void q_factor(QLds<S> &L, int kind, S *X, int64_t ld,
             }
             if (g == j) L.f.piv[par][k] = (double)x[0];  // the pivot row j is row group j's first row
             __syncthreads();
-            // the pivot column's entries of this thread's rows are read from LDS where used
-            // (twice) rather than held: the registers hold the thread's own column
-            const S *xj = &L.f.col[par][g * RPT];
+            S xj[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; i++) xj[i] = L.f.col[par][g * RPT + i];
             // rows below the pivot only: row g (i = 0) counts when g > j
             S pp[4] = {S(0), S(0), S(0), S(0)};
             if (g > j) pp[0] = xj[0] * x[0];
@@ -301,121 +589,8 @@ __device__ __forceinline__ void q_factor(QLds<S> &L, int kind, S *X, int64_t ld,
         // ---- 3. trailing update
         const int c0 = p0 + kb;
         if (c0 < width) {
-            const int nsub = (width - c0 + kQb - 1) / kQb;  // subtile nsub is G = V^T V
-            V4 acc[kQSub];
-#pragma unroll
-            for (int u = 0; u < kQSub; u++) acc[u] = V4{0, 0, 0, 0};
-            for (int rb = 0; rb < na; rb += kQCh) {
-                for (int e = t; e < kQCh * kQb; e += kQThreads) {
-                    const int rr = e / kQb, kk = e % kQb;
-                    L.u.vch[rr][kk] = rb + rr < na ? vbuf[(int64_t)(rb + rr) * kQb + kk] : S(0);
-                }
-                __syncthreads();
-#pragma unroll
-                for (int u = 0; u < kQSub; u++) {
-                    const int s = wv + kQWaves * u;
-                    if (s > nsub) continue;
-                    if (s == nsub) {
-                        const int nk = min(kQCh, na - rb + 3) / 4;
-                        for (int kk = 0; kk < nk; kk++) {
-                            const S a = L.u.vch[4 * kk + l4][l16];
-                            acc[u] = qmfma(a, a, acc[u]);
-                        }
-                    } else {
-                        const int col = c0 + kQb * s + l16;
-                        // batches of 16 loads, the next batch in flight during a batch's products
-                        // (rows past the active ones read 0, and whole batches past them are skipped)
-                        const int nk = min(kQCh, na - rb + 3) / 4;
-                        constexpr int NB = 8;
-                        S b[NB], bn[NB];
-#pragma unroll
-                        for (int kk = 0; kk < NB; kk++) b[kk] = q.load(rb + 4 * kk + l4, col);
-                        for (int k0 = 0; k0 < nk; k0 += NB) {
-                            if (k0 + NB < nk) {
-#pragma unroll
-                                for (int kk = 0; kk < NB; kk++) bn[kk] = q.load(rb + 4 * (k0 + NB + kk) + l4, col);
-                            }
-#pragma unroll
-                            for (int kk = 0; kk < NB; kk++)
-                                acc[u] = qmfma(L.u.vch[4 * (k0 + kk) + l4][l16], b[kk], acc[u]);
-#pragma unroll
-                            for (int kk = 0; kk < NB; kk++) b[kk] = bn[kk];
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int u = 0; u < kQSub; u++) {
-                if (wv + kQWaves * u == nsub) {
-#pragma unroll
-                    for (int r = 0; r < 4; r++) L.u.G[qrow_of<S>(l4, r)][l16] = (double)acc[u][r];
-                }
-            }
-            __syncthreads();
-            if (wv == 0 && lane < kQb) {
-                // row i = lane of T, left to right in LDS
-                const int i = lane;
-                for (int jj = 0; jj < kQb; jj++) L.u.T[i][jj] = jj == i ? L.tau[i] : 0.0;
-                for (int jj = i + 1; jj < kQb; jj++) {
-                    double a = 0.0;
-                    for (int kk = i; kk < jj; kk++) a = fma(L.u.T[i][kk], L.u.G[kk][jj], a);
-                    L.u.T[i][jj] = -L.tau[jj] * a;
-                }
-            }
-            __syncthreads();
-            // W = T^T Z for each of the wave's subtiles
-#pragma unroll
-            for (int u = 0; u < kQSub; u++) {
-                if (wv + kQWaves * u >= nsub) continue;
-#pragma unroll
-                for (int r = 0; r < 4; r++) L.u.zb[wv][qrow_of<S>(l4, r)][l16] = (double)acc[u][r];
-                q_wave_sync();
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int mm = qrow_of<S>(l4, r);
-                    double w = 0.0;
-                    for (int kk = 0; kk <= mm; kk++) w = fma(L.u.T[kk][mm], L.u.zb[wv][kk][l16], w);
-                    L.u.wb[wv][u][mm][l16] = (S)w;
-                }
-                q_wave_sync();
-            }
-            // A -= V W
-            for (int rb = 0; rb < na; rb += kQCh) {
-                __syncthreads();
-                for (int e = t; e < kQCh * kQb; e += kQThreads) {
-                    const int rr = e / kQb, kk = e % kQb;
-                    L.u.vch[rr][kk] = rb + rr < na ? vbuf[(int64_t)(rb + rr) * kQb + kk] : S(0);
-                }
-                __syncthreads();
-#pragma unroll
-                for (int u = 0; u < kQSub; u++) {
-                    const int s = wv + kQWaves * u;
-                    if (s >= nsub) continue;
-                    const int col = c0 + kQb * s + l16;
-                    // two 16-row blocks at a time: their 8 loads first, then products and stores
-                    for (int sub0 = 0; sub0 < kQCh / 16; sub0 += 2) {
-                        if (rb + 16 * sub0 >= na) break;
-                        S cur[2][4];
-#pragma unroll
-                        for (int b4 = 0; b4 < 2; b4++)
-#pragma unroll
-                            for (int r = 0; r < 4; r++)
-                                cur[b4][r] = q.load(rb + 16 * (sub0 + b4) + qrow_of<S>(l4, r), col);
-#pragma unroll
-                        for (int b4 = 0; b4 < 2; b4++) {
-                            V4 d = {0, 0, 0, 0};
-#pragma unroll
-                            for (int kk = 0; kk < 4; kk++)
-                                d = qmfma(L.u.vch[16 * (sub0 + b4) + l16][4 * kk + l4], L.u.wb[wv][u][4 * kk + l4][l16],
-                                          d);
-#pragma unroll
-                            for (int r = 0; r < 4; r++)
-                                q.store(rb + 16 * (sub0 + b4) + qrow_of<S>(l4, r), col, cur[b4][r] - d[r]);
-                        }
-                    }
-                }
-            }
+            if (width % (16 / (int)sizeof(S)) == 0) q_trail_vec<S>(L, q, vbuf, na, c0, width, wv, lane);
+            else q_trail_scalar<S>(L, q, vbuf, na, c0, width, wv, lane);
         }
         __syncthreads();
     }
@@ -472,14 +647,14 @@ __global__ __launch_bounds__(kQThreads) void k_wqr_tree(TreeRegion reg0, TreeReg
     const int64_t chunk = (rows + nleaves - 1) / nleaves;
     const int64_t r_begin = min(rows, (int64_t)g * chunk), r_end = min(rows, r_begin + chunk);
     S *X = (S *)rg.src.p + r_begin * rg.src.ld;
-    S *vb = (S *)rg.vbuf + (int64_t)g * QGeom<S>::MAXR * kQb;
-    q_factor<S>(Ls, 0, X, rg.src.ld, r_end - r_begin, nullptr, 0, width, vb);
+    S *vb = (S *)((char *)rg.vbuf + (int64_t)g * kQVbufBytes);
+    q_factor<S, QGeom<S>::RPT>(Ls, 0, X, rg.src.ld, r_end - r_begin, nullptr, 0, width, vb);
     double *R = rg.slots + (int64_t)g * tsz;
     q_store_tri<S>(R, np, X, rg.src.ld, r_end - r_begin, width);
 
     int node = g, n = nleaves;
     int64_t soff = 0, coff = 0;
-    double *vd = (double *)rg.vbuf + (int64_t)g * QGeom<S>::MAXR * kQb * sizeof(S) / sizeof(double);
+    double *vd = (double *)((char *)rg.vbuf + (int64_t)g * kQVbufBytes);
     while (n > 1) {
         const int parent = node >> 1, first = parent << 1;
         const int nchild = min(2, n - first);
@@ -497,7 +672,7 @@ __global__ __launch_bounds__(kQThreads) void k_wqr_tree(TreeRegion reg0, TreeReg
             if (Ld.flag != 1) return;  // the last child to arrive combines this node
             q_copy(P, rg.slots + (soff + first) * tsz, tsz);
             __syncthreads();
-            q_factor<double>(Ld, 1, P, np, width, rg.slots + (soff + first + 1) * tsz, np, width, vd);
+            q_factor<double, kQMergeRpt>(Ld, 1, P, np, width, rg.slots + (soff + first + 1) * tsz, np, width, vd);
         } else {
             q_copy(P, R, tsz);
         }
@@ -517,7 +692,7 @@ __global__ __launch_bounds__(kQThreads) void k_wqr_merge(double *top, int64_t ld
                                                          int width, double *vbuf)
 {
     __shared__ QLds<double> Ld;
-    q_factor<double>(Ld, 1, top, ld1, width, bottom, ld2, width, vbuf);
+    q_factor<double, kQMergeRpt>(Ld, 1, top, ld1, width, bottom, ld2, width, vbuf);
 }
 
 // dst (n x n, stride ldd) <- the triangle src (w x w, stride lds) placed at rows [0, w)
@@ -534,7 +709,7 @@ __global__ void k_wqr_pad(const double *src, int64_t lds, int w, int off, double
 }  // namespace
 
 int64_t wqr_leaf_rows(int in_f64) { return in_f64 ? QGeom<double>::MAXR : QGeom<float>::MAXR; }
-int64_t wqr_vbuf_bytes() { return (int64_t)QGeom<float>::MAXR * kQb * (int64_t)sizeof(float); }
+int64_t wqr_vbuf_bytes() { return kQVbufBytes; }
 
 hipError_t launch_wqr_tree(int np, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s)
 {
