@@ -68,6 +68,9 @@ __device__ inline double group_sum(double v)
     return v;
 }
 
+// Sum over the 64 lanes of a wave, the same value in every lane (defined below).
+__device__ inline double wave_sum(double v);
+
 // Rotation (c, s) that zeroes gamma for the pair (alpha, beta, gamma), gamma != 0.
 // u and v are scaled by a power of two first so that u^2 + v^2 neither overflows
 // nor underflows (c and s depend only on their ratio).
@@ -302,14 +305,14 @@ hipError_t launch_v_npc(const double *R, int n, int64_t ldr, double *sigma, int 
 // are split into blocks of 16.  A persistent grid of NPC / 32 workgroups runs
 // a round-robin over block pairs: in each round every workgroup loads one pair
 // of blocks (32 columns) into LDS, applies one sweep of the same pair rotations
-// over its 32 columns, writes them back, and meets the others at a grid
-// barrier.  nb - 1 rounds make an outer sweep in which every column pair meets
+// over its 32 columns (16 pairs at a time, one wave per pair), writes them back,
+// and meets the others at a grid barrier.  nb - 1 rounds make an outer sweep in which every column pair meets
 // at least once; the iteration stops after an outer sweep without rotations.
 // Every wait is bounded: a barrier that does not complete within the spin limit
 // marks the run as timed out and every workgroup leaves.
 
 constexpr int kBlk = 16;            // columns per block
-constexpr int kBlkThreads = 256;    // 16 pairs x 16 lanes
+constexpr int kBlkThreads = 1024;   // 16 pairs x 64 lanes: one wave per pair
 enum : int { CTRL_SWEEPS = 0, CTRL_BAR = 1, CTRL_FLAG = 2, CTRL_TIMEOUT = 5, CTRL_EXP = 6, CTRL_WORDS = 8 };
 constexpr int kSpinLimit = 1 << 22;
 
@@ -349,7 +352,7 @@ __device__ inline bool grid_barrier(int32_t *ctrl, int target)
 template <int NPC>
 __global__ __launch_bounds__(kBlkThreads) void k_jacobi_blk(double *C, int n, int max_sweeps, int32_t *ctrl)
 {
-    constexpr int LP = 16, RPL = NPC / LP, LOC = 2 * kBlk, LDC = NPC + 16;
+    constexpr int LP = 64, RPL = NPC / LP, LOC = 2 * kBlk, LDC = NPC + 16;
     __shared__ double Cs[LOC * LDC];
     __shared__ int s_rot;
     const int tid = threadIdx.x, pair = tid / LP, sub = tid % LP;
@@ -411,9 +414,9 @@ __global__ __launch_bounds__(kBlkThreads) void k_jacobi_blk(double *C, int n, in
                     b1 = fma(xq[r + 1], xq[r + 1], b1);
                     g1 = fma(xp[r + 1], xq[r + 1], g1);
                 }
-                const double a = group_sum<LP>(a0 + a1);
-                const double b = group_sum<LP>(b0 + b1);
-                const double g = group_sum<LP>(g0 + g1);
+                const double a = wave_sum(a0 + a1);
+                const double b = wave_sum(b0 + b1);
+                const double g = wave_sum(g0 + g1);
                 if (g * g > tol2 * a * b) {
                     double c, sn;
                     jacobi_rotation(a, b, g, c, sn);
