@@ -151,7 +151,7 @@ hipError_t launch_seg_scan(const ScanJob &j0, const ScanJob &j1, int cpt, int in
                            int cartesian, hipStream_t s, int pass = -1);
 // One pass (0 tile reduce, 1 carry scan, 2 tile write) over a batch of jobs (device table
 // `jobs`, each with its own group table): tile_map[b] = (job, tile) for each of the ntiles
-// tile blocks, col_map[b] = (job, column) for each of the ncols carry blocks; every job of
+// tile blocks, col_map[b] = (job, first of 64 columns) for each of the ncols carry blocks; every job of
 // the batch has the same cpt and the same input and storage types.
 hipError_t launch_seg_scan_batch(int pass, const ScanJob *jobs, const int2 *tile_map, int64_t ntiles,
                                  const int2 *col_map, int64_t ncols, int cpt, int in_f64, int out_f64, hipStream_t s);

@@ -1226,7 +1226,7 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
         std::vector<int2> tiles, cols;
         for (int j = 0; j < (int)jobs.size(); j++) {
             for (int64_t t = 0; t < jobs[j].ntiles; t++) tiles.push_back(make_int2(j, (int)t));
-            for (int c = 0; c < jobs[j].n; c++) cols.push_back(make_int2(j, c));
+            for (int c = 0; c < jobs[j].n; c += 64) cols.push_back(make_int2(j, c));  // 64 columns per carry block
         }
         const size_t jo = P.img.add(jobs), to = P.img.add(tiles), co = P.img.add(cols);
         const int64_t nt = (int64_t)tiles.size(), nc = (int64_t)cols.size();

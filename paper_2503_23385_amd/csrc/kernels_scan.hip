@@ -28,7 +28,7 @@ constexpr int kScanThreads = 256;
 constexpr int kMaxTileRows = 512;
 constexpr int kMaxCols = 512;
 constexpr int kCarryThreads = 1024;
-constexpr int kBatchCarryThreads = 64;
+constexpr int kBatchCarryThreads = 1024;  // 64 columns x 16 chunks of tiles (batched carry scan)
 
 template <typename T>
 __device__ inline double to_f64(T v) { return (double)v; }
@@ -325,14 +325,66 @@ __global__ __launch_bounds__(kCarryThreads) void k_carry_scan(ScanJob j0, ScanJo
     carry_scan<kCarryThreads>(second ? j1 : j0, (int)blockIdx.x - (second ? j0.n : 0));
 }
 
-// A batch (device table): block b scans column map[b].y of job map[b].x.  The jobs of a
-// batch have few tiles each, so a block is one wave.
+// A batch (device table): block b scans columns [map[b].y, map[b].y + 64) of job map[b].x.
+// Thread (q, c) of the block takes column c of the q-th of 16 chunks of the job's tiles,
+// so that a wave reads one tile's aggregates of 64 columns at once (one coalesced read)
+// and writes one carry row at once: each chunk's aggregate, then each chunk's carry-in
+// from the chunks before it (left to right), then the carries of the chunk's tiles.
+constexpr int kCarryChunks = kBatchCarryThreads / 64;
 __global__ __launch_bounds__(kBatchCarryThreads) void k_carry_scan_batch(const ScanJob *__restrict__ jobs,
                                                                         const int2 *__restrict__ map)
 {
+    __shared__ int sf[kCarryChunks][64];
+    __shared__ double ss[kCarryChunks][64];
     const int2 e = map[blockIdx.x];
     const ScanJob J = jobs[e.x];
-    carry_scan<kBatchCarryThreads>(J, e.y);
+    const int T = (int)J.ntiles, n2 = J.n;
+    const int lc = (int)threadIdx.x & 63, q = (int)threadIdx.x >> 6;
+    const int c = e.y + lc;
+    const bool live = c < n2;
+    const int cc = live ? c : n2 - 1;
+    const int L = (T + kCarryChunks - 1) / kCarryChunks;
+    const int tb = min(T, q * L), te = min(T, tb + L);
+    constexpr int U = 8;  // tiles whose aggregates are loaded together
+    int F = 0;
+    double S = 0.0;
+    for (int t0 = tb; t0 < te; t0 += U) {
+        int f[U];
+        double st[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int t = min(t0 + u, te - 1);
+            f[u] = J.tileF[t];
+            st[u] = J.tileS[(int64_t)t * n2 + cc];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (t0 + u >= te) break;
+            S = f[u] ? st[u] : S + st[u];
+            F |= f[u];
+        }
+    }
+    sf[q][lc] = F;
+    ss[q][lc] = S;
+    __syncthreads();
+    double run = 0.0;
+    for (int qq = 0; qq < q; qq++) run = sf[qq][lc] ? ss[qq][lc] : run + ss[qq][lc];
+    for (int t0 = tb; t0 < te; t0 += U) {
+        int f[U];
+        double st[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int t = min(t0 + u, te - 1);
+            f[u] = J.tileF[t];
+            st[u] = J.tileS[(int64_t)t * n2 + cc];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (t0 + u >= te) break;
+            if (live) J.carry[(int64_t)(t0 + u) * n2 + c] = run;
+            run = f[u] ? st[u] : run + st[u];
+        }
+    }
 }
 
 template <typename Tin, typename Tout>
