@@ -526,7 +526,10 @@ hipError_t launch_jacobi(const double *R, int n, int64_t ldr, double *sigma, int
 namespace figaro {
 namespace {
 
-constexpr int kGkThreads = 256;   // load and scale; four waves bidiagonalise
+constexpr int kGkThreads = 256;   // load and scale; four waves bidiagonalise (NPC <= 64)
+// Threads of the bidiagonalisation workgroup: eight waves at NPC = 128, four below.
+template <int NPC>
+__host__ __device__ constexpr int gk_threads() { return NPC == 128 ? 512 : kGkThreads; }
 constexpr int kMsThreads = 256;   // multisection points per round (one workgroup per value)
 constexpr int kMsRounds = 7;      // 257^7 > 2^55: the final interval is below 2^-53 of the bound
 
@@ -654,19 +657,20 @@ __device__ void gk_bidiag_wg(double *A, double (*red)[64], double *dd, double *e
     }
 }
 
-// The same by four waves at NPC = 128: every lane owns two columns (left half-step) or two
-// rows (right half-step), c = lane + 64 u, and each wave a quarter of the other index
-// (32 entries in registers); the partial dot products of the two columns (rows) meet in
+// The same by eight waves at NPC = 128: every lane owns two columns (left half-step) or
+// two rows (right half-step), c = lane + 64 u, and each wave an eighth of the other index
+// (16 entries in registers); the partial dot products of the two columns (rows) meet in
 // LDS as above.
 template <int NPC>
 __device__ void gk_bidiag_wg2(double *A, double (*red)[NPC], double *dd, double *ee, int n, int lane, int wv)
 {
     static_assert(NPC == 128, "two columns per lane");
-    constexpr int LDA = GkGeom<NPC>::LDA, RW = NPC / 4;
+    constexpr int W = gk_threads<NPC>() / 64;
+    constexpr int LDA = GkGeom<NPC>::LDA, RW = NPC / W;
     const int w = __builtin_amdgcn_readfirstlane(wv);
-    const int e0 = w * RW;      // first entry of this wave's quarter
-    const int vsel = w >> 1;    // the reflector entries e0 .. e0 + RW - 1 sit in v[vsel]
-    const int voff = (w & 1) * RW;
+    const int e0 = w * RW;          // first entry of this wave's share
+    const int vsel = e0 / 64;       // the reflector entries e0 .. e0 + RW - 1 sit in v[vsel]
+    const int voff = e0 % 64;
     for (int k = 0; k < n; k++) {
         // ---- left reflector from column k (rows k..n-1), applied to the columns j > k
         {
@@ -706,7 +710,10 @@ __device__ void gk_bidiag_wg2(double *A, double (*red)[NPC], double *dd, double 
 #pragma unroll
             for (int u = 0; u < 2; u++) {
                 const int j = lane + 64 * u;
-                const double t = ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) * tau;
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < W; q += 4) t += (red[q][j] + red[q + 1][j]) + (red[q + 2][j] + red[q + 3][j]);
+                t *= tau;
                 if (j > k && j < n && e0 + RW > k) {
 #pragma unroll
                     for (int r = 0; r < RW; r++) A[(e0 + r) * LDA + j] = fma(-t, ve[r], x[u][r]);
@@ -754,7 +761,10 @@ __device__ void gk_bidiag_wg2(double *A, double (*red)[NPC], double *dd, double 
 #pragma unroll
             for (int u = 0; u < 2; u++) {
                 const int i = lane + 64 * u;
-                const double t = ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i])) * tau;
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < W; q += 4) t += (red[q][i] + red[q + 1][i]) + (red[q + 2][i] + red[q + 3][i]);
+                t *= tau;
                 if (i > k && i < n && e0 + RW > k + 1) {
 #pragma unroll
                     for (int r = 0; r < RW; r++) A[i * LDA + e0 + r] = fma(-t, ve[r], x[u][r]);
@@ -772,7 +782,7 @@ __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ld
     using Gm = GkGeom<NPC>;
     constexpr int LDA = Gm::LDA;
     __shared__ double A[NPC * LDA];
-    __shared__ double red[4][NPC > 64 ? NPC : 64];
+    __shared__ double red[gk_threads<NPC>() / 64][NPC > 64 ? NPC : 64];
     __shared__ double dd[NPC], ee[NPC];
     __shared__ double sc[2];
     __shared__ int s_exp;
@@ -780,7 +790,7 @@ __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ld
     if (ctrl && tid < CTRL_WORDS) ctrl[tid] = 0;  // no sweeps: this route does not iterate
     if (tid == 0) s_exp = INT_MIN;
     staged_copy<16, double>(
-        NPC * NPC, tid, kGkThreads,
+        NPC * NPC, tid, gk_threads<NPC>(),
         [&](int e) {
             const int i = e / NPC, j = e - i * NPC;
             return R[(int64_t)(i < n ? i : n - 1) * ldr + (j < n ? j : n - 1)];
@@ -794,12 +804,12 @@ __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ld
     // reflector norms and the recurrence below stay in range.
     {
         double m = 0.0;
-        for (int e = tid; e < NPC * NPC; e += kGkThreads) m = fmax(m, fabs(A[(e / NPC) * LDA + e % NPC]));
+        for (int e = tid; e < NPC * NPC; e += gk_threads<NPC>()) m = fmax(m, fabs(A[(e / NPC) * LDA + e % NPC]));
         if (m > 0.0) atomicMax(&s_exp, ilogb(m));
     }
     __syncthreads();
     const int ex0 = s_exp == INT_MIN ? 0 : s_exp;
-    for (int e = tid; e < NPC * NPC; e += kGkThreads) {
+    for (int e = tid; e < NPC * NPC; e += gk_threads<NPC>()) {
         double &x = A[(e / NPC) * LDA + e % NPC];
         x = ldexp(x, -ex0);
     }
@@ -826,14 +836,14 @@ __device__ __forceinline__ void sigma_gk_body(const double *R, int n, int64_t ld
     }
     __syncthreads();
     const int ex = (int)sc[0];
-    for (int i = tid; i < 2 * n - 1; i += kGkThreads) {
+    for (int i = tid; i < 2 * n - 1; i += gk_threads<NPC>()) {
         const double b = ldexp((i & 1) ? ee[i >> 1] : dd[i >> 1], -ex);
         msin[2 + i] = b * b;
     }
 }
 
 template <int NPC>
-__global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n, int64_t ldr, double *msin, int32_t *ctrl)
+__global__ __launch_bounds__(gk_threads<NPC>()) void k_sigma_gk(const double *R, int n, int64_t ldr, double *msin, int32_t *ctrl)
 {
     sigma_gk_body<NPC>(R, n, ldr, msin, ctrl);
 }
@@ -841,7 +851,7 @@ __global__ __launch_bounds__(kGkThreads) void k_sigma_gk(const double *R, int n,
 // Many independent problems of one width class: workgroup b takes entry b of tab (4 int64
 // each: element offset of its n x n R, offset of its sigma, n, offset of its msin).
 template <int NPC>
-__global__ __launch_bounds__(kGkThreads) void k_sigma_gk_batch(const double *R, const int64_t *tab, double *msin)
+__global__ __launch_bounds__(gk_threads<NPC>()) void k_sigma_gk_batch(const double *R, const int64_t *tab, double *msin)
 {
     const int64_t *e = tab + 4 * (int64_t)blockIdx.x;
     const int n = (int)e[2];
@@ -1121,7 +1131,7 @@ __global__ __launch_bounds__(64) void k_sigma_dqds_batch(const int64_t *tab, con
 template <int NPC>
 hipError_t launch_gk(const double *R, int n, int64_t ldr, int32_t *ctrl, double *msin, hipStream_t s)
 {
-    k_sigma_gk<NPC><<<1, kGkThreads, 0, s>>>(R, n, ldr, msin, ctrl);
+    k_sigma_gk<NPC><<<1, gk_threads<NPC>(), 0, s>>>(R, n, ldr, msin, ctrl);
     return hipGetLastError();
 }
 
@@ -1183,11 +1193,11 @@ hipError_t launch_sigma_batch(int npc, const double *R, double *sigma, const int
 {
     if (count <= 0) return hipSuccess;
     switch (npc) {
-    case 8: k_sigma_gk_batch<8><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
-    case 16: k_sigma_gk_batch<16><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
-    case 32: k_sigma_gk_batch<32><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
-    case 64: k_sigma_gk_batch<64><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
-    case 128: k_sigma_gk_batch<128><<<count, kGkThreads, 0, s>>>(R, tab, msin); break;
+    case 8: k_sigma_gk_batch<8><<<count, gk_threads<8>(), 0, s>>>(R, tab, msin); break;
+    case 16: k_sigma_gk_batch<16><<<count, gk_threads<16>(), 0, s>>>(R, tab, msin); break;
+    case 32: k_sigma_gk_batch<32><<<count, gk_threads<32>(), 0, s>>>(R, tab, msin); break;
+    case 64: k_sigma_gk_batch<64><<<count, gk_threads<64>(), 0, s>>>(R, tab, msin); break;
+    case 128: k_sigma_gk_batch<128><<<count, gk_threads<128>(), 0, s>>>(R, tab, msin); break;
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
