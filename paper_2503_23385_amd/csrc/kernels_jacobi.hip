@@ -304,15 +304,19 @@ hipError_t launch_v_npc(const double *R, int n, int64_t ldr, double *sigma, int 
 // For wider R the columns live in global memory (column-major, NPC x NPC) and
 // are split into blocks of 16.  A persistent grid of NPC / 32 workgroups runs
 // a round-robin over block pairs: in each round every workgroup loads one pair
-// of blocks (32 columns) into LDS, applies one sweep of the same pair rotations
-// over its 32 columns (16 pairs at a time, one wave per pair), writes them back,
-// and meets the others at a grid barrier.  nb - 1 rounds make an outer sweep in which every column pair meets
+// of blocks (32 columns C) into LDS, forms G = C^T C on the matrix cores, applies
+// one cyclic sweep of the pair rotations to G (each rotation computed from
+// G_pp, G_qq, G_pq, exactly as from the columns, with G <- J^T G J) while
+// accumulating them in V, then C <- C V on the matrix cores, writes the columns
+// back, and meets the others at a grid barrier.  Each round starts from a G formed
+// afresh from the columns, so the rotations' rounding does not accumulate there.  nb - 1 rounds make an outer sweep in which every column pair meets
 // at least once; the iteration stops after an outer sweep without rotations.
 // Every wait is bounded: a barrier that does not complete within the spin limit
 // marks the run as timed out and every workgroup leaves.
 
 constexpr int kBlk = 16;            // columns per block
-constexpr int kBlkThreads = 1024;   // 16 pairs x 64 lanes: one wave per pair
+constexpr int kBlkThreads = 1024;
+constexpr int kBlkWaves = kBlkThreads / 64;
 enum : int { CTRL_SWEEPS = 0, CTRL_BAR = 1, CTRL_FLAG = 2, CTRL_TIMEOUT = 5, CTRL_EXP = 6, CTRL_WORDS = 8 };
 constexpr int kSpinLimit = 1 << 22;
 
@@ -352,10 +356,14 @@ __device__ inline bool grid_barrier(int32_t *ctrl, int target)
 template <int NPC>
 __global__ __launch_bounds__(kBlkThreads) void k_jacobi_blk(double *C, int n, int max_sweeps, int32_t *ctrl)
 {
-    constexpr int LP = 64, RPL = NPC / LP, LOC = 2 * kBlk, LDC = NPC + 16;
+    constexpr int LOC = 2 * kBlk, LDC = NPC + 1;  // odd stride: a column-strided access is conflict free
+    typedef double d4 __attribute__((ext_vector_type(4)));
     __shared__ double Cs[LOC * LDC];
+    __shared__ double Gs[LOC][LOC + 1], Vs[LOC][LOC + 1];
+    __shared__ double rc_[LOC / 2], rs_[LOC / 2];
+    __shared__ int rp_[LOC / 2], rq_[LOC / 2];
     __shared__ int s_rot;
-    const int tid = threadIdx.x, pair = tid / LP, sub = tid % LP;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, l16 = lane & 15, l4 = lane >> 4;
     const int P = gridDim.x, w = blockIdx.x;
     const int nb = 2 * P, M = nb - 1;
     const double tol2 = ((double)n * 0x1p-53) * ((double)n * 0x1p-53);
@@ -390,45 +398,92 @@ __global__ __launch_bounds__(kBlkThreads) void k_jacobi_blk(double *C, int n, in
             }
             if (tid == 0) s_rot = 0;
             __syncthreads();
+            // 1. G = C^T C of the 32 local columns on the FP64 matrix cores (waves 0..2 form
+            //    the tiles (0,0), (0,1), (1,1) over all rows); V = I
+            if (wv < 3) {
+                const int ti = wv == 2 ? 1 : 0, tj = wv == 0 ? 0 : 1;
+                const double *ca = Cs + (ti * 16 + l16) * LDC, *cb = Cs + (tj * 16 + l16) * LDC;
+                d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+                for (int k0 = 0; k0 < NPC; k0 += 4)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k0 + l4], cb[k0 + l4], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int i = ti * 16 + l4 + 4 * r, j = tj * 16 + l16;
+                    Gs[i][j] = acc[r];
+                    if (ti != tj) Gs[j][i] = acc[r];
+                }
+            }
+            for (int e = tid; e < LOC * LOC; e += kBlkThreads) Vs[e / LOC][e % LOC] = (e / LOC == e % LOC) ? 1.0 : 0.0;
+            __syncthreads();
+            // 2. one cyclic sweep of the same pair rotations on G = C^T C (the rotation of a
+            //    pair from (G_pp, G_qq, G_pq), as from the columns themselves), G <- J^T G J,
+            //    V <- V J; 16 disjoint pairs per step
             constexpr int ML = LOC - 1;
-            int pa = pair == 0 ? 0 : pair % ML, qa = pair == 0 ? LOC - 1 : (ML - pair % ML) % ML;
             for (int step = 0; step < ML; step++) {
-                int p = pa, q = qa;
-                if (p > q) { const int t = p; p = q; q = t; }
-                pa = pa + 1 == ML ? 0 : pa + 1;
-                if (pair != 0) qa = qa + 1 == ML ? 0 : qa + 1;
-                double *cp = Cs + p * LDC + sub, *cq = Cs + q * LDC + sub;
-                double xp[RPL], xq[RPL];
-#pragma unroll
-                for (int r = 0; r < RPL; r++) {
-                    xp[r] = cp[r * LP];
-                    xq[r] = cq[r * LP];
-                }
-                double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, g0 = 0.0, g1 = 0.0;
-#pragma unroll
-                for (int r = 0; r < RPL; r += 2) {
-                    a0 = fma(xp[r], xp[r], a0);
-                    b0 = fma(xq[r], xq[r], b0);
-                    g0 = fma(xp[r], xq[r], g0);
-                    a1 = fma(xp[r + 1], xp[r + 1], a1);
-                    b1 = fma(xq[r + 1], xq[r + 1], b1);
-                    g1 = fma(xp[r + 1], xq[r + 1], g1);
-                }
-                const double a = wave_sum(a0 + a1);
-                const double b = wave_sum(b0 + b1);
-                const double g = wave_sum(g0 + g1);
-                if (g * g > tol2 * a * b) {
-                    double c, sn;
-                    jacobi_rotation(a, b, g, c, sn);
-#pragma unroll
-                    for (int r = 0; r < RPL; r++) {
-                        cp[r * LP] = c * xp[r] - sn * xq[r];
-                        cq[r * LP] = sn * xp[r] + c * xq[r];
+                if (tid < LOC / 2) {
+                    const int pr = tid;
+                    int p = pr == 0 ? step % ML : (pr + step) % ML;
+                    int q = pr == 0 ? LOC - 1 : (ML - pr + step) % ML;
+                    if (p > q) { const int t = p; p = q; q = t; }
+                    const double a = Gs[p][p], b = Gs[q][q], g = Gs[p][q];
+                    double c = 1.0, sn = 0.0;
+                    if (g * g > tol2 * a * b) {
+                        jacobi_rotation(a, b, g, c, sn);
+                        s_rot = 1;
                     }
-                    if (sub == 0) s_rot = 1;
+                    rp_[pr] = p;
+                    rq_[pr] = q;
+                    rc_[pr] = c;
+                    rs_[pr] = sn;
+                }
+                __syncthreads();
+                {
+                    const int u = tid & 511, pr = u >> 5, x = u & 31;
+                    const int p = rp_[pr], q = rq_[pr];
+                    const double c = rc_[pr], sn = rs_[pr];
+                    if (tid < 512) {  // rows p, q of G
+                        const double gp = Gs[p][x], gq = Gs[q][x];
+                        Gs[p][x] = c * gp - sn * gq;
+                        Gs[q][x] = sn * gp + c * gq;
+                    } else {          // columns p, q of V
+                        const double vp = Vs[x][p], vq = Vs[x][q];
+                        Vs[x][p] = c * vp - sn * vq;
+                        Vs[x][q] = sn * vp + c * vq;
+                    }
+                }
+                __syncthreads();
+                if (tid < 512) {      // columns p, q of G
+                    const int pr = tid >> 5, x = tid & 31;
+                    const int p = rp_[pr], q = rq_[pr];
+                    const double c = rc_[pr], sn = rs_[pr];
+                    const double gp = Gs[x][p], gq = Gs[x][q];
+                    Gs[x][p] = c * gp - sn * gq;
+                    Gs[x][q] = sn * gp + c * gq;
                 }
                 __syncthreads();
             }
+            // 3. C <- C V on the matrix cores, in place: wave wv owns rows [32 wv, 32 wv + 32)
+            //    and reads all 32 columns of a 16-row tile before writing it
+            for (int rt = 0; rt < NPC / 16 / kBlkWaves; rt++) {
+                const int row0 = (wv * (NPC / 16 / kBlkWaves) + rt) * 16;
+                d4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < LOC / 4; kk++) {
+                    const double av = Cs[(4 * kk + l4) * LDC + row0 + l16];
+                    d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Vs[4 * kk + l4][l16], d0, 0, 0, 0);
+                    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Vs[4 * kk + l4][16 + l16], d1, 0, 0, 0);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    Cs[l16 * LDC + row0 + l4 + 4 * r] = d0[r];
+                    Cs[(16 + l16) * LDC + row0 + l4 + 4 * r] = d1[r];
+                }
+            }
+            __syncthreads();
             for (int e = tid; e < LOC * NPC; e += kBlkThreads) {
                 const int l = e / NPC, i = e - l * NPC;
                 const int col = (l < kBlk ? bp * kBlk + l : bq * kBlk + (l - kBlk));
