@@ -65,6 +65,8 @@ __device__ __forceinline__ void gram_tile(const GramJob &J, int ti, int tj, int 
     d4 acc[4];
 #pragma unroll
     for (int v = 0; v < 4; v++) acc[v] = d4{0.0, 0.0, 0.0, 0.0};
+    const bool wlive = ti * kTile + wv * 16 < nx;
+    const int vlive = min(4, ((mode == 0 ? nx : ny) - tj * kTile + 15) / 16);
     for (int64_t rb = r0; rb < r1; rb += kRowsPerStage) {
         if (tid < kRowsPerStage) {
             const int64_t s = rb + tid;
@@ -106,13 +108,17 @@ __device__ __forceinline__ void gram_tile(const GramJob &J, int ti, int tj, int 
             yj[rr][c] = (live && tj * kTile + c < (mode == 0 ? nx : ny)) ? vj[u] : 0.0;
         }
         __syncthreads();
+        // subtiles wholly past the block's rows or columns (narrow tables) are skipped
+        if (wlive) {
 #pragma unroll
-        for (int k0 = 0; k0 < kRowsPerStage; k0 += 4) {
-            const double a = xi[k0 + lane / 16][wv * 16 + lane % 16];
+            for (int k0 = 0; k0 < kRowsPerStage; k0 += 4) {
+                const double a = xi[k0 + lane / 16][wv * 16 + lane % 16];
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const double b = yj[k0 + lane / 16][v * 16 + lane % 16];
-                acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[v], 0, 0, 0);
+                for (int v = 0; v < 4; v++) {
+                    if (v >= vlive) break;
+                    const double b = yj[k0 + lane / 16][v * 16 + lane % 16];
+                    acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[v], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
