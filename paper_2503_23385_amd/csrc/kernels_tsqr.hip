@@ -11,10 +11,12 @@
 //     w_k = R_jk + d_k / (alpha - beta),  R_jk -= tau w_k,  x_k += (w_k / beta) x_j,
 // and sets R_jj = beta (tau * scale = -1 / beta folded in).  Q is never formed.
 //
-// Widths up to 64: one wave owns one triangle (packed in LDS); lane (k, h)
-// keeps RPT rows of column k of X in registers for row set h, column j is
-// broadcast through a per-wave LDS slot, and every reduction stays inside the
-// wave -- no workgroup barrier.  A region is reduced in one launch: each wave
+// Widths up to 64: one wave owns one triangle (packed in LDS) and keeps a block
+// of X in registers -- at padded widths 16 to 64 lane 16 g + p holds columns
+// p, p + 16, ... of row group g and column j reaches each group by a lane
+// permutation; at widths 4 and 8 lane (k, h) holds column k of row set h and
+// column j is broadcast through a per-wave LDS slot.  Every reduction stays
+// inside the wave -- no workgroup barrier.  A region is reduced in one launch: each wave
 // reduces its rows to a leaf triangle, then the waves climb a tree whose arity
 // is set so that one block of rows holds all siblings of a node; at each node
 // the last child to arrive (per-node atomic counter) combines them, always as
@@ -24,6 +26,8 @@
 // Wider rows (padded widths 128 to 512) go to the blocked panel kernel
 // (kernels_panel.hip); its tree levels are separate launches.
 #include <float.h>
+
+#include <type_traits>
 
 #include "common.h"
 
@@ -720,6 +724,210 @@ __device__ inline void wt_absorb_rows(Tacc *Rp, Tacc *xb, const RowSrc &src, int
     }
 }
 
+// ------------------------------------------------------------------ column-set layout (NP = 16, 32, 64)
+//
+// The wave as four row groups of 16 lanes: lane 16 g + p keeps columns p + 16 s (s < NS)
+// of RPT rows of the block (rows g RPT .. g RPT + RPT - 1).  Column j sits in lane j % 16
+// of every row group, so one lane permutation hands each group its own rows of the pivot
+// column (no lane reads, no LDS writes); a dot product is a lane-local sum and two half
+// swaps over the groups.  Column sets wholly left of the pivot are skipped, so the vector
+// work of a step shrinks with the columns that remain.
+// Rows per lane and set in a block (measured on the 256-instance batch): 16 at width 64
+// (64-row blocks: the per-step reduction and reflector scalars are shared by twice the
+// rows, worth more than the next block's loads in flight), otherwise 32 / NS with the next
+// block prefetched into registers.
+template <int NP>
+struct SetGeom {
+    static_assert(NP == 16 || NP == 32 || NP == 64, "column-set layout");
+    static constexpr int NS = NP / 16;                  // column sets per lane
+    static constexpr int RPT = NP == 64 ? 16 : 32 / NS;  // rows per lane and set in a block
+    static constexpr int BR = 4 * RPT;                  // rows per block
+    static constexpr bool PREFETCH_OK = NS * RPT <= 32;  // registers for the next block
+};
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// The value held by the lane at byte address `addr` (ds_bpermute: the LDS crossbar, no
+// LDS memory).
+__device__ __forceinline__ float lane_fetch(int addr, float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_fetch(int addr, double v)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the four lanes p, p + 16, p + 32, p + 48 (two VALU half swaps), the same bits
+// in all four lanes.
+__device__ __forceinline__ float group4_sum(float v)
+{
+    unsigned u = __float_as_uint(v);
+    auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    u = __float_as_uint(v);
+    auto b = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+__device__ __forceinline__ double group4_sum(double v)
+{
+    unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    v = __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+    lo = (unsigned)__double2loint(v);
+    hi = (unsigned)__double2hiint(v);
+    a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
+// Reflector scalars in the accumulation type: FP64 with Newton-refined reciprocals, or
+// FP32 with the hardware reciprocals (1 ulp) -- in an FP32 accumulation the dot products
+// that feed them are FP32 sums already, so FP64 scalars buy neither range nor accuracy.
+__device__ __forceinline__ double refl_rsq(double x) { return rsq_refined(x); }
+__device__ __forceinline__ double refl_rcp(double x) { return rcp_refined(x); }
+__device__ __forceinline__ float refl_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float refl_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double refl_min(double) { return DBL_MIN; }
+__device__ __forceinline__ float refl_min(float) { return FLT_MIN; }
+
+// Absorb one block (x[s][i]: column p + 16 s, row g RPT + i) into the wave's triangle,
+// columns [jstart, width).  The reflector of wt_block, with its scalars in the
+// accumulation type.  The pivot's column set S is a constant of each unrolled copy, so
+// the sets it touches are known at compile time.
+template <int NP, typename Tacc>
+__device__ inline void ws_block(Tacc (&x)[SetGeom<NP>::NS][SetGeom<NP>::RPT], Tacc *Rp, int p, int g, int jstart,
+                                int width)
+{
+    using Gm = SetGeom<NP>;
+    constexpr int NS = Gm::NS, RPT = Gm::RPT;
+    const int grp = (g * 16) << 2;  // byte address of this row group's lane 0
+    static_for<0, NS>([&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+        const int j0 = max(jstart, 16 * S), j1 = min(width, 16 * S + 16);
+        for (int j = j0; j < j1; j++) {
+            const int jj = j - 16 * S;
+            // Row j of R (only this step writes it, after these reads): issued first, so
+            // that the LDS latency hides behind the dot products.
+            // (for a column left of j the read lands on an earlier entry of the packed
+            // triangle and is not used)
+            const Tacc alpha = Rp[pidx(NP, j, j)];
+            Tacc *Rrow = Rp + (pidx(NP, j, j) - j);
+            Tacc rjk[NS];
+#pragma unroll
+            for (int s = S; s < NS; s++) rjk[s] = Rrow[p + 16 * s];
+            // this row group's rows of the pivot column
+            Tacc piv[RPT];
+#pragma unroll
+            for (int i = 0; i < RPT; i++) piv[i] = lane_fetch(grp + (jj << 2), x[S][i]);
+            Tacc d[NS];
+#pragma unroll
+            for (int s = S; s < NS; s++) {
+                Tacc a0 = piv[0] * x[s][0], a1 = piv[1] * x[s][1];
+#pragma unroll
+                for (int i = 2; i < RPT; i += 2) {
+                    a0 = fma(piv[i], x[s][i], a0);
+                    a1 = fma(piv[i + 1], x[s][i + 1], a1);
+                }
+                d[s] = group4_sum(a0 + a1);
+            }
+            const Tacc dj = readlane_t(d[S], jj);
+            const Tacc q = fma(alpha, alpha, dj);
+            // A column whose norm is below the normal range is left untouched (tau = 0).
+            const bool ok = dj > Tacc(0) && q >= refl_min(q);
+            const Tacc r = refl_rsq(ok ? q : Tacc(1));
+            const Tacc sg = alpha >= Tacc(0) ? Tacc(1) : Tacc(-1);
+            const Tacc nrm = q * r;
+            const Tacc beta = -sg * nrm;
+            const Tacc inv_beta = -sg * r;
+            const Tacc scl = refl_rcp(ok ? alpha + sg * nrm : Tacc(1));
+            const Tacc tau = Tacc(1) - alpha * inv_beta;
+#pragma unroll
+            for (int s = S; s < NS; s++) {
+                const int col = p + 16 * s;
+                const bool upd = ok && col > j && col < width;
+                const Tacc w = fma(scl, d[s], rjk[s]);
+                // c = 0 leaves the column as it is (no branch around the update)
+                const Tacc c = upd ? w * inv_beta : Tacc(0);
+#pragma unroll
+                for (int i = 0; i < RPT; i++) x[s][i] = fma(c, piv[i], x[s][i]);
+                if (ok && g == 0 && col >= j && col < width)
+                    Rrow[col] = upd ? fma(-tau, w, rjk[s]) : beta;
+            }
+        }
+    });
+}
+
+// Rows of a block of the wave tree's leaves.
+template <int NP>
+__host__ __device__ constexpr int wave_leaf_rows()
+{
+    if constexpr (NP >= 16)
+        return SetGeom<NP>::BR;
+    else
+        return WaveGeom<NP>::BR;
+}
+
+// wt_absorb_rows for the column-set layout.
+template <int NP, typename Tin, typename Tacc, bool PREFETCH>
+__device__ inline void ws_absorb_rows(Tacc *Rp, const RowSrc &src, int64_t r0, int64_t r1, int tri_rows, int width,
+                                      int p, int g)
+{
+    using Gm = SetGeom<NP>;
+    constexpr int NS = Gm::NS, RPT = Gm::RPT, BR = Gm::BR;
+    if (r0 >= r1) return;
+    const uint32_t row_bytes = (uint32_t)(src.ld * (int64_t)sizeof(Tin));
+    uint32_t loff[NS];
+    bool col_in[NS];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int c = p + 16 * s - src.col_off;
+        col_in[s] = p + 16 * s < width && c >= 0 && c < src.width;
+        loff[s] = (uint32_t)(((int64_t)g * RPT * src.ld + (c < 0 ? 0 : c)) * (int64_t)sizeof(Tin));
+    }
+    auto load_rows = [&](Tacc (&y)[NS][RPT], int64_t rb) {
+        const uint32_t nrec = (uint32_t)(min(r1 - rb, (int64_t)BR) * (int64_t)row_bytes);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const char *)src.p + rb * (int64_t)row_bytes), (short)0, (int)nrec, kBufWord3);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const uint32_t off = col_in[s] ? loff[s] : nrec;
+#pragma unroll
+            for (int i = 0; i < RPT; i++) y[s][i] = (Tacc)buf_load<Tin>(rs, off + (uint32_t)i * row_bytes);
+        }
+    };
+    Tacc xn[PREFETCH ? NS : 1][PREFETCH ? RPT : 1];
+    if constexpr (PREFETCH) load_rows(xn, r0);
+    for (int64_t rb = r0; rb < r1; rb += BR) {
+        Tacc x[NS][RPT];
+        if constexpr (PREFETCH) {
+#pragma unroll
+            for (int s = 0; s < NS; s++)
+#pragma unroll
+                for (int i = 0; i < RPT; i++) x[s][i] = xn[s][i];
+            if (rb + BR < r1) load_rows(xn, rb + BR);
+        } else {
+            load_rows(x, rb);
+        }
+        int jstart = src.col_off;
+        if (tri_rows > 0) {
+            const int64_t off = rb % tri_rows;
+            if (off + BR <= tri_rows) jstart += (int)off;
+        }
+        ws_block<NP, Tacc>(x, Rp, p, g, jstart, width);
+    }
+}
+
 template <int NP, typename Tacc>
 __device__ inline void wt_load_tri(Tacc *Rp, const double *T, int width, int lane)
 {
@@ -761,9 +969,14 @@ __device__ __forceinline__ void wt_leaf(const TreeRegion &rg, const int g, Tacc 
     if (g >= nleaves) return;
     wt_load_tri<NP, Tacc>(Rp, nullptr, width, lane);
     int64_t chunk = (rows + nleaves - 1) / nleaves;
-    chunk = ((chunk + Gm::BR - 1) / Gm::BR) * Gm::BR;
+    constexpr int LBR = wave_leaf_rows<NP>();
+    chunk = ((chunk + LBR - 1) / LBR) * LBR;
     const int64_t r0 = (int64_t)g * chunk, r1 = min(rows, r0 + chunk);
-    wt_absorb_rows<NP, Tin, Tacc, sizeof(Tacc) == 4>(Rp, xb, rg.src, r0, r1, 0, width, k, h);
+    if constexpr (NP >= 16)
+        ws_absorb_rows<NP, Tin, Tacc, sizeof(Tacc) == 4 && SetGeom<NP>::PREFETCH_OK>(Rp, rg.src, r0, r1, 0, width,
+                                                                                   lane & 15, lane >> 4);
+    else
+        wt_absorb_rows<NP, Tin, Tacc, sizeof(Tacc) == 4>(Rp, xb, rg.src, r0, r1, 0, width, k, h);
 
     const int64_t tsz = (int64_t)width * NP;
     const int A = rg.arity;
@@ -785,7 +998,10 @@ __device__ __forceinline__ void wt_leaf(const TreeRegion &rg, const int g, Tacc 
             wt_load_tri<NP, Tacc>(Rp, rg.slots + (soff + first) * tsz, width, lane);
             const RowSrc sib{rg.slots + (soff + first + 1) * tsz, nullptr, (int64_t)(nchild - 1) * width, NP, 0,
                              width};
-            wt_absorb_rows<NP, double, Tacc, false>(Rp, xb, sib, 0, sib.rows_host, width, width, k, h);
+            if constexpr (NP >= 16)
+                ws_absorb_rows<NP, double, Tacc, false>(Rp, sib, 0, sib.rows_host, width, width, lane & 15, lane >> 4);
+            else
+                wt_absorb_rows<NP, double, Tacc, false>(Rp, xb, sib, 0, sib.rows_host, width, width, k, h);
         }
         node = parent;
         soff += n;
@@ -826,8 +1042,8 @@ static_assert(kWtSlice >= wt_slice_tri(32) + 64 && kWtSlice >= wt_slice_tri(16) 
                   kWtSlice >= wt_slice_tri(8) + 256 && kWtSlice >= wt_slice_tri(4) + 512,
               "wave slice");
 
-// At least four waves per SIMD (measured on the 256-instance batch: 3.3 ms against 3.6 ms
-// with the registers the compiler would otherwise take, at the cost of a few spilled values).
+// At least four waves per SIMD (measured on the 256-instance batch, FP32: 2.19 ms against
+// 2.37 ms at three; the few values the compiler spills for it sit outside the column steps).
 template <typename Tin, typename Tacc>
 __global__ __launch_bounds__(64 * kWtWaves, 4) void k_tsqr_wtree_multi(const TreeRegion *__restrict__ regs,
                                                                     const int4 *__restrict__ map, int64_t nitems)
@@ -1134,7 +1350,15 @@ int tsqr_block_rows(int np, int acc_f64)
     return tsqr_panel_rows(np, acc_f64);                   // workgroup panel kernel
 }
 
-int tsqr_wave_block_rows(int np) { return wave_block_rows(np); }
+int tsqr_wave_block_rows(int np)
+{
+    switch (np) {
+    case 16: return wave_leaf_rows<16>();
+    case 32: return wave_leaf_rows<32>();
+    case 64: return wave_leaf_rows<64>();
+    default: return wave_block_rows(np);
+    }
+}
 
 int tsqr_tree_arity(int np, int width)
 {
