@@ -767,28 +767,89 @@ __device__ __forceinline__ double lane_fetch(int addr, double v)
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the four lanes p, p + 16, p + 32, p + 48 (two VALU half swaps), the same bits
-// in all four lanes.
-__device__ __forceinline__ float group4_sum(float v)
+// Half swaps of two registers (gfx950 v_permlane16_swap / v_permlane32_swap).  With rows
+// of 16 lanes r0..r3: swap16(a, b) gives ([a.r0 b.r0 a.r2 b.r2], [a.r1 b.r1 a.r3 b.r3]) and
+// swap32(a, b) gives ([a.r0 a.r1 b.r0 b.r1], [a.r2 a.r3 b.r2 b.r3]).
+template <typename T>
+struct Pair {
+    T x, y;
+};
+__device__ __forceinline__ Pair<float> swap16(float a, float b)
 {
-    unsigned u = __float_as_uint(v);
-    auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
-    u = __float_as_uint(v);
-    auto b = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return {__uint_as_float(r[0]), __uint_as_float(r[1])};
 }
-__device__ __forceinline__ double group4_sum(double v)
+__device__ __forceinline__ Pair<float> swap32(float a, float b)
 {
-    unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    v = __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
-    lo = (unsigned)__double2loint(v);
-    hi = (unsigned)__double2hiint(v);
-    a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return {__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+__device__ __forceinline__ Pair<double> swap16(double a, double b)
+{
+    const auto l = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                    false);
+    const auto h = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                    false);
+    return {__hiloint2double((int)h[0], (int)l[0]), __hiloint2double((int)h[1], (int)l[1])};
+}
+__device__ __forceinline__ Pair<double> swap32(double a, double b)
+{
+    const auto l = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                    false);
+    const auto h = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                    false);
+    return {__hiloint2double((int)h[0], (int)l[0]), __hiloint2double((int)h[1], (int)l[1])};
+}
+
+// Sums over the four row groups of NA values at once (a[k]: this lane's partial of set k;
+// entries k >= NA are ignored).  The result in row group g is the sum of set
+// group_set<NA>(g): one set per group for NA = 3 or 4 (group 3 idle at 3), sets 0 1 0 1
+// for NA = 2, set 0 everywhere for NA = 1.  Each group's sum adds the same partials in the
+// same order in every lane that holds it.
+template <int NA>
+__device__ __forceinline__ int group_set(int g)
+{
+    return NA >= 3 ? g : (NA == 2 ? (g & 1) : 0);
+}
+template <int NA, typename T>
+__device__ __forceinline__ T group_reduce(const T (&a)[4])
+{
+    if constexpr (NA == 1) {
+        const Pair<T> u = swap16(a[0], a[0]);
+        const T t = u.x + u.y;
+        const Pair<T> v = swap32(t, t);
+        return v.x + v.y;
+    } else if constexpr (NA == 2) {
+        const Pair<T> u = swap16(a[0], a[1]);
+        const T t = u.x + u.y;
+        const Pair<T> v = swap32(t, t);
+        return v.x + v.y;
+    } else {
+        const Pair<T> u = swap16(a[0], a[1]);
+        const Pair<T> w = swap16(a[2], NA == 4 ? a[3] : T(0));
+        const Pair<T> v = swap32(u.x + u.y, w.x + w.y);
+        return v.x + v.y;
+    }
+}
+// The inverse: z holds, in group g, the value of set group_set<NA>(g); c[k] (k < NA) gets
+// the value of set k in every lane.
+template <int NA, typename T>
+__device__ __forceinline__ void group_spread(T z, T (&c)[4])
+{
+    if constexpr (NA == 1) {
+        c[0] = z;
+    } else if constexpr (NA == 2) {
+        const Pair<T> u = swap16(z, z);
+        c[0] = u.x;
+        c[1] = u.y;
+    } else {
+        const Pair<T> e = swap32(z, z);
+        const Pair<T> u = swap16(e.x, e.x), v = swap16(e.y, e.y);
+        c[0] = u.x;
+        c[1] = u.y;
+        c[2] = v.x;
+        c[3] = v.y;
+    }
 }
 
 // Reflector scalars in the accumulation type: FP64 with Newton-refined reciprocals, or
@@ -804,7 +865,10 @@ __device__ __forceinline__ float refl_min(float) { return FLT_MIN; }
 // Absorb one block (x[s][i]: column p + 16 s, row g RPT + i) into the wave's triangle,
 // columns [jstart, width).  The reflector of wt_block, with its scalars in the
 // accumulation type.  The pivot's column set S is a constant of each unrolled copy, so
-// the sets it touches are known at compile time.
+// the sets it touches (NA = NS - S) are known at compile time.  The dot products of the
+// NA sets are summed over the row groups together, each group then finishes one set's
+// column (w, the update coefficient, the new R entry) and the coefficients come back to
+// every group by half swaps.
 template <int NP, typename Tacc>
 __device__ inline void ws_block(Tacc (&x)[SetGeom<NP>::NS][SetGeom<NP>::RPT], Tacc *Rp, int p, int g, int jstart,
                                 int width)
@@ -813,35 +877,38 @@ __device__ inline void ws_block(Tacc (&x)[SetGeom<NP>::NS][SetGeom<NP>::RPT], Ta
     constexpr int NS = Gm::NS, RPT = Gm::RPT;
     const int grp = (g * 16) << 2;  // byte address of this row group's lane 0
     static_for<0, NS>([&](auto sc) {
-        constexpr int S = decltype(sc)::value;
+        constexpr int S = decltype(sc)::value, NA = NS - S;
+        const int gs = group_set<NA>(g);  // the set this row group finishes (relative to S)
+        const bool g_owns = g < NA;      // and writes back (one group per set)
+        const int col = p + 16 * (S + (gs < NA ? gs : 0));
         const int j0 = max(jstart, 16 * S), j1 = min(width, 16 * S + 16);
         for (int j = j0; j < j1; j++) {
             const int jj = j - 16 * S;
             // Row j of R (only this step writes it, after these reads): issued first, so
-            // that the LDS latency hides behind the dot products.
-            // (for a column left of j the read lands on an earlier entry of the packed
-            // triangle and is not used)
+            // that the LDS latency hides behind the dot products.  (For a column left of j
+            // the read lands on an earlier entry of the packed triangle and is not used.)
             const Tacc alpha = Rp[pidx(NP, j, j)];
             Tacc *Rrow = Rp + (pidx(NP, j, j) - j);
-            Tacc rjk[NS];
-#pragma unroll
-            for (int s = S; s < NS; s++) rjk[s] = Rrow[p + 16 * s];
+            const Tacc rjk = Rrow[col];
             // this row group's rows of the pivot column
             Tacc piv[RPT];
 #pragma unroll
             for (int i = 0; i < RPT; i++) piv[i] = lane_fetch(grp + (jj << 2), x[S][i]);
-            Tacc d[NS];
+            Tacc part[4];
 #pragma unroll
-            for (int s = S; s < NS; s++) {
-                Tacc a0 = piv[0] * x[s][0], a1 = piv[1] * x[s][1];
+            for (int k = 0; k < 4; k++) part[k] = Tacc(0);
+#pragma unroll
+            for (int k = 0; k < NA; k++) {
+                Tacc a0 = piv[0] * x[S + k][0], a1 = piv[1] * x[S + k][1];
 #pragma unroll
                 for (int i = 2; i < RPT; i += 2) {
-                    a0 = fma(piv[i], x[s][i], a0);
-                    a1 = fma(piv[i + 1], x[s][i + 1], a1);
+                    a0 = fma(piv[i], x[S + k][i], a0);
+                    a1 = fma(piv[i + 1], x[S + k][i + 1], a1);
                 }
-                d[s] = group4_sum(a0 + a1);
+                part[k] = a0 + a1;
             }
-            const Tacc dj = readlane_t(d[S], jj);
+            const Tacc d = group_reduce<NA>(part);  // x_j . x_col, col of this group's set
+            const Tacc dj = readlane_t(d, jj);       // group 0 finishes set S, pivot lane jj
             const Tacc q = fma(alpha, alpha, dj);
             // A column whose norm is below the normal range is left untouched (tau = 0).
             const bool ok = dj > Tacc(0) && q >= refl_min(q);
@@ -852,18 +919,16 @@ __device__ inline void ws_block(Tacc (&x)[SetGeom<NP>::NS][SetGeom<NP>::RPT], Ta
             const Tacc inv_beta = -sg * r;
             const Tacc scl = refl_rcp(ok ? alpha + sg * nrm : Tacc(1));
             const Tacc tau = Tacc(1) - alpha * inv_beta;
+            const bool upd = ok && col > j && col < width;
+            const Tacc w = fma(scl, d, rjk);
+            if (ok && g_owns && col >= j && col < width) Rrow[col] = upd ? fma(-tau, w, rjk) : beta;
+            // c = 0 leaves a column as it is (no branch around the update)
+            Tacc c[4];
+            group_spread<NA>(upd ? w * inv_beta : Tacc(0), c);
 #pragma unroll
-            for (int s = S; s < NS; s++) {
-                const int col = p + 16 * s;
-                const bool upd = ok && col > j && col < width;
-                const Tacc w = fma(scl, d[s], rjk[s]);
-                // c = 0 leaves the column as it is (no branch around the update)
-                const Tacc c = upd ? w * inv_beta : Tacc(0);
+            for (int k = 0; k < NA; k++)
 #pragma unroll
-                for (int i = 0; i < RPT; i++) x[s][i] = fma(c, piv[i], x[s][i]);
-                if (ok && g == 0 && col >= j && col < width)
-                    Rrow[col] = upd ? fma(-tau, w, rjk[s]) : beta;
-            }
+                for (int i = 0; i < RPT; i++) x[S + k][i] = fma(c[k], piv[i], x[S + k][i]);
         }
     });
 }
