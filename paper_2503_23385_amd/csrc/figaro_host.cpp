@@ -1661,26 +1661,34 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
             if (r.wave && !r.skip && r.rows_cap > 0) cls[r.np].push_back(rows_log2(r.rows_cap));
     plan_drop_execs(plan);
     TimingGuard tg;
+    // time of `stage` (summed over kTuneReps runs after a warm-up) with candidate `cand` for
+    // the tuning key `key`, the trees of each class in their own launch or all in one
+    auto time_cand = [&](const TuneKey &key, const TreeTune &cand, bool fused, const char *stage, double *ms) {
+        tune_override(&key, &cand);
+        plan_relayout(plan);
+        const Program prog = build_program(plan, ws, R, sigma, fused);
+        figaro_plan::Exec *ex = nullptr;
+        int e = plan_exec(plan, ws, R, sigma, prog, &ex);
+        if (!e) e = run_program(prog, ex->tables, s);  // warm-up
+        double t = 0.0;
+        if (!e) e = take_stage_ms([](const char *) { return false; }, &t);
+        for (int i = 0; i < kTuneReps && !e; i++) e = run_program(prog, ex->tables, s);
+        *ms = 0.0;
+        if (!e) e = take_stage_ms([stage](const char *n) { return std::strcmp(n, stage) == 0; }, ms);
+        plan_drop_execs(plan);
+        tune_override(nullptr, nullptr);
+        return e;
+    };
+    // each class alone
     for (auto &kv : cls) {
         const int np = kv.first;
         const TuneKey key{acc, np, 1, 0};
-        const char *stage = class_name(kTreeNames, np);
         double best_ms = 1e300;
         TreeTune best = tune_default(key);
         for (const TreeTune &cand : tune_candidates(key)) {
-            tune_override(&key, &cand);
-            plan_relayout(plan);
-            const Program prog = build_program(plan, ws, R, sigma, false);
-            figaro_plan::Exec *ex = nullptr;
-            rc = plan_exec(plan, ws, R, sigma, prog, &ex);
-            if (!rc) rc = run_program(prog, ex->tables, s);  // warm-up
             double ms = 0.0;
-            if (!rc) rc = take_stage_ms([](const char *) { return false; }, &ms);
-            for (int i = 0; i < kTuneReps && !rc; i++) rc = run_program(prog, ex->tables, s);
-            if (!rc) rc = take_stage_ms([stage](const char *n) { return std::strcmp(n, stage) == 0; }, &ms);
-            plan_drop_execs(plan);
+            rc = time_cand(key, cand, false, class_name(kTreeNames, np), &ms);
             if (rc) {
-                tune_override(nullptr, nullptr);
                 plan_relayout(plan);
                 return rc;
             }
@@ -1689,8 +1697,31 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
                 best = cand;
             }
         }
-        tune_override(nullptr, nullptr);
         for (int l : kv.second) tune_set(TuneKey{acc, np, 1, l}, best, best_ms / kTuneReps);
+    }
+    // then the classes together: a plan runs every narrow width in one launch, where the
+    // balance of the leaves over the compute units sets the time -- one pass of coordinate
+    // descent over the classes, widest first, on the fused launch
+    if (cls.size() > 1) {
+        for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
+            const int np = it->first;
+            const TuneKey key{acc, np, 1, 0};
+            double best_ms = 1e300;
+            TreeTune best = tune_get(TuneKey{acc, np, 1, it->second.front()});
+            for (const TreeTune &cand : tune_candidates(key)) {
+                double ms = 0.0;
+                rc = time_cand(key, cand, true, "tsqr_narrow", &ms);
+                if (rc) {
+                    plan_relayout(plan);
+                    return rc;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand;
+                }
+            }
+            for (int l : it->second) tune_set(TuneKey{acc, np, 1, l}, best, best_ms / kTuneReps);
+        }
     }
     plan_relayout(plan);
     // sigma route per width class (multisection or dqds after the bidiagonalisation)

@@ -114,7 +114,7 @@ std::vector<TreeTune> tune_candidates(const TuneKey &k)
         return c;
     }
     if (k.batched) {
-        for (int b : {8, 16, 32, 64}) c.push_back(TreeTune{TREE_WAVE, b, 2});
+        for (int b : {4, 8, 16, 32, 64}) c.push_back(TreeTune{TREE_WAVE, b, 2});
     } else {
         for (int b : {0, 2, 4, 8}) c.push_back(TreeTune{TREE_WG, b, 0});
         for (int b : {8, 16, 32}) c.push_back(TreeTune{TREE_WAVE, b, 2});
