@@ -98,9 +98,12 @@ TreeTune tune_default(const TuneKey &k)
 {
     if (k.acc_f64 == TUNE_SIGMA) return TreeTune{SIGMA_MSECT, 0, 2};
     if (k.batched) {
-        // measured on the 256-instance batch: 32 blocks per leaf at padded widths 32 and 64,
-        // 16 at narrower widths; binary trees (the shortest climb for the last leaf)
-        return TreeTune{TREE_WAVE, k.np >= 32 ? 32 : 16, 2};
+        // measured on the 256-instance batch (all widths in one launch): 16 blocks per leaf
+        // at padded width 64, 64 at 32, 32 at 16 and 64 below; trees of arity 4 (a binary
+        // climb over short leaves costs more node stores and loads than its shorter merges
+        // save)
+        const int b = k.np >= 64 ? 16 : (k.np == 32 ? 64 : (k.np == 16 ? 32 : 64));
+        return TreeTune{TREE_WAVE, b, 4};
     }
     return TreeTune{TREE_WG, 0, 0};
 }
@@ -114,10 +117,12 @@ std::vector<TreeTune> tune_candidates(const TuneKey &k)
         return c;
     }
     if (k.batched) {
-        for (int b : {4, 8, 16, 32, 64}) c.push_back(TreeTune{TREE_WAVE, b, 2});
+        for (int b : {4, 8, 16, 32, 64})
+            for (int a : {2, 4, 8}) c.push_back(TreeTune{TREE_WAVE, b, a});
     } else {
         for (int b : {0, 2, 4, 8}) c.push_back(TreeTune{TREE_WG, b, 0});
-        for (int b : {8, 16, 32}) c.push_back(TreeTune{TREE_WAVE, b, 2});
+        for (int b : {8, 16, 32})
+            for (int a : {2, 4}) c.push_back(TreeTune{TREE_WAVE, b, a});
     }
     return c;
 }
