@@ -142,7 +142,7 @@ struct Region {
     int64_t rows_cap;
     int cnt;
     int width, col_off, np;
-    bool wave;                // narrow tree kernel (np <= 64); else the panel tree kernel
+    bool wave;                // tuned tree kernel (np <= 128); else the blocked QR tree
     bool wave_tree;           // narrow regions: one wave per leaf (else one workgroup per leaf)
     bool givens;              // narrow regions: leaves absorb rows by Givens rotations
     bool skip;                // rows absorbed directly by the root merge (no tree of its own)
@@ -239,6 +239,16 @@ constexpr int kMaxWaveLeaves = 1 << 16;
 void apply_tree(Region &r, const TreeTune &t, int acc_f64)
 {
     int64_t leaves;
+    if (r.np > 64 && t.kind != TREE_WAVE) {
+        // the workgroup kernel of width 128 is the panel tree: rows streamed through LDS
+        // into each leaf's triangle, leaves of 4 blocks, binary tree
+        r.wave_tree = false;
+        r.arity = 2;
+        r.rows_per_leaf = (int64_t)4 * tsqr_block_rows(r.np, acc_f64);
+        leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+        r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxPanelLeaves));
+        return;
+    }
     if (t.kind == TREE_WAVE) {
         r.wave_tree = true;
         r.rows_per_leaf = (int64_t)std::max(1, t.leaf_blocks) * tsqr_wave_block_rows(r.np);
@@ -264,10 +274,18 @@ void apply_tree(Region &r, const TreeTune &t, int acc_f64)
     r.arity = tsqr_tree_arity(r.np, r.width);
 }
 
-// A region of rows_cap rows reduced by a tree: narrow regions (np <= 64) take the tree
-// kernel and leaf length of the tuning table; their node storage is sized for every
-// candidate the autotuner may switch to, so that the workspace size does not depend on
-// the tuning.  Wide regions take the panel tree with leaves of 4 panel blocks.
+// Node slots and counters of a region's tree under its current kernel.
+void region_tree_sizes(const Region &r, int64_t *slots, int64_t *counters)
+{
+    if (r.np > 64 && !r.wave_tree) tsqr_panel_tree_sizes(r.leaves, slots, counters);
+    else tsqr_tree_sizes(r.leaves, r.arity, slots, counters);
+}
+
+// A region of rows_cap rows reduced by a tree: regions up to padded width 128 take the
+// tree kernel and leaf length of the tuning table (at 128 the panel tree or one wave per
+// leaf); their node storage is sized for every candidate the autotuner may switch to, so
+// that the workspace size does not depend on the tuning.  Wider regions take the blocked
+// QR tree.
 constexpr int64_t kGivensLeafRows = 256;
 
 Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int col_off, int acc_f64,
@@ -281,24 +299,17 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
     r.width = width;
     r.col_off = col_off;
     r.np = tsqr_padded_width(width);
-    r.wave = r.np <= 64;
+    r.wave = r.np <= kPanelTreeMaxNp;  // tuned tree kernel (wave or workgroup / panel tree)
     r.ncounters = 0;
     r.skip = false;
     if (!r.wave) {
         r.wave_tree = false;
         r.arity = 2;
-        if (r.np <= kPanelTreeMaxNp) {
-            // rows streamed through LDS into each leaf's triangle, leaves of 4 blocks
-            r.rows_per_leaf = (int64_t)4 * tsqr_block_rows(r.np, acc_f64);
-            const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
-            r.leaves = (int)std::max<int64_t>(1, std::min<int64_t>(leaves, kMaxPanelLeaves));
-        } else {
-            // blocked QR of each leaf's rows at once: leaves as long as the kernel takes
-            // (the regions of a form are stored in FP64 exactly when it accumulates in FP64)
-            r.rows_per_leaf = wqr_leaf_rows(acc_f64);
-            const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
-            r.leaves = (int)std::max<int64_t>(1, leaves);
-        }
+        // blocked QR of each leaf's rows at once: leaves as long as the kernel takes
+        // (the regions of a form are stored in FP64 exactly when it accumulates in FP64)
+        r.rows_per_leaf = wqr_leaf_rows(acc_f64);
+        const int64_t leaves = (r.rows_cap + r.rows_per_leaf - 1) / r.rows_per_leaf;
+        r.leaves = (int)std::max<int64_t>(1, leaves);
         tsqr_panel_tree_sizes(r.leaves, &r.nslots, &r.ncnt);
         return r;
     }
@@ -321,13 +332,13 @@ Region make_region(const char *name, int64_t rows_cap, int cnt, int width, int c
         Region c = r;
         apply_tree(c, t, acc_f64);
         int64_t ns = 0, nc = 0;
-        tsqr_tree_sizes(c.leaves, c.arity, &ns, &nc);
+        region_tree_sizes(c, &ns, &nc);
         r.nslots = std::max(r.nslots, ns);
         r.ncnt = std::max(r.ncnt, nc);
     }
     apply_tree(r, tune_get(key), acc_f64);
     int64_t ns = 0, nc = 0;
-    tsqr_tree_sizes(r.leaves, r.arity, &ns, &nc);
+    region_tree_sizes(r, &ns, &nc);
     r.nslots = std::max(r.nslots, ns);
     r.ncnt = std::max(r.ncnt, nc);
     return r;
@@ -592,7 +603,6 @@ int run_regions(const Layout &L, int acc_f64, void *ws, hipStream_t s)
         Stage st(name, s);
         if (r.givens) HIPCHK(launch_givens_tree(r.np, L.m_f64, tr, n, s), "givens tree");
         else if (r.wave) HIPCHK(launch_tsqr_tree(r.np, acc_f64, L.m_f64, tr, n, s, r.wave_tree), "tsqr tree");
-        else if (r.np <= kPanelTreeMaxNp) HIPCHK(launch_tsqr_panel_tree(r.np, acc_f64, L.m_f64, tr, n, s), "tsqr panel tree");
         else HIPCHK(launch_wqr_tree(r.np, L.m_f64, tr, n, s), "wide tsqr tree");
     }
     return FIGARO_OK;
@@ -1262,15 +1272,16 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
         void *lws = slice(i);
         for (const Region &r : L.regions) {
             if (r.skip || r.rows_cap == 0) continue;
-            if (r.wave) {
+            if (r.wave && r.np <= 64) {
                 tree_cls[{r.np, r.wave_tree ? 1 : 0}].push_back(tree_region(r, L, lws));
             } else {
+                // width 128 (wave or panel tree, by the tuning) and wider: a launch per region
                 const TreeRegion tr = tree_region(r, L, lws);
-                const int np = r.np;
-                const char *name = r.name;
-                P.steps.push_back([tr, np, name, acc, m_f64](const unsigned char *, hipStream_t s) {
+                const int np = r.np, wave_tree = r.wave_tree ? 1 : 0;
+                const char *name = r.wave ? class_name(kTreeNames, np) : r.name;
+                P.steps.push_back([tr, np, wave_tree, name, acc, m_f64](const unsigned char *, hipStream_t s) {
                     Stage st(name, s);
-                    if (np <= kPanelTreeMaxNp) HIPCHK(launch_tsqr_panel_tree(np, acc, m_f64, &tr, 1, s), "tsqr panel tree");
+                    if (np <= kPanelTreeMaxNp) HIPCHK(launch_tsqr_tree(np, acc, m_f64, &tr, 1, s, wave_tree), "tsqr tree");
                     else HIPCHK(launch_wqr_tree(np, m_f64, &tr, 1, s), "wide tsqr tree");
                     return FIGARO_OK;
                 });
@@ -1702,9 +1713,10 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
     // then the classes together: a plan runs every narrow width in one launch, where the
     // balance of the leaves over the compute units sets the time -- one pass of coordinate
     // descent over the classes, widest first, on the fused launch
-    if (cls.size() > 1) {
+    if (std::count_if(cls.begin(), cls.end(), [](const auto &kv) { return kv.first <= 64; }) > 1) {
         for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
             const int np = it->first;
+            if (np > 64) continue;  // not in the fused launch
             const TuneKey key{acc, np, 1, 0};
             double best_ms = 1e300;
             TreeTune best = tune_get(TuneKey{acc, np, 1, it->second.front()});

@@ -734,14 +734,14 @@ __device__ inline void wt_absorb_rows(Tacc *Rp, Tacc *xb, const RowSrc &src, int
 // work of a step shrinks with the columns that remain.
 // Rows per lane and set in a block (measured on the 256-instance batch): 16 at width 64
 // (64-row blocks: the per-step reduction and reflector scalars are shared by twice the
-// rows, worth more than the next block's loads in flight), otherwise 32 / NS with the next
-// block prefetched into registers.
+// rows, worth more than the next block's loads in flight), 8 at width 128 (64 registers of
+// X), otherwise 32 / NS with the next block prefetched into registers.
 template <int NP>
 struct SetGeom {
-    static_assert(NP == 16 || NP == 32 || NP == 64, "column-set layout");
-    static constexpr int NS = NP / 16;                  // column sets per lane
-    static constexpr int RPT = NP == 64 ? 16 : 32 / NS;  // rows per lane and set in a block
-    static constexpr int BR = 4 * RPT;                  // rows per block
+    static_assert(NP == 16 || NP == 32 || NP == 64 || NP == 128, "column-set layout");
+    static constexpr int NS = NP / 16;                                       // column sets per lane
+    static constexpr int RPT = NP == 64 ? 16 : (NP == 128 ? 8 : 32 / NS);  // rows per lane and set
+    static constexpr int BR = 4 * RPT;                                       // rows per block
     static constexpr bool PREFETCH_OK = NS * RPT <= 32;  // registers for the next block
 };
 
@@ -865,10 +865,10 @@ __device__ __forceinline__ float refl_min(float) { return FLT_MIN; }
 // Absorb one block (x[s][i]: column p + 16 s, row g RPT + i) into the wave's triangle,
 // columns [jstart, width).  The reflector of wt_block, with its scalars in the
 // accumulation type.  The pivot's column set S is a constant of each unrolled copy, so
-// the sets it touches (NA = NS - S) are known at compile time.  The dot products of the
-// NA sets are summed over the row groups together, each group then finishes one set's
-// column (w, the update coefficient, the new R entry) and the coefficients come back to
-// every group by half swaps.
+// the sets it touches (NA = NS - S) are known at compile time.  They are taken in chunks
+// of up to four: the dot products of a chunk's sets are summed over the row groups
+// together, each group then finishes one set's column (w, the update coefficient, the new
+// R entry) and the coefficients come back to every group by half swaps.
 template <int NP, typename Tacc>
 __device__ inline void ws_block(Tacc (&x)[SetGeom<NP>::NS][SetGeom<NP>::RPT], Tacc *Rp, int p, int g, int jstart,
                                 int width)
@@ -877,10 +877,17 @@ __device__ inline void ws_block(Tacc (&x)[SetGeom<NP>::NS][SetGeom<NP>::RPT], Ta
     constexpr int NS = Gm::NS, RPT = Gm::RPT;
     const int grp = (g * 16) << 2;  // byte address of this row group's lane 0
     static_for<0, NS>([&](auto sc) {
-        constexpr int S = decltype(sc)::value, NA = NS - S;
-        const int gs = group_set<NA>(g);  // the set this row group finishes (relative to S)
-        const bool g_owns = g < NA;      // and writes back (one group per set)
-        const int col = p + 16 * (S + (gs < NA ? gs : 0));
+        constexpr int S = decltype(sc)::value, NA = NS - S, NC = (NA + 3) / 4;
+        // per chunk: the column this row group finishes, and whether it writes it back
+        // (one group per set)
+        int col[NC];
+        bool owns[NC];
+        static_for<0, NC>([&](auto cc) {
+            constexpr int C = decltype(cc)::value, NAC = NA - 4 * C < 4 ? NA - 4 * C : 4;
+            const int gs = group_set<NAC>(g);
+            owns[C] = g < NAC;
+            col[C] = p + 16 * (S + 4 * C + (gs < NAC ? gs : 0));
+        });
         const int j0 = max(jstart, 16 * S), j1 = min(width, 16 * S + 16);
         for (int j = j0; j < j1; j++) {
             const int jj = j - 16 * S;
@@ -889,26 +896,33 @@ __device__ inline void ws_block(Tacc (&x)[SetGeom<NP>::NS][SetGeom<NP>::RPT], Ta
             // the read lands on an earlier entry of the packed triangle and is not used.)
             const Tacc alpha = Rp[pidx(NP, j, j)];
             Tacc *Rrow = Rp + (pidx(NP, j, j) - j);
-            const Tacc rjk = Rrow[col];
+            Tacc rjk[NC];
+#pragma unroll
+            for (int c = 0; c < NC; c++) rjk[c] = Rrow[col[c]];
             // this row group's rows of the pivot column
             Tacc piv[RPT];
 #pragma unroll
             for (int i = 0; i < RPT; i++) piv[i] = lane_fetch(grp + (jj << 2), x[S][i]);
-            Tacc part[4];
+            Tacc d[NC];  // x_j . x_col for this group's column of each chunk
+            static_for<0, NC>([&](auto cc) {
+                constexpr int C = decltype(cc)::value, NAC = NA - 4 * C < 4 ? NA - 4 * C : 4;
+                Tacc part[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) part[k] = Tacc(0);
+                for (int k = 0; k < 4; k++) part[k] = Tacc(0);
 #pragma unroll
-            for (int k = 0; k < NA; k++) {
-                Tacc a0 = piv[0] * x[S + k][0], a1 = piv[1] * x[S + k][1];
+                for (int k = 0; k < NAC; k++) {
+                    const int sx = S + 4 * C + k;
+                    Tacc a0 = piv[0] * x[sx][0], a1 = piv[1] * x[sx][1];
 #pragma unroll
-                for (int i = 2; i < RPT; i += 2) {
-                    a0 = fma(piv[i], x[S + k][i], a0);
-                    a1 = fma(piv[i + 1], x[S + k][i + 1], a1);
+                    for (int i = 2; i < RPT; i += 2) {
+                        a0 = fma(piv[i], x[sx][i], a0);
+                        a1 = fma(piv[i + 1], x[sx][i + 1], a1);
+                    }
+                    part[k] = a0 + a1;
                 }
-                part[k] = a0 + a1;
-            }
-            const Tacc d = group_reduce<NA>(part);  // x_j . x_col, col of this group's set
-            const Tacc dj = readlane_t(d, jj);       // group 0 finishes set S, pivot lane jj
+                d[C] = group_reduce<NAC>(part);
+            });
+            const Tacc dj = readlane_t(d[0], jj);  // group 0 finishes set S, pivot lane jj
             const Tacc q = fma(alpha, alpha, dj);
             // A column whose norm is below the normal range is left untouched (tau = 0).
             const bool ok = dj > Tacc(0) && q >= refl_min(q);
@@ -919,16 +933,19 @@ __device__ inline void ws_block(Tacc (&x)[SetGeom<NP>::NS][SetGeom<NP>::RPT], Ta
             const Tacc inv_beta = -sg * r;
             const Tacc scl = refl_rcp(ok ? alpha + sg * nrm : Tacc(1));
             const Tacc tau = Tacc(1) - alpha * inv_beta;
-            const bool upd = ok && col > j && col < width;
-            const Tacc w = fma(scl, d, rjk);
-            if (ok && g_owns && col >= j && col < width) Rrow[col] = upd ? fma(-tau, w, rjk) : beta;
-            // c = 0 leaves a column as it is (no branch around the update)
-            Tacc c[4];
-            group_spread<NA>(upd ? w * inv_beta : Tacc(0), c);
+            static_for<0, NC>([&](auto cc) {
+                constexpr int C = decltype(cc)::value, NAC = NA - 4 * C < 4 ? NA - 4 * C : 4;
+                const bool upd = ok && col[C] > j && col[C] < width;
+                const Tacc w = fma(scl, d[C], rjk[C]);
+                if (ok && owns[C] && col[C] >= j && col[C] < width) Rrow[col[C]] = upd ? fma(-tau, w, rjk[C]) : beta;
+                // c = 0 leaves a column as it is (no branch around the update)
+                Tacc cf[4];
+                group_spread<NAC>(upd ? w * inv_beta : Tacc(0), cf);
 #pragma unroll
-            for (int k = 0; k < NA; k++)
+                for (int k = 0; k < NAC; k++)
 #pragma unroll
-                for (int i = 0; i < RPT; i++) x[S + k][i] = fma(c[k], piv[i], x[S + k][i]);
+                    for (int i = 0; i < RPT; i++) x[S + 4 * C + k][i] = fma(cf[k], piv[i], x[S + 4 * C + k][i]);
+            });
         }
     });
 }
@@ -1328,6 +1345,36 @@ __global__ __launch_bounds__(64 * kWtWaves) void k_tsqr_wtree(TreeRegion reg0, T
     wt_leaf<NP, Tin, Tacc>(second ? reg1 : reg0, item - (second ? reg0.nleaves : 0), Rs[wv], Xs[wv], lane);
 }
 
+// Padded width 128: one wave per workgroup (its packed triangle takes 33 KB of LDS in
+// FP32, 66 KB in FP64).
+template <typename Tin, typename Tacc>
+__global__ __launch_bounds__(64) void k_tsqr_wtree128(TreeRegion reg0, TreeRegion reg1)
+{
+    __shared__ Tacc Rs[WaveGeom<128>::PS];
+    const int lane = threadIdx.x;
+    const int item = (int)blockIdx.x;
+    if (item >= reg0.nleaves + reg1.nleaves) return;
+    const bool second = item >= reg0.nleaves;
+    wt_leaf<128, Tin, Tacc>(second ? reg1 : reg0, item - (second ? reg0.nleaves : 0), Rs, Rs, lane);
+}
+
+hipError_t launch_wtree128(int acc_f64, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s)
+{
+    TreeRegion r0 = regs[0];
+    TreeRegion r1 = nreg > 1 ? regs[1] : TreeRegion{};
+    const unsigned grid = (unsigned)(r0.nleaves + r1.nleaves);
+#define FIGARO_TREE(TI, TA) k_tsqr_wtree128<TI, TA><<<grid, 64, 0, s>>>(r0, r1)
+    if (acc_f64) {
+        if (in_f64) FIGARO_TREE(double, double);
+        else FIGARO_TREE(float, double);
+    } else {
+        if (in_f64) FIGARO_TREE(double, float);
+        else FIGARO_TREE(float, float);
+    }
+#undef FIGARO_TREE
+    return hipGetLastError();
+}
+
 template <int NP>
 hipError_t launch_wtree_np(int acc_f64, int in_f64, const TreeRegion *regs, int nreg, hipStream_t s)
 {
@@ -1421,6 +1468,7 @@ int tsqr_wave_block_rows(int np)
     case 16: return wave_leaf_rows<16>();
     case 32: return wave_leaf_rows<32>();
     case 64: return wave_leaf_rows<64>();
+    case 128: return wave_leaf_rows<128>();
     default: return wave_block_rows(np);
     }
 }
@@ -1486,6 +1534,10 @@ hipError_t launch_tsqr_tree(int np, int acc_f64, int in_f64, const TreeRegion *r
                                : launch_tree_np<NPV>(acc_f64, in_f64, regs, nreg, s);
     FIGARO_CASE(4) FIGARO_CASE(8) FIGARO_CASE(16) FIGARO_CASE(32) FIGARO_CASE(64)
 #undef FIGARO_CASE
+    case 128:
+        // the workgroup kernel of this width is the streaming panel tree
+        return wave_tree ? launch_wtree128(acc_f64, in_f64, regs, nreg, s)
+                         : launch_tsqr_panel_tree(128, acc_f64, in_f64, regs, nreg, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -97,6 +97,7 @@ int rows_log2(int64_t rows)
 TreeTune tune_default(const TuneKey &k)
 {
     if (k.acc_f64 == TUNE_SIGMA) return TreeTune{SIGMA_MSECT, 0, 2};
+    if (k.np > 64) return TreeTune{TREE_WG, 0, 2};  // width 128: the panel tree
     if (k.batched) {
         // measured on the 256-instance batch (all widths in one launch): 16 blocks per leaf
         // at padded width 64, 64 at 32, 32 at 16 and 64 below; trees of arity 4 (a binary
@@ -114,6 +115,13 @@ std::vector<TreeTune> tune_candidates(const TuneKey &k)
     if (k.acc_f64 == TUNE_SIGMA) {
         c.push_back(TreeTune{SIGMA_MSECT, 0, 2});
         c.push_back(TreeTune{SIGMA_DQDS, 0, 2});
+        return c;
+    }
+    if (k.np > 64) {
+        // width 128: the panel tree (the workgroup kernel of this width) or one wave per leaf
+        c.push_back(TreeTune{TREE_WG, 0, 2});
+        for (int b : {4, 8, 16, 32})
+            for (int a : {2, 4}) c.push_back(TreeTune{TREE_WAVE, b, a});
         return c;
     }
     if (k.batched) {

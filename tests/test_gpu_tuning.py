@@ -15,9 +15,11 @@ TOL = {"fp64": 1e-12, "fp32": 1e-5}
 
 
 def cache_lines(kind, leaf_blocks, arity, batched):
+    """Tuning entries for every padded width up to 128 (kind 0 at width 128 is the panel
+    tree, its workgroup kernel)."""
     out = []
     for acc in (0, 1):
-        for np_ in (4, 8, 16, 32, 64):
+        for np_ in (4, 8, 16, 32, 64, 128):
             for rl in range(0, 41):
                 out.append(f'{{"arch":"gfx950","acc_f64":{acc},"np":{np_},"batched":{batched},"rows_log2":{rl},'
                            f'"kind":{kind},"leaf_blocks":{leaf_blocks},"arity":{arity},"ms":0}}')
@@ -36,7 +38,7 @@ def wave_tree_single_calls(tmp_path):
 
 
 @pytest.mark.parametrize("name", ["cart_ragged", "keyed_zipf_n64", "keyed_uniform_sparse", "cart_tail_leaf",
-                                  "keyed_singleton_B", "cart_n125_ragged"])
+                                  "keyed_singleton_B", "cart_n125_ragged", "keyed_n128"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("two_sided", [False, True])
 def test_single_call_wave_tree(wave_tree_single_calls, name, prec, two_sided):
@@ -65,6 +67,46 @@ def test_r_autotune_then_parity(prec):
     er = relF(R.cpu().numpy(), oracle.r(inst))
     assert er <= TOL[prec]
     assert any(e["batched"] == 0 for e in fg().tune_table())
+
+
+@pytest.mark.parametrize("arity", [2, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("two_sided", [False, True])
+def test_plan_wave_trees_all_widths(tmp_path, arity, prec, two_sided):
+    """A plan with every tree up to padded width 128 reduced one wave per leaf (short
+    leaves, so that every region climbs a tree), each instance against the oracle."""
+    path = tmp_path / "wave_plan.jsonl"
+    path.write_text(cache_lines(1, 4, arity, 1))
+    fg().tune_load(str(path))
+    try:
+        insts = mixed_plan_instances()
+        say(f"[plan wave trees] arity={arity} {prec} two_sided={two_sided}")
+        tens = [to_dev(i) for i in insts]
+        plan = fg().Plan(tens, prec, two_sided=two_sided)
+        d = dev()
+        ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=d)
+        R = torch.zeros(plan.r_total, dtype=torch.float64, device=d)
+        S = torch.zeros(plan.s_total, dtype=torch.float64, device=d)
+        plan.execute(ws, R, S)
+        torch.cuda.synchronize()
+        Rh = R.cpu().numpy()
+        for i, inst in enumerate(insts):
+            N = inst.A.shape[1] + inst.B.shape[1]
+            Rg = Rh[plan.r_off[i]:plan.r_off[i] + N * N].reshape(N, N)
+            Ro = oracle.r(inst)
+            if not np.any(Ro):
+                assert not np.any(Rg)
+                continue
+            assert relF(Rg, Ro) <= TOL[prec], i
+    finally:
+        # back to the plan defaults: wave trees up to width 64, the panel tree at 128
+        back = tmp_path / "default_plan.jsonl"
+        blocks = {4: 64, 8: 64, 16: 32, 32: 64, 64: 16}
+        back.write_text("".join(
+            f'{{"arch":"gfx950","acc_f64":{acc},"np":{np_},"batched":1,"rows_log2":{rl},"kind":{1 if np_ <= 64 else 0},'
+            f'"leaf_blocks":{blocks.get(np_, 0)},"arity":{4 if np_ <= 64 else 2},"ms":0}}\n'
+            for acc in (0, 1) for np_ in (4, 8, 16, 32, 64, 128) for rl in range(0, 41)))
+        fg().tune_load(str(back))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
