@@ -1135,6 +1135,12 @@ struct figaro_plan {
     size_t ws_bytes = 0;
     size_t msin_off = 0;               // multisection inputs of every instance (2 N_i + 2 doubles each)
     hipStream_t cap_stream = nullptr;
+    // Side streams (default priority) and events of the sigma stage, whose width classes
+    // run side by side: each class fills only part of the GPU (a workgroup per instance).
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[kSide] = {};
     // Per (ws, R, sigma): the device launch tables (built and uploaded when that triple
     // is first executed, owned by the plan) and the captured graph.
     struct Exec {
@@ -1422,8 +1428,15 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
     }
 
     // 6. sigma: per width class, one bidiagonalisation workgroup per instance, then one
-    // multisection workgroup per singular value
-    for (int c = 8; c <= 128; c *= 2) {
+    // multisection workgroup per singular value; the classes on the plan's side streams
+    // (forked from and joined back into the launch stream), widest first
+    struct SigmaClass {
+        int c, n, dqds;
+        size_t off;
+        const char *name;
+    };
+    std::vector<SigmaClass> scls;
+    for (int c = 128; c >= 8; c /= 2) {
         std::vector<int64_t> tab;
         for (size_t i = 0; i < count; i++) {
             if (sigma_width_class((int)plan->shapes[i].N()) != c) continue;
@@ -1433,14 +1446,27 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
             tab.push_back(2 * plan->s_off[i] + 2 * (int64_t)i);
         }
         if (tab.empty()) continue;
-        const size_t off = P.img.add(tab);
-        const int n = (int)(tab.size() / 4);
+        scls.push_back(SigmaClass{c, (int)(tab.size() / 4), tune_get(TuneKey{TUNE_SIGMA, c, 1, 0}).kind == SIGMA_DQDS,
+                                  P.img.add(tab), class_name(kSigmaNames, c)});
+    }
+    if (!scls.empty()) {
         double *msin = at<double>(ws, plan->msin_off);
-        const char *name = class_name(kSigmaNames, c);
-        const int dqds = tune_get(TuneKey{TUNE_SIGMA, c, 1, 0}).kind == SIGMA_DQDS;
         P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
-            Stage st(name, s);
-            HIPCHK(launch_sigma_batch(c, R, sigma, (const int64_t *)(t + off), n, msin, s, dqds), "batched sigma");
+            const bool ready = plan->ev_fork && plan->side[figaro_plan::kSide - 1] && plan->ev_join[figaro_plan::kSide - 1];
+            const int nb = ready ? std::min<int>((int)scls.size(), figaro_plan::kSide) : 1;
+            if (nb > 1) HIPCHK(hipEventRecord(plan->ev_fork, s), "sigma fork");
+            for (int k = 0; k < (int)scls.size(); k++) {
+                hipStream_t sk = nb > 1 ? plan->side[k % nb] : s;
+                if (nb > 1 && k < nb) HIPCHK(hipStreamWaitEvent(sk, plan->ev_fork, 0), "sigma fork wait");
+                const SigmaClass &e = scls[k];
+                Stage st(e.name, sk);
+                HIPCHK(launch_sigma_batch(e.c, R, sigma, (const int64_t *)(t + e.off), e.n, msin, sk, e.dqds),
+                       "batched sigma");
+            }
+            for (int k = 0; k < nb && nb > 1; k++) {
+                HIPCHK(hipEventRecord(plan->ev_join[k], plan->side[k]), "sigma join");
+                HIPCHK(hipStreamWaitEvent(s, plan->ev_join[k], 0), "sigma join wait");
+            }
             return FIGARO_OK;
         });
     }
@@ -1530,6 +1556,14 @@ int plan_check(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *
 int plan_exec(figaro_plan *plan, void *ws, double *R, double *sigma, const Program &prog,
               figaro_plan::Exec **out)
 {
+    // the sigma stage's side streams and events, made on the first execution (a failed
+    // attempt leaves the missing ones null and the stage on the launch stream alone)
+    if (!plan->ev_fork) HIPCHK(hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming), "plan fork event");
+    for (int k = 0; k < figaro_plan::kSide; k++) {
+        if (!plan->side[k]) HIPCHK(hipStreamCreateWithFlags(&plan->side[k], hipStreamNonBlocking), "plan side stream");
+        if (!plan->ev_join[k])
+            HIPCHK(hipEventCreateWithFlags(&plan->ev_join[k], hipEventDisableTiming), "plan join event");
+    }
     auto key = std::make_tuple(ws, R, sigma);
     auto it = plan->execs.find(key);
     if (it == plan->execs.end()) {
@@ -1854,6 +1888,11 @@ void figaro_plan_destroy(figaro_plan *plan)
         if (kv.second.tables) (void)hipFree(kv.second.tables);
     }
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    for (int k = 0; k < figaro_plan::kSide; k++) {
+        if (plan->side[k]) (void)hipStreamDestroy(plan->side[k]);
+        if (plan->ev_join[k]) (void)hipEventDestroy(plan->ev_join[k]);
+    }
+    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
     delete plan;
 }
 
