@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the tree autotuner (run before timing; its choices are listed under tuning)")
+    ap.add_argument("--tune-save", default=None,
+                    help="write the tuning table to this file at the end (FIGARO_TUNE_CACHE reloads it, so that a "
+                         "profiled run with --no-autotune takes the same tree kernels and leaves)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
@@ -155,7 +158,10 @@ def batch_stage_work(insts, precision):
 
 # Kernel source and symbol behind each single-kernel stage.
 STAGE_KERNELS = {
+    # tree stages: the workgroup tree (k_tsqr_tree) or the wave tree (k_tsqr_wtree,
+    # k_tsqr_wtree128 at width 128), as the tuner chose
     "tsqr_tails": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
+    "tsqr_heads": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_wtree128"),
     "tsqr_m1": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
     "tsqr_m2": ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_tree"),
     "jacobi": ("paper_2503_23385_amd/csrc/kernels_jacobi.hip", "k_jacobi_lds"),
@@ -543,6 +549,8 @@ def main():
         "tuning": fg.tune_table(),
         "memory": out.get("memory"),
     }
+    if args.tune_save:
+        fg.tune_save(args.tune_save)
     print(json.dumps(line))
 
 
