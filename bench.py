@@ -136,20 +136,27 @@ def stage_work(inst, two_sided, precision, sweeps):
     return work
 
 
-def batch_stage_work(insts, precision):
-    """Algorithmic work of the single-kernel stages of the batched two-sided form."""
+def batch_stage_work(insts, precision, chains):
+    """Algorithmic work of the single-kernel stages of the batched two-sided form.  chains:
+    the plan ran two chains side by side (its stages list "tsqr_narrow_b"): the instances
+    with n1 + n2 in (64, 128] ("tsqr_narrow": their trees in one launch) and the rest
+    ("tsqr_narrow_b"); otherwise every narrow tree is in the one "tsqr_narrow" launch."""
     work = {}
     in_bytes = out_bytes = 0.0
     esz = 8 if precision == "fp64" else 4
-    for inst in insts:
+    wide = [inst.A.shape[1] + inst.B.shape[1] > 64 for inst in insts]
+    narrow = {"tsqr_narrow": 0.0, "tsqr_narrow_b": 0.0}
+    for inst, wd in zip(insts, wide):
         (m1, n1), (m2, n2) = inst.A.shape, inst.B.shape
         for rows, w in ((m1 - 1, n1), (m2 - 1, n2)):
             k = f"tsqr_np{padded(w)}"
             work[k] = ("alu", work.get(k, ("alu", 0.0))[1] + flops(rows, w))
+            narrow["tsqr_narrow_b" if chains and not wd else "tsqr_narrow"] += flops(rows, w)
         in_bytes += inst.A.nbytes + inst.B.nbytes
         out_bytes += ((m1 - 1) * n1 + (m2 - 1) * n2) * esz
-    # every narrow width's trees in one launch
-    work["tsqr_narrow"] = ("alu", sum(v[1] for k, v in work.items() if k.startswith("tsqr_np")))
+    for k, v in narrow.items():
+        if v > 0:
+            work[k] = ("alu", v)
     # the write pass reads every table and writes every tail row once; the reduce pass reads
     work["scan_write"] = ("hbm", (in_bytes + out_bytes) / 1e9)
     work["scan_reduce"] = ("hbm", in_bytes / 1e9)
@@ -173,6 +180,7 @@ STAGE_KERNELS = {
 for _np in (4, 8, 16, 32, 64):
     STAGE_KERNELS[f"tsqr_np{_np}"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_wtree_batch")
 STAGE_KERNELS["tsqr_narrow"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_wtree_multi")
+STAGE_KERNELS["tsqr_narrow_b"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_wtree_multi")
 
 
 def measured_traffic(workload, stage, form=None):
@@ -418,7 +426,7 @@ def bench_batch(args, insts, desc, forms_spec, torch, fg, dev, stream, refs, tim
                                              and f["errors_vs_oracle"]["sigma_rel2"] <= TOL))]
     chosen = min(ok, key=lambda k: forms[k]["ms_per_step"])
     f = forms[chosen]
-    work = batch_stage_work(insts, f["precision"])
+    work = batch_stage_work(insts, f["precision"], "tsqr_narrow_b" in f["stage_ms"])
     roof = roofline_of(f, work, f["precision"], bound="alu")
     roof_hbm = roofline_of(f, work, f["precision"], bound="hbm")
     return {"value": f["value"], "ms_per_step": f["ms_per_step"], "chosen": chosen, "precision": f["precision"],

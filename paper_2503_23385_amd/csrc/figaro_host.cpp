@@ -1138,6 +1138,7 @@ struct figaro_plan {
     // Side streams (default priority) and events of the sigma stage, whose width classes
     // run side by side: each class fills only part of the GPU (a workgroup per instance).
     static constexpr int kSide = 4;
+    int chains = 1;  // run the two chains side by side (set by the autotuner)
     hipStream_t side[kSide] = {};
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join[kSide] = {};
@@ -1186,6 +1187,14 @@ using Step = std::function<int(const unsigned char *tables, hipStream_t s)>;
 struct Program {
     TableImage img;
     std::vector<Step> steps;
+    std::vector<int> lanes;  // per step: 0 the launch stream, k > 0 the plan's side stream k - 1
+    int lane = 0;            // lane of the steps pushed from now on
+    const figaro_plan *plan = nullptr;
+    void set_lane(int k)
+    {
+        lanes.resize(steps.size(), lane);
+        lane = k;
+    }
 };
 
 // The steps and tables of one execution of the plan with these buffers.
@@ -1194,6 +1203,7 @@ struct Program {
 Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigma, bool fuse_trees = true)
 {
     Program P;
+    P.plan = plan;
     const size_t count = plan->inst.size();
     const int prec = plan->shapes[0].precision;
     const int acc = prec == FIGARO_PLAIN_FP64;
@@ -1271,107 +1281,181 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
         });
     }
 
-    // 4. trees: narrow regions batched by padded width, wide ones per region
-    std::map<std::pair<int, int>, std::vector<TreeRegion>> tree_cls;
-    for (size_t i = 0; i < count; i++) {
-        const Layout &L = plan->layouts[i];
-        void *lws = slice(i);
-        for (const Region &r : L.regions) {
-            if (r.skip || r.rows_cap == 0) continue;
-            if (r.wave && r.np <= 64) {
-                tree_cls[{r.np, r.wave_tree ? 1 : 0}].push_back(tree_region(r, L, lws));
-            } else {
-                // width 128 (wave or panel tree, by the tuning) and wider: a launch per region
-                const TreeRegion tr = tree_region(r, L, lws);
-                const int np = r.np, wave_tree = r.wave_tree ? 1 : 0;
-                const char *name = r.wave ? class_name(kTreeNames, np) : r.name;
-                P.steps.push_back([tr, np, wave_tree, name, acc, m_f64](const unsigned char *, hipStream_t s) {
-                    Stage st(name, s);
-                    if (np <= kPanelTreeMaxNp) HIPCHK(launch_tsqr_tree(np, acc, m_f64, &tr, 1, s, wave_tree), "tsqr tree");
-                    else HIPCHK(launch_wqr_tree(np, m_f64, &tr, 1, s), "wide tsqr tree");
+    // 4-6. trees, roots, (refinement,) sigma.  Without refinement the instances of sigma
+    // width class 128 and the others form two chains that run side by side on the plan's
+    // side streams (forked after the assembly, joined at the end): one chain's
+    // bidiagonalisations then overlap the other's trees.
+    auto emit_trees = [&](const std::vector<size_t> &idx, const char *narrow_name) {
+        // 4. trees: narrow regions batched by padded width, wide ones per region
+        std::map<std::pair<int, int>, std::vector<TreeRegion>> tree_cls;
+        for (size_t i : idx) {
+            const Layout &L = plan->layouts[i];
+            void *lws = slice(i);
+            for (const Region &r : L.regions) {
+                if (r.skip || r.rows_cap == 0) continue;
+                if (r.wave && r.np <= 64) {
+                    tree_cls[{r.np, r.wave_tree ? 1 : 0}].push_back(tree_region(r, L, lws));
+                } else {
+                    // width 128 (wave or panel tree, by the tuning) and wider: a launch per region
+                    const TreeRegion tr = tree_region(r, L, lws);
+                    const int np = r.np, wave_tree = r.wave_tree ? 1 : 0;
+                    const char *name = r.wave ? class_name(kTreeNames, np) : r.name;
+                    P.steps.push_back([tr, np, wave_tree, name, acc, m_f64](const unsigned char *, hipStream_t s) {
+                        Stage st(name, s);
+                        if (np <= kPanelTreeMaxNp) HIPCHK(launch_tsqr_tree(np, acc, m_f64, &tr, 1, s, wave_tree), "tsqr tree");
+                        else HIPCHK(launch_wqr_tree(np, m_f64, &tr, 1, s), "wide tsqr tree");
+                        return FIGARO_OK;
+                    });
+                }
+            }
+        }
+        if (fuse_trees) {
+            // every wave-tree class in one launch, the widest leaves first
+            std::vector<TreeRegion> regs;
+            std::vector<int4> map;
+            for (auto it = tree_cls.rbegin(); it != tree_cls.rend(); ++it) {
+                if (!it->first.second) continue;
+                const int np = it->first.first;
+                for (const TreeRegion &tr : it->second) {
+                    const int j = (int)regs.size();
+                    regs.push_back(tr);
+                    for (int l = 0; l < tr.nleaves; l++) map.push_back(make_int4(j, l, np, 0));
+                }
+            }
+            for (auto it = tree_cls.begin(); it != tree_cls.end();) {
+                if (it->first.second) it = tree_cls.erase(it);
+                else ++it;
+            }
+            if (!map.empty()) {
+                const size_t ro = P.img.add(regs), mo = P.img.add(map);
+                const int64_t nb = (int64_t)map.size();
+                P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+                    Stage st(narrow_name, s);
+                    HIPCHK(launch_tsqr_wtree_multi(acc, m_f64, (const TreeRegion *)(t + ro), (const int4 *)(t + mo), nb,
+                                                   s),
+                           "batched tsqr trees");
                     return FIGARO_OK;
                 });
             }
         }
-    }
-    if (fuse_trees) {
-        // every wave-tree class in one launch, the widest leaves first
-        std::vector<TreeRegion> regs;
-        std::vector<int4> map;
-        for (auto it = tree_cls.rbegin(); it != tree_cls.rend(); ++it) {
-            if (!it->first.second) continue;
-            const int np = it->first.first;
-            for (const TreeRegion &tr : it->second) {
-                const int j = (int)regs.size();
-                regs.push_back(tr);
-                for (int l = 0; l < tr.nleaves; l++) map.push_back(make_int4(j, l, np, 0));
-            }
-        }
-        for (auto it = tree_cls.begin(); it != tree_cls.end();) {
-            if (it->first.second) it = tree_cls.erase(it);
-            else ++it;
-        }
-        if (!map.empty()) {
+        for (auto &kv : tree_cls) {
+            const std::vector<TreeRegion> &regs = kv.second;
+            std::vector<int2> map;
+            for (int j = 0; j < (int)regs.size(); j++)
+                for (int l = 0; l < regs[j].nleaves; l++) map.push_back(make_int2(j, l));
             const size_t ro = P.img.add(regs), mo = P.img.add(map);
             const int64_t nb = (int64_t)map.size();
+            const int np = kv.first.first, wave_tree = kv.first.second;
+            const char *name = class_name(kTreeNames, np);
             P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
-                Stage st("tsqr_narrow", s);
-                HIPCHK(launch_tsqr_wtree_multi(acc, m_f64, (const TreeRegion *)(t + ro), (const int4 *)(t + mo), nb,
-                                               s),
-                       "batched tsqr trees");
+                Stage st(name, s);
+                HIPCHK(launch_tsqr_tree_batch(wave_tree, np, acc, m_f64, (const TreeRegion *)(t + ro),
+                                              (const int2 *)(t + mo), nb, s),
+                       "batched tsqr tree");
                 return FIGARO_OK;
             });
         }
-    }
-    for (auto &kv : tree_cls) {
-        const std::vector<TreeRegion> &regs = kv.second;
-        std::vector<int2> map;
-        for (int j = 0; j < (int)regs.size(); j++)
-            for (int l = 0; l < regs[j].nleaves; l++) map.push_back(make_int2(j, l));
-        const size_t ro = P.img.add(regs), mo = P.img.add(map);
-        const int64_t nb = (int64_t)map.size();
-        const int np = kv.first.first, wave_tree = kv.first.second;
-        const char *name = class_name(kTreeNames, np);
-        P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
-            Stage st(name, s);
-            HIPCHK(launch_tsqr_tree_batch(wave_tree, np, acc, m_f64, (const TreeRegion *)(t + ro),
-                                          (const int2 *)(t + mo), nb, s),
-                   "batched tsqr tree");
-            return FIGARO_OK;
-        });
-    }
 
-    // 5. roots: Cartesian two-sided instances batched by padded width, the rest per instance
-    std::map<int, std::vector<CartRoot>> root_cls;
-    for (size_t i = 0; i < count; i++) {
-        const Shape &sh = plan->shapes[i];
-        const Layout &L = plan->layouts[i];
-        void *lws = slice(i);
-        const int N = (int)sh.N();
-        double *Ri = R + plan->r_off[i];
-        if (cartesian_root(sh, L)) {
-            const Region &ra = L.regions[1], &rb = L.regions[2];
-            root_cls[L.np_root].push_back(CartRoot{at<double>(lws, ra.root), ra.np, ra.width, at<double>(lws, rb.root),
-                                                   rb.np, rb.width, groups_of(lws, L), at<double>(lws, L.headsA),
-                                                   at<double>(lws, L.headsB), L.refine ? at<double>(lws, L.rt) : Ri,
-                                                   L.refine ? N : (int64_t)N});
-        } else {
-            const figaro_instance *in = &plan->inst[i];
-            P.steps.push_back([in, sh, &L, Ri, N, lws](const unsigned char *, hipStream_t s) {
-                return run_root(&in->A, &in->B, sh, L, Ri, N, lws, s, false);
+    };
+    auto emit_roots = [&](const std::vector<size_t> &idx) {
+        // 5. roots: Cartesian two-sided instances batched by padded width, the rest per instance
+        std::map<int, std::vector<CartRoot>> root_cls;
+        for (size_t i : idx) {
+            const Shape &sh = plan->shapes[i];
+            const Layout &L = plan->layouts[i];
+            void *lws = slice(i);
+            const int N = (int)sh.N();
+            double *Ri = R + plan->r_off[i];
+            if (cartesian_root(sh, L)) {
+                const Region &ra = L.regions[1], &rb = L.regions[2];
+                root_cls[L.np_root].push_back(CartRoot{at<double>(lws, ra.root), ra.np, ra.width, at<double>(lws, rb.root),
+                                                       rb.np, rb.width, groups_of(lws, L), at<double>(lws, L.headsA),
+                                                       at<double>(lws, L.headsB), L.refine ? at<double>(lws, L.rt) : Ri,
+                                                       L.refine ? N : (int64_t)N});
+            } else {
+                const figaro_instance *in = &plan->inst[i];
+                P.steps.push_back([in, sh, &L, Ri, N, lws](const unsigned char *, hipStream_t s) {
+                    return run_root(&in->A, &in->B, sh, L, Ri, N, lws, s, false);
+                });
+            }
+        }
+        for (auto &kv : root_cls) {
+            const size_t off = P.img.add(kv.second);
+            const int n = (int)kv.second.size(), np = kv.first;
+            const char *name = class_name(kRootNames, np);
+            P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+                Stage st(name, s);
+                HIPCHK(launch_merge_cartesian_batch(np, (const CartRoot *)(t + off), n, s), "batched cartesian roots");
+                return FIGARO_OK;
             });
         }
+    };
+    auto emit_sigma = [&](const std::vector<size_t> &idx, bool fork_sigma) {
+        // 6. sigma: per width class, one bidiagonalisation workgroup per instance, then one
+        // multisection workgroup per singular value; the classes on the plan's side streams
+        // (forked from and joined back into the launch stream), widest first
+        struct SigmaClass {
+            int c, n, dqds;
+            size_t off;
+            const char *name;
+        };
+        std::vector<SigmaClass> scls;
+        for (int c = 128; c >= 8; c /= 2) {
+            std::vector<int64_t> tab;
+            for (size_t i : idx) {
+                if (sigma_width_class((int)plan->shapes[i].N()) != c) continue;
+                tab.push_back(plan->r_off[i]);
+                tab.push_back(plan->s_off[i]);
+                tab.push_back(plan->shapes[i].N());
+                tab.push_back(2 * plan->s_off[i] + 2 * (int64_t)i);
+            }
+            if (tab.empty()) continue;
+            scls.push_back(SigmaClass{c, (int)(tab.size() / 4), tune_get(TuneKey{TUNE_SIGMA, c, 1, 0}).kind == SIGMA_DQDS,
+                                      P.img.add(tab), class_name(kSigmaNames, c)});
+        }
+        if (!scls.empty()) {
+            double *msin = at<double>(ws, plan->msin_off);
+            P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
+                const bool ready = fork_sigma && plan->ev_fork && plan->side[figaro_plan::kSide - 1] &&
+                                   plan->ev_join[figaro_plan::kSide - 1];
+                const int nb = ready ? std::min<int>((int)scls.size(), figaro_plan::kSide) : 1;
+                if (nb > 1) HIPCHK(hipEventRecord(plan->ev_fork, s), "sigma fork");
+                for (int k = 0; k < (int)scls.size(); k++) {
+                    hipStream_t sk = nb > 1 ? plan->side[k % nb] : s;
+                    if (nb > 1 && k < nb) HIPCHK(hipStreamWaitEvent(sk, plan->ev_fork, 0), "sigma fork wait");
+                    const SigmaClass &e = scls[k];
+                    Stage st(e.name, sk);
+                    HIPCHK(launch_sigma_batch(e.c, R, sigma, (const int64_t *)(t + e.off), e.n, msin, sk, e.dqds),
+                           "batched sigma");
+                }
+                for (int k = 0; k < nb && nb > 1; k++) {
+                    HIPCHK(hipEventRecord(plan->ev_join[k], plan->side[k]), "sigma join");
+                    HIPCHK(hipStreamWaitEvent(s, plan->ev_join[k], 0), "sigma join wait");
+                }
+                return FIGARO_OK;
+            });
+        }
+    };
+    bool refine_any = false;
+    for (const Layout &L : plan->layouts) refine_any = refine_any || L.refine;
+    std::vector<size_t> all, wide, rest;
+    for (size_t i = 0; i < count; i++) {
+        all.push_back(i);
+        (sigma_width_class((int)plan->shapes[i].N()) == 128 ? wide : rest).push_back(i);
     }
-    for (auto &kv : root_cls) {
-        const size_t off = P.img.add(kv.second);
-        const int n = (int)kv.second.size(), np = kv.first;
-        const char *name = class_name(kRootNames, np);
-        P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
-            Stage st(name, s);
-            HIPCHK(launch_merge_cartesian_batch(np, (const CartRoot *)(t + off), n, s), "batched cartesian roots");
-            return FIGARO_OK;
-        });
-    }
+    if (!refine_any && fuse_trees && plan->chains && !wide.empty() && !rest.empty()) {
+        P.set_lane(1);
+        emit_trees(wide, "tsqr_narrow");
+        emit_roots(wide);
+        emit_sigma(wide, false);
+        P.set_lane(2);
+        emit_trees(rest, "tsqr_narrow_b");
+        emit_roots(rest);
+        emit_sigma(rest, false);
+        P.set_lane(0);
+    } else {
+        emit_trees(all, "tsqr_narrow");
+        emit_roots(all);
     // refinement sweep of every instance (refined forms): the Gram blocks of all instances
     // in one tile launch and one reduce launch per input type, then one workgroup per
     // instance for the N x N part
@@ -1427,58 +1511,47 @@ Program build_program(const figaro_plan *plan, void *ws, double *R, double *sigm
         });
     }
 
-    // 6. sigma: per width class, one bidiagonalisation workgroup per instance, then one
-    // multisection workgroup per singular value; the classes on the plan's side streams
-    // (forked from and joined back into the launch stream), widest first
-    struct SigmaClass {
-        int c, n, dqds;
-        size_t off;
-        const char *name;
-    };
-    std::vector<SigmaClass> scls;
-    for (int c = 128; c >= 8; c /= 2) {
-        std::vector<int64_t> tab;
-        for (size_t i = 0; i < count; i++) {
-            if (sigma_width_class((int)plan->shapes[i].N()) != c) continue;
-            tab.push_back(plan->r_off[i]);
-            tab.push_back(plan->s_off[i]);
-            tab.push_back(plan->shapes[i].N());
-            tab.push_back(2 * plan->s_off[i] + 2 * (int64_t)i);
-        }
-        if (tab.empty()) continue;
-        scls.push_back(SigmaClass{c, (int)(tab.size() / 4), tune_get(TuneKey{TUNE_SIGMA, c, 1, 0}).kind == SIGMA_DQDS,
-                                  P.img.add(tab), class_name(kSigmaNames, c)});
+        emit_sigma(all, true);
     }
-    if (!scls.empty()) {
-        double *msin = at<double>(ws, plan->msin_off);
-        P.steps.push_back([=](const unsigned char *t, hipStream_t s) {
-            const bool ready = plan->ev_fork && plan->side[figaro_plan::kSide - 1] && plan->ev_join[figaro_plan::kSide - 1];
-            const int nb = ready ? std::min<int>((int)scls.size(), figaro_plan::kSide) : 1;
-            if (nb > 1) HIPCHK(hipEventRecord(plan->ev_fork, s), "sigma fork");
-            for (int k = 0; k < (int)scls.size(); k++) {
-                hipStream_t sk = nb > 1 ? plan->side[k % nb] : s;
-                if (nb > 1 && k < nb) HIPCHK(hipStreamWaitEvent(sk, plan->ev_fork, 0), "sigma fork wait");
-                const SigmaClass &e = scls[k];
-                Stage st(e.name, sk);
-                HIPCHK(launch_sigma_batch(e.c, R, sigma, (const int64_t *)(t + e.off), e.n, msin, sk, e.dqds),
-                       "batched sigma");
-            }
-            for (int k = 0; k < nb && nb > 1; k++) {
-                HIPCHK(hipEventRecord(plan->ev_join[k], plan->side[k]), "sigma join");
-                HIPCHK(hipStreamWaitEvent(s, plan->ev_join[k], 0), "sigma join wait");
-            }
-            return FIGARO_OK;
-        });
-    }
+    P.set_lane(0);
     return P;
 }
 
+// The steps in order; a run of side-lane steps is forked from the launch stream (every
+// side stream waits on it) and joined back before the next launch-stream step or the end.
+// Without the plan's side streams every step runs on the launch stream.
 int run_program(const Program &P, const unsigned char *tables, hipStream_t s)
 {
-    for (const Step &st : P.steps) {
-        int rc = st(tables, s);
+    const figaro_plan *pl = P.plan;
+    const bool side_ok = pl && pl->ev_fork && pl->side[figaro_plan::kSide - 1] && pl->ev_join[figaro_plan::kSide - 1];
+    bool forked = false;
+    auto join = [&]() -> int {
+        for (int k = 0; k < figaro_plan::kSide; k++) {
+            HIPCHK(hipEventRecord(pl->ev_join[k], pl->side[k]), "join record");
+            HIPCHK(hipStreamWaitEvent(s, pl->ev_join[k], 0), "join wait");
+        }
+        forked = false;
+        return FIGARO_OK;
+    };
+    for (size_t i = 0; i < P.steps.size(); i++) {
+        const int lane = i < P.lanes.size() ? P.lanes[i] : 0;
+        hipStream_t st = s;
+        if (lane > 0 && side_ok) {
+            if (!forked) {
+                HIPCHK(hipEventRecord(pl->ev_fork, s), "fork record");
+                for (int k = 0; k < figaro_plan::kSide; k++)
+                    HIPCHK(hipStreamWaitEvent(pl->side[k], pl->ev_fork, 0), "fork wait");
+                forked = true;
+            }
+            st = pl->side[(lane - 1) % figaro_plan::kSide];
+        } else if (forked) {
+            int rc = join();
+            if (rc) return rc;
+        }
+        int rc = P.steps[i](tables, st);
         if (rc) return rc;
     }
+    if (forked) return join();
     return FIGARO_OK;
 }
 
@@ -1684,8 +1757,11 @@ void plan_drop_execs(figaro_plan *plan)
     plan->execs.clear();
 }
 
+// New layouts from the tuning table.  The cached launch tables and graphs were built for
+// the old ones (tree sizes, leaf counts), so they go too.
 void plan_relayout(figaro_plan *plan)
 {
+    plan_drop_execs(plan);
     for (size_t i = 0; i < plan->inst.size(); i++) plan->layouts[i] = make_layout(plan->shapes[i], true);
 }
 
@@ -1717,7 +1793,10 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         if (!e) e = run_program(prog, ex->tables, s);  // warm-up
         double t = 0.0;
         if (!e) e = take_stage_ms([](const char *) { return false; }, &t);
-        for (int i = 0; i < kTuneReps && !e; i++) e = run_program(prog, ex->tables, s);
+        for (int i = 0; i < kTuneReps && !e; i++) {
+            Stage wall("plan_wall", s);  // the whole program, side streams joined
+            e = run_program(prog, ex->tables, s);
+        }
         *ms = 0.0;
         if (!e) e = take_stage_ms([stage](const char *n) { return std::strcmp(n, stage) == 0; }, ms);
         plan_drop_execs(plan);
@@ -1744,31 +1823,74 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         }
         for (int l : kv.second) tune_set(TuneKey{acc, np, 1, l}, best, best_ms / kTuneReps);
     }
-    // then the classes together: a plan runs every narrow width in one launch, where the
-    // balance of the leaves over the compute units sets the time -- one pass of coordinate
-    // descent over the classes, widest first, on the fused launch
-    if (std::count_if(cls.begin(), cls.end(), [](const auto &kv) { return kv.first <= 64; }) > 1) {
-        for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
+    // then the classes together, once with the two chains side by side and once one after
+    // the other: a plan runs the narrow widths of its instances in shared launches, where
+    // the balance of the leaves over the compute units sets the time.  For each mode, one
+    // pass of coordinate descent over the classes (widest first) on the whole program's
+    // time, then the replay time of the captured graph (as the plan runs it); the faster
+    // mode and its choices are kept.
+    std::map<int, TreeTune> alone;  // each class's choice when timed alone
+    for (auto &kv : cls) alone[kv.first] = tune_get(TuneKey{acc, kv.first, 1, kv.second.front()});
+    auto set_class = [&](int np, const TreeTune &t) {
+        for (int l : cls[np]) tune_set(TuneKey{acc, np, 1, l}, t, 0.0);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0), "tuning event");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "tuning event");
+    }
+    double mode_ms[2] = {1e300, 1e300};
+    std::map<int, TreeTune> mode_pick[2];
+    const bool several = std::count_if(cls.begin(), cls.end(), [](const auto &kv) { return kv.first <= 64; }) > 1;
+    for (int ch : {1, 0}) {
+        plan->chains = ch;
+        for (auto &kv : alone) set_class(kv.first, kv.second);
+        for (auto it = cls.rbegin(); several && it != cls.rend() && !rc; ++it) {
             const int np = it->first;
-            if (np > 64) continue;  // not in the fused launch
+            if (np > 64) continue;  // not in the shared launches
             const TuneKey key{acc, np, 1, 0};
             double best_ms = 1e300;
-            TreeTune best = tune_get(TuneKey{acc, np, 1, it->second.front()});
+            TreeTune best = alone[np];
             for (const TreeTune &cand : tune_candidates(key)) {
                 double ms = 0.0;
-                rc = time_cand(key, cand, true, "tsqr_narrow", &ms);
-                if (rc) {
-                    plan_relayout(plan);
-                    return rc;
-                }
+                rc = time_cand(key, cand, true, "plan_wall", &ms);
+                if (rc) break;
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = cand;
                 }
             }
-            for (int l : it->second) tune_set(TuneKey{acc, np, 1, l}, best, best_ms / kTuneReps);
+            set_class(np, best);
         }
+        if (rc) break;
+        for (auto &kv : cls) mode_pick[ch][kv.first] = tune_get(TuneKey{acc, kv.first, 1, kv.second.front()});
+        plan_relayout(plan);
+        plan_drop_execs(plan);
+        rc = figaro_plan_execute(plan, ws, ws_bytes, R, sigma, s);  // capture and warm-up
+        if (!rc) he = hipEventRecord(e0, s);
+        for (int i = 0; i < kTuneReps && !rc && he == hipSuccess; i++)
+            rc = figaro_plan_execute(plan, ws, ws_bytes, R, sigma, s);
+        if (!rc && he == hipSuccess) he = hipEventRecord(e1, s);
+        if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (!rc && he != hipSuccess) rc = hip_fail(he, "tuning replay");
+        if (!rc) mode_ms[ch] = ms / kTuneReps;
+        plan_drop_execs(plan);  // the next mode's layouts differ: no stale tables or graph
     }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan_drop_execs(plan);
+    if (rc) {
+        plan->chains = 1;
+        plan_relayout(plan);
+        return rc;
+    }
+    plan->chains = mode_ms[1] <= mode_ms[0] ? 1 : 0;
+    for (auto &kv : mode_pick[plan->chains])
+        for (int l : cls[kv.first]) tune_set(TuneKey{acc, kv.first, 1, l}, kv.second, mode_ms[plan->chains]);
     plan_relayout(plan);
     // sigma route per width class (multisection or dqds after the bidiagonalisation)
     std::vector<int> scls;
