@@ -1138,7 +1138,7 @@ struct figaro_plan {
     // Side streams (default priority) and events of the sigma stage, whose width classes
     // run side by side: each class fills only part of the GPU (a workgroup per instance).
     static constexpr int kSide = 4;
-    int chains = 1;  // run the two chains side by side (set by the autotuner)
+    int chains = 1;  // run the two chains side by side (from the tuning table; set by the autotuner)
     hipStream_t side[kSide] = {};
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join[kSide] = {};
@@ -1588,6 +1588,7 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
         p->s_total += sh.N();
     }
     p->msin_off = off;
+    p->chains = tune_get(TuneKey{TUNE_PLAN, 0, 1, 0}).kind != 0;
     // multisection inputs: 2 N + 2 doubles per instance
     p->ws_bytes = p->msin_off + align_up(sizeof(double) * (size_t)(2 * p->s_total + 2 * (int64_t)count));
     *out = p;
@@ -1889,6 +1890,7 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         return rc;
     }
     plan->chains = mode_ms[1] <= mode_ms[0] ? 1 : 0;
+    tune_set(TuneKey{TUNE_PLAN, 0, 1, 0}, TreeTune{plan->chains, 0, 2}, mode_ms[plan->chains]);
     for (auto &kv : mode_pick[plan->chains])
         for (int l : cls[kv.first]) tune_set(TuneKey{acc, kv.first, 1, l}, kv.second, mode_ms[plan->chains]);
     plan_relayout(plan);

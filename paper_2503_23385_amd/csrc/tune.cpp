@@ -68,7 +68,7 @@ int load_locked(const std::string &path)
             continue;
         parse_double(line, "ms", &ms);
         if ((t.kind != TREE_WG && t.kind != TREE_WAVE) || t.leaf_blocks < 0 || t.leaf_blocks > 1024 || t.arity < 2 ||
-            t.arity > 32 || k.acc_f64 < 0 || k.acc_f64 > TUNE_SIGMA)
+            t.arity > 32 || k.acc_f64 < 0 || k.acc_f64 > TUNE_PLAN)
             continue;
         g_table[key4(k)] = Entry{t, ms};
         n++;
@@ -97,6 +97,7 @@ int rows_log2(int64_t rows)
 TreeTune tune_default(const TuneKey &k)
 {
     if (k.acc_f64 == TUNE_SIGMA) return TreeTune{SIGMA_MSECT, 0, 2};
+    if (k.acc_f64 == TUNE_PLAN) return TreeTune{1, 0, 2};  // chains side by side
     if (k.np > 64) return TreeTune{TREE_WG, 0, 2};  // width 128: the panel tree
     if (k.batched) {
         // measured on the 256-instance batch (all widths in one launch): 16 blocks per leaf

@@ -15,6 +15,9 @@ enum : int { TREE_WG = 0, TREE_WAVE = 1 };
 // Entries with acc_f64 == TUNE_SIGMA hold the route of a plan's sigma width class np
 // (kind SIGMA_MSECT or SIGMA_DQDS after the bidiagonalisation).
 enum : int { TUNE_SIGMA = 2, SIGMA_MSECT = 0, SIGMA_DQDS = 1 };
+// The entry with acc_f64 == TUNE_PLAN (np 0, batched 1, rows_log2 0) holds how plans
+// schedule their chains: kind 1 side by side on side streams, 0 one after the other.
+enum : int { TUNE_PLAN = 3 };
 
 struct TreeTune {
     int kind;         // TREE_WG: one workgroup per leaf; TREE_WAVE: one wave per leaf
@@ -24,7 +27,7 @@ struct TreeTune {
 
 struct TuneKey {
     int acc_f64;    // FP64 accumulation (plain form) or FP32 (mixed forms)
-    int np;         // padded width (4 .. 64)
+    int np;         // padded width (4 .. 128; the class width for sigma entries)
     int batched;    // regions of a plan (1) or of a single call (0)
     int rows_log2;  // ceil(log2) of the rows the launch reduces
 };
