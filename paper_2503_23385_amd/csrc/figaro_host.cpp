@@ -1889,7 +1889,9 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         plan_relayout(plan);
         return rc;
     }
-    plan->chains = mode_ms[1] <= mode_ms[0] ? 1 : 0;
+    // side by side only when clearly faster (the concurrent launches share the compute
+    // units; within a few percent the simpler order wins)
+    plan->chains = mode_ms[1] < 0.97 * mode_ms[0] ? 1 : 0;
     tune_set(TuneKey{TUNE_PLAN, 0, 1, 0}, TreeTune{plan->chains, 0, 2}, mode_ms[plan->chains]);
     for (auto &kv : mode_pick[plan->chains])
         for (int l : cls[kv.first]) tune_set(TuneKey{acc, kv.first, 1, l}, kv.second, mode_ms[plan->chains]);
