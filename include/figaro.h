@@ -349,11 +349,19 @@ int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
  *   the roots (one launch per padded width for the Cartesian instances of the
  *   two-sided form; the others, and the refinement sweep, per instance), and
  *   sigma by the bidiagonal route of figaro_sigma_bidiag (two launches per width
- *   class over all instances; the multisection there locates each value with
- *   16 lanes and 16 points per round, 14 rounds).  Each instance owns one slice of `ws`; the
- *   multisection inputs sit after the slices.  Instances need n1 + n2 <= 128.
- * The first call with a given (ws, R, sigma) allocates and uploads that
- * triple's launch tables (synchronous; freed by figaro_plan_destroy) and
+ *   class over all instances, the classes side by side on the plan's side
+ *   streams; the multisection there locates each value with 16 lanes and 16
+ *   points per round, 14 rounds).  Without refinement, where the tuning table
+ *   says so, the instances with n1 + n2 > 64 and the others run their trees,
+ *   roots and sigma as two chains side by side instead (after the assembly).
+ *   The side streams (four, default priority) are forked from `stream` by an
+ *   event and joined back before the call's last launch.  Each instance owns one
+ *   slice of `ws`; the multisection inputs sit after the slices.  Instances need
+ *   n1 + n2 <= 128.
+ * The first call on a plan creates its side streams and events (destroyed by
+ * figaro_plan_destroy).  The first call with a given (ws, R, sigma) allocates
+ * and uploads that triple's launch tables (synchronous; freed by
+ * figaro_plan_destroy) and
  * captures the launch sequence into a HIP graph on a private stream; every call
  * (the first included) launches that graph on `stream`.  Later calls with the
  * same triple allocate nothing.  Calls that share `ws` must not overlap.
@@ -372,17 +380,22 @@ void figaro_plan_destroy(figaro_plan *plan);
 /* ------------------------------------------------------------ autotuning */
 
 /*
- * The TSQR reduction of each narrow region (padded width <= 64) runs one of two
- * tree kernels (one workgroup per leaf, or one wave per leaf) with leaves of a
- * chosen number of row blocks.  A process-wide tuning table, keyed by
+ * The TSQR reduction of each region of padded width <= 128 runs one of two
+ * tree kernels (one workgroup per leaf -- at width 128 the streaming panel
+ * tree -- or one wave per leaf) with leaves of a chosen number of row blocks
+ * and a chosen tree arity.  A process-wide tuning table, keyed by
  * (accumulation type, padded width, single call or plan, log2 of the rows),
- * holds the choice; its built-in defaults were measured on MI355X.
+ * holds the choice; its built-in defaults were measured on MI355X.  It also
+ * holds each plan sigma class's route and whether plans run their two chains
+ * side by side.
  *
  * figaro_plan_autotune / figaro_r_autotune time every candidate of the table
  * on the caller's own problem (the same buffers figaro_plan_execute / figaro_r
  * take: one warm-up and three timed runs per candidate, stage events on
  * `stream`), keep the fastest per class of regions, and set the table entries
- * of the row counts the problem holds.  Synchronous; they allocate launch
+ * of the row counts the problem holds.  A plan's classes are tuned alone, then
+ * together on the whole program's time (once per chaining mode); the mode
+ * whose captured graph replays faster is kept.  Synchronous; they allocate launch
  * tables, overwrite R / sigma / ws, drop the plan's captured graphs (the next
  * execution captures again), and record stage events into the timing of
  * figaro_timing_enable (consumed).  Workspace sizes do not depend on the
@@ -394,7 +407,8 @@ int figaro_r_autotune(const figaro_table *A, const figaro_table *B, int32_t prec
 /*
  * Tuning cache: JSON lines, one entry per line with the fields arch ("gfx950"),
  * acc_f64, np, batched, rows_log2, kind (0 workgroup tree, 1 wave tree),
- * leaf_blocks, arity, ms.  figaro_tune_load merges a file into the table (the
+ * leaf_blocks, arity, ms (acc_f64 2: a plan sigma class's route, kind 0
+ * multisection, 1 dqds; acc_f64 3: kind 1 plans run their chains side by side).  figaro_tune_load merges a file into the table (the
  * file named by the environment variable FIGARO_TUNE_CACHE is merged at first
  * use); figaro_tune_save writes the whole table; figaro_tune_dump copies it into
  * buf (NUL-terminated, at most cap bytes) and its full length into *len.
