@@ -408,7 +408,9 @@ int figaro_r_autotune(const figaro_table *A, const figaro_table *B, int32_t prec
  * Tuning cache: JSON lines, one entry per line with the fields arch ("gfx950"),
  * acc_f64, np, batched, rows_log2, kind (0 workgroup tree, 1 wave tree),
  * leaf_blocks, arity, ms (acc_f64 2: a plan sigma class's route, kind 0
- * multisection, 1 dqds; acc_f64 3: kind 1 plans run their chains side by side).  figaro_tune_load merges a file into the table (the
+ * multisection, 1 dqds; acc_f64 3, np 1 for FP64 accumulation else 0: kind 1
+ * plans run their chains side by side).  figaro_tune_load merges a file into
+ * the table (the
  * file named by the environment variable FIGARO_TUNE_CACHE is merged at first
  * use); figaro_tune_save writes the whole table; figaro_tune_dump copies it into
  * buf (NUL-terminated, at most cap bytes) and its full length into *len.

@@ -1588,7 +1588,7 @@ int figaro_plan_create(const figaro_instance *inst, int32_t count, int32_t preci
         p->s_total += sh.N();
     }
     p->msin_off = off;
-    p->chains = tune_get(TuneKey{TUNE_PLAN, 0, 1, 0}).kind != 0;
+    p->chains = tune_get(TuneKey{TUNE_PLAN, p->shapes[0].precision == FIGARO_PLAIN_FP64, 1, 0}).kind != 0;
     // multisection inputs: 2 N + 2 doubles per instance
     p->ws_bytes = p->msin_off + align_up(sizeof(double) * (size_t)(2 * p->s_total + 2 * (int64_t)count));
     *out = p;
@@ -1842,8 +1842,25 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         (void)hipEventDestroy(e0);
         return hip_fail(he, "tuning event");
     }
-    double mode_ms[2] = {1e300, 1e300};
-    std::map<int, TreeTune> mode_pick[2];
+    // modes: 0 and 1 the tuned choices with the chains one after the other / side by side,
+    // 2 the built-in defaults (as a plan made without tuning runs)
+    double mode_ms[3] = {1e300, 1e300, 1e300};
+    std::map<int, TreeTune> mode_pick[3];
+    int mode_chains[3] = {0, 1, tune_default(TuneKey{TUNE_PLAN, acc, 1, 0}).kind != 0};
+    auto replay = [&](double *out) -> int {  // ms per replay of the captured graph
+        plan_relayout(plan);
+        int e = figaro_plan_execute(plan, ws, ws_bytes, R, sigma, s);  // capture and warm-up
+        if (!e) he = hipEventRecord(e0, s);
+        for (int i = 0; i < kTuneReps && !e && he == hipSuccess; i++) e = figaro_plan_execute(plan, ws, ws_bytes, R, sigma, s);
+        if (!e && he == hipSuccess) he = hipEventRecord(e1, s);
+        if (!e && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (!e && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (!e && he != hipSuccess) e = hip_fail(he, "tuning replay");
+        if (!e) *out = ms / kTuneReps;
+        plan_drop_execs(plan);  // the next mode's layouts differ: no stale tables or graph
+        return e;
+    };
     const bool several = std::count_if(cls.begin(), cls.end(), [](const auto &kv) { return kv.first <= 64; }) > 1;
     for (int ch : {1, 0}) {
         plan->chains = ch;
@@ -1867,19 +1884,16 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         }
         if (rc) break;
         for (auto &kv : cls) mode_pick[ch][kv.first] = tune_get(TuneKey{acc, kv.first, 1, kv.second.front()});
-        plan_relayout(plan);
-        plan_drop_execs(plan);
-        rc = figaro_plan_execute(plan, ws, ws_bytes, R, sigma, s);  // capture and warm-up
-        if (!rc) he = hipEventRecord(e0, s);
-        for (int i = 0; i < kTuneReps && !rc && he == hipSuccess; i++)
-            rc = figaro_plan_execute(plan, ws, ws_bytes, R, sigma, s);
-        if (!rc && he == hipSuccess) he = hipEventRecord(e1, s);
-        if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (!rc && he != hipSuccess) rc = hip_fail(he, "tuning replay");
-        if (!rc) mode_ms[ch] = ms / kTuneReps;
-        plan_drop_execs(plan);  // the next mode's layouts differ: no stale tables or graph
+        rc = replay(&mode_ms[ch]);
+        if (rc) break;
+    }
+    if (!rc) {
+        for (auto &kv : cls) {
+            mode_pick[2][kv.first] = tune_default(TuneKey{acc, kv.first, 1, kv.second.front()});
+            set_class(kv.first, mode_pick[2][kv.first]);
+        }
+        plan->chains = mode_chains[2];
+        rc = replay(&mode_ms[2]);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1890,11 +1904,14 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         return rc;
     }
     // side by side only when clearly faster (the concurrent launches share the compute
-    // units; within a few percent the simpler order wins)
-    plan->chains = mode_ms[1] < 0.97 * mode_ms[0] ? 1 : 0;
-    tune_set(TuneKey{TUNE_PLAN, 0, 1, 0}, TreeTune{plan->chains, 0, 2}, mode_ms[plan->chains]);
-    for (auto &kv : mode_pick[plan->chains])
-        for (int l : cls[kv.first]) tune_set(TuneKey{acc, kv.first, 1, l}, kv.second, mode_ms[plan->chains]);
+    // units; within a few percent the simpler order wins), and the tuned choices only when
+    // they beat the defaults by more than the replays' noise
+    int mode = mode_ms[1] < 0.97 * mode_ms[0] ? 1 : 0;
+    if (mode_ms[mode] > 0.98 * mode_ms[2]) mode = 2;
+    plan->chains = mode_chains[mode];
+    tune_set(TuneKey{TUNE_PLAN, acc, 1, 0}, TreeTune{plan->chains, 0, 2}, mode_ms[mode]);
+    for (auto &kv : mode_pick[mode])
+        for (int l : cls[kv.first]) tune_set(TuneKey{acc, kv.first, 1, l}, kv.second, mode_ms[mode]);
     plan_relayout(plan);
     // sigma route per width class (multisection or dqds after the bidiagonalisation)
     std::vector<int> scls;

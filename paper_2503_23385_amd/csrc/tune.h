@@ -15,8 +15,9 @@ enum : int { TREE_WG = 0, TREE_WAVE = 1 };
 // Entries with acc_f64 == TUNE_SIGMA hold the route of a plan's sigma width class np
 // (kind SIGMA_MSECT or SIGMA_DQDS after the bidiagonalisation).
 enum : int { TUNE_SIGMA = 2, SIGMA_MSECT = 0, SIGMA_DQDS = 1 };
-// The entry with acc_f64 == TUNE_PLAN (np 0, batched 1, rows_log2 0) holds how plans
-// schedule their chains: kind 1 side by side on side streams, 0 one after the other.
+// Entries with acc_f64 == TUNE_PLAN (np: 1 for plans accumulating in FP64, else 0;
+// batched 1, rows_log2 0) hold how plans schedule their chains: kind 1 side by side on
+// side streams, 0 one after the other.
 enum : int { TUNE_PLAN = 3 };
 
 struct TreeTune {
