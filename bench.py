@@ -183,9 +183,10 @@ STAGE_KERNELS["tsqr_narrow"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k
 STAGE_KERNELS["tsqr_narrow_b"] = ("paper_2503_23385_amd/csrc/kernels_tsqr.hip", "k_tsqr_wtree_multi")
 
 
-def measured_traffic(workload, stage, form=None):
+def measured_traffic(workload, stage, form=None, chains=False):
     """HBM bytes per launch of the stage's kernel for this form from the committed counter
-    summary, if the kernel source is unchanged since the counters were taken (else None)."""
+    summary, if the kernel source is unchanged since the counters were taken and the plan
+    ran its chains the same way (a chain's launch covers only its instances; else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.md")
     if stage not in STAGE_KERNELS or not os.path.exists(path):
@@ -198,7 +199,7 @@ def measured_traffic(workload, stage, form=None):
             if line.startswith("TRAFFIC "):
                 rec = json.loads(line[len("TRAFFIC "):])
                 if (rec.get("stage") == stage and rec.get("source_sha1") == sha
-                        and rec.get("form") in (None, form)):
+                        and rec.get("form") in (None, form) and bool(rec.get("chains", False)) == chains):
                     return rec["bytes_per_launch"]
     return None
 
@@ -534,7 +535,9 @@ def main():
 
     for key in ("roofline", "roofline_hbm"):
         if out.get(key) is not None:
-            out[key]["traffic"] = measured_traffic(wl, out[key]["kernel"], out["config"].get("form"))
+            chosen = out.get("forms", {}).get(out["config"].get("form"), {})
+            chains = "tsqr_narrow_b" in chosen.get("stage_ms", {})
+            out[key]["traffic"] = measured_traffic(wl, out[key]["kernel"], out["config"].get("form"), chains)
 
     line = {
         "metric": METRIC,

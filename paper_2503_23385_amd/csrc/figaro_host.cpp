@@ -1138,7 +1138,7 @@ struct figaro_plan {
     // Side streams (default priority) and events of the sigma stage, whose width classes
     // run side by side: each class fills only part of the GPU (a workgroup per instance).
     static constexpr int kSide = 4;
-    int chains = 1;  // run the two chains side by side (from the tuning table; set by the autotuner)
+    int chains = 0;  // run the two chains side by side (from the tuning table; set by the autotuner)
     hipStream_t side[kSide] = {};
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join[kSide] = {};
@@ -1899,7 +1899,7 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
     (void)hipEventDestroy(e1);
     plan_drop_execs(plan);
     if (rc) {
-        plan->chains = 1;
+        plan->chains = mode_chains[2];
         plan_relayout(plan);
         return rc;
     }

@@ -97,7 +97,7 @@ int rows_log2(int64_t rows)
 TreeTune tune_default(const TuneKey &k)
 {
     if (k.acc_f64 == TUNE_SIGMA) return TreeTune{SIGMA_MSECT, 0, 2};
-    if (k.acc_f64 == TUNE_PLAN) return TreeTune{1, 0, 2};  // chains side by side
+    if (k.acc_f64 == TUNE_PLAN) return TreeTune{0, 0, 2};  // chains one after the other
     if (k.np > 64) return TreeTune{TREE_WG, 0, 2};  // width 128: the panel tree
     if (k.batched) {
         // measured on the 256-instance batch (all widths in one launch): 16 blocks per leaf
