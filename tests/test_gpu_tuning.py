@@ -110,6 +110,48 @@ def test_plan_wave_trees_all_widths(tmp_path, arity, prec, two_sided):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plan_chains_side_by_side(tmp_path, prec):
+    """A plan whose two chains (the instances with n1 + n2 > 64, the rest) run side by side
+    on its side streams (forced through the tuning table), against the oracle on two graph
+    replays and on an eager run."""
+    acc = 1 if prec == "fp64" else 0
+    path = tmp_path / "chains.jsonl"
+    path.write_text(f'{{"arch":"gfx950","acc_f64":3,"np":{acc},"batched":1,"rows_log2":0,"kind":1,'
+                    f'"leaf_blocks":0,"arity":2,"ms":0}}\n')
+    fg().tune_load(str(path))
+    try:
+        insts = mixed_plan_instances()
+        say(f"[plan chains] {prec}")
+        tens = [to_dev(i) for i in insts]
+        plan = fg().Plan(tens, prec, two_sided=True)
+        d = dev()
+        ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=d)
+        R = torch.zeros(plan.r_total, dtype=torch.float64, device=d)
+        S = torch.zeros(plan.s_total, dtype=torch.float64, device=d)
+        for run in ("graph", "graph", "eager"):
+            R.fill_(3.0)
+            S.fill_(3.0)
+            (plan.execute if run == "graph" else plan.execute_eager)(ws, R, S)
+            torch.cuda.synchronize()
+            Rh, Sh = R.cpu().numpy(), S.cpu().numpy()
+            for i, inst in enumerate(insts):
+                N = inst.A.shape[1] + inst.B.shape[1]
+                Rg = Rh[plan.r_off[i]:plan.r_off[i] + N * N].reshape(N, N)
+                Ro = oracle.r(inst)
+                if not np.any(Ro):
+                    assert not np.any(Rg)
+                    continue
+                assert relF(Rg, Ro) <= TOL[prec], (run, i)
+                So = oracle.sigma(Ro)
+                Sg = Sh[plan.s_off[i]:plan.s_off[i] + N]
+                assert np.linalg.norm(Sg - So) / np.linalg.norm(So) <= TOL[prec], (run, i)
+    finally:
+        path.write_text(f'{{"arch":"gfx950","acc_f64":3,"np":{acc},"batched":1,"rows_log2":0,"kind":0,'
+                        f'"leaf_blocks":0,"arity":2,"ms":0}}\n')
+        fg().tune_load(str(path))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_plan_autotune_then_parity(prec):
     insts = mixed_plan_instances()
     tens = [to_dev(i) for i in insts]
