@@ -159,6 +159,42 @@ def test_plan_host_checks():
     assert L.figaro_plan_create(bad, 1, 0, ctypes.byref(h)) == fg.FIGARO_EINVAL
 
 
+def test_tuning_cache_plan_entries(tmp_path):
+    """Plan-level tuning entries (host only): the chaining mode per accumulation type
+    (acc_f64 3) and the width-128 tree choice load and save; out-of-range kinds are
+    skipped; plan workspace sizes do not depend on them."""
+    arr = (fg.Instance * 2)()
+    arr[0].A, arr[0].B = table(3000, 64), table(2000, 64)
+    arr[1].A, arr[1].B = table(500, 8), table(700, 8)
+    h = ctypes.c_void_p()
+    n0 = ctypes.c_size_t(0)
+    assert fg.lib().figaro_plan_create(arr, 2, 0, ctypes.byref(h)) == 0
+    assert fg.lib().figaro_plan_workspace_size(h, ctypes.byref(n0)) == 0
+    fg.lib().figaro_plan_destroy(h)
+    path = tmp_path / "plan.jsonl"
+    lines = ['{"arch":"gfx950","acc_f64":3,"np":0,"batched":1,"rows_log2":0,"kind":1,"leaf_blocks":0,"arity":2,"ms":1}',
+             '{"arch":"gfx950","acc_f64":0,"np":128,"batched":0,"rows_log2":20,"kind":1,"leaf_blocks":4,'
+             '"arity":2,"ms":1}',
+             '{"arch":"gfx950","acc_f64":4,"np":0,"batched":1,"rows_log2":0,"kind":1,"leaf_blocks":0,"arity":2}']
+    path.write_text("\n".join(lines) + "\n")
+    assert fg.lib().figaro_tune_load(os.fsencode(str(path))) == 0
+    tab = fg.tune_table()
+    assert any(e["acc_f64"] == 3 and e["np"] == 0 and e["kind"] == 1 for e in tab)
+    assert any(e["acc_f64"] == 0 and e["np"] == 128 and e["kind"] == 1 and e["leaf_blocks"] == 4 for e in tab)
+    assert not any(e["acc_f64"] == 4 for e in tab)
+    n1 = ctypes.c_size_t(0)
+    assert fg.lib().figaro_plan_create(arr, 2, 0, ctypes.byref(h)) == 0
+    assert fg.lib().figaro_plan_workspace_size(h, ctypes.byref(n1)) == 0
+    fg.lib().figaro_plan_destroy(h)
+    assert n0.value == n1.value
+    # back to the defaults: chains one after the other, the panel tree at width 128
+    path.write_text('{"arch":"gfx950","acc_f64":3,"np":0,"batched":1,"rows_log2":0,"kind":0,"leaf_blocks":0,'
+                    '"arity":2,"ms":0}\n'
+                    '{"arch":"gfx950","acc_f64":0,"np":128,"batched":0,"rows_log2":20,"kind":0,"leaf_blocks":0,'
+                    '"arity":2,"ms":0}\n')
+    assert fg.lib().figaro_tune_load(os.fsencode(str(path))) == 0
+
+
 def test_tuning_cache_round_trip(tmp_path):
     """The tuning cache (host only): entries load, malformed or foreign lines are skipped,
     the table saves and reloads, and workspace sizes do not depend on the table."""
