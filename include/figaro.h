@@ -387,15 +387,15 @@ void figaro_plan_destroy(figaro_plan *plan);
  * (accumulation type, padded width, single call or plan, log2 of the rows),
  * holds the choice; its built-in defaults were measured on MI355X.  It also
  * holds each plan sigma class's route and whether plans run their two chains
- * side by side.
+ * side by side (set by hand or a cache file; the autotuner leaves it).
  *
  * figaro_plan_autotune / figaro_r_autotune time every candidate of the table
  * on the caller's own problem (the same buffers figaro_plan_execute / figaro_r
  * take: one warm-up and three timed runs per candidate, stage events on
  * `stream`), keep the fastest per class of regions, and set the table entries
  * of the row counts the problem holds.  A plan's classes are tuned alone, then
- * together on the whole program's time (once per chaining mode); the mode
- * whose captured graph replays faster is kept.  Synchronous; they allocate launch
+ * together on their shared launch.  The chaining mode is not tuned (the table
+ * entry, default one chain after the other).  Synchronous; they allocate launch
  * tables, overwrite R / sigma / ws, drop the plan's captured graphs (the next
  * execution captures again), and record stage events into the timing of
  * figaro_timing_enable (consumed).  Workspace sizes do not depend on the

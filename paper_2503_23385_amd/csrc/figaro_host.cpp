@@ -1794,10 +1794,7 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         if (!e) e = run_program(prog, ex->tables, s);  // warm-up
         double t = 0.0;
         if (!e) e = take_stage_ms([](const char *) { return false; }, &t);
-        for (int i = 0; i < kTuneReps && !e; i++) {
-            Stage wall("plan_wall", s);  // the whole program, side streams joined
-            e = run_program(prog, ex->tables, s);
-        }
+        for (int i = 0; i < kTuneReps && !e; i++) e = run_program(prog, ex->tables, s);
         *ms = 0.0;
         if (!e) e = take_stage_ms([stage](const char *n) { return std::strcmp(n, stage) == 0; }, ms);
         plan_drop_execs(plan);
@@ -1824,94 +1821,32 @@ int figaro_plan_autotune(figaro_plan *plan, void *ws, size_t ws_bytes, double *R
         }
         for (int l : kv.second) tune_set(TuneKey{acc, np, 1, l}, best, best_ms / kTuneReps);
     }
-    // then the classes together, once with the two chains side by side and once one after
-    // the other: a plan runs the narrow widths of its instances in shared launches, where
-    // the balance of the leaves over the compute units sets the time.  For each mode, one
-    // pass of coordinate descent over the classes (widest first) on the whole program's
-    // time, then the replay time of the captured graph (as the plan runs it); the faster
-    // mode and its choices are kept.
-    std::map<int, TreeTune> alone;  // each class's choice when timed alone
-    for (auto &kv : cls) alone[kv.first] = tune_get(TuneKey{acc, kv.first, 1, kv.second.front()});
-    auto set_class = [&](int np, const TreeTune &t) {
-        for (int l : cls[np]) tune_set(TuneKey{acc, np, 1, l}, t, 0.0);
-    };
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(hipEventCreate(&e0), "tuning event");
-    hipError_t he = hipEventCreate(&e1);
-    if (he != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return hip_fail(he, "tuning event");
-    }
-    // modes: 0 and 1 the tuned choices with the chains one after the other / side by side,
-    // 2 the built-in defaults (as a plan made without tuning runs)
-    double mode_ms[3] = {1e300, 1e300, 1e300};
-    std::map<int, TreeTune> mode_pick[3];
-    int mode_chains[3] = {0, 1, tune_default(TuneKey{TUNE_PLAN, acc, 1, 0}).kind != 0};
-    auto replay = [&](double *out) -> int {  // ms per replay of the captured graph
-        plan_relayout(plan);
-        int e = figaro_plan_execute(plan, ws, ws_bytes, R, sigma, s);  // capture and warm-up
-        if (!e) he = hipEventRecord(e0, s);
-        for (int i = 0; i < kTuneReps && !e && he == hipSuccess; i++) e = figaro_plan_execute(plan, ws, ws_bytes, R, sigma, s);
-        if (!e && he == hipSuccess) he = hipEventRecord(e1, s);
-        if (!e && he == hipSuccess) he = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (!e && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (!e && he != hipSuccess) e = hip_fail(he, "tuning replay");
-        if (!e) *out = ms / kTuneReps;
-        plan_drop_execs(plan);  // the next mode's layouts differ: no stale tables or graph
-        return e;
-    };
-    const bool several = std::count_if(cls.begin(), cls.end(), [](const auto &kv) { return kv.first <= 64; }) > 1;
-    for (int ch : {1, 0}) {
-        plan->chains = ch;
-        for (auto &kv : alone) set_class(kv.first, kv.second);
-        for (auto it = cls.rbegin(); several && it != cls.rend() && !rc; ++it) {
+    // then the classes together: a plan runs every narrow width in one launch, where the
+    // balance of the leaves over the compute units sets the time -- one pass of coordinate
+    // descent over the classes, widest first, on the shared launch (chains are not tuned:
+    // a plan runs them as the tuning table says, one after the other by default)
+    if (std::count_if(cls.begin(), cls.end(), [](const auto &kv) { return kv.first <= 64; }) > 1) {
+        for (auto it = cls.rbegin(); it != cls.rend(); ++it) {
             const int np = it->first;
-            if (np > 64) continue;  // not in the shared launches
+            if (np > 64) continue;  // not in the shared launch
             const TuneKey key{acc, np, 1, 0};
             double best_ms = 1e300;
-            TreeTune best = alone[np];
+            TreeTune best = tune_get(TuneKey{acc, np, 1, it->second.front()});
             for (const TreeTune &cand : tune_candidates(key)) {
                 double ms = 0.0;
-                rc = time_cand(key, cand, true, "plan_wall", &ms);
-                if (rc) break;
+                rc = time_cand(key, cand, true, "tsqr_narrow", &ms);
+                if (rc) {
+                    plan_relayout(plan);
+                    return rc;
+                }
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = cand;
                 }
             }
-            set_class(np, best);
+            for (int l : it->second) tune_set(TuneKey{acc, np, 1, l}, best, best_ms / kTuneReps);
         }
-        if (rc) break;
-        for (auto &kv : cls) mode_pick[ch][kv.first] = tune_get(TuneKey{acc, kv.first, 1, kv.second.front()});
-        rc = replay(&mode_ms[ch]);
-        if (rc) break;
     }
-    if (!rc) {
-        for (auto &kv : cls) {
-            mode_pick[2][kv.first] = tune_default(TuneKey{acc, kv.first, 1, kv.second.front()});
-            set_class(kv.first, mode_pick[2][kv.first]);
-        }
-        plan->chains = mode_chains[2];
-        rc = replay(&mode_ms[2]);
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    plan_drop_execs(plan);
-    if (rc) {
-        plan->chains = mode_chains[2];
-        plan_relayout(plan);
-        return rc;
-    }
-    // side by side only when clearly faster (the concurrent launches share the compute
-    // units; within a few percent the simpler order wins), and the tuned choices only when
-    // they beat the defaults by more than the replays' noise
-    int mode = mode_ms[1] < 0.97 * mode_ms[0] ? 1 : 0;
-    if (mode_ms[mode] > 0.98 * mode_ms[2]) mode = 2;
-    plan->chains = mode_chains[mode];
-    tune_set(TuneKey{TUNE_PLAN, acc, 1, 0}, TreeTune{plan->chains, 0, 2}, mode_ms[mode]);
-    for (auto &kv : mode_pick[mode])
-        for (int l : cls[kv.first]) tune_set(TuneKey{acc, kv.first, 1, l}, kv.second, mode_ms[mode]);
     plan_relayout(plan);
     // sigma route per width class (multisection or dqds after the bidiagonalisation)
     std::vector<int> scls;
