@@ -1524,9 +1524,12 @@ int run_program(const Program &P, const unsigned char *tables, hipStream_t s)
 {
     const figaro_plan *pl = P.plan;
     const bool side_ok = pl && pl->ev_fork && pl->side[figaro_plan::kSide - 1] && pl->ev_join[figaro_plan::kSide - 1];
+    // only the side streams the program uses are forked and joined (no empty branches)
+    int nside = 0;
+    for (int l : P.lanes) nside = std::max(nside, std::min(l, (int)figaro_plan::kSide));
     bool forked = false;
     auto join = [&]() -> int {
-        for (int k = 0; k < figaro_plan::kSide; k++) {
+        for (int k = 0; k < nside; k++) {
             HIPCHK(hipEventRecord(pl->ev_join[k], pl->side[k]), "join record");
             HIPCHK(hipStreamWaitEvent(s, pl->ev_join[k], 0), "join wait");
         }
@@ -1539,7 +1542,7 @@ int run_program(const Program &P, const unsigned char *tables, hipStream_t s)
         if (lane > 0 && side_ok) {
             if (!forked) {
                 HIPCHK(hipEventRecord(pl->ev_fork, s), "fork record");
-                for (int k = 0; k < figaro_plan::kSide; k++)
+                for (int k = 0; k < nside; k++)
                     HIPCHK(hipStreamWaitEvent(pl->side[k], pl->ev_fork, 0), "fork wait");
                 forked = true;
             }
