@@ -87,7 +87,7 @@ __device__ T block_exclusive_scan(T v, T *lds, T *total)
     return incl - v;
 }
 
-// Round 1a: run starts per block, and sortedness.  Blocks [0, nbA) scan A, the rest B.
+// Pass 1a: run starts per block, and sortedness.  Blocks [0, nbA) scan A, the rest B.
 __global__ __launch_bounds__(kGroupThreads) void k_run_count(const int32_t *kA, int64_t m1,
                                                              const int32_t *kB, int64_t m2,
                                                              int nbA, int32_t *blkA, int32_t *blkB,
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(1024) void k_scan_small(T *arr0, int n0, int64_t *t
     }
 }
 
-// Round 1b: scatter the first row index of every run.
+// Pass 1b: scatter the first row index of every run.
 __global__ __launch_bounds__(kGroupThreads) void k_run_scatter(const int32_t *kA, int64_t m1,
                                                                const int32_t *kB, int64_t m2,
                                                                int nbA, const int32_t *blkA,
@@ -178,8 +178,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_run_scatter(const int32_t *kA
     }
 }
 
-// Round 2a: match each run of A against the runs of B (binary search on run keys).
-// With unsorted keys (status set by round 1a) no run matches: a key may then recur in
+// Pass 2a: match each run of A against the runs of B (binary search on run keys).
+// With unsorted keys (status set by pass 1a) no run matches: a key may then recur in
 // several runs, and the sizes the later rounds derive from matches would no longer be
 // bounded by the group table's and the regions' capacities.  The join is taken as empty.
 __global__ __launch_bounds__(kGroupThreads) void k_match(const int32_t *kA, const int32_t *runA,
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_match(const int32_t *kA, cons
     if (threadIdx.x == 0) blkM[blockIdx.x] = tot;
 }
 
-// Round 2b: emit groups; per-block sums of m1_g, m2_g - 1 and m1_g * m2_g.
+// Pass 2b: emit groups; per-block sums of m1_g, m2_g - 1 and m1_g * m2_g.
 __global__ __launch_bounds__(kGroupThreads) void k_group_emit(
     const int32_t *kA, const int32_t *runA, const int64_t *UAp, const int32_t *runB,
     const int32_t *matchA, const int32_t *blkM, Groups g, int64_t *blkS, int nb)
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(1024) void k_scan_sums(int64_t *blkS, int nb, int64
     }
 }
 
-// Round 3: r1_g, r2_g from the block offsets and a block-local scan.
+// Pass 3: r1_g, r2_g from the block offsets and a block-local scan.
 __global__ __launch_bounds__(kGroupThreads) void k_group_offsets(const int64_t *UAp,
                                                                  const int32_t *matchA,
                                                                  const int32_t *blkM,
