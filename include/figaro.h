@@ -375,6 +375,12 @@ int figaro_plan_execute(figaro_plan *plan, void *ws, size_t ws_bytes, double *R,
  */
 int figaro_plan_execute_eager(figaro_plan *plan, void *ws, size_t ws_bytes, double *R, double *sigma,
                               void *stream);
+/*
+ * Frees the plan, its graphs, launch tables, side streams and events.  A plan that
+ * has executed first waits for the device (hipDeviceSynchronize), so that launches
+ * of its graphs still in flight finish before their resources go; the autotuner
+ * does the same before it drops the plan's graphs.
+ */
 void figaro_plan_destroy(figaro_plan *plan);
 
 /* ------------------------------------------------------------ autotuning */

@@ -1752,8 +1752,12 @@ int take_stage_ms(F want, double *ms)
 
 constexpr int kTuneReps = 3;
 
+// The caller may still have a launch of one of these graphs (or an eager execution that
+// reads these tables) in flight on any stream: the device is drained before they go.
 void plan_drop_execs(figaro_plan *plan)
 {
+    if (plan->execs.empty()) return;
+    (void)hipDeviceSynchronize();
     for (auto &kv : plan->execs) {
         if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
         if (kv.second.tables) (void)hipFree(kv.second.tables);
@@ -1964,10 +1968,7 @@ int figaro_tune_dump(char *buf, size_t cap, size_t *len)
 void figaro_plan_destroy(figaro_plan *plan)
 {
     if (!plan) return;
-    for (auto &kv : plan->execs) {
-        if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
-        if (kv.second.tables) (void)hipFree(kv.second.tables);
-    }
+    plan_drop_execs(plan);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     for (int k = 0; k < figaro_plan::kSide; k++) {
         if (plan->side[k]) (void)hipStreamDestroy(plan->side[k]);
