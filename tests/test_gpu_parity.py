@@ -440,6 +440,32 @@ def test_plan_mixed_instances(prec, tol, two_sided):
             assert er <= tol and es <= tol, (rep, i, inst.shape, er, es)
 
 
+def test_plan_destroyed_while_in_flight():
+    """A plan destroyed right after its graph was launched, with no synchronisation in
+    between: destruction waits for the launch, the results are whole, and a new plan on
+    the same buffers runs normally (regression: plans used to destroy in-flight graphs)."""
+    import gc
+    insts = W.config4(count=6, lo=2.0, hi=3.3)
+    say(f"[plan destroy] shapes={[i.shape for i in insts]}")
+    tens = [to_dev(i) for i in insts]
+    refs = [oracle.r(inst) for inst in insts]
+    d = tens[0][0].device
+    for rep in range(2):
+        plan = fg().Plan(tens, "fp32", two_sided=True)
+        r_off = list(plan.r_off)
+        ws = torch.empty(plan.ws_bytes, dtype=torch.uint8, device=d)
+        R = torch.full((plan.r_total,), 7.0, dtype=torch.float64, device=d)
+        S = torch.zeros(plan.s_total, dtype=torch.float64, device=d)
+        plan.execute(ws, R, S)
+        del plan
+        gc.collect()
+        Rh = R.cpu().numpy()
+        for i, inst in enumerate(insts):
+            N = inst.A.shape[1] + inst.B.shape[1]
+            Rg = Rh[r_off[i]:r_off[i] + N * N].reshape(N, N)
+            assert relF(Rg, refs[i]) <= 1e-5, (rep, i)
+
+
 # ------------------------------------------------------------------ the Givens route
 
 @pytest.mark.parametrize("name", ["cart_tiny", "cart_ragged", "cart_uniform_paper", "keyed_zipf_n64",
