@@ -351,7 +351,8 @@ int figaro_plan_offsets(const figaro_plan *plan, int64_t *r_off, int64_t *s_off,
  *   sigma by the bidiagonal route of figaro_sigma_bidiag (two launches per width
  *   class over all instances, the classes side by side on the plan's side
  *   streams; the multisection there locates each value with 16 lanes and 16
- *   points per round, 14 rounds).  Without refinement, where the tuning table
+ *   points per round, 14 rounds, or at width class 128 with 4 lanes and 4
+ *   points per round, 24 rounds).  Without refinement, where the tuning table
  *   says so, the instances with n1 + n2 > 64 and the others run their trees,
  *   roots and sigma as two chains side by side instead (after the assembly).
  *   The side streams (four, default priority) are forked from `stream` by an

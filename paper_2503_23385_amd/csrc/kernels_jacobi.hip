@@ -1258,7 +1258,15 @@ hipError_t launch_sigma_batch(int npc, const double *R, double *sigma, const int
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dqds) k_sigma_dqds_batch<<<count, 64, 0, s>>>(tab, msin, sigma);
-    else {
+    else if (npc == 128) {
+        // the widest class holds the most values, and its launch is bound by the issue rate
+        // of the Sturm counts: 4 lanes per value (24 rounds, 96 counts per value) beat 16
+        // (14 rounds, 224 counts) there, while the narrower classes, with fewer values, are
+        // bound by the rounds' latency and keep 16 (measured on the 256-instance batch)
+        constexpr int G = 4;
+        const unsigned nb = (unsigned)((npc + MsWave<G>::VPB - 1) / MsWave<G>::VPB);
+        k_sigma_msect_wave_batch<G><<<dim3(nb, count), 256, 0, s>>>(tab, msin, sigma);
+    } else {
         constexpr int G = 16;
         const unsigned nb = (unsigned)((npc + MsWave<G>::VPB - 1) / MsWave<G>::VPB);
         k_sigma_msect_wave_batch<G><<<dim3(nb, count), 256, 0, s>>>(tab, msin, sigma);
